@@ -1,0 +1,200 @@
+"""FP64 CPU oracle for the quantum-walk hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the HIP engine and imports nothing from it; the two meet only at
+the seeded input generators, which hold none of the walk arithmetic.
+
+Contents
+--------
+* ``qw_oracle.c`` (loaded here through ctypes): the coined step and the
+  CTQW Taylor step written out from their definitions, plus probabilities.
+* :mod:`oracle.taylor`: the truncation-order / step-size rule for the
+  Taylor propagator.
+* :mod:`oracle.closed_forms`: exact results the physics fixes (Bessel
+  images on cycles, Kronecker-product torus, complete-graph search, the
+  symmetric-subspace reduction of hypercube search), used as pins and as
+  full-size checks.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qw_oracle.c")
+_LIB = os.path.join(_HERE, "libqworacle.so")
+
+GROVER = 0
+HADAMARD = 1
+
+FAULTS = {
+    "coin_delta_sign": 1,
+    "no_shift": 2,
+    "head_prob": 3,
+    "ctqw_no_mark": 4,
+    "ctqw_plus_i": 5,
+    "taylor_short": 6,
+    "hadamard_swap": 7,
+    "mark_plus": 8,
+    "gamma_on_mark": 9,
+}
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain IEEE double, no contraction)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    cmd = ["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = C.CDLL(_LIB)
+        i64p = C.POINTER(C.c_int64)
+        i32p = C.POINTER(C.c_int32)
+        u8p = C.POINTER(C.c_uint8)
+        dp = C.POINTER(C.c_double)
+        lib.orc_reverse_arcs.argtypes = [C.c_int64, i64p, i32p, i64p]
+        lib.orc_reverse_arcs.restype = C.c_int
+        lib.orc_coined_evolve.argtypes = [C.c_int64, i64p, i32p, i64p, C.c_int, u8p, dp, C.c_int64]
+        lib.orc_coined_evolve.restype = C.c_int
+        lib.orc_coined_prob.argtypes = [C.c_int64, i64p, i32p, dp, dp]
+        lib.orc_coined_prob.restype = None
+        lib.orc_ctqw_evolve.argtypes = [C.c_int64, i64p, i32p, C.c_double, u8p, C.c_double,
+                                        C.c_int32, dp, C.c_int64]
+        lib.orc_ctqw_evolve.restype = C.c_int
+        lib.orc_vertex_prob.argtypes = [C.c_int64, dp, dp]
+        lib.orc_vertex_prob.restype = None
+        lib.orc_set_fault.argtypes = [C.c_int]
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_max_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _csr(row_ptr, col):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    return rp, cl
+
+
+def _marked_bytes(n, marked):
+    m = np.zeros(max(n, 1), dtype=np.uint8)
+    if marked is not None and len(marked):
+        m[np.asarray(marked, dtype=np.int64)] = 1
+    return m
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+class fault:
+    """Context manager that plants one named mistake in the oracle."""
+
+    def __init__(self, name: str):
+        self.code = FAULTS[name]
+
+    def __enter__(self):
+        _load().orc_set_fault(self.code)
+        return self
+
+    def __exit__(self, *exc):
+        _load().orc_set_fault(0)
+        return False
+
+
+def reverse_arcs(row_ptr, col) -> np.ndarray:
+    """rev[a] = position of the reverse arc; ValueError if the graph is invalid."""
+    rp, cl = _csr(row_ptr, col)
+    n = rp.size - 1
+    rev = np.empty(max(cl.size, 1), dtype=np.int64)
+    st = _load().orc_reverse_arcs(n, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32), _ptr(rev, C.c_int64))
+    if st == -1:
+        raise ValueError("adjacency is not symmetric")
+    if st == -2:
+        raise ValueError("self-loop")
+    return rev[:cl.size]
+
+
+def coined_evolve(row_ptr, col, psi0, steps: int, coin: int = GROVER, marked=None) -> np.ndarray:
+    """(S C)^steps psi0 on the CSR arc basis; returns complex128[n_arcs]."""
+    rp, cl = _csr(row_ptr, col)
+    n = rp.size - 1
+    rev = reverse_arcs(rp, cl)
+    if rev.size == 0:
+        rev = np.zeros(1, np.int64)
+    psi = np.ascontiguousarray(np.array(psi0, dtype=np.complex128, copy=True))
+    if psi.size != cl.size:
+        raise ValueError("state length must equal the arc count")
+    m = _marked_bytes(n, marked)
+    buf = psi.view(np.float64) if psi.size else np.zeros(2, np.float64)
+    st = _load().orc_coined_evolve(n, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
+                                   _ptr(rev, C.c_int64), int(coin), _ptr(m, C.c_uint8),
+                                   _ptr(buf, C.c_double), int(steps))
+    if st == -3:
+        raise ValueError("Hadamard coin needs degree 2 at every unmarked vertex")
+    if st != 0:
+        raise RuntimeError(f"oracle coined evolve failed ({st})")
+    return psi
+
+
+def coined_prob(row_ptr, col, psi) -> np.ndarray:
+    rp, cl = _csr(row_ptr, col)
+    n = rp.size - 1
+    x = np.ascontiguousarray(psi, dtype=np.complex128)
+    p = np.empty(max(n, 1), dtype=np.float64)
+    buf = x.view(np.float64) if x.size else np.zeros(2)
+    _load().orc_coined_prob(n, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32), _ptr(buf, C.c_double),
+                            _ptr(p, C.c_double))
+    return p[:n]
+
+
+def ctqw_evolve(row_ptr, col, psi0, steps: int, gamma: float, dt: float, K: int,
+                marked=None) -> np.ndarray:
+    """T_K(-i H dt)^steps psi0 with H = -gamma A - sum_M |v><v| (power form)."""
+    rp, cl = _csr(row_ptr, col)
+    n = rp.size - 1
+    psi = np.ascontiguousarray(np.array(psi0, dtype=np.complex128, copy=True))
+    if psi.size != n:
+        raise ValueError("state length must equal the vertex count")
+    m = _marked_bytes(n, marked)
+    cl2 = cl if cl.size else np.zeros(1, np.int32)
+    st = _load().orc_ctqw_evolve(n, _ptr(rp, C.c_int64), _ptr(cl2, C.c_int32), float(gamma),
+                                 _ptr(m, C.c_uint8), float(dt), int(K),
+                                 _ptr(psi.view(np.float64), C.c_double), int(steps))
+    if st != 0:
+        raise RuntimeError(f"oracle ctqw evolve failed ({st})")
+    return psi
+
+
+def vertex_prob(psi) -> np.ndarray:
+    x = np.ascontiguousarray(psi, dtype=np.complex128)
+    p = np.empty(max(x.size, 1), dtype=np.float64)
+    buf = x.view(np.float64) if x.size else np.zeros(2)
+    _load().orc_vertex_prob(x.size, _ptr(buf, C.c_double), _ptr(p, C.c_double))
+    return p[:x.size]
+
+
+from . import closed_forms, taylor  # noqa: E402,F401
