@@ -1,0 +1,207 @@
+/*
+ * qwalk.h -- C ABI of the MI355X quantum-walk step engine.
+ *
+ * The engine applies the time-evolution step of the two walk models of
+ * Hiperwalk (arXiv 2406.08186) to a complex state vector held in device
+ * memory, and reduces the state to per-vertex probabilities in FP64.
+ *
+ *   Coined walk (Sec. 3.2): one step is psi <- S C psi, with the flip-flop
+ *   shift S|v,w> = |w,v> and the Grover coin
+ *   C|v,w> = sum_{v' in N(v)} (2/d(v) - delta_{w,v'}) |v,v'>.  The arc basis is
+ *   the paper's: arcs grouped by tail, the group of tail v being row v of the
+ *   CSR adjacency.  Two extensions serve the benchmark workloads: the
+ *   Hadamard coin (1/sqrt2)[[1,1],[1,-1]] on a degree-2 vertex's two arcs in
+ *   row order, and the coin -I at marked vertices (spatial search).
+ *   Probability (Sec. 3.2): p_v = sum over arcs with tail v of |psi_a|^2.
+ *
+ *   Continuous-time walk (Sec. 3.1): H = -gamma A - sum_{v in M} |v><v|,
+ *   psi(t) = exp(-iHt) psi(0).  One step of length dt applies the order-K
+ *   Taylor polynomial T_K(-iH dt) = sum_{k=0..K} (-iH dt)^k / k!, evaluated
+ *   as K sparse products (Horner form).  Probability (Sec. 3.1):
+ *   p_v = |psi_v|^2.
+ *
+ * Conventions
+ *   - Every function returns a status (QW_OK or an error code) and never
+ *     throws; qw_last_error() gives a thread-local description of the last
+ *     failure on the calling thread.
+ *   - Host pointers are read during the call only; the library copies what
+ *     it keeps.  Device pointers are caller-owned: the library never
+ *     allocates, frees or retains device memory beyond what the caller
+ *     passes in, and never frees caller memory.
+ *   - Complex arrays are interleaved (re, im): float2 for QW_C64, double2
+ *     for QW_C128 (the layout of torch.complex64 / torch.complex128).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device-side calls are asynchronous on it: they enqueue kernels and
+ *     copies and return; errors of the kernels themselves surface at the
+ *     caller's next synchronising call.  They perform no allocation and no
+ *     host synchronisation, so they may be captured into a hipGraph.
+ */
+#ifndef QWALK_H
+#define QWALK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define QW_OK 0
+#define QW_EINVAL 1       /* null pointer, bad enum, out-of-range scalar       */
+#define QW_EGRAPH 2       /* adjacency not a simple symmetric graph            */
+#define QW_EUNSUPPORTED 3 /* valid input outside what the engine implements    */
+#define QW_ENOMEM 4       /* caller buffer smaller than the size query / host  */
+#define QW_EDEVICE 5      /* a HIP runtime call or kernel launch failed        */
+#define QW_ESTATE 6       /* call out of order (e.g. evolve before upload)     */
+
+/* ---- enums ------------------------------------------------------------- */
+#define QW_COINED 0
+#define QW_CTQW 1
+
+#define QW_GROVER 0
+#define QW_HADAMARD 1
+
+#define QW_C64 0  /* complex64 state, FP64 reductions */
+#define QW_C128 1 /* complex128 state                 */
+
+/* Path choice.  AUTO runs a walk small enough for one workgroup's LDS in a
+ * single launch, otherwise recognises cycles, periodic 2-D grids and
+ * hypercubes in the CSR and uses index-free structured kernels for them, and
+ * otherwise the general sparse kernels.  CSR forces the general sparse
+ * kernels.  STRUCTURED is AUTO without the one-workgroup path. */
+#define QW_LAYOUT_AUTO 0
+#define QW_LAYOUT_CSR 1
+#define QW_LAYOUT_STRUCTURED 2
+
+/* Structure the plan chose (reported by qw_plan_get_info). */
+#define QW_STRUCT_GENERAL 0
+#define QW_STRUCT_CYCLE 1
+#define QW_STRUCT_TORUS 2
+#define QW_STRUCT_HYPERCUBE 3
+#define QW_STRUCT_SMALL 4 /* whole walk resident in one workgroup's LDS */
+
+/* ---- graph ------------------------------------------------------------- */
+/* Adjacency pattern of a simple undirected graph (Sec. 3.1 and 3.2 take the
+ * graph as its adjacency matrix A).  Host memory, read at plan creation.
+ *   n        vertices, 0 <= n < 2^31
+ *   row_ptr  int64[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = number
+ *            of arcs (= nnz(A) = 2|E|), below 2^31
+ *   col      int32[row_ptr[n]]: heads of the arcs whose tail is the row.
+ * A must be symmetric with no self-loops and no repeated entries in a row
+ * (else QW_EGRAPH).  Rows need not be sorted: the order of row v is the
+ * order of v's coin basis (the paper's default is ascending head labels). */
+typedef struct qw_csr {
+  int64_t n;
+  const int64_t *row_ptr;
+  const int32_t *col;
+} qw_csr;
+
+/* ---- walk description --------------------------------------------------- */
+typedef struct qw_walk_desc {
+  int32_t kind;         /* QW_COINED or QW_CTQW                                */
+  int32_t coin;         /* coined: QW_GROVER or QW_HADAMARD (degree 2 only)    */
+  int32_t dtype;        /* QW_C64 or QW_C128                                   */
+  int32_t layout;       /* QW_LAYOUT_AUTO or QW_LAYOUT_CSR                     */
+  double gamma;         /* CTQW: gamma > 0 (Sec. 3.1)                          */
+  double dt;            /* CTQW: step length > 0                               */
+  int32_t taylor_order; /* CTQW: K in [1, 64]; 0 = smallest K meeting trunc_tol
+                           over horizon_steps steps (qw_taylor_order)          */
+  double trunc_tol;     /* CTQW, taylor_order = 0: bound on the accumulated
+                           truncation error                                    */
+  int64_t horizon_steps;/* CTQW, taylor_order = 0: steps the bound must cover  */
+  const int32_t *marked;/* host int32[n_marked], distinct vertices in [0, n):
+                           coin -I (coined) / -|v><v| term (CTQW); may be NULL
+                           when n_marked = 0                                   */
+  int64_t n_marked;
+} qw_walk_desc;
+
+typedef struct qw_plan qw_plan;
+
+typedef struct qw_plan_info {
+  int64_t n;               /* vertices                                        */
+  int64_t n_arcs;          /* arcs (= 2|E|)                                   */
+  int64_t state_len;       /* complex elements of the state: n_arcs (coined)
+                              or n (CTQW)                                     */
+  int32_t kind, coin, dtype, structure;
+  int32_t dims[2];         /* CYCLE: {n,0}; TORUS: {l1,l2}; HYPERCUBE: {dim,0}*/
+  int32_t max_degree;
+  int32_t taylor_order;    /* CTQW: K in use                                  */
+  double dt;               /* CTQW: step length                               */
+  double h_norm_bound;     /* CTQW: max_v gamma d(v) + [v in M]               */
+  double trunc_bound;      /* CTQW: per-step truncation bound at (dt, K)      */
+  size_t graph_bytes;      /* device bytes qw_plan_upload needs               */
+  size_t state_bytes;      /* bytes of one state vector                       */
+  size_t work_bytes;       /* device workspace qw_evolve/qw_probabilities need*/
+} qw_plan_info;
+
+/* Validate the graph and the walk, precompute the host-side tables (reverse
+ * arcs, degree tiles, structure recognition, Taylor order), and return a new
+ * plan in *out.  Host only: touches no device.  Errors: QW_EINVAL (null
+ * pointers, bad enums, gamma/dt not positive, marked vertex out of range or
+ * repeated), QW_EGRAPH (asymmetric, self-loop, repeated arc, malformed
+ * row_ptr, head out of range), QW_EUNSUPPORTED (Hadamard at an unmarked
+ * vertex of degree other than 0 or 2, arcs >= 2^31, no K <= 64 meets
+ * trunc_tol), QW_ENOMEM (host allocation).  On error *out is NULL. */
+int qw_plan_create(const qw_csr *graph, const qw_walk_desc *walk, qw_plan **out);
+
+/* Free a plan (host memory only).  NULL is accepted. */
+int qw_plan_destroy(qw_plan *plan);
+
+/* Sizes and choices of a plan. */
+int qw_plan_get_info(const qw_plan *plan, qw_plan_info *info);
+
+/* Copy the plan's device tables into the caller's device buffer d_graph
+ * (at least info.graph_bytes bytes, 256-byte aligned) on `stream`, and bind
+ * the plan to that buffer: later calls read it, so it must stay allocated
+ * and unmodified while the plan is used.  A plan is bound to one buffer at a
+ * time; uploading again rebinds it.  Not thread-safe against concurrent
+ * calls on the same plan.  Errors: QW_EINVAL, QW_ENOMEM (buffer too small),
+ * QW_EDEVICE. */
+int qw_plan_upload(qw_plan *plan, void *d_graph, size_t graph_bytes, void *stream);
+
+/* Advance the state by `steps` steps in place: psi <- U^steps psi (coined)
+ * or psi <- T_K(-iH dt)^steps psi (CTQW).  d_psi: device state of
+ * info.state_len complex elements in the boundary layout (coined: CSR arc
+ * order; CTQW: vertex order), read and written.  d_work: device workspace of
+ * at least info.work_bytes bytes, contents undefined on return.  If any of
+ * d_p (double[n]), d_norm (double[1]), d_pmarked (double[1]) is non-NULL the
+ * readout of qw_probabilities is produced from the final state as part of
+ * the same call (fused into the last kernel where the layout permits).
+ * steps = 0 leaves psi unchanged.  Errors: QW_EINVAL, QW_ENOMEM (workspace
+ * too small), QW_ESTATE (not uploaded), QW_EDEVICE. */
+int qw_evolve(const qw_plan *plan, void *d_psi, void *d_work, size_t work_bytes, int64_t steps,
+              double *d_p, double *d_norm, double *d_pmarked, void *stream);
+
+/* FP64 readout of a state (Sec. 3.1, Sec. 3.2): d_p[v] = probability of
+ * vertex v (coined: summed over arcs with tail v; CTQW: |psi_v|^2),
+ * *d_norm = sum_v p_v, *d_pmarked = sum over the marked set of p_v.  Each
+ * output pointer may be NULL.  Sums run in a fixed order: results are
+ * bitwise reproducible for a given plan.  Errors as qw_evolve. */
+int qw_probabilities(const qw_plan *plan, const void *d_psi, double *d_p, double *d_norm,
+                     double *d_pmarked, void *d_work, size_t work_bytes, void *stream);
+
+/* ---- Taylor truncation rule (FP64, host) -------------------------------- */
+/* With rho = dt * ||H|| the one-step remainder of the order-K series is at
+ * most rho^(K+1)/(K+1)! * (K+2)/(K+2-rho) (valid for rho < K+2).
+ * qw_taylor_order: smallest K in [1, 64] with steps * bound <= tol, in *K;
+ * QW_EUNSUPPORTED if none.  qw_taylor_plan: for a total time t_total, the
+ * smallest step count keeping rho <= rho_max, dt = t_total / steps, and K
+ * from qw_taylor_order.  Errors: QW_EINVAL for non-positive or non-finite
+ * arguments. */
+int qw_taylor_order(double rho, int64_t steps, double tol, int32_t *K);
+int qw_taylor_plan(double h_bound, double t_total, double rho_max, double tol, int32_t *K,
+                   double *dt, int64_t *steps);
+double qw_taylor_tail_bound(double rho, int32_t K);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *qw_last_error(void);
+
+/* Library version string. */
+const char *qw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QWALK_H */

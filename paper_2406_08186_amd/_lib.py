@@ -1,0 +1,145 @@
+"""ctypes binding of libqwalk.so (the C ABI in include/qwalk.h).
+
+Argument marshalling only: every step of the walk runs in the library's HIP
+kernels.  The library is loaded after torch so that both share torch's HIP
+runtime (same SONAME); if it is missing, loading fails loudly -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqwalk.so")
+
+QW_OK, QW_EINVAL, QW_EGRAPH, QW_EUNSUPPORTED, QW_ENOMEM, QW_EDEVICE, QW_ESTATE = range(7)
+ERRORS = {1: "QW_EINVAL", 2: "QW_EGRAPH", 3: "QW_EUNSUPPORTED", 4: "QW_ENOMEM", 5: "QW_EDEVICE",
+          6: "QW_ESTATE"}
+QW_COINED, QW_CTQW = 0, 1
+QW_GROVER, QW_HADAMARD = 0, 1
+QW_C64, QW_C128 = 0, 1
+QW_LAYOUT_AUTO, QW_LAYOUT_CSR, QW_LAYOUT_STRUCTURED = 0, 1, 2
+STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small"}
+
+EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upload", "qw_evolve",
+           "qw_probabilities", "qw_taylor_order", "qw_taylor_plan", "qw_taylor_tail_bound",
+           "qw_last_error", "qw_version"]
+
+
+class QwCsr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("row_ptr", C.POINTER(C.c_int64)), ("col", C.POINTER(C.c_int32))]
+
+
+class QwWalkDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("coin", C.c_int32), ("dtype", C.c_int32), ("layout", C.c_int32),
+                ("gamma", C.c_double), ("dt", C.c_double), ("taylor_order", C.c_int32),
+                ("trunc_tol", C.c_double), ("horizon_steps", C.c_int64),
+                ("marked", C.POINTER(C.c_int32)), ("n_marked", C.c_int64)]
+
+
+class QwPlanInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_arcs", C.c_int64), ("state_len", C.c_int64),
+                ("kind", C.c_int32), ("coin", C.c_int32), ("dtype", C.c_int32), ("structure", C.c_int32),
+                ("dims", C.c_int32 * 2), ("max_degree", C.c_int32), ("taylor_order", C.c_int32),
+                ("dt", C.c_double), ("h_norm_bound", C.c_double), ("trunc_bound", C.c_double),
+                ("graph_bytes", C.c_size_t), ("state_bytes", C.c_size_t), ("work_bytes", C.c_size_t)]
+
+
+class QwError(RuntimeError):
+    def __init__(self, code: int, fn: str, msg: str):
+        super().__init__(f"{fn}: {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2406_08186_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        dp = C.POINTER(C.c_double)
+        L.qw_plan_create.argtypes = [C.POINTER(QwCsr), C.POINTER(QwWalkDesc), C.POINTER(vp)]
+        L.qw_plan_destroy.argtypes = [vp]
+        L.qw_plan_get_info.argtypes = [vp, C.POINTER(QwPlanInfo)]
+        L.qw_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
+        L.qw_evolve.argtypes = [vp, vp, vp, C.c_size_t, C.c_int64, vp, vp, vp, vp]
+        L.qw_probabilities.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.qw_taylor_order.argtypes = [C.c_double, C.c_int64, C.c_double, C.POINTER(C.c_int32)]
+        L.qw_taylor_plan.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int32),
+                                     dp, C.POINTER(C.c_int64)]
+        L.qw_taylor_tail_bound.argtypes = [C.c_double, C.c_int32]
+        L.qw_taylor_tail_bound.restype = C.c_double
+        L.qw_last_error.restype = C.c_char_p
+        L.qw_version.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("qw_taylor_tail_bound", "qw_last_error", "qw_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(code: int, fn: str) -> None:
+    if code != QW_OK:
+        raise QwError(code, fn, lib().qw_last_error().decode())
+
+
+# ---- same-named thin wrappers ------------------------------------------------
+
+def qw_plan_create(csr: QwCsr, desc: QwWalkDesc) -> C.c_void_p:
+    out = C.c_void_p()
+    check(lib().qw_plan_create(C.byref(csr), C.byref(desc), C.byref(out)), "qw_plan_create")
+    return out
+
+
+def qw_plan_destroy(plan) -> None:
+    check(lib().qw_plan_destroy(plan), "qw_plan_destroy")
+
+
+def qw_plan_get_info(plan) -> QwPlanInfo:
+    info = QwPlanInfo()
+    check(lib().qw_plan_get_info(plan, C.byref(info)), "qw_plan_get_info")
+    return info
+
+
+def qw_plan_upload(plan, d_graph: int, nbytes: int, stream: int) -> None:
+    check(lib().qw_plan_upload(plan, d_graph, nbytes, stream), "qw_plan_upload")
+
+
+def qw_evolve(plan, d_psi: int, d_work: int, work_bytes: int, steps: int, d_p, d_norm, d_pmarked,
+              stream: int) -> None:
+    check(lib().qw_evolve(plan, d_psi, d_work, work_bytes, steps, d_p, d_norm, d_pmarked, stream),
+          "qw_evolve")
+
+
+def qw_probabilities(plan, d_psi: int, d_p, d_norm, d_pmarked, d_work: int, work_bytes: int,
+                     stream: int) -> None:
+    check(lib().qw_probabilities(plan, d_psi, d_p, d_norm, d_pmarked, d_work, work_bytes, stream),
+          "qw_probabilities")
+
+
+def qw_taylor_order(rho: float, steps: int, tol: float) -> int:
+    k = C.c_int32()
+    check(lib().qw_taylor_order(rho, steps, tol, C.byref(k)), "qw_taylor_order")
+    return k.value
+
+
+def qw_taylor_plan(h_bound: float, t_total: float, rho_max: float, tol: float):
+    k, dt, n = C.c_int32(), C.c_double(), C.c_int64()
+    check(lib().qw_taylor_plan(h_bound, t_total, rho_max, tol, C.byref(k), C.byref(dt), C.byref(n)),
+          "qw_taylor_plan")
+    return k.value, dt.value, n.value
+
+
+def qw_taylor_tail_bound(rho: float, K: int) -> float:
+    return float(lib().qw_taylor_tail_bound(rho, K))
+
+
+def qw_version() -> str:
+    return lib().qw_version().decode()

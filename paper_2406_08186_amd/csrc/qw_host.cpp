@@ -1,0 +1,627 @@
+// Host runtime of the quantum-walk step engine: the C ABI declared in
+// include/qwalk.h.  Plan creation validates the adjacency, builds the device
+// tables (reverse arcs for the flip-flop shift, LDS tiles, structure maps,
+// marked-vertex bitmap) into one host image, and fixes the Taylor order; the
+// device-side calls only enqueue kernels on the caller's stream.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "qw_internal.h"
+#include "qwalk.h"
+
+using namespace qwk;
+
+struct qw_plan {
+  int32_t kind = QW_COINED, coin = QW_GROVER, dtype = QW_C128, layout = QW_LAYOUT_AUTO;
+  int32_t structure = kGeneral;
+  int64_t n = 0, n_arcs = 0;
+  int32_t dims[2] = {0, 0};
+  int32_t max_degree = 0;
+  double gamma = 0.0, dt = 0.0, h_bound = 0.0, trunc_bound = 0.0;
+  int32_t K = 0;
+  int32_t n_marked = 0;
+  int32_t n_tiles = 0;
+  int32_t group = 1;
+  // host image of the device graph buffer, and section offsets into it
+  std::vector<unsigned char> image;
+  size_t off_rp = 0, off_col = 0, off_rev = 0, off_tiles = 0, off_perm = 0, off_bits = 0, off_mlist = 0;
+  bool has_col = false, has_rev = false, has_tiles = false, has_perm = false;
+  // device binding
+  unsigned char *d_graph = nullptr;
+  GraphView view;
+  // workspace layout
+  size_t state_bytes = 0, off_w1 = 0, off_pscratch = 0, off_partials = 0, work_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return QW_OK;
+}
+
+int dev_fail(hipError_t e, const char *what) {
+  return fail(QW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// ---- Taylor remainder bound -------------------------------------------------
+double tail_bound(double rho, int K) {
+  if (rho <= 0.0) return 0.0;
+  if (rho >= K + 2) return std::numeric_limits<double>::infinity();
+  const double lead = std::exp((K + 1) * std::log(rho) - std::lgamma(K + 2.0));
+  return lead * (K + 2) / (K + 2 - rho);
+}
+
+int taylor_order(double rho, int64_t steps, double tol) {
+  for (int K = 1; K <= 64; ++K)
+    if (static_cast<double>(steps) * tail_bound(rho, K) <= tol) return K;
+  return -1;
+}
+
+// ---- structure recognition ---------------------------------------------------
+int ctz32(uint32_t x) { return __builtin_ctz(x); }
+
+bool is_hypercube(int64_t n, const std::vector<int64_t> &rp, const int32_t *col, int32_t *dim_out) {
+  if (n < 2 || (n & (n - 1)) != 0) return false;
+  const int dim = ctz32(static_cast<uint32_t>(n));
+  if (dim > kMaxHypercubeDim) return false;
+  for (int64_t v = 0; v < n; ++v) {
+    if (rp[v + 1] - rp[v] != dim) return false;
+    for (int64_t a = rp[v]; a < rp[v + 1]; ++a) {
+      const uint32_t x = static_cast<uint32_t>(v) ^ static_cast<uint32_t>(col[a]);
+      if (x == 0 || (x & (x - 1)) != 0) return false;
+    }
+  }
+  *dim_out = dim;
+  return true;
+}
+
+bool is_cycle(int64_t n, const std::vector<int64_t> &rp, const int32_t *col, bool ordered) {
+  if (n < 3) return false;
+  for (int64_t v = 0; v < n; ++v) {
+    if (rp[v + 1] - rp[v] != 2) return false;
+    const int64_t up = (v + 1) % n, dn = (v + n - 1) % n;
+    const int64_t h0 = col[rp[v]], h1 = col[rp[v] + 1];
+    const bool fwd = (h0 == up && h1 == dn), bwd = (h0 == dn && h1 == up);
+    if (!(fwd || (!ordered && bwd))) return false;
+  }
+  return true;
+}
+
+bool is_torus(int64_t n, const std::vector<int64_t> &rp, const int32_t *col, int32_t *l1o, int32_t *l2o) {
+  if (n < 9 || rp[1] - rp[0] != 4) return false;
+  int64_t s[4];
+  for (int i = 0; i < 4; ++i) s[i] = col[rp[0] + i];
+  std::sort(s, s + 4);
+  const int64_t l2 = s[2];
+  if (s[0] != 1 || s[1] != l2 - 1 || l2 < 3 || n % l2 != 0) return false;
+  const int64_t l1 = n / l2;
+  if (l1 < 3 || s[3] != n - l2) return false;
+  for (int64_t v = 0; v < n; ++v) {
+    if (rp[v + 1] - rp[v] != 4) return false;
+    const int64_t r = v / l2, c = v % l2;
+    int64_t want[4] = {r * l2 + (c + 1) % l2, r * l2 + (c + l2 - 1) % l2, ((r + 1) % l1) * l2 + c,
+                       ((r + l1 - 1) % l1) * l2 + c};
+    int64_t got[4];
+    for (int i = 0; i < 4; ++i) got[i] = col[rp[v] + i];
+    std::sort(want, want + 4);
+    std::sort(got, got + 4);
+    if (!std::equal(want, want + 4, got)) return false;
+  }
+  *l1o = static_cast<int32_t>(l1);
+  *l2o = static_cast<int32_t>(l2);
+  return true;
+}
+
+// slot of arc (v, w) in the slot-major structured layouts
+int slot_of(int structure, int64_t v, int64_t w, int64_t n, int32_t l2) {
+  if (structure == kCycle) return w == (v + 1) % n ? 0 : 1;
+  if (structure == kTorus) {
+    const int64_t l1 = n / l2;
+    const int64_t r = v / l2, c = v % l2, rw = w / l2, cw = w % l2;
+    if (rw == r) return cw == (c + 1) % l2 ? 0 : 1;
+    (void)l1;
+    return rw == (r + 1) % l1 ? 2 : 3;
+  }
+  return ctz32(static_cast<uint32_t>(v ^ w));
+}
+
+template <typename X>
+void put(std::vector<unsigned char> &img, size_t off, const X *src, size_t count) {
+  if (count) std::memcpy(img.data() + off, src, count * sizeof(X));
+}
+
+int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
+  if (!g || !w) return fail(QW_EINVAL, "null graph or walk descriptor");
+  const int64_t n = g->n;
+  if (n < 0 || n >= (int64_t{1} << 31)) return fail(QW_EINVAL, "vertex count %lld out of range", (long long)n);
+  if (w->kind != QW_COINED && w->kind != QW_CTQW) return fail(QW_EINVAL, "bad walk kind %d", w->kind);
+  if (w->dtype != QW_C64 && w->dtype != QW_C128) return fail(QW_EINVAL, "bad dtype %d", w->dtype);
+  if (w->layout < QW_LAYOUT_AUTO || w->layout > QW_LAYOUT_STRUCTURED)
+    return fail(QW_EINVAL, "bad layout %d", w->layout);
+  if (w->kind == QW_COINED && w->coin != QW_GROVER && w->coin != QW_HADAMARD)
+    return fail(QW_EINVAL, "bad coin %d", w->coin);
+  if (w->n_marked < 0 || (w->n_marked > 0 && !w->marked)) return fail(QW_EINVAL, "bad marked list");
+  if (n > 0 && (!g->row_ptr)) return fail(QW_EINVAL, "null row_ptr");
+  p->kind = w->kind;
+  p->coin = w->kind == QW_COINED ? w->coin : QW_GROVER;
+  p->dtype = w->dtype;
+  p->layout = w->layout;
+  p->n = n;
+
+  // ---- CSR validation
+  std::vector<int64_t> rp(static_cast<size_t>(n) + 1, 0);
+  if (n > 0) std::memcpy(rp.data(), g->row_ptr, sizeof(int64_t) * (n + 1));
+  if (rp[0] != 0) return fail(QW_EGRAPH, "row_ptr[0] must be 0");
+  for (int64_t v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v]) return fail(QW_EGRAPH, "row_ptr decreases at row %lld", (long long)v);
+  const int64_t na = rp[n];
+  if (na >= (int64_t{1} << 31)) return fail(QW_EUNSUPPORTED, "%lld arcs: the engine indexes arcs with int32", (long long)na);
+  if (na > 0 && !g->col) return fail(QW_EINVAL, "null col");
+  p->n_arcs = na;
+  const int32_t *col = g->col;
+  int32_t maxd = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    maxd = std::max<int32_t>(maxd, static_cast<int32_t>(rp[v + 1] - rp[v]));
+    for (int64_t a = rp[v]; a < rp[v + 1]; ++a) {
+      if (col[a] < 0 || col[a] >= n) return fail(QW_EGRAPH, "head %d out of range in row %lld", col[a], (long long)v);
+      if (col[a] == v) return fail(QW_EGRAPH, "self-loop at vertex %lld", (long long)v);
+    }
+  }
+  p->max_degree = maxd;
+  // rows sorted by head (positions), duplicates, reverse arcs
+  std::vector<int32_t> order(static_cast<size_t>(na));
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t *o = order.data() + rp[v];
+    const int64_t d = rp[v + 1] - rp[v];
+    for (int64_t i = 0; i < d; ++i) o[i] = static_cast<int32_t>(rp[v] + i);
+    std::sort(o, o + d, [&](int32_t x, int32_t y) { return col[x] < col[y]; });
+    for (int64_t i = 1; i < d; ++i)
+      if (col[o[i]] == col[o[i - 1]]) return fail(QW_EGRAPH, "repeated arc (%lld,%d)", (long long)v, col[o[i]]);
+  }
+  std::vector<int32_t> rev(static_cast<size_t>(na));
+  for (int64_t v = 0; v < n; ++v) {
+    for (int64_t a = rp[v]; a < rp[v + 1]; ++a) {
+      const int64_t u = col[a];
+      const int32_t *lo = order.data() + rp[u], *hi = order.data() + rp[u + 1];
+      const int32_t *it = std::lower_bound(lo, hi, v, [&](int32_t x, int64_t key) { return col[x] < key; });
+      if (it == hi || col[*it] != v)
+        return fail(QW_EGRAPH, "adjacency not symmetric: arc (%lld,%lld) has no reverse", (long long)v, (long long)u);
+      rev[a] = *it;
+    }
+  }
+  std::vector<int32_t>().swap(order);
+
+  // ---- marked set
+  std::vector<uint32_t> bits(static_cast<size_t>((n + 31) / 32) + 1, 0u);
+  std::vector<int32_t> mlist(static_cast<size_t>(w->n_marked));
+  for (int64_t i = 0; i < w->n_marked; ++i) {
+    const int32_t m = w->marked[i];
+    if (m < 0 || m >= n) return fail(QW_EINVAL, "marked vertex %d out of range", m);
+    if ((bits[m >> 5] >> (m & 31)) & 1u) return fail(QW_EINVAL, "marked vertex %d repeated", m);
+    bits[m >> 5] |= 1u << (m & 31);
+    mlist[i] = m;
+  }
+  p->n_marked = static_cast<int32_t>(w->n_marked);
+
+  // ---- walk parameters
+  if (p->kind == QW_COINED && p->coin == QW_HADAMARD) {
+    for (int64_t v = 0; v < n; ++v) {
+      const int64_t d = rp[v + 1] - rp[v];
+      const bool mk = (bits[v >> 5] >> (v & 31)) & 1u;
+      if (!mk && d != 0 && d != 2)
+        return fail(QW_EUNSUPPORTED, "Hadamard coin needs degree 2, vertex %lld has %lld", (long long)v, (long long)d);
+    }
+  }
+  if (p->kind == QW_CTQW) {
+    if (!(w->gamma > 0.0) || !std::isfinite(w->gamma)) return fail(QW_EINVAL, "gamma must be positive");
+    if (!(w->dt > 0.0) || !std::isfinite(w->dt)) return fail(QW_EINVAL, "dt must be positive");
+    p->gamma = w->gamma;
+    p->dt = w->dt;
+    double h = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+      const bool mk = (bits[v >> 5] >> (v & 31)) & 1u;
+      h = std::max(h, w->gamma * static_cast<double>(rp[v + 1] - rp[v]) + (mk ? 1.0 : 0.0));
+    }
+    p->h_bound = h;
+    if (w->taylor_order > 0) {
+      if (w->taylor_order > 64) return fail(QW_EINVAL, "taylor_order above 64");
+      p->K = w->taylor_order;
+    } else {
+      if (!(w->trunc_tol > 0.0) || w->horizon_steps < 1)
+        return fail(QW_EINVAL, "automatic Taylor order needs trunc_tol > 0 and horizon_steps >= 1");
+      const int K = taylor_order(w->dt * h, w->horizon_steps, w->trunc_tol);
+      if (K < 0) return fail(QW_EUNSUPPORTED, "no Taylor order <= 64 meets the tolerance at rho = %g", w->dt * h);
+      p->K = K;
+    }
+    p->trunc_bound = tail_bound(w->dt * h, p->K);
+  }
+
+  // ---- path choice: small (one workgroup), structured, or general CSR
+  const bool c128 = p->dtype == QW_C128;
+  int structure = kGeneral;
+  const bool small_fits = p->kind == QW_COINED
+                              ? coined_small_lds(c128, static_cast<int>(n), static_cast<int>(na)) <= kSmallLdsBytes
+                              : ctqw_small_lds(c128, static_cast<int>(n), static_cast<int>(na)) <= kSmallLdsBytes;
+  if (p->layout == QW_LAYOUT_AUTO && small_fits && n > 0) {
+    structure = kSmall;
+  } else if (p->layout != QW_LAYOUT_CSR && n > 0) {
+    int32_t a = 0, b = 0;
+    const bool ordered = p->kind == QW_COINED && p->coin == QW_HADAMARD;
+    if (!ordered && is_hypercube(n, rp, col, &a)) {
+      structure = kHypercube;
+      p->dims[0] = a;
+    } else if (is_cycle(n, rp, col, ordered)) {
+      structure = kCycle;
+      p->dims[0] = static_cast<int32_t>(n);
+    } else if (!ordered && is_torus(n, rp, col, &a, &b)) {
+      structure = kTorus;
+      p->dims[0] = a;
+      p->dims[1] = b;
+    }
+  }
+  p->structure = structure;
+
+  // ---- device tables
+  const bool coined = p->kind == QW_COINED;
+  p->has_rev = coined && (structure == kGeneral || structure == kSmall);
+  p->has_tiles = coined && structure == kGeneral;
+  p->has_perm = coined && (structure == kCycle || structure == kTorus || structure == kHypercube);
+  p->has_col = !coined && (structure == kGeneral || structure == kSmall);
+
+  std::vector<int32_t> tiles;
+  if (p->has_tiles) {
+    tiles.push_back(0);
+    int64_t arcs = 0, verts = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      const int64_t d = rp[v + 1] - rp[v];
+      if (verts > 0 && (arcs + d > kTileArcs || verts == kTileMaxVerts)) {
+        tiles.push_back(static_cast<int32_t>(v));
+        arcs = verts = 0;
+      }
+      arcs += d;
+      ++verts;
+      if (d > kTileArcs) {
+        tiles.push_back(static_cast<int32_t>(v + 1));
+        arcs = verts = 0;
+      }
+    }
+    if (tiles.back() != n) tiles.push_back(static_cast<int32_t>(n));
+    p->n_tiles = static_cast<int32_t>(tiles.size()) - 1;
+  }
+  std::vector<int32_t> perm;
+  if (p->has_perm) {
+    perm.assign(static_cast<size_t>(na), -1);
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t a = rp[v]; a < rp[v + 1]; ++a) {
+        const int j = slot_of(structure, v, col[a], n, p->dims[1]);
+        const size_t slot = static_cast<size_t>(j) * n + v;
+        if (j < 0 || slot >= perm.size() || perm[slot] != -1)
+          return fail(QW_EINVAL, "internal: structured slot map is not a bijection at vertex %lld", (long long)v);
+        perm[slot] = static_cast<int32_t>(a);
+      }
+    for (int32_t x : perm)
+      if (x < 0) return fail(QW_EINVAL, "internal: structured slot map has a hole");
+  }
+  if (!coined && structure == kGeneral) {
+    const double avg = n > 0 ? static_cast<double>(na) / n : 0.0;
+    p->group = avg <= 6 ? 1 : avg <= 12 ? 2 : avg <= 24 ? 4 : avg <= 48 ? 8 : avg <= 96 ? 16 : avg <= 192 ? 32 : 64;
+  }
+
+  size_t off = 0;
+  auto section = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + std::max<size_t>(bytes, 4));
+    return o;
+  };
+  p->off_rp = section(sizeof(int32_t) * (n + 1));
+  if (p->has_col) p->off_col = section(sizeof(int32_t) * na);
+  if (p->has_rev) p->off_rev = section(sizeof(int32_t) * na);
+  if (p->has_tiles) p->off_tiles = section(sizeof(int32_t) * tiles.size());
+  if (p->has_perm) p->off_perm = section(sizeof(int32_t) * na);
+  p->off_bits = section(sizeof(uint32_t) * bits.size());
+  p->off_mlist = section(sizeof(int32_t) * std::max<size_t>(mlist.size(), 1));
+  p->image.assign(off, 0);
+  std::vector<int32_t> rp32(static_cast<size_t>(n) + 1);
+  for (int64_t v = 0; v <= n; ++v) rp32[v] = static_cast<int32_t>(rp[v]);
+  put(p->image, p->off_rp, rp32.data(), rp32.size());
+  if (p->has_col) put(p->image, p->off_col, col, static_cast<size_t>(na));
+  if (p->has_rev) put(p->image, p->off_rev, rev.data(), rev.size());
+  if (p->has_tiles) put(p->image, p->off_tiles, tiles.data(), tiles.size());
+  if (p->has_perm) put(p->image, p->off_perm, perm.data(), perm.size());
+  put(p->image, p->off_bits, bits.data(), bits.size());
+  put(p->image, p->off_mlist, mlist.data(), mlist.size());
+
+  // ---- workspace
+  const size_t es = c128 ? 16 : 8;
+  const int64_t len = coined ? na : n;
+  p->state_bytes = es * static_cast<size_t>(len);
+  GraphView probe;
+  probe.n = static_cast<int32_t>(n);
+  probe.structure = structure;
+  probe.group = p->group;
+  const size_t partials = static_cast<size_t>(std::max(readout_partials(probe), ctqw_stage_partials(probe))) + 1;
+  size_t w_off = 0;
+  auto wsec = [&](size_t bytes) {
+    const size_t o = w_off;
+    w_off = align256(w_off + std::max<size_t>(bytes, 8));
+    return o;
+  };
+  wsec(p->state_bytes);                    // buffer 0 at offset 0
+  p->off_w1 = wsec(p->state_bytes);        // buffer 1
+  p->off_pscratch = wsec(sizeof(double) * static_cast<size_t>(n));
+  p->off_partials = wsec(sizeof(double) * partials);
+  p->work_bytes = w_off;
+  return ok();
+}
+
+int check_bound(const qw_plan *p) {
+  if (!p) return fail(QW_EINVAL, "null plan");
+  if (!p->d_graph) return fail(QW_ESTATE, "plan not uploaded (call qw_plan_upload first)");
+  return QW_OK;
+}
+
+Readout make_readout(const qw_plan *p, unsigned char *work, double *d_p, double *d_norm, double *d_pm) {
+  Readout r;
+  r.p = d_p;
+  r.norm = d_norm;
+  r.pmarked = d_pm;
+  r.pscratch = reinterpret_cast<double *>(work + p->off_pscratch);
+  r.partials = reinterpret_cast<double *>(work + p->off_partials);
+  return r;
+}
+
+#define QW_TRY(expr, what)                   \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return dev_fail(e_, what); \
+  } while (0)
+
+int readout_only(const qw_plan *p, const void *psi, const Readout &ro, hipStream_t s) {
+  const bool c128 = p->dtype == QW_C128;
+  const GraphView &g = p->view;
+  if (!ro.any()) return QW_OK;
+  if (p->kind == QW_COINED) {
+    QW_TRY(coined_prob_csr(c128, g, psi, ro, s), "coined probability kernel");
+  } else {
+    QW_TRY(vertex_prob(c128, g, psi, ro, s), "vertex probability kernel");
+  }
+  QW_TRY(finish_readout(g, readout_partials(g), ro, s), "readout reduction kernel");
+  return QW_OK;
+}
+
+int evolve_coined(const qw_plan *p, void *psi, unsigned char *work, int64_t steps, const Readout &ro,
+                  hipStream_t s) {
+  const bool c128 = p->dtype == QW_C128;
+  const GraphView &g = p->view;
+  const int had = p->coin == QW_HADAMARD;
+  void *w0 = work, *w1 = work + p->off_w1;
+  if (p->structure == kSmall) {
+    QW_TRY(coined_small(c128, g, psi, had, steps, ro, s), "coined small-graph kernel");
+    return QW_OK;
+  }
+  if (steps == 0) return readout_only(p, psi, ro, s);
+  if (p->structure == kGeneral) {
+    void *cur = psi, *oth = w0;
+    for (int64_t i = 0; i < steps; ++i) {
+      QW_TRY(coined_tile_step(c128, g, cur, oth, had, s), "coined step kernel");
+      std::swap(cur, oth);
+    }
+    if (cur != psi) QW_TRY(copy_state(c128, p->n_arcs, cur, psi, s), "state copy kernel");
+    return readout_only(p, psi, ro, s);
+  }
+  QW_TRY(coined_perm_in(c128, g, psi, w0, s), "layout permutation kernel");
+  void *cur = w0, *oth = w1;
+  for (int64_t i = 0; i < steps; ++i) {
+    QW_TRY(coined_struct_step(c128, g, cur, oth, had, s), "coined structured step kernel");
+    std::swap(cur, oth);
+  }
+  QW_TRY(coined_perm_out(c128, g, cur, psi, ro, s), "layout permutation kernel");
+  if (ro.any()) QW_TRY(finish_readout(g, readout_partials(g), ro, s), "readout reduction kernel");
+  return QW_OK;
+}
+
+int evolve_ctqw(const qw_plan *p, void *psi, unsigned char *work, int64_t steps, const Readout &ro,
+                hipStream_t s) {
+  const bool c128 = p->dtype == QW_C128;
+  const GraphView &g = p->view;
+  const int K = p->K;
+  std::vector<double> alpha(K), beta(K);
+  for (int k = 1; k <= K; ++k) {
+    beta[k - 1] = p->dt / k;
+    alpha[k - 1] = p->gamma * p->dt / k;
+  }
+  if (p->structure == kSmall) {
+    QW_TRY(ctqw_small(c128, g, psi, alpha.data(), beta.data(), K, steps, ro, s), "CTQW small-graph kernel");
+    return QW_OK;
+  }
+  if (steps == 0) return readout_only(p, psi, ro, s);
+  void *w0 = work, *w1 = work + p->off_w1;
+  bool fused_done = false;
+  for (int64_t i = 0; i < steps; ++i) {
+    const void *yin = psi;
+    for (int k = K; k >= 1; --k) {
+      void *yout = (k == 1) ? (K == 1 ? w0 : psi) : (((K - k) & 1) ? w1 : w0);
+      const bool fuse = ro.any() && k == 1 && K >= 2 && i == steps - 1;
+      StageCoef c{alpha[k - 1], beta[k - 1]};
+      QW_TRY(ctqw_stage(c128, g, yin, psi, yout, c, fuse ? &ro : nullptr, s), "CTQW Horner stage kernel");
+      fused_done |= fuse;
+      yin = yout;
+    }
+    if (K == 1) QW_TRY(copy_state(c128, p->n, w0, psi, s), "state copy kernel");
+  }
+  if (!ro.any()) return QW_OK;
+  if (!fused_done) return readout_only(p, psi, ro, s);
+  QW_TRY(finish_readout(g, ctqw_stage_partials(g), ro, s), "readout reduction kernel");
+  return QW_OK;
+}
+
+}  // namespace
+
+// =============================== C ABI =======================================
+
+extern "C" {
+
+int qw_plan_create(const qw_csr *graph, const qw_walk_desc *walk, qw_plan **out) {
+  if (!out) return fail(QW_EINVAL, "null output pointer");
+  *out = nullptr;
+  qw_plan *p = nullptr;
+  try {
+    p = new qw_plan();
+    const int st = build_plan(graph, walk, p);
+    if (st != QW_OK) {
+      delete p;
+      return st;
+    }
+  } catch (const std::bad_alloc &) {
+    delete p;
+    return fail(QW_ENOMEM, "host allocation failed");
+  } catch (...) {
+    delete p;
+    return fail(QW_EINVAL, "unexpected host exception");
+  }
+  *out = p;
+  return ok();
+}
+
+int qw_plan_destroy(qw_plan *plan) {
+  delete plan;
+  return ok();
+}
+
+int qw_plan_get_info(const qw_plan *p, qw_plan_info *info) {
+  if (!p || !info) return fail(QW_EINVAL, "null argument");
+  std::memset(info, 0, sizeof *info);
+  info->n = p->n;
+  info->n_arcs = p->n_arcs;
+  info->state_len = p->kind == QW_COINED ? p->n_arcs : p->n;
+  info->kind = p->kind;
+  info->coin = p->coin;
+  info->dtype = p->dtype;
+  info->structure = p->structure;
+  info->dims[0] = p->dims[0];
+  info->dims[1] = p->dims[1];
+  info->max_degree = p->max_degree;
+  info->taylor_order = p->K;
+  info->dt = p->dt;
+  info->h_norm_bound = p->h_bound;
+  info->trunc_bound = p->trunc_bound;
+  info->graph_bytes = p->image.size();
+  info->state_bytes = p->state_bytes;
+  info->work_bytes = p->work_bytes;
+  return ok();
+}
+
+int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) {
+  if (!p || !d_graph) return fail(QW_EINVAL, "null plan or graph buffer");
+  if (graph_bytes < p->image.size())
+    return fail(QW_ENOMEM, "graph buffer of %zu bytes, plan needs %zu", graph_bytes, p->image.size());
+  if (reinterpret_cast<uintptr_t>(d_graph) % 256 != 0) return fail(QW_EINVAL, "graph buffer not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  QW_TRY(hipMemcpyAsync(d_graph, p->image.data(), p->image.size(), hipMemcpyHostToDevice, s), "graph upload");
+  auto *base = static_cast<unsigned char *>(d_graph);
+  p->d_graph = base;
+  GraphView &g = p->view;
+  g = GraphView();
+  g.n = static_cast<int32_t>(p->n);
+  g.n_arcs = static_cast<int32_t>(p->n_arcs);
+  g.structure = p->structure;
+  g.dims[0] = p->dims[0];
+  g.dims[1] = p->dims[1];
+  g.n_marked = p->n_marked;
+  g.n_tiles = p->n_tiles;
+  g.group = p->group;
+  g.rp = reinterpret_cast<const int32_t *>(base + p->off_rp);
+  if (p->has_col) g.col = reinterpret_cast<const int32_t *>(base + p->off_col);
+  if (p->has_rev) g.rev = reinterpret_cast<const int32_t *>(base + p->off_rev);
+  if (p->has_tiles) g.tiles = reinterpret_cast<const int32_t *>(base + p->off_tiles);
+  if (p->has_perm) g.perm = reinterpret_cast<const int32_t *>(base + p->off_perm);
+  g.markbits = reinterpret_cast<const uint32_t *>(base + p->off_bits);
+  g.marklist = reinterpret_cast<const int32_t *>(base + p->off_mlist);
+  return ok();
+}
+
+int qw_evolve(const qw_plan *p, void *d_psi, void *d_work, size_t work_bytes, int64_t steps, double *d_p,
+              double *d_norm, double *d_pmarked, void *stream) {
+  int st = check_bound(p);
+  if (st != QW_OK) return st;
+  if (steps < 0) return fail(QW_EINVAL, "negative step count");
+  if (!d_psi && p->state_bytes) return fail(QW_EINVAL, "null state");
+  if (!d_work) return fail(QW_EINVAL, "null workspace");
+  if (work_bytes < p->work_bytes) return fail(QW_ENOMEM, "workspace of %zu bytes, plan needs %zu", work_bytes, p->work_bytes);
+  auto *work = static_cast<unsigned char *>(d_work);
+  const Readout ro = make_readout(p, work, d_p, d_norm, d_pmarked);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = p->kind == QW_COINED ? evolve_coined(p, d_psi, work, steps, ro, s) : evolve_ctqw(p, d_psi, work, steps, ro, s);
+  return st == QW_OK ? ok() : st;
+}
+
+int qw_probabilities(const qw_plan *p, const void *d_psi, double *d_p, double *d_norm, double *d_pmarked,
+                     void *d_work, size_t work_bytes, void *stream) {
+  int st = check_bound(p);
+  if (st != QW_OK) return st;
+  if (!d_psi && p->state_bytes) return fail(QW_EINVAL, "null state");
+  if (!d_work) return fail(QW_EINVAL, "null workspace");
+  if (work_bytes < p->work_bytes) return fail(QW_ENOMEM, "workspace of %zu bytes, plan needs %zu", work_bytes, p->work_bytes);
+  auto *work = static_cast<unsigned char *>(d_work);
+  const Readout ro = make_readout(p, work, d_p, d_norm, d_pmarked);
+  st = readout_only(p, d_psi, ro, static_cast<hipStream_t>(stream));
+  return st == QW_OK ? ok() : st;
+}
+
+int qw_taylor_order(double rho, int64_t steps, double tol, int32_t *K) {
+  if (!K) return fail(QW_EINVAL, "null output");
+  if (!(rho >= 0.0) || !std::isfinite(rho) || steps < 1 || !(tol > 0.0))
+    return fail(QW_EINVAL, "rho >= 0, steps >= 1 and tol > 0 required");
+  const int k = taylor_order(rho, steps, tol);
+  if (k < 0) return fail(QW_EUNSUPPORTED, "no order <= 64 meets the tolerance");
+  *K = k;
+  return ok();
+}
+
+int qw_taylor_plan(double h_bound, double t_total, double rho_max, double tol, int32_t *K, double *dt,
+                   int64_t *steps) {
+  if (!K || !dt || !steps) return fail(QW_EINVAL, "null output");
+  if (!(h_bound >= 0.0) || !(t_total > 0.0) || !(rho_max > 0.0) || !(tol > 0.0) || !std::isfinite(t_total))
+    return fail(QW_EINVAL, "h_bound >= 0, t_total > 0, rho_max > 0 and tol > 0 required");
+  int64_t n = h_bound > 0.0 ? static_cast<int64_t>(std::ceil(t_total * h_bound / rho_max)) : 1;
+  if (n < 1) n = 1;
+  const double d = t_total / static_cast<double>(n);
+  const int k = taylor_order(d * h_bound, n, tol);
+  if (k < 0) return fail(QW_EUNSUPPORTED, "no order <= 64 meets the tolerance");
+  *K = k;
+  *dt = d;
+  *steps = n;
+  return ok();
+}
+
+double qw_taylor_tail_bound(double rho, int32_t K) { return tail_bound(rho, K); }
+
+const char *qw_last_error(void) { return g_err.c_str(); }
+
+const char *qw_version(void) { return "qwalk-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

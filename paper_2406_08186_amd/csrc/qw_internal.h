@@ -1,0 +1,97 @@
+// Internal declarations shared by the host runtime (qw_host.cpp) and the
+// HIP kernels (qw_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qwk {
+
+// Layout of the coined general path: contiguous vertex ranges whose arcs fit
+// one workgroup's LDS tile are processed together.
+constexpr int kTileArcs = 2048;
+constexpr int kTileThreads = 256;
+constexpr int kTileMaxVerts = 1024;
+// Threads per workgroup of the elementwise/stencil kernels.
+constexpr int kBlock = 256;
+// LDS budget of the one-workgroup whole-walk kernels.
+constexpr size_t kSmallLdsBytes = 60 * 1024;  // dynamic LDS, leaves room for static
+// Largest hypercube dimension the structured kernels handle.
+constexpr int kMaxHypercubeDim = 30;
+
+enum Structure : int32_t { kGeneral = 0, kCycle = 1, kTorus = 2, kHypercube = 3, kSmall = 4 };
+
+// Device view of a plan's graph tables (pointers into the caller's buffer).
+struct GraphView {
+  int32_t n = 0;
+  int32_t n_arcs = 0;
+  int32_t structure = kGeneral;
+  int32_t dims[2] = {0, 0};
+  int32_t n_marked = 0;
+  int32_t n_tiles = 0;
+  int32_t group = 1;           // CTQW CSR: lanes per row
+  const int32_t *rp = nullptr;      // n+1
+  const int32_t *col = nullptr;     // n_arcs (CTQW general/small)
+  const int32_t *rev = nullptr;     // n_arcs (coined general/small)
+  const int32_t *tiles = nullptr;   // n_tiles+1 (coined general)
+  const int32_t *perm = nullptr;    // n_arcs (coined structured: slot-major -> CSR position)
+  const uint32_t *markbits = nullptr;  // ceil(n/32)
+  const int32_t *marklist = nullptr;   // n_marked
+};
+
+// Readout request: any pointer may be null.  `pscratch` (n doubles) and
+// `partials` (enough for the launch) come from the workspace.
+struct Readout {
+  double *p = nullptr;
+  double *norm = nullptr;
+  double *pmarked = nullptr;
+  double *pscratch = nullptr;
+  double *partials = nullptr;
+  bool any() const { return p || norm || pmarked; }
+  double *p_out() const { return p ? p : pscratch; }
+};
+
+// Coefficients of one Horner stage y_out = psi + i*(alpha*sum_nbr y + beta*[marked] y_v),
+// alpha = gamma*dt/k, beta = dt/k (FP64; rounded once for complex64).
+struct StageCoef {
+  double alpha;
+  double beta;
+};
+
+// ---- launchers (qw_kernels.hip) -------------------------------------------
+// All return the hipError_t of the launch (hipGetLastError after it).
+hipError_t coined_small(bool c128, const GraphView &g, void *psi, int hadamard, int64_t steps,
+                        const Readout &ro, hipStream_t s);
+size_t coined_small_lds(bool c128, int n, int n_arcs);
+
+hipError_t coined_tile_step(bool c128, const GraphView &g, const void *in, void *out,
+                            int hadamard, hipStream_t s);
+hipError_t coined_struct_step(bool c128, const GraphView &g, const void *in, void *out,
+                              int hadamard, hipStream_t s);
+hipError_t coined_perm_in(bool c128, const GraphView &g, const void *psi, void *internal,
+                          hipStream_t s);
+hipError_t coined_perm_out(bool c128, const GraphView &g, const void *internal, void *psi,
+                           const Readout &ro, hipStream_t s);
+hipError_t copy_state(bool c128, int64_t len, const void *in, void *out, hipStream_t s);
+hipError_t coined_prob_csr(bool c128, const GraphView &g, const void *psi, const Readout &ro,
+                           hipStream_t s);
+
+hipError_t ctqw_small(bool c128, const GraphView &g, void *psi, const double *alpha,
+                      const double *beta, int K, int64_t steps, const Readout &ro, hipStream_t s);
+size_t ctqw_small_lds(bool c128, int n, int n_arcs);
+hipError_t ctqw_stage(bool c128, const GraphView &g, const void *y, const void *psi, void *out,
+                      StageCoef c, const Readout *fused, hipStream_t s);
+hipError_t vertex_prob(bool c128, const GraphView &g, const void *psi, const Readout &ro,
+                       hipStream_t s);
+
+// Sum of `count` partials -> *norm; sum over the marked list of p -> *pmarked.
+hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s);
+
+// Number of partial sums the readout kernels (one thread per vertex) write.
+int readout_partials(const GraphView &g);
+// Number of partial sums a CTQW stage with the readout fused writes.
+int ctqw_stage_partials(const GraphView &g);
+
+}  // namespace qwk

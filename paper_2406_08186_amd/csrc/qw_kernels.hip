@@ -1,0 +1,740 @@
+// HIP kernels of the quantum-walk step engine (gfx950 / CDNA4, wave64).
+//
+// State storage is T = float2 (complex64) or double2 (complex128).  Every
+// kernel loads T, does its arithmetic in FP64 registers and rounds once when
+// it stores, so a complex64 walk differs from the FP64 one only by one
+// rounding of each stored amplitude per kernel (no systematically biased
+// coefficient such as a rounded 2/d).  All reductions are FP64 with a fixed
+// order, so results are bitwise reproducible.
+//
+// Coined step (Hiperwalk Sec. 3.2): psi' = S C psi with the flip-flop shift
+// S|v,w> = |w,v> and, per vertex block, the Grover coin
+// (C psi)_{v,v'} = (2/d) sum_w psi_{v,w} - psi_{v,v'}, the Hadamard coin on a
+// degree-2 block, or -I at marked vertices.
+// CTQW Horner stage (Sec. 3.1 Hamiltonian): y_out = psi + (-i dt/k) H y_in with
+// (H y)_v = -gamma sum_{u ~ v} y_u - [v in M] y_v, i.e.
+// y_out = psi + i (alpha sum_u y_u + beta [v in M] y_v), alpha = gamma dt/k,
+// beta = dt/k.
+
+#include "qw_internal.h"
+
+namespace qwk {
+namespace {
+
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+
+// ---- storage <-> FP64 -------------------------------------------------------
+__device__ __forceinline__ double2 ld(const float2 *p, int64_t i) {
+  float2 v = p[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ld(const double2 *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ double2 cvt(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 cvt(double2 v) { return v; }
+__device__ __forceinline__ void st(float2 *p, int64_t i, double2 v) {
+  p[i] = make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+}
+__device__ __forceinline__ void st(double2 *p, int64_t i, double2 v) { p[i] = v; }
+template <typename T> __device__ __forceinline__ T pack(double2 v);
+template <> __device__ __forceinline__ float2 pack<float2>(double2 v) {
+  return make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+}
+template <> __device__ __forceinline__ double2 pack<double2>(double2 v) { return v; }
+
+__device__ __forceinline__ double2 add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double abs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ bool marked(const uint32_t *bits, int v) {
+  return (bits[v >> 5] >> (v & 31)) & 1u;
+}
+
+// Grover on one block given its sum s: phi = 2 s/d - psi.  The mean is the
+// correctly rounded FP64 quotient; doubling it is exact.
+__device__ __forceinline__ double2 grover_mean(double2 s, int d) {
+  double inv = 1.0 / static_cast<double>(d);
+  return make_double2(s.x * inv, s.y * inv);
+}
+
+// ---- deterministic FP64 block reduction ---------------------------------------
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Sum of x over the block (blockDim.x a multiple of 64, <= 1024); result valid
+// in every thread.  Uses `red` (>= 16 doubles of LDS).
+__device__ double block_sum(double x, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  x = wave_sum(x);
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+// ---- readout tail: partial norms ---------------------------------------------
+__global__ __launch_bounds__(256) void k_finish(const double *partials, int count, const double *p,
+                                                const int32_t *marklist, int n_marked,
+                                                double *norm, double *pmarked) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partials[i];
+  double tot = block_sum(acc, red);
+  double pm = 0.0;
+  for (int i = threadIdx.x; i < n_marked; i += blockDim.x) pm += p[marklist[i]];
+  double ptot = block_sum(pm, red);
+  if (threadIdx.x == 0) {
+    if (norm) *norm = tot;
+    if (pmarked) *pmarked = ptot;
+  }
+}
+
+// ---- coined: whole walk in one workgroup's LDS -------------------------------
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coined_small(GraphView g, T *psi, int hadamard,
+                                                       int64_t steps, Readout ro) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  const int n = g.n, na = g.n_arcs;
+  T *a = reinterpret_cast<T *>(smem);
+  T *b = a + na;
+  int32_t *srp = reinterpret_cast<int32_t *>(b + na);
+  int32_t *srev = srp + n + 1;
+  for (int i = threadIdx.x; i < na; i += blockDim.x) {
+    a[i] = psi[i];
+    srev[i] = g.rev[i];
+  }
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) srp[i] = g.rp[i];
+  __syncthreads();
+  for (int64_t s = 0; s < steps; ++s) {
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      const int lo = srp[v], hi = srp[v + 1], d = hi - lo;
+      if (d == 0) continue;
+      if (marked(g.markbits, v)) {
+        for (int i = lo; i < hi; ++i) a[i] = pack<T>(scale(cvt(a[i]), -1.0));
+      } else if (hadamard) {
+        double2 x0 = cvt(a[lo]), x1 = cvt(a[lo + 1]);
+        a[lo] = pack<T>(scale(add(x0, x1), kInvSqrt2));
+        a[lo + 1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+      } else {
+        double2 sum = make_double2(0.0, 0.0);
+        for (int i = lo; i < hi; ++i) sum = add(sum, cvt(a[i]));
+        double2 m = grover_mean(sum, d);
+        for (int i = lo; i < hi; ++i) a[i] = pack<T>(sub(add(m, m), cvt(a[i])));
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < na; i += blockDim.x) b[srev[i]] = a[i];
+    __syncthreads();
+    T *t = a;
+    a = b;
+    b = t;
+  }
+  for (int i = threadIdx.x; i < na; i += blockDim.x) psi[i] = a[i];
+  if (ro.p || ro.norm || ro.pmarked) {
+    double *pout = ro.p ? ro.p : ro.pscratch;
+    double acc = 0.0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      double pv = 0.0;
+      for (int i = srp[v]; i < srp[v + 1]; ++i) pv += abs2(cvt(a[i]));
+      pout[v] = pv;
+      acc += pv;
+    }
+    double tot = block_sum(acc, red);
+    __threadfence_block();
+    __syncthreads();
+    double pm = 0.0;
+    for (int i = threadIdx.x; i < g.n_marked; i += blockDim.x) pm += pout[g.marklist[i]];
+    double ptot = block_sum(pm, red);
+    if (threadIdx.x == 0) {
+      if (ro.norm) *ro.norm = tot;
+      if (ro.pmarked) *ro.pmarked = ptot;
+    }
+  }
+}
+
+// ---- coined: general CSR, one LDS tile of whole vertex blocks per workgroup --
+// Tile t covers vertices [tiles[t], tiles[t+1]); its arcs fit kTileArcs unless
+// the tile is a single vertex of larger degree.  Loads are coalesced in arc
+// order; the flip-flop shift scatters phi_a to out[rev[a]].
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_coined_tile(GraphView g, const T *__restrict__ in,
+                                                              T *__restrict__ out, int hadamard) {
+  __shared__ T s[kTileArcs];
+  __shared__ double red[16];
+  const int t = blockIdx.x;
+  const int vb = g.tiles[t], ve = g.tiles[t + 1];
+  const int ab = g.rp[vb], ae = g.rp[ve];
+  const int na = ae - ab;
+  if (na <= kTileArcs) {
+    for (int i = threadIdx.x; i < na; i += blockDim.x) s[i] = in[ab + i];
+    __syncthreads();
+    for (int v = vb + threadIdx.x; v < ve; v += blockDim.x) {
+      const int lo = g.rp[v] - ab, hi = g.rp[v + 1] - ab, d = hi - lo;
+      if (d == 0) continue;
+      if (marked(g.markbits, v)) {
+        for (int i = lo; i < hi; ++i) s[i] = pack<T>(scale(cvt(s[i]), -1.0));
+      } else if (hadamard) {
+        double2 x0 = cvt(s[lo]), x1 = cvt(s[lo + 1]);
+        s[lo] = pack<T>(scale(add(x0, x1), kInvSqrt2));
+        s[lo + 1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+      } else {
+        double2 sum = make_double2(0.0, 0.0);
+        for (int i = lo; i < hi; ++i) sum = add(sum, cvt(s[i]));
+        double2 m = grover_mean(sum, d);
+        for (int i = lo; i < hi; ++i) s[i] = pack<T>(sub(add(m, m), cvt(s[i])));
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < na; i += blockDim.x) out[g.rev[ab + i]] = s[i];
+  } else {
+    // one vertex of degree > kTileArcs (Hadamard is never here: d = 2)
+    const int v = vb;
+    const bool mk = marked(g.markbits, v);
+    double2 m = make_double2(0.0, 0.0);
+    if (!mk) {
+      double sx = 0.0, sy = 0.0;
+      for (int i = ab + threadIdx.x; i < ae; i += blockDim.x) {
+        double2 x = ld(in, i);
+        sx += x.x;
+        sy += x.y;
+      }
+      sx = block_sum(sx, red);
+      sy = block_sum(sy, red);
+      m = grover_mean(make_double2(sx, sy), na);
+    }
+    for (int i = ab + threadIdx.x; i < ae; i += blockDim.x) {
+      double2 x = ld(in, i);
+      double2 phi = mk ? scale(x, -1.0) : sub(add(m, m), x);
+      st(out, g.rev[i], phi);
+    }
+  }
+}
+
+// ---- coined: index-free structured layouts ------------------------------------
+// Internal state is slot-major: element (slot j, vertex v) at j*n + v.
+//   CYCLE:     slot 0 -> v+1, slot 1 -> v-1; reverse slot 1-j.
+//   TORUS:     v = r*l2 + c; slots c+1, c-1, r+1, r-1; reverse slot j^1.
+//   HYPERCUBE: slot j -> v xor 2^j; reverse slot j.
+// One thread per vertex: the d loads and the d stores are each coalesced
+// across the wavefront.
+template <int KIND>
+__device__ __forceinline__ int head_of(int v, int j, int n, int l2) {
+  if (KIND == kCycle) {
+    return j == 0 ? (v + 1 == n ? 0 : v + 1) : (v == 0 ? n - 1 : v - 1);
+  } else if (KIND == kTorus) {
+    const int r = v / l2, c = v - r * l2;
+    switch (j) {
+      case 0: return r * l2 + (c + 1 == l2 ? 0 : c + 1);
+      case 1: return r * l2 + (c == 0 ? l2 - 1 : c - 1);
+      case 2: return (r + 1 == n / l2 ? 0 : r + 1) * l2 + c;
+      default: return (r == 0 ? n / l2 - 1 : r - 1) * l2 + c;
+    }
+  } else {
+    return v ^ (1 << j);
+  }
+}
+template <int KIND> __device__ __forceinline__ int rev_slot(int j) {
+  return KIND == kCycle ? 1 - j : (KIND == kTorus ? (j ^ 1) : j);
+}
+
+template <typename T, int KIND, int D>
+__global__ __launch_bounds__(kBlock) void k_coined_struct(GraphView g, const T *__restrict__ in,
+                                                          T *__restrict__ out, int dim,
+                                                          int hadamard) {
+  const int n = g.n;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int d = (KIND == kHypercube) ? dim : D;
+  const int l2 = g.dims[1];
+  T x[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (j < d) x[j] = in[static_cast<int64_t>(j) * n + v];
+  const bool mk = marked(g.markbits, v);
+  if (mk) {
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) x[j] = pack<T>(scale(cvt(x[j]), -1.0));
+  } else if (KIND == kCycle && hadamard) {
+    double2 x0 = cvt(x[0]), x1 = cvt(x[1]);
+    x[0] = pack<T>(scale(add(x0, x1), kInvSqrt2));
+    x[1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+  } else {
+    double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) sum = add(sum, cvt(x[j]));
+    double2 m = grover_mean(sum, d);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) x[j] = pack<T>(sub(add(m, m), cvt(x[j])));
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (j < d) out[static_cast<int64_t>(rev_slot<KIND>(j)) * n + head_of<KIND>(v, j, n, l2)] = x[j];
+}
+
+// internal[i] = psi[perm[i]]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_perm_in(const T *__restrict__ psi, T *__restrict__ internal,
+                                                    const int32_t *__restrict__ perm, int na) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < na) internal[i] = psi[perm[i]];
+}
+
+// psi[perm[j*n+v]] = internal[j*n+v], one thread per vertex, with the vertex
+// probability fused: p_v = sum_j |internal[j*n+v]|^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_perm_out(const T *__restrict__ internal, T *__restrict__ psi,
+                                                     const int32_t *__restrict__ perm, int n, int d,
+                                                     double *p, double *partials) {
+  __shared__ double red[16];
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double pv = 0.0;
+  if (v < n) {
+    for (int j = 0; j < d; ++j) {
+      const int64_t i = static_cast<int64_t>(j) * n + v;
+      T x = internal[i];
+      psi[perm[i]] = x;
+      pv += abs2(cvt(x));
+    }
+    if (p) p[v] = pv;
+  }
+  if (partials) {
+    double tot = block_sum(pv, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(const T *__restrict__ in, T *__restrict__ out, int64_t len) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < len) out[i] = in[i];
+}
+
+// Coined readout on the CSR arc order: p_v = sum over row v of |psi_a|^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prob_csr(GraphView g, const T *__restrict__ psi, double *p,
+                                                     double *partials) {
+  __shared__ double red[16];
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double pv = 0.0;
+  if (v < g.n) {
+    for (int i = g.rp[v]; i < g.rp[v + 1]; ++i) pv += abs2(ld(psi, i));
+    p[v] = pv;
+  }
+  double tot = block_sum(pv, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// CTQW readout: p_v = |psi_v|^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prob_vertex(const T *__restrict__ psi, int n, double *p,
+                                                        double *partials) {
+  __shared__ double red[16];
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double pv = 0.0;
+  if (v < n) {
+    pv = abs2(ld(psi, v));
+    p[v] = pv;
+  }
+  double tot = block_sum(pv, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// ---- CTQW: one Horner stage ---------------------------------------------------
+// y_out = psi + i (alpha sum_{u~v} y_u + beta [v in M] y_v)
+__device__ __forceinline__ double2 horner_out(double2 psi, double2 nsum, double2 yv, bool mk,
+                                              double alpha, double beta) {
+  double tx = alpha * nsum.x, ty = alpha * nsum.y;
+  if (mk) {
+    tx += beta * yv.x;
+    ty += beta * yv.y;
+  }
+  return make_double2(psi.x - ty, psi.y + tx);
+}
+
+// General CSR, G lanes per row (G in 1..64, power of two), lane sums strided
+// by G then a butterfly across the G lanes.  PROB fuses the readout.
+template <typename T, int G, bool PROB>
+__global__ __launch_bounds__(kBlock) void k_ctqw_csr(GraphView g, const T *__restrict__ y,
+                                                     const T *psi, T *out, double alpha, double beta,
+                                                     double *p, double *partials) {
+  __shared__ double red[16];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = gid / G, lane = gid % G;
+  double sx = 0.0, sy = 0.0;
+  if (row < g.n) {
+    const int lo = g.rp[row], hi = g.rp[row + 1];
+    for (int a = lo + lane; a < hi; a += G) {
+      double2 x = ld(y, g.col[a]);
+      sx += x.x;
+      sy += x.y;
+    }
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    sx += __shfl_xor(sx, off, 64);
+    sy += __shfl_xor(sy, off, 64);
+  }
+  double pv = 0.0;
+  if (row < g.n && lane == 0) {
+    const bool mk = marked(g.markbits, row);
+    double2 yv = mk ? ld(y, row) : make_double2(0.0, 0.0);
+    double2 r = horner_out(ld(psi, row), make_double2(sx, sy), yv, mk, alpha, beta);
+    st(out, row, r);
+    if (PROB) {
+      T stored = pack<T>(r);
+      pv = abs2(cvt(stored));
+      p[row] = pv;
+    }
+  }
+  if (PROB) {
+    double tot = block_sum(pv, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
+}
+
+// Structured stencils (no index arrays): neighbours computed from v.
+template <typename T, int KIND, bool PROB>
+__global__ __launch_bounds__(kBlock) void k_ctqw_struct(GraphView g, const T *__restrict__ y,
+                                                        const T *psi, T *out, double alpha,
+                                                        double beta, double *p, double *partials) {
+  __shared__ double red[16];
+  const int n = g.n;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double pv = 0.0;
+  if (v < n) {
+    double2 s = make_double2(0.0, 0.0);
+    if (KIND == kHypercube) {
+      const int dim = g.dims[0];
+      for (int j = 0; j < dim; ++j) s = add(s, ld(y, v ^ (1 << j)));
+    } else if (KIND == kCycle) {
+      s = add(ld(y, head_of<kCycle>(v, 0, n, 0)), ld(y, head_of<kCycle>(v, 1, n, 0)));
+    } else {
+      const int l2 = g.dims[1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s = add(s, ld(y, head_of<kTorus>(v, j, n, l2)));
+    }
+    const bool mk = marked(g.markbits, v);
+    double2 yv = mk ? ld(y, v) : make_double2(0.0, 0.0);
+    double2 r = horner_out(ld(psi, v), s, yv, mk, alpha, beta);
+    st(out, v, r);
+    if (PROB) {
+      pv = abs2(cvt(pack<T>(r)));
+      p[v] = pv;
+    }
+  }
+  if (PROB) {
+    double tot = block_sum(pv, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
+}
+
+// CTQW small graphs: every stage of every step in one workgroup, vectors in LDS.
+struct Coefs {
+  double alpha[64];
+  double beta[64];
+};
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_ctqw_small(GraphView g, T *psi, Coefs c, int K,
+                                                     int64_t steps, Readout ro) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  const int n = g.n, na = g.n_arcs;
+  T *ps = reinterpret_cast<T *>(smem);
+  T *ya = ps + n;
+  T *yb = ya + n;
+  int32_t *srp = reinterpret_cast<int32_t *>(yb + n);
+  int32_t *scol = srp + n + 1;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ps[i] = psi[i];
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) srp[i] = g.rp[i];
+  for (int i = threadIdx.x; i < na; i += blockDim.x) scol[i] = g.col[i];
+  __syncthreads();
+  for (int64_t s = 0; s < steps; ++s) {
+    const T *yin = ps;
+    for (int k = K; k >= 1; --k) {
+      T *yout = (k == 1) ? ((K == 1) ? ya : ps) : (((K - k) & 1) ? yb : ya);
+      // k == 1 with K >= 2 writes psi in place: each thread reads psi[v] before
+      // writing it and the gathers read yin != ps.
+      for (int v = threadIdx.x; v < n; v += blockDim.x) {
+        double2 sum = make_double2(0.0, 0.0);
+        for (int a = srp[v]; a < srp[v + 1]; ++a) sum = add(sum, cvt(yin[scol[a]]));
+        const bool mk = marked(g.markbits, v);
+        double2 yv = mk ? cvt(yin[v]) : make_double2(0.0, 0.0);
+        double2 r = horner_out(cvt(ps[v]), sum, yv, mk, c.alpha[k - 1], c.beta[k - 1]);
+        yout[v] = pack<T>(r);
+      }
+      __syncthreads();
+      yin = yout;
+    }
+    if (K == 1) {
+      for (int v = threadIdx.x; v < n; v += blockDim.x) ps[v] = ya[v];
+      __syncthreads();
+    }
+  }
+  for (int v = threadIdx.x; v < n; v += blockDim.x) psi[v] = ps[v];
+  if (ro.p || ro.norm || ro.pmarked) {
+    double *pout = ro.p ? ro.p : ro.pscratch;
+    double acc = 0.0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      double pv = abs2(cvt(ps[v]));
+      pout[v] = pv;
+      acc += pv;
+    }
+    double tot = block_sum(acc, red);
+    __syncthreads();
+    double pm = 0.0;
+    for (int i = threadIdx.x; i < g.n_marked; i += blockDim.x) pm += abs2(cvt(ps[g.marklist[i]]));
+    double ptot = block_sum(pm, red);
+    if (threadIdx.x == 0) {
+      if (ro.norm) *ro.norm = tot;
+      if (ro.pmarked) *ro.pmarked = ptot;
+    }
+  }
+}
+
+inline int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
+
+template <typename T> hipError_t launch_coined_small(const GraphView &g, void *psi, int hadamard,
+                                                     int64_t steps, const Readout &ro, hipStream_t s) {
+  size_t lds = coined_small_lds(sizeof(T) == 16, g.n, g.n_arcs);
+  int threads = 64;
+  while (threads < 1024 && threads < g.n_arcs) threads *= 2;
+  hipLaunchKernelGGL(k_coined_small<T>, dim3(1), dim3(threads), lds, s, g, static_cast<T *>(psi),
+                     hadamard, steps, ro);
+  return hipGetLastError();
+}
+
+template <typename T> hipError_t launch_ctqw_small(const GraphView &g, void *psi, const double *alpha,
+                                                   const double *beta, int K, int64_t steps,
+                                                   const Readout &ro, hipStream_t s) {
+  Coefs c;
+  for (int k = 0; k < 64; ++k) {
+    c.alpha[k] = k < K ? alpha[k] : 0.0;
+    c.beta[k] = k < K ? beta[k] : 0.0;
+  }
+  size_t lds = ctqw_small_lds(sizeof(T) == 16, g.n, g.n_arcs);
+  int threads = 64;
+  while (threads < 1024 && threads < g.n) threads *= 2;
+  hipLaunchKernelGGL(k_ctqw_small<T>, dim3(1), dim3(threads), lds, s, g, static_cast<T *>(psi), c, K,
+                     steps, ro);
+  return hipGetLastError();
+}
+
+template <typename T, int KIND, int D>
+void launch_struct(const GraphView &g, const void *in, void *out, int dim, int hadamard, hipStream_t s) {
+  hipLaunchKernelGGL((k_coined_struct<T, KIND, D>), dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, s, g,
+                     static_cast<const T *>(in), static_cast<T *>(out), dim, hadamard);
+}
+
+template <typename T>
+hipError_t launch_coined_struct(const GraphView &g, const void *in, void *out, int hadamard, hipStream_t s) {
+  switch (g.structure) {
+    case kCycle: launch_struct<T, kCycle, 2>(g, in, out, 2, hadamard, s); break;
+    case kTorus: launch_struct<T, kTorus, 4>(g, in, out, 4, 0, s); break;
+    case kHypercube: {
+      const int dim = g.dims[0];
+      if (dim <= 8) launch_struct<T, kHypercube, 8>(g, in, out, dim, 0, s);
+      else if (dim <= 16) launch_struct<T, kHypercube, 16>(g, in, out, dim, 0, s);
+      else if (dim <= 24) launch_struct<T, kHypercube, 24>(g, in, out, dim, 0, s);
+      else launch_struct<T, kHypercube, 32>(g, in, out, dim, 0, s);
+      break;
+    }
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int G, bool PROB>
+void launch_csr_g(const GraphView &g, const T *y, const T *psi, T *out, StageCoef c, double *p,
+                  double *partials, hipStream_t s) {
+  const int64_t threads = static_cast<int64_t>(g.n) * G;
+  hipLaunchKernelGGL((k_ctqw_csr<T, G, PROB>), dim3(blocks_for(threads, kBlock)), dim3(kBlock), 0, s, g, y,
+                     psi, out, c.alpha, c.beta, p, partials);
+}
+
+template <typename T, bool PROB>
+hipError_t launch_ctqw_stage(const GraphView &g, const T *y, const T *psi, T *out, StageCoef c, double *p,
+                             double *partials, hipStream_t s) {
+  if (g.structure == kGeneral) {
+    switch (g.group) {
+      case 1: launch_csr_g<T, 1, PROB>(g, y, psi, out, c, p, partials, s); break;
+      case 2: launch_csr_g<T, 2, PROB>(g, y, psi, out, c, p, partials, s); break;
+      case 4: launch_csr_g<T, 4, PROB>(g, y, psi, out, c, p, partials, s); break;
+      case 8: launch_csr_g<T, 8, PROB>(g, y, psi, out, c, p, partials, s); break;
+      case 16: launch_csr_g<T, 16, PROB>(g, y, psi, out, c, p, partials, s); break;
+      case 32: launch_csr_g<T, 32, PROB>(g, y, psi, out, c, p, partials, s); break;
+      default: launch_csr_g<T, 64, PROB>(g, y, psi, out, c, p, partials, s); break;
+    }
+  } else {
+    const dim3 grid(blocks_for(g.n, kBlock));
+    switch (g.structure) {
+      case kCycle:
+        hipLaunchKernelGGL((k_ctqw_struct<T, kCycle, PROB>), grid, dim3(kBlock), 0, s, g, y, psi, out,
+                           c.alpha, c.beta, p, partials);
+        break;
+      case kTorus:
+        hipLaunchKernelGGL((k_ctqw_struct<T, kTorus, PROB>), grid, dim3(kBlock), 0, s, g, y, psi, out,
+                           c.alpha, c.beta, p, partials);
+        break;
+      case kHypercube:
+        hipLaunchKernelGGL((k_ctqw_struct<T, kHypercube, PROB>), grid, dim3(kBlock), 0, s, g, y, psi,
+                           out, c.alpha, c.beta, p, partials);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// ============================ launchers ======================================
+
+size_t coined_small_lds(bool c128, int n, int n_arcs) {
+  const size_t es = c128 ? 16 : 8;
+  return 2 * es * static_cast<size_t>(n_arcs) + 4 * (static_cast<size_t>(n) + 1 + n_arcs);
+}
+
+size_t ctqw_small_lds(bool c128, int n, int n_arcs) {
+  const size_t es = c128 ? 16 : 8;
+  return 3 * es * static_cast<size_t>(n) + 4 * (static_cast<size_t>(n) + 1 + n_arcs);
+}
+
+hipError_t coined_small(bool c128, const GraphView &g, void *psi, int hadamard, int64_t steps,
+                        const Readout &ro, hipStream_t s) {
+  return c128 ? launch_coined_small<double2>(g, psi, hadamard, steps, ro, s)
+              : launch_coined_small<float2>(g, psi, hadamard, steps, ro, s);
+}
+
+hipError_t coined_tile_step(bool c128, const GraphView &g, const void *in, void *out, int hadamard,
+                            hipStream_t s) {
+  if (g.n_tiles == 0) return hipSuccess;
+  if (c128)
+    hipLaunchKernelGGL(k_coined_tile<double2>, dim3(g.n_tiles), dim3(kTileThreads), 0, s, g,
+                       static_cast<const double2 *>(in), static_cast<double2 *>(out), hadamard);
+  else
+    hipLaunchKernelGGL(k_coined_tile<float2>, dim3(g.n_tiles), dim3(kTileThreads), 0, s, g,
+                       static_cast<const float2 *>(in), static_cast<float2 *>(out), hadamard);
+  return hipGetLastError();
+}
+
+hipError_t coined_struct_step(bool c128, const GraphView &g, const void *in, void *out, int hadamard,
+                              hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  return c128 ? launch_coined_struct<double2>(g, in, out, hadamard, s)
+              : launch_coined_struct<float2>(g, in, out, hadamard, s);
+}
+
+hipError_t coined_perm_in(bool c128, const GraphView &g, const void *psi, void *internal, hipStream_t s) {
+  if (g.n_arcs == 0) return hipSuccess;
+  const dim3 grid(blocks_for(g.n_arcs, kBlock));
+  if (c128)
+    hipLaunchKernelGGL(k_perm_in<double2>, grid, dim3(kBlock), 0, s, static_cast<const double2 *>(psi),
+                       static_cast<double2 *>(internal), g.perm, g.n_arcs);
+  else
+    hipLaunchKernelGGL(k_perm_in<float2>, grid, dim3(kBlock), 0, s, static_cast<const float2 *>(psi),
+                       static_cast<float2 *>(internal), g.perm, g.n_arcs);
+  return hipGetLastError();
+}
+
+hipError_t coined_perm_out(bool c128, const GraphView &g, const void *internal, void *psi,
+                           const Readout &ro, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  const int d = g.n > 0 ? g.n_arcs / g.n : 0;
+  const dim3 grid(blocks_for(g.n, kBlock));
+  double *p = ro.any() ? ro.p_out() : nullptr;
+  double *partials = ro.any() ? ro.partials : nullptr;
+  if (c128)
+    hipLaunchKernelGGL(k_perm_out<double2>, grid, dim3(kBlock), 0, s,
+                       static_cast<const double2 *>(internal), static_cast<double2 *>(psi), g.perm, g.n, d,
+                       p, partials);
+  else
+    hipLaunchKernelGGL(k_perm_out<float2>, grid, dim3(kBlock), 0, s, static_cast<const float2 *>(internal),
+                       static_cast<float2 *>(psi), g.perm, g.n, d, p, partials);
+  return hipGetLastError();
+}
+
+hipError_t copy_state(bool c128, int64_t len, const void *in, void *out, hipStream_t s) {
+  if (len == 0) return hipSuccess;
+  const dim3 grid(blocks_for(len, kBlock));
+  if (c128)
+    hipLaunchKernelGGL(k_copy<double2>, grid, dim3(kBlock), 0, s, static_cast<const double2 *>(in),
+                       static_cast<double2 *>(out), len);
+  else
+    hipLaunchKernelGGL(k_copy<float2>, grid, dim3(kBlock), 0, s, static_cast<const float2 *>(in),
+                       static_cast<float2 *>(out), len);
+  return hipGetLastError();
+}
+
+int readout_partials(const GraphView &g) { return blocks_for(g.n, kBlock); }
+
+int ctqw_stage_partials(const GraphView &g) {
+  const int64_t lanes = g.structure == kGeneral ? static_cast<int64_t>(g.n) * g.group : g.n;
+  return blocks_for(lanes, kBlock);
+}
+
+hipError_t coined_prob_csr(bool c128, const GraphView &g, const void *psi, const Readout &ro,
+                           hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  const dim3 grid(blocks_for(g.n, kBlock));
+  if (c128)
+    hipLaunchKernelGGL(k_prob_csr<double2>, grid, dim3(kBlock), 0, s, g, static_cast<const double2 *>(psi),
+                       ro.p_out(), ro.partials);
+  else
+    hipLaunchKernelGGL(k_prob_csr<float2>, grid, dim3(kBlock), 0, s, g, static_cast<const float2 *>(psi),
+                       ro.p_out(), ro.partials);
+  return hipGetLastError();
+}
+
+hipError_t ctqw_small(bool c128, const GraphView &g, void *psi, const double *alpha, const double *beta,
+                      int K, int64_t steps, const Readout &ro, hipStream_t s) {
+  return c128 ? launch_ctqw_small<double2>(g, psi, alpha, beta, K, steps, ro, s)
+              : launch_ctqw_small<float2>(g, psi, alpha, beta, K, steps, ro, s);
+}
+
+hipError_t ctqw_stage(bool c128, const GraphView &g, const void *y, const void *psi, void *out, StageCoef c,
+                      const Readout *fused, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  if (c128) {
+    auto *yy = static_cast<const double2 *>(y);
+    auto *pp = static_cast<const double2 *>(psi);
+    auto *oo = static_cast<double2 *>(out);
+    return fused ? launch_ctqw_stage<double2, true>(g, yy, pp, oo, c, fused->p_out(), fused->partials, s)
+                 : launch_ctqw_stage<double2, false>(g, yy, pp, oo, c, nullptr, nullptr, s);
+  }
+  auto *yy = static_cast<const float2 *>(y);
+  auto *pp = static_cast<const float2 *>(psi);
+  auto *oo = static_cast<float2 *>(out);
+  return fused ? launch_ctqw_stage<float2, true>(g, yy, pp, oo, c, fused->p_out(), fused->partials, s)
+               : launch_ctqw_stage<float2, false>(g, yy, pp, oo, c, nullptr, nullptr, s);
+}
+
+hipError_t vertex_prob(bool c128, const GraphView &g, const void *psi, const Readout &ro, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  const dim3 grid(blocks_for(g.n, kBlock));
+  if (c128)
+    hipLaunchKernelGGL(k_prob_vertex<double2>, grid, dim3(kBlock), 0, s, static_cast<const double2 *>(psi),
+                       g.n, ro.p_out(), ro.partials);
+  else
+    hipLaunchKernelGGL(k_prob_vertex<float2>, grid, dim3(kBlock), 0, s, static_cast<const float2 *>(psi),
+                       g.n, ro.p_out(), ro.partials);
+  return hipGetLastError();
+}
+
+hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s) {
+  if (!ro.norm && !ro.pmarked) return hipSuccess;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, ro.partials, count, ro.p_out(), g.marklist,
+                     g.n_marked, ro.norm, ro.pmarked);
+  return hipGetLastError();
+}
+
+}  // namespace qwk

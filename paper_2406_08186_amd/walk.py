@@ -1,0 +1,195 @@
+"""Python surface of the engine: plans over torch device memory, and the
+user-level walk classes modelled on Hiperwalk's frontend (Sec. 3.1, 3.2).
+
+Torch owns every device buffer and stream; the library only enqueues
+kernels on the stream it is given.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Iterable, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .inputs import Graph, arc_index
+
+_DT = {"c64": L.QW_C64, "c128": L.QW_C128}
+_TORCH_DT = {"c64": torch.complex64, "c128": torch.complex128}
+_LAYOUT = {"auto": L.QW_LAYOUT_AUTO, "csr": L.QW_LAYOUT_CSR, "structured": L.QW_LAYOUT_STRUCTURED}
+
+
+def _stream_ptr(stream, device) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A validated walk on one graph with its device tables uploaded.
+
+    kind: "coined" or "ctqw"; coin: "grover" or "hadamard"; dtype: "c64" or
+    "c128"; layout: "auto", "csr" or "structured".  CTQW takes gamma, dt and
+    either taylor_order or (trunc_tol, horizon_steps).
+    """
+
+    def __init__(self, graph: Graph, kind: str = "coined", *, coin: str = "grover",
+                 dtype: str = "c128", layout: str = "auto", gamma: float = 0.0, dt: float = 0.0,
+                 taylor_order: int = 0, trunc_tol: float = 0.0, horizon_steps: int = 0,
+                 marked: Sequence[int] = (), device=None, stream=None):
+        self.graph = graph
+        self.kind = kind
+        self.dtype = dtype
+        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self._rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int64)
+        self._col = np.ascontiguousarray(graph.col, dtype=np.int32)
+        if self._col.size == 0:
+            self._col = np.zeros(1, dtype=np.int32)
+        self._marked = np.ascontiguousarray(np.asarray(list(marked), dtype=np.int32))
+        csr = L.QwCsr(graph.n, self._rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                      self._col.ctypes.data_as(C.POINTER(C.c_int32)))
+        desc = L.QwWalkDesc(
+            kind=L.QW_COINED if kind == "coined" else L.QW_CTQW,
+            coin=L.QW_HADAMARD if coin == "hadamard" else L.QW_GROVER,
+            dtype=_DT[dtype], layout=_LAYOUT[layout], gamma=float(gamma), dt=float(dt),
+            taylor_order=int(taylor_order), trunc_tol=float(trunc_tol),
+            horizon_steps=int(horizon_steps),
+            marked=self._marked.ctypes.data_as(C.POINTER(C.c_int32)) if self._marked.size else None,
+            n_marked=int(self._marked.size))
+        self._plan = L.qw_plan_create(csr, desc)
+        self.info = L.qw_plan_get_info(self._plan)
+        self.structure = L.STRUCTURES[self.info.structure]
+        self.d_graph = torch.empty(max(self.info.graph_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(max(self.info.work_bytes, 256), dtype=torch.uint8, device=self.device)
+        self._p = torch.empty(max(graph.n, 1), dtype=torch.float64, device=self.device)
+        self._scal = torch.zeros(2, dtype=torch.float64, device=self.device)
+        L.qw_plan_upload(self._plan, self.d_graph.data_ptr(), self.d_graph.numel(),
+                         _stream_ptr(stream, self.device))
+
+    # -- lifetime
+    def close(self) -> None:
+        if getattr(self, "_plan", None):
+            L.qw_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- states
+    @property
+    def state_len(self) -> int:
+        return int(self.info.state_len)
+
+    def state(self, psi0) -> torch.Tensor:
+        """Device copy of psi0 in this plan's precision."""
+        t = torch.as_tensor(np.asarray(psi0) if not torch.is_tensor(psi0) else psi0)
+        if t.numel() != self.state_len:
+            raise ValueError(f"state has {t.numel()} elements, plan needs {self.state_len}")
+        return t.to(device=self.device, dtype=_TORCH_DT[self.dtype]).contiguous()
+
+    def _check(self, psi: torch.Tensor) -> None:
+        if psi.device != self.device or psi.dtype != _TORCH_DT[self.dtype] or not psi.is_contiguous() \
+                or psi.numel() != self.state_len:
+            raise ValueError("state tensor does not match the plan (device/dtype/length/contiguity)")
+
+    # -- hot path
+    def evolve(self, psi: torch.Tensor, steps: int, readout: bool = False, stream=None):
+        """psi <- U^steps psi in place; with readout, also (p, norm, p_marked) on device."""
+        self._check(psi)
+        sp = _stream_ptr(stream, self.device)
+        if readout:
+            p, scal = self._p, self._scal
+            L.qw_evolve(self._plan, psi.data_ptr(), self.work.data_ptr(), self.work.numel(), int(steps),
+                        p.data_ptr(), scal.data_ptr(), scal.data_ptr() + 8, sp)
+            return p[:self.graph.n], scal[0], scal[1]
+        L.qw_evolve(self._plan, psi.data_ptr(), self.work.data_ptr(), self.work.numel(), int(steps),
+                    None, None, None, sp)
+        return None
+
+    def probabilities(self, psi: torch.Tensor, stream=None):
+        """(p, norm, p_marked) of a state, FP64, on device."""
+        self._check(psi)
+        p = torch.empty(max(self.graph.n, 1), dtype=torch.float64, device=self.device)
+        scal = torch.zeros(2, dtype=torch.float64, device=self.device)
+        L.qw_probabilities(self._plan, psi.data_ptr(), p.data_ptr(), scal.data_ptr(),
+                           scal.data_ptr() + 8, self.work.data_ptr(), self.work.numel(),
+                           _stream_ptr(stream, self.device))
+        return p[:self.graph.n], scal[0], scal[1]
+
+
+def _steps_of(rng) -> list[int]:
+    if isinstance(rng, int):
+        return list(range(rng))
+    if isinstance(rng, range):
+        return list(rng)
+    return list(range(*rng))
+
+
+class _Walk:
+    plan: Plan
+
+    def simulate(self, range=1, state=None) -> list[torch.Tensor]:
+        """States at the step indices of Python's range(...) (snapshots include step 0
+        when the range starts at 0).  Returns device tensors."""
+        idx = _steps_of(range)
+        if any(b <= a for a, b in zip(idx, idx[1:])) or (idx and idx[0] < 0):
+            raise ValueError("range must be increasing and non-negative")
+        psi = self.plan.state(state)
+        out, at = [], 0
+        for k in idx:
+            self.plan.evolve(psi, k - at)
+            at = k
+            out.append(psi.clone())
+        return out
+
+    def probability_distribution(self, states: Iterable[torch.Tensor]) -> list[torch.Tensor]:
+        return [self.plan.probabilities(s)[0].clone() for s in states]
+
+
+class Coined(_Walk):
+    """Coined walk U = S C with the flip-flop shift (Sec. 3.2)."""
+
+    def __init__(self, graph: Graph, shift: str = "flipflop", coin: str = "grover",
+                 marked: Sequence[int] = (), dtype: str = "c128", layout: str = "auto", device=None):
+        if shift != "flipflop":
+            raise NotImplementedError("only the flip-flop shift is implemented")
+        self.graph = graph
+        self.plan = Plan(graph, "coined", coin=coin, dtype=dtype, layout=layout, marked=marked,
+                         device=device)
+
+    def ket(self, v: int, w: int) -> np.ndarray:
+        psi = np.zeros(self.graph.n_arcs, dtype=np.complex128)
+        psi[arc_index(self.graph, v, w)] = 1.0
+        return psi
+
+
+class ContinuousTime(_Walk):
+    """Continuous-time walk, H = -gamma A - sum_M |v><v| (Sec. 3.1); `time` is the
+    step length of simulate()."""
+
+    def __init__(self, graph: Graph, gamma: float, time: float, marked: Sequence[int] = (),
+                 dtype: str = "c128", taylor_order: int = 0, trunc_tol: float = 1e-13,
+                 horizon_steps: int = 10**4, layout: str = "auto", device=None):
+        self.graph = graph
+        self.gamma = gamma
+        self.marked = list(marked)
+        self.plan = Plan(graph, "ctqw", dtype=dtype, layout=layout, gamma=gamma, dt=time,
+                         taylor_order=taylor_order, trunc_tol=trunc_tol,
+                         horizon_steps=horizon_steps, marked=marked, device=device)
+
+    def ket(self, v: int) -> np.ndarray:
+        psi = np.zeros(self.graph.n, dtype=np.complex128)
+        psi[v] = 1.0
+        return psi
+
+    def get_hamiltonian(self):
+        """H as (row_ptr, col, value of the off-diagonal -gamma, diagonal marked list)."""
+        return self.graph.row_ptr, self.graph.col, -self.gamma, list(self.marked)
+
+
+def uniform_state(n: int) -> np.ndarray:
+    return np.full(n, 1.0 / math.sqrt(n), dtype=np.complex128)

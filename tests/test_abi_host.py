@@ -1,0 +1,185 @@
+"""Host-side checks of the C ABI (no GPU): exports, validation, error codes,
+path choice, sizes, and the Taylor rule against the oracle's."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2406_08186_amd import _lib as L
+from paper_2406_08186_amd import inputs as I
+from oracle import taylor as ot
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "qwalk.h")
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int|double|const char \*)\s*(qw_\w+)\s*\(", text, re.M))
+    assert len(declared) >= 11
+    lib = L.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTS) == declared
+
+
+def _csr(n, rp, col):
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    col = np.ascontiguousarray(col if len(col) else [0], dtype=np.int32)
+    keep = (rp, col)
+    return L.QwCsr(n, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                   col.ctypes.data_as(C.POINTER(C.c_int32))), keep
+
+
+def _desc(**kw):
+    marked = kw.pop("marked", None)
+    d = L.QwWalkDesc(**kw)
+    keep = None
+    if marked is not None:
+        keep = np.ascontiguousarray(marked, dtype=np.int32)
+        d.marked = keep.ctypes.data_as(C.POINTER(C.c_int32))
+        d.n_marked = keep.size
+    return d, keep
+
+
+def _create(g_or_tuple, **kw):
+    if isinstance(g_or_tuple, I.Graph):
+        csr, k1 = _csr(g_or_tuple.n, g_or_tuple.row_ptr, g_or_tuple.col)
+    else:
+        csr, k1 = _csr(*g_or_tuple)
+    desc, k2 = _desc(**kw)
+    return L.qw_plan_create(csr, desc)
+
+
+def _code(fn):
+    with pytest.raises(L.QwError) as e:
+        fn()
+    return e.value.code
+
+
+@pytest.mark.parametrize("bad,code", [
+    ((3, [0, 1, 1, 1], [1]), L.QW_EGRAPH),             # asymmetric
+    ((2, [0, 1, 2], [0, 1]), L.QW_EGRAPH),             # self-loops
+    ((2, [0, 2, 4], [1, 1, 0, 0]), L.QW_EGRAPH),       # repeated arc
+    ((2, [0, 2, 1], [1, 0]), L.QW_EGRAPH),             # decreasing row_ptr
+    ((2, [0, 1, 2], [5, 0]), L.QW_EGRAPH),             # head out of range
+    ((2, [1, 1, 2], [1, 0]), L.QW_EGRAPH),             # row_ptr[0] != 0
+])
+def test_invalid_graphs_rejected(bad, code):
+    assert _code(lambda: _create(bad, kind=0, coin=0, dtype=1)) == code
+    msg = L.lib().qw_last_error().decode()
+    assert msg
+
+
+def test_walk_validation():
+    g = I.hypercube(4)
+    assert _code(lambda: _create(g, kind=0, coin=1, dtype=1)) == L.QW_EUNSUPPORTED  # Hadamard d=4
+    assert _code(lambda: _create(g, kind=7, dtype=1)) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=0, dtype=9)) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=1, dtype=1, gamma=0.0, dt=0.1, taylor_order=4)) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=1, dtype=1, gamma=1.0, dt=-1.0, taylor_order=4)) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=1, dtype=1, gamma=1.0, dt=0.1, taylor_order=65)) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=1, dtype=1, gamma=1.0, dt=0.1)) == L.QW_EINVAL  # auto K w/o tol
+    assert _code(lambda: _create(g, kind=0, dtype=1, marked=[16])) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=0, dtype=1, marked=[3, 3])) == L.QW_EINVAL
+    # Hadamard with a marked vertex of other degree, and isolated vertices, is fine
+    c = I.cycle(6)
+    L.qw_plan_destroy(_create(c, kind=0, coin=1, dtype=1, marked=[2]))
+    # huge rho: no order meets the tolerance
+    assert _code(lambda: _create(g, kind=1, dtype=1, gamma=100.0, dt=10.0, trunc_tol=1e-12,
+                                 horizon_steps=10)) == L.QW_EUNSUPPORTED
+
+
+def test_null_arguments():
+    assert L.lib().qw_plan_create(None, None, None) == L.QW_EINVAL
+    out = C.c_void_p()
+    assert L.lib().qw_plan_create(None, None, C.byref(out)) == L.QW_EINVAL and not out.value
+    assert L.lib().qw_plan_get_info(None, None) == L.QW_EINVAL
+    assert L.lib().qw_plan_destroy(None) == L.QW_OK
+
+
+def test_evolve_before_upload_is_state_error():
+    p = _create(I.cycle(8), kind=0, coin=0, dtype=1)
+    rc = L.lib().qw_evolve(p, None, None, 0, 1, None, None, None, None)
+    assert rc == L.QW_ESTATE
+    L.qw_plan_destroy(p)
+
+
+@pytest.mark.parametrize("g,kind,layout,expect", [
+    (I.hypercube(10), 0, L.QW_LAYOUT_AUTO, "hypercube"),
+    (I.hypercube(3), 0, L.QW_LAYOUT_AUTO, "small"),
+    (I.hypercube(3), 0, L.QW_LAYOUT_STRUCTURED, "hypercube"),
+    (I.hypercube(10), 0, L.QW_LAYOUT_CSR, "general"),
+    (I.torus(40, 30), 0, L.QW_LAYOUT_AUTO, "torus"),
+    (I.torus(40, 30), 1, L.QW_LAYOUT_AUTO, "torus"),
+    (I.torus(3, 3), 1, L.QW_LAYOUT_STRUCTURED, "torus"),
+    (I.cycle(5000), 0, L.QW_LAYOUT_AUTO, "cycle"),
+    (I.cycle_sorted(5000), 1, L.QW_LAYOUT_AUTO, "cycle"),
+    (I.random_regular(3000, 4, 1), 0, L.QW_LAYOUT_AUTO, "general"),
+    (I.random_regular(3000, 4, 1), 1, L.QW_LAYOUT_STRUCTURED, "general"),
+])
+def test_path_choice(g, kind, layout, expect):
+    kw = dict(kind=kind, coin=0, dtype=1, layout=layout)
+    if kind == 1:
+        kw.update(gamma=0.25, dt=0.1, taylor_order=20)
+    p = _create(g, **kw)
+    info = L.qw_plan_get_info(p)
+    assert L.STRUCTURES[info.structure] == expect
+    assert info.n == g.n and info.n_arcs == g.n_arcs
+    assert info.state_len == (g.n_arcs if kind == 0 else g.n)
+    assert info.state_bytes == 16 * info.state_len
+    assert info.work_bytes >= 2 * info.state_bytes and info.graph_bytes > 0
+    if expect == "torus":
+        assert tuple(info.dims) == (40, 30) or tuple(info.dims) == (3, 3)
+    L.qw_plan_destroy(p)
+
+
+def test_hadamard_cycle_structured_needs_direction_order():
+    p = _create(I.cycle(5000), kind=0, coin=1, dtype=1)
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "cycle"
+    L.qw_plan_destroy(p)
+    p = _create(I.cycle_sorted(5000), kind=0, coin=1, dtype=1)
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "general"
+    L.qw_plan_destroy(p)
+
+
+@pytest.mark.parametrize("rho", [0.05, 0.1, 0.5, 1.0, 1.7, 2.0, 3.0])
+@pytest.mark.parametrize("steps", [1, 100, 10**4])
+@pytest.mark.parametrize("tol", [1e-6, 1e-10, 1e-13])
+def test_taylor_order_matches_oracle_rule(rho, steps, tol):
+    k_or = ot.taylor_order(rho, steps, tol)
+    if k_or < 0:
+        assert _code(lambda: L.qw_taylor_order(rho, steps, tol)) == L.QW_EUNSUPPORTED
+    else:
+        assert L.qw_taylor_order(rho, steps, tol) == k_or
+    assert L.qw_taylor_tail_bound(rho, 12) == pytest.approx(ot.tail_bound(rho, 12), rel=1e-12)
+
+
+def test_taylor_plan_matches_oracle_rule():
+    for hb, t, rmax, tol in [(2.0, 15.0, 1.0, 1e-8), (1.25, 100.0, 2.0, 1e-10), (9.0, 3.3, 0.5, 1e-12)]:
+        k, dt, n = L.qw_taylor_plan(hb, t, rmax, tol)
+        k2, dt2, n2 = ot.taylor_plan(hb, t, rmax, tol)
+        assert (k, n) == (k2, n2) and dt == dt2
+
+
+def test_plan_reports_auto_order_and_bound():
+    g = I.random_regular(200, 5, 3)
+    p = _create(g, kind=1, dtype=0, gamma=0.2, dt=0.5, trunc_tol=1e-9, horizon_steps=400, marked=[3])
+    info = L.qw_plan_get_info(p)
+    hb = ot.h_norm_bound(np.diff(g.row_ptr), 0.2, [3])
+    assert info.h_norm_bound == pytest.approx(hb)
+    assert info.taylor_order == ot.taylor_order(0.5 * hb, 400, 1e-9)
+    assert info.trunc_bound == pytest.approx(ot.tail_bound(0.5 * hb, info.taylor_order), rel=1e-12)
+    L.qw_plan_destroy(p)
+
+
+def test_empty_and_isolated_graphs_plan():
+    p = _create((0, [0], []), kind=0, dtype=1)
+    info = L.qw_plan_get_info(p)
+    assert info.n == 0 and info.state_len == 0
+    L.qw_plan_destroy(p)
+    p = _create((4, [0, 0, 1, 2, 2], [2, 1]), kind=1, dtype=1, gamma=1.0, dt=0.1, taylor_order=8)
+    assert L.qw_plan_get_info(p).state_len == 4
+    L.qw_plan_destroy(p)
