@@ -41,19 +41,35 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--steps-per-pass", type=int, default=STEPS_PER_PASS,
+                    help="time steps per pass (profiling runs shorten it; rates are per arc-step)")
+    ap.add_argument("--dtypes", default="c64,c128")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
 
 
-def timed_passes(plan, psi, steps, warmup):
+def copy_probe(mib):
+    import torch
+    n = mib * 2**20 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 8, "launches": 5}), flush=True)
+
+
+def timed_passes(plan, psi, steps, warmup, spp):
     import torch
     for _ in range(warmup):
-        plan.evolve(psi, STEPS_PER_PASS, readout=True)
+        plan.evolve(psi, spp, readout=True)
     torch.cuda.synchronize()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     evs[0].record()
     for i in range(steps):
-        out = plan.evolve(psi, STEPS_PER_PASS, readout=True)
+        out = plan.evolve(psi, spp, readout=True)
         evs[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -108,6 +124,11 @@ def main():
         print(f"bench.py runs on one GPU only: the walk engine has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    spp = args.steps_per_pass
+    dtypes = args.dtypes.split(",")
     import numpy as np
     import torch
 
@@ -119,11 +140,11 @@ def main():
     v0 = (L_SIDE // 2) * L_SIDE + L_SIDE // 2
     psi0 = I.ket_vertex(g.n, v0)
     res = {}
-    for dtype in ("c64", "c128"):
+    for dtype in dtypes:
         pl = Plan(g, "ctqw", dtype=dtype, gamma=GAMMA, dt=DT, taylor_order=K_ORDER)
         psi = pl.state(psi0)
-        wall, per, (p, norm, _) = timed_passes(pl, psi, args.steps, args.warmup)
-        total_steps = (args.steps + args.warmup) * STEPS_PER_PASS
+        wall, per, (p, norm, _) = timed_passes(pl, psi, args.steps, args.warmup, spp)
+        total_steps = (args.steps + args.warmup) * spp
         state = psi.cpu().numpy().astype(np.complex128)
         launch_ms = stage_launch_ms(pl, pl.state(psi0))
         es = 8 if dtype == "c64" else 16
@@ -132,15 +153,21 @@ def main():
                           total_steps=total_steps, launch_ms=launch_ms,
                           bytes_per_launch=bytes_per_launch, structure=pl.structure)
         del psi
-    t_final = res["c64"]["total_steps"] * DT
+    t_final = res[dtypes[0]]["total_steps"] * DT
     ref1 = cf.cycle_ctqw(L_SIDE, GAMMA, t_final, L_SIDE // 2)
     ref = np.outer(ref1, ref1).reshape(-1)
-    l2_64 = float(np.linalg.norm(res["c64"]["state"] - ref))
-    l2_128 = float(np.linalg.norm(res["c128"]["state"] - ref))
+    for r in res.values():
+        r["l2"] = float(np.linalg.norm(r["state"] - ref))
+    if "c64" not in res or "c128" not in res:
+        r = res[dtypes[0]]
+        print(json.dumps({"dtype": dtypes[0], "steps_per_pass": spp, "ms_per_step": r["wall"] / args.steps * 1e3,
+                          "stage_launch_ms": r["launch_ms"], "l2_vs_closed_form": r["l2"]}), flush=True)
+        return
+    l2_64, l2_128 = res["c64"]["l2"], res["c128"]["l2"]
     l2_64_128 = float(np.linalg.norm(res["c64"]["state"] - res["c128"]["state"]))
 
     def rate(r):
-        return g.n_arcs * STEPS_PER_PASS * args.steps / r["wall"]
+        return g.n_arcs * spp * args.steps / r["wall"]
 
     r64, r128 = res["c64"], res["c128"]
     achieved = r64["bytes_per_launch"] / (r64["launch_ms"] * 1e-3) / 1e9
@@ -159,7 +186,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ctqw_torus_1024x1024_gamma0.25_K20_dt0.1_1000steps",
                    "n": g.n, "arcs": g.n_arcs, "gamma": GAMMA, "dt": DT, "taylor_order": K_ORDER,
-                   "steps_per_pass": STEPS_PER_PASS, "start_vertex": v0,
+                   "steps_per_pass": spp, "start_vertex": v0,
                    "path": r64["structure"], "parallelism": "single-gpu"},
         "arc_spmv_per_s": rate(r64) * K_ORDER,
         "p50_ms": pct(r64["per"], 50), "p99_ms": pct(r64["per"], 99),

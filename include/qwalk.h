@@ -181,6 +181,78 @@ int qw_evolve(const qw_plan *plan, void *d_psi, void *d_work, size_t work_bytes,
 int qw_probabilities(const qw_plan *plan, const void *d_psi, double *d_p, double *d_norm,
                      double *d_pmarked, void *d_work, size_t work_bytes, void *stream);
 
+/* ---- batched walks ------------------------------------------------------ */
+/* A batch advances many walks (of different graphs, sizes, kinds and step
+ * counts) together: each launch moves every active slot one unit forward --
+ * a Horner stage of a CTQW step, or one coined step -- so small walks share
+ * launches with large ones.  Launch sequences are captured into a hipGraph
+ * and replayed.  Slots can be filled and emptied between runs, which is how a
+ * serving loop does continuous batching; the per-walk arithmetic and its order
+ * do not depend on the other slots, so a walk's result is bitwise the same
+ * alone and in any mix.  All slots share one dtype.  Walks need plans on the
+ * general CSR path (QW_LAYOUT_CSR); CTQW walks need K >= 2; coined walks need
+ * every vertex degree <= 2048.
+ *
+ * Typical use: qw_batch_create -> qw_batch_device_bytes -> (caller allocates)
+ * -> qw_batch_bind -> qw_batch_set_slot... -> qw_batch_commit -> [optional
+ * qw_batch_autotune] -> qw_batch_run(launches) -> qw_batch_remaining /
+ * qw_batch_readout -> qw_batch_clear_slot / qw_batch_set_slot -> commit ...
+ * Host calls on one batch are not thread-safe. */
+typedef struct qw_batch qw_batch;
+
+/* capacity: slots (1..2^20); max_tiles: upper bound on the tile table (a tile
+ * is up to rows_per_tile CTQW rows or one LDS tile of a coined walk; rounded
+ * up to a multiple of 8); dtype: QW_C64 or QW_C128.  Host only. */
+int qw_batch_create(int32_t capacity, int32_t max_tiles, int32_t dtype, qw_batch **out);
+/* Frees the batch's host state, pinned staging buffer, capture stream and
+ * graph.  Does not touch caller device memory.  NULL is accepted. */
+int qw_batch_destroy(qw_batch *batch);
+/* Device bytes for the batch's tables (control word, slots, coefficients,
+ * tiles). */
+int qw_batch_device_bytes(const qw_batch *batch, size_t *bytes);
+/* Bind the batch to a caller-owned device buffer (>= qw_batch_device_bytes,
+ * 256-byte aligned), reset the launch counter and empty every slot (tables
+ * uploaded on `stream`). */
+int qw_batch_bind(qw_batch *batch, void *d_buf, size_t bytes, void *stream);
+/* Stage a walk into `slot` (host side; takes effect at the next commit).  The
+ * plan must be uploaded and outlive the slot; d_psi (state, in/out) and
+ * d_work (>= the plan's work_bytes) are caller-owned and must not be used by
+ * anything else while the walk runs.  `steps` time steps are run starting at
+ * the next launch.  d_hist (CTQW only, may be NULL): double[steps], zeroed by
+ * the caller, receives p_marked after each step (atomic adds, so with several
+ * marked vertices the last bits depend on order). */
+int qw_batch_set_slot(qw_batch *batch, int32_t slot, const qw_plan *plan, void *d_psi, void *d_work,
+                      size_t work_bytes, int64_t steps, double *d_hist);
+/* Empty a slot (host side; takes effect at the next commit). */
+int qw_batch_clear_slot(qw_batch *batch, int32_t slot);
+/* Rebuild the tile table (each walk's tiles on one XCD when the schedule says
+ * so) and upload slots and tiles on `stream`.  QW_ENOMEM if the tiles exceed
+ * max_tiles. */
+int qw_batch_commit(qw_batch *batch, void *stream);
+/* Enqueue `launches` batched launches on `stream` (graph replays plus single
+ * launches).  Slots whose walks finished are skipped by the kernel. */
+int qw_batch_run(qw_batch *batch, int64_t launches, void *stream);
+/* Launches still needed by a slot (host mirror; 0 for an empty or finished
+ * slot), and launches enqueued since bind. */
+int qw_batch_remaining(const qw_batch *batch, int32_t slot, int64_t *remaining);
+int qw_batch_launches(const qw_batch *batch, int64_t *launches);
+/* Finish a walk: bring its final state into d_psi (coined walks with an odd
+ * step count end in the workspace) and produce the FP64 readout of
+ * qw_probabilities into the given device pointers (each may be NULL).
+ * QW_ESTATE if the slot has launches left. */
+int qw_batch_readout(qw_batch *batch, int32_t slot, double *d_p, double *d_norm, double *d_pmarked,
+                     void *stream);
+/* Schedule knobs: CTQW rows per tile (64..2^20) and XCD-aware placement. */
+int qw_batch_set_schedule(qw_batch *batch, int32_t rows_per_tile, int32_t xcd_aware);
+/* Autotuner: time each candidate schedule (rows per tile in {256..4096}, XCD
+ * placement on/off) with `reps` probe launches in which every active walk
+ * computes its first unit without advancing (states unchanged), keep the
+ * fastest, and cache it in-process by (dtype, log2 total rows, mean degree).
+ * Synchronises `stream`.  QW_ESTATE unless every active walk is at its first
+ * unit.  Outputs may be NULL; *ms_per_launch is -1 on a cache hit. */
+int qw_batch_autotune(qw_batch *batch, int32_t reps, void *stream, int32_t *rows_per_tile,
+                      int32_t *xcd_aware, double *ms_per_launch);
+
 /* ---- Taylor truncation rule (FP64, host) -------------------------------- */
 /* With rho = dt * ||H|| the one-step remainder of the order-K series is at
  * most rho^(K+1)/(K+1)! * (K+2)/(K+2-rho) (valid for rho < K+2).

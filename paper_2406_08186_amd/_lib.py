@@ -26,7 +26,11 @@ STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small"}
 
 EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upload", "qw_evolve",
            "qw_probabilities", "qw_taylor_order", "qw_taylor_plan", "qw_taylor_tail_bound",
-           "qw_last_error", "qw_version"]
+           "qw_last_error", "qw_version",
+           "qw_batch_create", "qw_batch_destroy", "qw_batch_device_bytes", "qw_batch_bind",
+           "qw_batch_set_slot", "qw_batch_clear_slot", "qw_batch_commit", "qw_batch_run",
+           "qw_batch_remaining", "qw_batch_launches", "qw_batch_readout", "qw_batch_set_schedule",
+           "qw_batch_autotune"]
 
 
 class QwCsr(C.Structure):
@@ -76,6 +80,21 @@ def lib():
                                      dp, C.POINTER(C.c_int64)]
         L.qw_taylor_tail_bound.argtypes = [C.c_double, C.c_int32]
         L.qw_taylor_tail_bound.restype = C.c_double
+        i32p = C.POINTER(C.c_int32)
+        i64p = C.POINTER(C.c_int64)
+        L.qw_batch_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(vp)]
+        L.qw_batch_destroy.argtypes = [vp]
+        L.qw_batch_device_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.qw_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
+        L.qw_batch_set_slot.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_size_t, C.c_int64, vp]
+        L.qw_batch_clear_slot.argtypes = [vp, C.c_int32]
+        L.qw_batch_commit.argtypes = [vp, vp]
+        L.qw_batch_run.argtypes = [vp, C.c_int64, vp]
+        L.qw_batch_remaining.argtypes = [vp, C.c_int32, i64p]
+        L.qw_batch_launches.argtypes = [vp, i64p]
+        L.qw_batch_readout.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+        L.qw_batch_set_schedule.argtypes = [vp, C.c_int32, C.c_int32]
+        L.qw_batch_autotune.argtypes = [vp, C.c_int32, vp, i32p, i32p, dp]
         L.qw_last_error.restype = C.c_char_p
         L.qw_version.restype = C.c_char_p
         for name in EXPORTS:
@@ -143,3 +162,70 @@ def qw_taylor_tail_bound(rho: float, K: int) -> float:
 
 def qw_version() -> str:
     return lib().qw_version().decode()
+
+
+# ---- batches --------------------------------------------------------------------
+
+def qw_batch_create(capacity: int, max_tiles: int, dtype: int) -> C.c_void_p:
+    out = C.c_void_p()
+    check(lib().qw_batch_create(capacity, max_tiles, dtype, C.byref(out)), "qw_batch_create")
+    return out
+
+
+def qw_batch_destroy(batch) -> None:
+    check(lib().qw_batch_destroy(batch), "qw_batch_destroy")
+
+
+def qw_batch_device_bytes(batch) -> int:
+    n = C.c_size_t()
+    check(lib().qw_batch_device_bytes(batch, C.byref(n)), "qw_batch_device_bytes")
+    return n.value
+
+
+def qw_batch_bind(batch, d_buf: int, nbytes: int, stream: int) -> None:
+    check(lib().qw_batch_bind(batch, d_buf, nbytes, stream), "qw_batch_bind")
+
+
+def qw_batch_set_slot(batch, slot: int, plan, d_psi: int, d_work: int, work_bytes: int, steps: int,
+                      d_hist) -> None:
+    check(lib().qw_batch_set_slot(batch, slot, plan, d_psi, d_work, work_bytes, steps, d_hist),
+          "qw_batch_set_slot")
+
+
+def qw_batch_clear_slot(batch, slot: int) -> None:
+    check(lib().qw_batch_clear_slot(batch, slot), "qw_batch_clear_slot")
+
+
+def qw_batch_commit(batch, stream: int) -> None:
+    check(lib().qw_batch_commit(batch, stream), "qw_batch_commit")
+
+
+def qw_batch_run(batch, launches: int, stream: int) -> None:
+    check(lib().qw_batch_run(batch, launches, stream), "qw_batch_run")
+
+
+def qw_batch_remaining(batch, slot: int) -> int:
+    r = C.c_int64()
+    check(lib().qw_batch_remaining(batch, slot, C.byref(r)), "qw_batch_remaining")
+    return r.value
+
+
+def qw_batch_launches(batch) -> int:
+    r = C.c_int64()
+    check(lib().qw_batch_launches(batch, C.byref(r)), "qw_batch_launches")
+    return r.value
+
+
+def qw_batch_readout(batch, slot: int, d_p, d_norm, d_pmarked, stream: int) -> None:
+    check(lib().qw_batch_readout(batch, slot, d_p, d_norm, d_pmarked, stream), "qw_batch_readout")
+
+
+def qw_batch_set_schedule(batch, rows_per_tile: int, xcd_aware: int) -> None:
+    check(lib().qw_batch_set_schedule(batch, rows_per_tile, xcd_aware), "qw_batch_set_schedule")
+
+
+def qw_batch_autotune(batch, reps: int, stream: int):
+    r, x, ms = C.c_int32(), C.c_int32(), C.c_double()
+    check(lib().qw_batch_autotune(batch, reps, stream, C.byref(r), C.byref(x), C.byref(ms)),
+          "qw_batch_autotune")
+    return r.value, x.value, ms.value

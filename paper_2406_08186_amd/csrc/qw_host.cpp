@@ -16,31 +16,10 @@
 #include <vector>
 
 #include "qw_internal.h"
+#include "qw_plan.h"
 #include "qwalk.h"
 
 using namespace qwk;
-
-struct qw_plan {
-  int32_t kind = QW_COINED, coin = QW_GROVER, dtype = QW_C128, layout = QW_LAYOUT_AUTO;
-  int32_t structure = kGeneral;
-  int64_t n = 0, n_arcs = 0;
-  int32_t dims[2] = {0, 0};
-  int32_t max_degree = 0;
-  double gamma = 0.0, dt = 0.0, h_bound = 0.0, trunc_bound = 0.0;
-  int32_t K = 0;
-  int32_t n_marked = 0;
-  int32_t n_tiles = 0;
-  int32_t group = 1;
-  // host image of the device graph buffer, and section offsets into it
-  std::vector<unsigned char> image;
-  size_t off_rp = 0, off_col = 0, off_rev = 0, off_tiles = 0, off_perm = 0, off_bits = 0, off_mlist = 0;
-  bool has_col = false, has_rev = false, has_tiles = false, has_perm = false;
-  // device binding
-  unsigned char *d_graph = nullptr;
-  GraphView view;
-  // workspace layout
-  size_t state_bytes = 0, off_w1 = 0, off_pscratch = 0, off_partials = 0, work_bytes = 0;
-};
 
 namespace {
 
@@ -480,6 +459,28 @@ int evolve_ctqw(const qw_plan *p, void *psi, unsigned char *work, int64_t steps,
 }
 
 }  // namespace
+
+namespace qwk {
+
+int set_error(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int clear_error() { return ok(); }
+
+int plan_readout(const qw_plan *p, const void *psi, unsigned char *work, double *d_p, double *d_norm,
+                 double *d_pmarked, hipStream_t s) {
+  const Readout ro = make_readout(p, work, d_p, d_norm, d_pmarked);
+  return readout_only(p, psi, ro, s);
+}
+
+}  // namespace qwk
 
 // =============================== C ABI =======================================
 

@@ -89,6 +89,46 @@ hipError_t vertex_prob(bool c128, const GraphView &g, const void *psi, const Rea
 // Sum of `count` partials -> *norm; sum over the marked list of p -> *pmarked.
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s);
 
+// ---- batched execution ------------------------------------------------------
+// Launch counter shared by all workgroups of a batched launch: every
+// workgroup reads L at its start; the last one to finish advances it.
+struct BatchCtl {
+  unsigned long long L;      // launches completed
+  unsigned int done;         // workgroups finished in the current launch
+  unsigned int probe;        // 1: timing probe (every walk runs its first stage, L frozen)
+};
+
+// One walk of a batch (device copy).  kind < 0 marks an empty slot.
+struct WalkSlot {
+  int32_t kind;      // QW_COINED / QW_CTQW, -1 = empty
+  int32_t n;
+  int32_t K;         // CTQW Taylor order (>= 2); 1 for coined
+  int32_t hadamard;
+  int64_t L0;        // global launch index at which the walk starts
+  int64_t units;     // launches it needs: steps * K (CTQW) or steps (coined)
+  const int32_t *rp;
+  const int32_t *col;     // CTQW
+  const int32_t *rev;     // coined
+  const uint32_t *markbits;
+  void *psi;
+  void *w0;
+  void *w1;
+  const double *alpha;    // K entries, stage k at [k-1]
+  const double *beta;
+  double *hist;           // CTQW: p_marked after each step (caller-zeroed), may be null
+};
+
+// A unit of work of a batched launch: rows (CTQW) or vertices (coined) [begin, end) of a slot.
+struct TileEntry {
+  int32_t slot;      // -1 = padding
+  int32_t begin;
+  int32_t end;
+  int32_t pad;
+};
+
+hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
+                       const int32_t *n_tiles, int grid, hipStream_t s);
+
 // Number of partial sums the readout kernels (one thread per vertex) write.
 int readout_partials(const GraphView &g);
 // Number of partial sums a CTQW stage with the readout fused writes.

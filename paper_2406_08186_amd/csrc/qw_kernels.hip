@@ -50,6 +50,15 @@ __device__ __forceinline__ bool marked(const uint32_t *bits, int v) {
   return (bits[v >> 5] >> (v & 31)) & 1u;
 }
 
+// Workgroup b is dispatched to XCD b % 8 (round-robin over the 8 XCDs).  This
+// remap gives XCD x one contiguous range of logical blocks, so neighbouring
+// rows of a stencil are read through the same L2.  It is a bijection on
+// [0, nb) for any nb.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // Grover on one block given its sum s: phi = 2 s/d - psi.  The mean is the
 // correctly rounded FP64 quotient; doubling it is exact.
 __device__ __forceinline__ double2 grover_mean(double2 s, int d) {
@@ -248,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_coined_struct(GraphView g, const T *
                                                           T *__restrict__ out, int dim,
                                                           int hadamard) {
   const int n = g.n;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int d = (KIND == kHypercube) ? dim : D;
   const int l2 = g.dims[1];
@@ -408,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_struct(GraphView g, const T *__
                                                         double beta, double *p, double *partials) {
   __shared__ double red[16];
   const int n = g.n;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   double pv = 0.0;
   if (v < n) {
     double2 s = make_double2(0.0, 0.0);
@@ -497,6 +506,100 @@ __global__ __launch_bounds__(1024) void k_ctqw_small(GraphView g, T *psi, Coefs 
     if (threadIdx.x == 0) {
       if (ro.norm) *ro.norm = tot;
       if (ro.pmarked) *ro.pmarked = ptot;
+    }
+  }
+}
+
+// ---- batched launch over many walks -------------------------------------------
+// One launch advances every active walk of a batch by one unit: a Horner
+// stage (CTQW) or a whole step (coined).  Workgroups grid-stride over a tile
+// table; the host places each walk's tiles on indices of one residue mod 8, so
+// with a grid that is a multiple of 8 all of a walk's tiles run on the same
+// XCD (workgroups are dispatched round-robin over the 8 XCDs) and its gathers
+// stay in that XCD's L2.
+template <typename T>
+__device__ void batch_ctqw_tile(const WalkSlot &w, const TileEntry &te, int64_t u) {
+  const int K = w.K;
+  const int64_t step = u / K;
+  const int k = K - static_cast<int>(u % K);
+  const T *psi = static_cast<const T *>(w.psi);
+  const T *yin = (k == K) ? psi : static_cast<const T *>(((K - k - 1) & 1) ? w.w1 : w.w0);
+  T *yout = (k == 1) ? static_cast<T *>(w.psi) : static_cast<T *>(((K - k) & 1) ? w.w1 : w.w0);
+  const double alpha = w.alpha[k - 1], beta = w.beta[k - 1];
+  for (int row = te.begin + threadIdx.x; row < te.end; row += blockDim.x) {
+    double2 sum = make_double2(0.0, 0.0);
+    for (int a = w.rp[row]; a < w.rp[row + 1]; ++a) sum = add(sum, ld(yin, w.col[a]));
+    const bool mk = marked(w.markbits, row);
+    const double2 yv = mk ? ld(yin, row) : make_double2(0.0, 0.0);
+    const double2 r = horner_out(ld(psi, row), sum, yv, mk, alpha, beta);
+    const T stored = pack<T>(r);
+    yout[row] = stored;
+    if (k == 1 && mk && w.hist) atomicAdd(&w.hist[step], abs2(cvt(stored)));
+  }
+}
+
+template <typename T>
+__device__ void batch_coined_tile(const WalkSlot &w, const TileEntry &te, int64_t u, T *s) {
+  const T *in = static_cast<const T *>((u & 1) ? w.w0 : w.psi);
+  T *out = static_cast<T *>((u & 1) ? w.psi : w.w0);
+  const int vb = te.begin, ve = te.end;
+  const int ab = w.rp[vb], ae = w.rp[ve];
+  const int na = ae - ab;
+  // tiles of batched coined walks always fit the LDS tile (built from the
+  // plan's tiles; single-vertex tiles above kTileArcs are refused on the host)
+  for (int i = threadIdx.x; i < na; i += blockDim.x) s[i] = in[ab + i];
+  __syncthreads();
+  for (int v = vb + threadIdx.x; v < ve; v += blockDim.x) {
+    const int lo = w.rp[v] - ab, hi = w.rp[v + 1] - ab, d = hi - lo;
+    if (d == 0) continue;
+    if (marked(w.markbits, v)) {
+      for (int i = lo; i < hi; ++i) s[i] = pack<T>(scale(cvt(s[i]), -1.0));
+    } else if (w.hadamard) {
+      double2 x0 = cvt(s[lo]), x1 = cvt(s[lo + 1]);
+      s[lo] = pack<T>(scale(add(x0, x1), kInvSqrt2));
+      s[lo + 1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+    } else {
+      double2 sum = make_double2(0.0, 0.0);
+      for (int i = lo; i < hi; ++i) sum = add(sum, cvt(s[i]));
+      double2 m = grover_mean(sum, d);
+      for (int i = lo; i < hi; ++i) s[i] = pack<T>(sub(add(m, m), cvt(s[i])));
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < na; i += blockDim.x) out[w.rev[ab + i]] = s[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, const WalkSlot *slots,
+                                                              const TileEntry *tiles,
+                                                              const int32_t *n_tiles) {
+  __shared__ T s[kTileArcs];
+  const int64_t L = static_cast<int64_t>(ctl->L);
+  const bool probe = ctl->probe != 0;
+  const int nt = *n_tiles;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const TileEntry te = tiles[t];
+    if (te.slot < 0) continue;
+    const WalkSlot &w = slots[te.slot];
+    if (w.kind < 0) continue;
+    const int64_t u = probe ? 0 : L - w.L0;
+    if (u < 0 || u >= w.units) continue;
+    if (w.kind == 1) {
+      batch_ctqw_tile<T>(w, te, u);
+    } else {
+      batch_coined_tile<T>(w, te, u, s);
+    }
+    __syncthreads();
+  }
+  if (probe) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int prev = atomicAdd(&ctl->done, 1u);
+    if (prev == gridDim.x - 1) {
+      atomicExch(&ctl->done, 0u);
+      atomicAdd(&ctl->L, 1ull);
+      __threadfence();
     }
   }
 }
@@ -727,6 +830,16 @@ hipError_t vertex_prob(bool c128, const GraphView &g, const void *psi, const Rea
   else
     hipLaunchKernelGGL(k_prob_vertex<float2>, grid, dim3(kBlock), 0, s, static_cast<const float2 *>(psi),
                        g.n, ro.p_out(), ro.partials);
+  return hipGetLastError();
+}
+
+hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
+                       const int32_t *n_tiles, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (c128)
+    hipLaunchKernelGGL(k_batch_stage<double2>, dim3(grid), dim3(kTileThreads), 0, s, ctl, slots, tiles, n_tiles);
+  else
+    hipLaunchKernelGGL(k_batch_stage<float2>, dim3(grid), dim3(kTileThreads), 0, s, ctl, slots, tiles, n_tiles);
   return hipGetLastError();
 }
 

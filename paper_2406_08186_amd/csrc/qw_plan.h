@@ -1,0 +1,41 @@
+// Host-side plan object shared by the plan and batch halves of the C ABI.
+// Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "qw_internal.h"
+#include "qwalk.h"
+
+struct qw_plan {
+  // walk description
+  int32_t kind = QW_COINED, coin = QW_GROVER, dtype = QW_C128, layout = QW_LAYOUT_AUTO;
+  int32_t structure = qwk::kGeneral;
+  int64_t n = 0, n_arcs = 0;
+  int32_t dims[2] = {0, 0};
+  int32_t max_degree = 0;
+  double gamma = 0.0, dt = 0.0, h_bound = 0.0, trunc_bound = 0.0;
+  int32_t K = 0;
+  int32_t n_marked = 0;
+  int32_t n_tiles = 0;
+  int32_t group = 1;
+  // host image of the device graph buffer, and section offsets into it
+  std::vector<unsigned char> image;
+  size_t off_rp = 0, off_col = 0, off_rev = 0, off_tiles = 0, off_perm = 0, off_bits = 0, off_mlist = 0;
+  bool has_col = false, has_rev = false, has_tiles = false, has_perm = false;
+  // device binding
+  unsigned char *d_graph = nullptr;
+  qwk::GraphView view;
+  // workspace layout
+  size_t state_bytes = 0, off_w1 = 0, off_pscratch = 0, off_partials = 0, work_bytes = 0;
+};
+
+namespace qwk {
+// Host helpers shared by the plan and batch entry points (qw_host.cpp).
+int set_error(int code, const char *fmt, ...);
+int clear_error();
+int plan_readout(const qw_plan *p, const void *psi, unsigned char *work, double *d_p, double *d_norm,
+                 double *d_pmarked, hipStream_t s);
+}  // namespace qwk

@@ -121,6 +121,84 @@ class Plan:
         return p[:self.graph.n], scal[0], scal[1]
 
 
+class Batch:
+    """Many walks advanced together (qw_batch_*): slots hold (plan, state, steps).
+
+    Plans must use layout "csr".  Each slot keeps references to its plan, state
+    and history tensors until it is cleared.
+    """
+
+    def __init__(self, capacity: int, max_tiles: int, dtype: str = "c64", device=None, stream=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self.dtype = dtype
+        self.capacity = capacity
+        self._b = L.qw_batch_create(capacity, max_tiles, _DT[dtype])
+        nbytes = L.qw_batch_device_bytes(self._b)
+        self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        L.qw_batch_bind(self._b, self.buf.data_ptr(), self.buf.numel(), _stream_ptr(stream, self.device))
+        self._held = {}
+
+    def close(self) -> None:
+        if getattr(self, "_b", None):
+            L.qw_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_slot(self, slot: int, plan: Plan, psi: torch.Tensor, steps: int,
+                 hist: torch.Tensor | None = None) -> None:
+        plan._check(psi)
+        if hist is not None and (hist.dtype != torch.float64 or hist.numel() < steps
+                                 or hist.device != self.device):
+            raise ValueError("hist must be a float64 device tensor of at least `steps` elements")
+        L.qw_batch_set_slot(self._b, slot, plan._plan, psi.data_ptr(), plan.work.data_ptr(),
+                            plan.work.numel(), int(steps), hist.data_ptr() if hist is not None else None)
+        self._held[slot] = (plan, psi, hist)
+
+    def clear_slot(self, slot: int) -> None:
+        L.qw_batch_clear_slot(self._b, slot)
+        self._held.pop(slot, None)
+
+    def commit(self, stream=None) -> None:
+        L.qw_batch_commit(self._b, _stream_ptr(stream, self.device))
+
+    def run(self, launches: int, stream=None) -> None:
+        L.qw_batch_run(self._b, int(launches), _stream_ptr(stream, self.device))
+
+    def remaining(self, slot: int) -> int:
+        return L.qw_batch_remaining(self._b, slot)
+
+    @property
+    def launches(self) -> int:
+        return L.qw_batch_launches(self._b)
+
+    def active_slots(self) -> list[int]:
+        return sorted(self._held)
+
+    def run_to_completion(self, stream=None) -> int:
+        n = max((self.remaining(s) for s in self._held), default=0)
+        self.run(n, stream)
+        return n
+
+    def readout(self, slot: int, stream=None):
+        plan = self._held[slot][0]
+        p = torch.empty(max(plan.graph.n, 1), dtype=torch.float64, device=self.device)
+        scal = torch.zeros(2, dtype=torch.float64, device=self.device)
+        L.qw_batch_readout(self._b, slot, p.data_ptr(), scal.data_ptr(), scal.data_ptr() + 8,
+                           _stream_ptr(stream, self.device))
+        return p[:plan.graph.n], scal[0], scal[1]
+
+    def set_schedule(self, rows_per_tile: int, xcd_aware: bool = True) -> None:
+        L.qw_batch_set_schedule(self._b, rows_per_tile, int(xcd_aware))
+
+    def autotune(self, reps: int = 3, stream=None):
+        return L.qw_batch_autotune(self._b, reps, _stream_ptr(stream, self.device))
+
+
 def _steps_of(rng) -> list[int]:
     if isinstance(rng, int):
         return list(range(rng))

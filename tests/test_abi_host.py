@@ -183,3 +183,24 @@ def test_empty_and_isolated_graphs_plan():
     p = _create((4, [0, 0, 1, 2, 2], [2, 1]), kind=1, dtype=1, gamma=1.0, dt=0.1, taylor_order=8)
     assert L.qw_plan_get_info(p).state_len == 4
     L.qw_plan_destroy(p)
+
+
+def test_batch_host_side():
+    lib = L.lib()
+    out = C.c_void_p()
+    assert lib.qw_batch_create(0, 64, 0, C.byref(out)) == L.QW_EINVAL
+    assert lib.qw_batch_create(4, 4, 0, C.byref(out)) == L.QW_EINVAL
+    assert lib.qw_batch_create(4, 64, 7, C.byref(out)) == L.QW_EINVAL
+    b = L.qw_batch_create(4, 100, L.QW_C64)
+    nbytes = L.qw_batch_device_bytes(b)
+    assert nbytes >= 100 * 16
+    # unbound batches refuse device work
+    assert lib.qw_batch_run(b, 1, None) == L.QW_ESTATE
+    assert lib.qw_batch_commit(b, None) == L.QW_ESTATE
+    assert lib.qw_batch_set_schedule(b, 8, 1) == L.QW_EINVAL
+    assert lib.qw_batch_set_schedule(b, 512, 0) == L.QW_OK
+    r = C.c_int64(-1)
+    assert lib.qw_batch_remaining(b, 0, C.byref(r)) == L.QW_OK and r.value == 0
+    assert lib.qw_batch_remaining(b, 9, C.byref(r)) == L.QW_EINVAL
+    L.qw_batch_destroy(b)
+    assert lib.qw_batch_destroy(None) == L.QW_OK

@@ -1,0 +1,199 @@
+"""GPU tests of batched execution (qw_batch_*): every walk's result in a mixed
+batch equals the same walk run alone (bitwise), the plain single-walk path
+(to rounding) and the FP64 oracle (c128 within 1e-12)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2406_08186_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    yield
+    torch.cuda.synchronize()
+
+
+def _walks(dtype):
+    """(graph, kind, params, steps) of a ragged mix."""
+    return [
+        (I.random_regular(500, 3, seed=1), "ctqw", dict(gamma=1 / 3, dt=0.3, taylor_order=14, marked=[7]), 9),
+        (I.random_regular(1200, 5, seed=2), "ctqw", dict(gamma=0.2, dt=0.5, taylor_order=16, marked=[0]), 5),
+        (I.random_regular(2000, 8, seed=3), "ctqw", dict(gamma=0.125, dt=0.4, taylor_order=12, marked=[1999]), 12),
+        (I.erdos_renyi(1500, 6 / 1499, seed=4), "ctqw", dict(gamma=0.2, dt=0.25, taylor_order=10, marked=[3]), 7),
+        (I.cycle(300), "coined", dict(coin="hadamard"), 31),
+        (I.erdos_renyi(900, 8 / 899, seed=5), "coined", dict(coin="grover", marked=[2]), 24),
+        (I.hypercube(9), "coined", dict(coin="grover", marked=[0]), 17),
+        (I.random_regular(4000, 4, seed=6), "coined", dict(coin="grover", marked=[11]), 10),
+    ]
+
+
+def _plan(g, kind, params, dtype):
+    from paper_2406_08186_amd.walk import Plan
+    return Plan(g, kind, dtype=dtype, layout="csr", **params)
+
+
+def _psi0(pl, seed):
+    return I.random_state(pl.state_len, seed)
+
+
+def _run_batch(entries, dtype, schedule=None, autotune=False):
+    from paper_2406_08186_amd.walk import Batch
+    b = Batch(capacity=max(8, len(entries)), max_tiles=8192, dtype=dtype)
+    states = []
+    for slot, (pl, psi0, steps) in enumerate(entries):
+        psi = pl.state(psi0)
+        b.set_slot(slot, pl, psi, steps)
+        states.append(psi)
+    if schedule:
+        b.set_schedule(*schedule)
+    b.commit()
+    if autotune:
+        b.autotune(reps=2)
+    b.run_to_completion()
+    outs = []
+    for slot in range(len(entries)):
+        p, norm, pm = b.readout(slot)
+        outs.append((states[slot].clone(), p.clone(), float(norm), float(pm)))
+    torch.cuda.synchronize()
+    b.close()
+    return outs
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_alone_vs_mix_and_oracle(dtype):
+    walks = _walks(dtype)
+    print(f"[case] batch mix {dtype} walks={len(walks)}", flush=True)
+    entries = []
+    for i, (g, kind, params, steps) in enumerate(walks):
+        pl = _plan(g, kind, params, dtype)
+        entries.append((pl, _psi0(pl, 100 + i), steps))
+    mixed = _run_batch(entries, dtype)
+    for i, (pl, psi0, steps) in enumerate(entries):
+        alone = _run_batch([(pl, psi0, steps)], dtype)[0]
+        assert torch.equal(alone[0], mixed[i][0]), f"walk {i} differs alone vs in the mix"
+        assert torch.equal(alone[1], mixed[i][1])
+        g, kind, params, _ = walks[i]
+        if kind == "ctqw":
+            ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps, gamma=params["gamma"], dt=params["dt"],
+                                     K=params["taylor_order"], marked=params["marked"])
+            pref = oracle.vertex_prob(ref)
+        else:
+            ref = oracle.coined_evolve(g.row_ptr, g.col, psi0, steps,
+                                       coin=oracle.HADAMARD if params["coin"] == "hadamard" else oracle.GROVER,
+                                       marked=params.get("marked", ()))
+            pref = oracle.coined_prob(g.row_ptr, g.col, ref)
+        got = mixed[i][0].cpu().numpy().astype(np.complex128)
+        if dtype == "c128":
+            assert np.abs(got - ref).max() < 1e-12, i
+            assert np.abs(mixed[i][1].cpu().numpy() - pref).max() < 1e-12
+        else:
+            assert np.linalg.norm(got - ref) < 1e-5, i
+        # the plain single-walk path agrees to rounding
+        plain = pl.state(psi0)
+        pl.evolve(plain, steps)
+        torch.cuda.synchronize()
+        tol = 1e-13 if dtype == "c128" else 1e-6
+        assert (plain - mixed[i][0]).abs().max().item() < tol, i
+
+
+def test_batch_continuous_join_and_schedules():
+    """A walk that joins mid-run, or runs under another schedule, gives the same bits."""
+    from paper_2406_08186_amd.walk import Batch
+    dtype = "c64"
+    walks = _walks(dtype)
+    pls = [_plan(g, kind, params, dtype) for g, kind, params, _ in walks]
+    late = 5
+    ref = _run_batch([(pls[late], _psi0(pls[late], 7), walks[late][3])], dtype)[0]
+    b = Batch(capacity=8, max_tiles=8192, dtype=dtype)
+    keep = []
+    for slot in (0, 1, 4):
+        psi = pls[slot].state(_psi0(pls[slot], 50 + slot))
+        keep.append(psi)
+        b.set_slot(slot, pls[slot], psi, walks[slot][3])
+    b.commit()
+    b.run(23)  # replay path (>= 16) plus single launches
+    psi = pls[late].state(_psi0(pls[late], 7))
+    b.set_slot(6, pls[late], psi, walks[late][3])
+    b.commit()
+    assert b.remaining(6) == walks[late][3]
+    b.run_to_completion()
+    b.readout(6)
+    torch.cuda.synchronize()
+    assert torch.equal(psi, ref[0])
+    for sched in ((256, False), (4096, True)):
+        out = _run_batch([(pls[late], _psi0(pls[late], 7), walks[late][3])], dtype, schedule=sched)[0]
+        assert torch.equal(out[0], ref[0])
+    b.close()
+
+
+def test_batch_autotune_keeps_results():
+    dtype = "c64"
+    walks = _walks(dtype)[:4]
+    entries = []
+    for i, (g, kind, params, steps) in enumerate(walks):
+        pl = _plan(g, kind, params, dtype)
+        entries.append((pl, _psi0(pl, 200 + i), steps))
+    base = _run_batch(entries, dtype)
+    tuned = _run_batch(entries, dtype, autotune=True)
+    for a, t in zip(base, tuned):
+        assert torch.equal(a[0], t[0])
+
+
+def test_batch_marked_history():
+    """CTQW search: p_marked after every step, recorded on the device, equals the oracle's."""
+    from paper_2406_08186_amd.walk import Batch
+    g = I.random_regular(800, 4, seed=9)
+    params = dict(gamma=0.25, dt=0.5, taylor_order=16, marked=[17])
+    steps = 30
+    pl = _plan(g, "ctqw", params, "c128")
+    b = Batch(capacity=2, max_tiles=1024, dtype="c128")
+    psi = pl.state(I.uniform(g.n))
+    hist = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    b.set_slot(0, pl, psi, steps, hist=hist)
+    b.commit()
+    b.run_to_completion()
+    torch.cuda.synchronize()
+    x = I.uniform(g.n)
+    for s in range(steps):
+        x = oracle.ctqw_evolve(g.row_ptr, g.col, x, 1, gamma=0.25, dt=0.5, K=16, marked=[17])
+        assert abs(hist[s].item() - abs(x[17]) ** 2) < 1e-12
+    b.close()
+
+
+def test_batch_errors():
+    from paper_2406_08186_amd import _lib as L
+    from paper_2406_08186_amd.walk import Batch, Plan
+    b = Batch(capacity=2, max_tiles=64, dtype="c64")
+    g = I.torus(20, 20)
+    auto = Plan(g, "ctqw", dtype="c64", gamma=0.25, dt=0.1, taylor_order=8, layout="structured")
+    with pytest.raises(L.QwError) as e:
+        b.set_slot(0, auto, auto.state(I.uniform(g.n)), 3)
+    assert e.value.code == L.QW_EUNSUPPORTED
+    p128 = Plan(g, "ctqw", dtype="c128", gamma=0.25, dt=0.1, taylor_order=8, layout="csr")
+    with pytest.raises(L.QwError) as e:
+        L.qw_batch_set_slot(b._b, 0, p128._plan, p128.state(I.uniform(g.n)).data_ptr(),
+                            p128.work.data_ptr(), p128.work.numel(), 3, None)
+    assert e.value.code == L.QW_EINVAL
+    k1 = Plan(g, "ctqw", dtype="c64", gamma=0.25, dt=0.1, taylor_order=1, layout="csr")
+    with pytest.raises(L.QwError) as e:
+        b.set_slot(0, k1, k1.state(I.uniform(g.n)), 3)
+    assert e.value.code == L.QW_EUNSUPPORTED
+    ok = Plan(g, "ctqw", dtype="c64", gamma=0.25, dt=0.1, taylor_order=8, layout="csr")
+    b.set_slot(1, ok, ok.state(I.uniform(g.n)), 3)
+    b.commit()
+    with pytest.raises(L.QwError) as e:
+        b.readout(1)
+    assert e.value.code == L.QW_ESTATE
+    big = I.random_regular(20000, 4, seed=1)
+    pb = Plan(big, "ctqw", dtype="c64", gamma=0.25, dt=0.1, taylor_order=8, layout="csr")
+    b.set_slot(0, pb, pb.state(I.uniform(big.n)), 3)
+    b.set_schedule(64, True)
+    with pytest.raises(L.QwError) as e:
+        b.commit()
+    assert e.value.code == L.QW_ENOMEM
+    b.close()
