@@ -46,6 +46,22 @@ def parse():
     ap.add_argument("--dtypes", default="c64,c128")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--workload", default="grid", choices=["grid", "batch", "serve", "dense"],
+                    help="grid: the 1024^2 CTQW (default); batch: many CTQW searches on random "
+                         "regular graphs in one batch; serve: the Poisson job stream")
+    ap.add_argument("--batch-walks", type=int, default=4096)
+    ap.add_argument("--batch-seed", type=int, default=1)
+    ap.add_argument("--plain-sample", type=int, default=32,
+                    help="walks of the batch also run one at a time on the single-walk path")
+    ap.add_argument("--serve-jobs", type=int, default=120)
+    ap.add_argument("--serve-rates", default="0.5,0.9",
+                    help="arrival rates as fractions of the measured saturated capacity")
+    ap.add_argument("--serve-max-arcs", type=float, default=4e6)
+    ap.add_argument("--serve-max-steps", type=int, default=5000)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--dense-n", type=int, default=15000)
+    ap.add_argument("--dense-columns", default="1,8,32,128")
+    ap.add_argument("--dense-dtype", default="c128")
     return ap.parse_args()
 
 
@@ -126,6 +142,15 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.workload == "batch":
+        run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
+        return
+    if args.workload == "dense":
+        run_dense(args)
         return
     spp = args.steps_per_pass
     dtypes = args.dtypes.split(",")
@@ -208,6 +233,263 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, v0, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------- batch workload
+
+def _gen_regular(spec):
+    from paper_2406_08186_amd import inputs as I
+    g = I.random_regular(spec["n"], spec["d"], spec["graph_seed"])
+    return g.row_ptr, g.col
+
+
+def run_batch(args):
+    """Many CTQW searches on random d-regular graphs advanced in one batch.
+
+    Walk i: N log-uniform in [1e3, 2e5], d uniform in 3..8, gamma = 1/d, one
+    uniformly drawn marked vertex, uniform start, total time 2 sqrt(N); step
+    count and Taylor order from the truncation rule (rho <= 1, tolerance 1e-8
+    over the whole walk); complex64 with FP64 readouts and a per-step
+    p_marked history.
+    """
+    import multiprocessing as mp
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    from paper_2406_08186_amd import inputs as I
+    specs = I.batch_regular_specs(args.batch_walks, seed=args.batch_seed)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(args.workers, os.cpu_count() or 1)) as pool:
+        csrs = pool.map(_gen_regular, specs, chunksize=4)
+    gen_s = time.perf_counter() - t0
+    print(f"[batch] generated {len(specs)} graphs in {gen_s:.1f} s", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_2406_08186_amd import _lib as L
+    from paper_2406_08186_amd.walk import Batch, Plan
+    graphs = [I.Graph(n=sp["n"], row_ptr=rp, col=cl, name=f"rr{i}") for i, (sp, (rp, cl)) in
+              enumerate(zip(specs, csrs))]
+    sched = []
+    for sp in specs:
+        hb = sp["gamma"] * sp["d"] + 1.0
+        K, dt, steps = L.qw_taylor_plan(hb, sp["t_final"], 1.0, 1e-8)
+        sched.append((K, dt, steps))
+
+    def mk(i):
+        sp = specs[i]
+        K, dt, steps = sched[i]
+        return Plan(graphs[i], "ctqw", dtype="c64", layout="structured", gamma=sp["gamma"], dt=dt,
+                    taylor_order=K, marked=[sp["marked"]], upload=False)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(args.workers) as ex:
+        plans = list(ex.map(mk, range(len(specs))))
+    plan_s = time.perf_counter() - t0
+    total_rows = sum(g.n for g in graphs)
+    max_tiles = total_rows // 256 + 16 * len(graphs) + 64
+    batch = Batch(capacity=len(plans), max_tiles=max_tiles, dtype="c64")
+    states, hists = [], []
+    for i, pl in enumerate(plans):
+        pl.upload()
+        psi = pl.state(I.uniform(graphs[i].n))
+        hist = torch.zeros(sched[i][2], dtype=torch.float64, device="cuda")
+        batch.set_slot(i, pl, psi, sched[i][2], hist=hist)
+        states.append(psi)
+        hists.append(hist)
+    batch.commit()
+    rows, xcd, probe_ms = batch.autotune(reps=2)
+    torch.cuda.synchronize()
+    launches = max(batch.remaining(i) for i in range(len(plans)))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    batch.run(launches)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    arc_steps = sum(g.n_arcs * sc[2] for g, sc in zip(graphs, sched))
+    arc_spmv = sum(g.n_arcs * sc[2] * sc[0] for g, sc in zip(graphs, sched))
+    # algorithmic bytes: per row-stage 4 (row_ptr) + 4d (col) + 8d? no: gathers ideally cached,
+    # so 4 + 4d + 3*8 (y gather once, psi, y')
+    alg_bytes = sum(g.n * (4 + 4 * sp["d"] + 24) * sc[2] * sc[0] for g, sp, sc in zip(graphs, specs, sched))
+    pm_final, pm_peak = [], []
+    for i in range(len(plans)):
+        _, norm, pm = batch.readout(i)
+        pm_final.append(float(pm))
+    for h in hists:
+        pm_peak.append(float(h.max()))
+    torch.cuda.synchronize()
+    drift = max(abs(float(batch.readout(i)[1]) - 1.0) for i in range(0, len(plans), max(1, len(plans) // 64)))
+    # plain form on a sample: one walk at a time on the single-walk path
+    stride = max(1, len(plans) // max(1, args.plain_sample))
+    sample = list(range(0, len(plans), stride))[:args.plain_sample]
+    plain_as, plain_t, maxdiff = 0, 0.0, 0.0
+    for i in sample:
+        pl = Plan(graphs[i], "ctqw", dtype="c64", layout="structured", gamma=specs[i]["gamma"], dt=sched[i][1],
+                  taylor_order=sched[i][0], marked=[specs[i]["marked"]])
+        psi = pl.state(I.uniform(graphs[i].n))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pl.evolve(psi, sched[i][2])
+        torch.cuda.synchronize()
+        plain_t += time.perf_counter() - t1
+        plain_as += graphs[i].n_arcs * sched[i][2]
+        maxdiff = max(maxdiff, float((psi - states[i]).abs().max()))
+        pl.close()
+    line = {
+        "metric": METRIC, "value": arc_steps / wall, "unit": "arc-steps/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"batch_{len(plans)}_ctqw_search_random_regular", "walks": len(plans),
+                   "path": sorted({pl.structure for pl in plans}),
+                   "total_vertices": total_rows, "total_arcs": sum(g.n_arcs for g in graphs),
+                   "launches": launches, "rows_per_tile": rows, "xcd_aware": bool(xcd),
+                   "graph_gen_s": gen_s, "plan_build_s": plan_s, "parallelism": "single-gpu"},
+        "arc_spmv_per_s": arc_spmv / wall,
+        "gpu_ms": gpu_ms,
+        "roofline": {"bound": "hbm", "kernel": "k_batch_stage<float2>", "achieved": alg_bytes / (gpu_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_bytes / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_total": alg_bytes, "launches": launches},
+        "plain_one_walk_per_launch": {"value": plain_as / plain_t, "unit": "arc-steps/s",
+                                      "walks": len(sample), "max_abs_diff_vs_batch": maxdiff},
+        "speedup_vs_plain": (arc_steps / wall) / (plain_as / plain_t),
+        "p_marked_peak_mean": float(np.mean(pm_peak)), "p_marked_final_mean": float(np.mean(pm_final)),
+        "norm_drift_max_sampled": drift,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------- serving stream
+
+def _gen_job(args_tuple):
+    from paper_2406_08186_amd.serve import make_job
+    import numpy as np
+    i, seed, max_arcs, max_steps = args_tuple
+    return make_job(i, np.random.default_rng(seed), arc_range=(1e3, max_arcs), steps_range=(100, max_steps))
+
+
+def run_serve(args):
+    """Poisson stream of mixed coined / CTQW jobs served with continuous batching,
+    against the plain one-job-at-a-time form on the same GPU."""
+    import copy
+    import multiprocessing as mp
+
+    import numpy as np
+    t0 = time.perf_counter()
+    tasks = [(i, 1000 + i, args.serve_max_arcs, args.serve_max_steps) for i in range(args.serve_jobs)]
+    with mp.get_context("fork").Pool(min(args.workers, os.cpu_count() or 1)) as pool:
+        base_jobs = pool.map(_gen_job, tasks)
+    print(f"[serve] generated {len(base_jobs)} jobs in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    import torch
+
+    from paper_2406_08186_amd.serve import WalkServer, latency_stats, poisson_arrivals, serve_sequential, serve_stream
+
+    def arc_work(jobs):
+        return sum(j.arcs * j.steps for j in jobs if j.status == "done")
+
+    def fresh():
+        return [copy.copy(j) for j in base_jobs]
+
+    # saturated capacity: every job at t = 0
+    jobs = fresh()
+    for j in jobs:
+        j.arrival = 0.0
+    srv = WalkServer(capacity=64, chunk=64, dtype="c64", workers=args.workers)
+    t1 = time.perf_counter()
+    done = serve_stream(srv, jobs, time_limit=900)
+    sat_s = time.perf_counter() - t1
+    srv.close()
+    cap_jobs_s = len(done) / sat_s
+    cap_rate = arc_work(done) / sat_s
+    print(f"[serve] saturated: {len(done)} jobs in {sat_s:.1f} s", file=sys.stderr, flush=True)
+    results = []
+    rng = np.random.default_rng(7)
+    for frac in [float(x) for x in args.serve_rates.split(",")]:
+        lam = frac * cap_jobs_s
+        jobs = fresh()
+        for j, a in zip(jobs, poisson_arrivals(len(jobs), lam, rng)):
+            j.arrival = float(a)
+        srv = WalkServer(capacity=64, chunk=64, dtype="c64", workers=args.workers)
+        t1 = time.perf_counter()
+        done = serve_stream(srv, jobs, time_limit=900)
+        el = time.perf_counter() - t1
+        srv.close()
+        st = latency_stats(done)
+        results.append({"load": frac, "rate_jobs_per_s": lam, "arc_steps_per_s": arc_work(done) / el,
+                        **st, "cycles": srv.cycles})
+        print(f"[serve] load {frac}: p50 {st['p50_s']:.3f} s p99 {st['p99_s']:.3f} s", file=sys.stderr,
+              flush=True)
+    # plain form at the first load
+    lam = float(args.serve_rates.split(",")[0]) * cap_jobs_s
+    jobs = fresh()
+    for j, a in zip(jobs, poisson_arrivals(len(jobs), lam, np.random.default_rng(7))):
+        j.arrival = float(a)
+    t1 = time.perf_counter()
+    serve_sequential(jobs, time_limit=1800)
+    el = time.perf_counter() - t1
+    plain = {"load": float(args.serve_rates.split(",")[0]), "arc_steps_per_s": arc_work(jobs) / el,
+             **latency_stats(jobs)}
+    line = {
+        "metric": METRIC, "value": cap_rate, "unit": "arc-steps/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": sat_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"serve_{len(base_jobs)}_mixed_jobs", "jobs": len(base_jobs),
+                   "arcs_range": [1e3, args.serve_max_arcs], "steps_range": [100, args.serve_max_steps],
+                   "slots": 64, "chunk": 64, "parallelism": "single-gpu"},
+        "saturated_jobs_per_s": cap_jobs_s,
+        "loads": results,
+        "plain_sequential": plain,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------- dense H on MFMA
+
+def run_dense(args):
+    """CTQW search on the complete graph K_n through the dense-H path: every
+    Horner stage is an n x n by n x 2B real GEMM on the matrix cores, for B
+    walks sharing H (n = 15000 is the dense vector-matrix size the paper times,
+    Sec. 4.6.1).  Reports per-stage time, GB/s of H streamed and MFMA TFLOP/s."""
+    import numpy as np
+    import torch
+
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Plan
+    n = args.dense_n
+    g = I.complete(n)
+    es = 8 if args.dense_dtype == "c128" else 4
+    peak_tf = 78.6 if args.dense_dtype == "c128" else 157.3
+    out = []
+    for cols in [int(x) for x in args.dense_columns.split(",")]:
+        pl = Plan(g, "ctqw", dtype=args.dense_dtype, layout="dense", gamma=1.0 / n, dt=0.5, taylor_order=16,
+                  marked=[7], columns=cols)
+        u = np.full(n * cols, 1 / math.sqrt(n), dtype=np.complex128)
+        psi = pl.state(u)
+        pl.evolve(psi, 1)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        a.record()
+        pl.evolve(psi, reps)
+        b.record()
+        torch.cuda.synchronize()
+        ms_stage = a.elapsed_time(b) / (reps * 16)
+        flops = 2.0 * n * n * 2 * cols
+        hbytes = float(n) * n * es
+        out.append({"columns": cols, "ms_per_stage": ms_stage, "tflops": flops / (ms_stage * 1e-3) / 1e12,
+                    "mfma_frac": flops / (ms_stage * 1e-3) / 1e12 / peak_tf,
+                    "h_gbs": hbytes / (ms_stage * 1e-3) / 1e9,
+                    "hbm_frac": hbytes / (ms_stage * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "arc_steps_per_s": g.n_arcs * cols * reps / (a.elapsed_time(b) * 1e-3)})
+        pl.close()
+        del psi
+    print(json.dumps({"workload": f"dense_complete_{n}", "dtype": args.dense_dtype, "taylor_order": 16,
+                      "points": out}), flush=True)
 
 
 if __name__ == "__main__":

@@ -67,12 +67,20 @@ extern "C" {
 
 /* Path choice.  AUTO runs a walk small enough for one workgroup's LDS in a
  * single launch, otherwise recognises cycles, periodic 2-D grids and
- * hypercubes in the CSR and uses index-free structured kernels for them, and
- * otherwise the general sparse kernels.  CSR forces the general sparse
+ * hypercubes in the CSR and uses index-free structured kernels for them
+ * (for a CTQW on any other regular graph of degree <= 64, a column-major
+ * neighbour table without row pointers), and otherwise the general sparse
+ * kernels.  CSR forces the general sparse
  * kernels.  STRUCTURED is AUTO without the one-workgroup path. */
 #define QW_LAYOUT_AUTO 0
 #define QW_LAYOUT_CSR 1
 #define QW_LAYOUT_STRUCTURED 2
+/* CTQW only: H stored densely (N x N, FP64 for QW_C128, FP32 for QW_C64) and
+ * each Horner stage run as a real-split complex GEMM on the matrix cores, for
+ * `columns` walks that share H (state: N x columns complex, vertex-major:
+ * element (v, b) at v*columns + b).  For dense graphs and batches of walks
+ * (the paper's dense vector-matrix product, Sec. 4.6.1, is the B = 1 case). */
+#define QW_LAYOUT_DENSE 3
 
 /* Structure the plan chose (reported by qw_plan_get_info). */
 #define QW_STRUCT_GENERAL 0
@@ -80,6 +88,8 @@ extern "C" {
 #define QW_STRUCT_TORUS 2
 #define QW_STRUCT_HYPERCUBE 3
 #define QW_STRUCT_SMALL 4 /* whole walk resident in one workgroup's LDS */
+#define QW_STRUCT_ELL 5   /* CTQW on a regular graph: column-major neighbour table */
+#define QW_STRUCT_DENSE 6 /* CTQW with a dense H on MFMA (QW_LAYOUT_DENSE)        */
 
 /* ---- graph ------------------------------------------------------------- */
 /* Adjacency pattern of a simple undirected graph (Sec. 3.1 and 3.2 take the
@@ -114,6 +124,8 @@ typedef struct qw_walk_desc {
                            coin -I (coined) / -|v><v| term (CTQW); may be NULL
                            when n_marked = 0                                   */
   int64_t n_marked;
+  int32_t columns;      /* QW_LAYOUT_DENSE: walks sharing H, 1..128 (0 = 1);
+                           other layouts: must be 0 or 1                      */
 } qw_walk_desc;
 
 typedef struct qw_plan qw_plan;
@@ -121,8 +133,8 @@ typedef struct qw_plan qw_plan;
 typedef struct qw_plan_info {
   int64_t n;               /* vertices                                        */
   int64_t n_arcs;          /* arcs (= 2|E|)                                   */
-  int64_t state_len;       /* complex elements of the state: n_arcs (coined)
-                              or n (CTQW)                                     */
+  int64_t state_len;       /* complex elements of the state: n_arcs (coined),
+                              n (CTQW) or n * columns (dense)                 */
   int32_t kind, coin, dtype, structure;
   int32_t dims[2];         /* CYCLE: {n,0}; TORUS: {l1,l2}; HYPERCUBE: {dim,0}*/
   int32_t max_degree;
@@ -133,6 +145,7 @@ typedef struct qw_plan_info {
   size_t graph_bytes;      /* device bytes qw_plan_upload needs               */
   size_t state_bytes;      /* bytes of one state vector                       */
   size_t work_bytes;       /* device workspace qw_evolve/qw_probabilities need*/
+  int32_t columns;         /* walks per state (dense layout), else 1          */
 } qw_plan_info;
 
 /* Validate the graph and the walk, precompute the host-side tables (reverse
@@ -174,7 +187,9 @@ int qw_evolve(const qw_plan *plan, void *d_psi, void *d_work, size_t work_bytes,
               double *d_p, double *d_norm, double *d_pmarked, void *stream);
 
 /* FP64 readout of a state (Sec. 3.1, Sec. 3.2): d_p[v] = probability of
- * vertex v (coined: summed over arcs with tail v; CTQW: |psi_v|^2),
+ * vertex v (coined: summed over arcs with tail v; CTQW: |psi_v|^2; dense
+ * layout: d_p has n * columns entries, p of walk b at v*columns + b, and the
+ * norm and marked sums run over all walks),
  * *d_norm = sum_v p_v, *d_pmarked = sum over the marked set of p_v.  Each
  * output pointer may be NULL.  Sums run in a fixed order: results are
  * bitwise reproducible for a given plan.  Errors as qw_evolve. */

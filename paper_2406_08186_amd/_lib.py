@@ -21,8 +21,8 @@ ERRORS = {1: "QW_EINVAL", 2: "QW_EGRAPH", 3: "QW_EUNSUPPORTED", 4: "QW_ENOMEM", 
 QW_COINED, QW_CTQW = 0, 1
 QW_GROVER, QW_HADAMARD = 0, 1
 QW_C64, QW_C128 = 0, 1
-QW_LAYOUT_AUTO, QW_LAYOUT_CSR, QW_LAYOUT_STRUCTURED = 0, 1, 2
-STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small"}
+QW_LAYOUT_AUTO, QW_LAYOUT_CSR, QW_LAYOUT_STRUCTURED, QW_LAYOUT_DENSE = 0, 1, 2, 3
+STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small", 5: "ell", 6: "dense"}
 
 EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upload", "qw_evolve",
            "qw_probabilities", "qw_taylor_order", "qw_taylor_plan", "qw_taylor_tail_bound",
@@ -41,7 +41,7 @@ class QwWalkDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("coin", C.c_int32), ("dtype", C.c_int32), ("layout", C.c_int32),
                 ("gamma", C.c_double), ("dt", C.c_double), ("taylor_order", C.c_int32),
                 ("trunc_tol", C.c_double), ("horizon_steps", C.c_int64),
-                ("marked", C.POINTER(C.c_int32)), ("n_marked", C.c_int64)]
+                ("marked", C.POINTER(C.c_int32)), ("n_marked", C.c_int64), ("columns", C.c_int32)]
 
 
 class QwPlanInfo(C.Structure):
@@ -49,7 +49,8 @@ class QwPlanInfo(C.Structure):
                 ("kind", C.c_int32), ("coin", C.c_int32), ("dtype", C.c_int32), ("structure", C.c_int32),
                 ("dims", C.c_int32 * 2), ("max_degree", C.c_int32), ("taylor_order", C.c_int32),
                 ("dt", C.c_double), ("h_norm_bound", C.c_double), ("trunc_bound", C.c_double),
-                ("graph_bytes", C.c_size_t), ("state_bytes", C.c_size_t), ("work_bytes", C.c_size_t)]
+                ("graph_bytes", C.c_size_t), ("state_bytes", C.c_size_t), ("work_bytes", C.c_size_t),
+                ("columns", C.c_int32)]
 
 
 class QwError(RuntimeError):

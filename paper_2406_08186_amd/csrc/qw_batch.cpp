@@ -174,6 +174,15 @@ int build_table(qw_batch *b) {
     return set_error(QW_ENOMEM, "batch needs %zu tiles, capacity is %d", table.size(), b->max_tiles);
   b->table = std::move(table);
   b->n_tiles = static_cast<int32_t>(b->table.size());
+  // grid: a multiple of 8 (keeps the XCD placement), no larger than the work
+  const int grid = std::max(8, std::min(kMaxGrid, (b->n_tiles + 7) / 8 * 8));
+  if (grid != b->grid) {
+    b->grid = grid;
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);  // re-captured with the new grid at the next run
+      b->exec = nullptr;
+    }
+  }
   return QW_OK;
 }
 
@@ -309,8 +318,9 @@ int qw_batch_set_slot(qw_batch *b, int32_t slot, const qw_plan *p, void *d_psi, 
   if (!p || !d_psi || !d_work) return set_error(QW_EINVAL, "null plan, state or workspace");
   if (!p->d_graph) return set_error(QW_ESTATE, "plan not uploaded");
   if (p->dtype != b->dtype) return set_error(QW_EINVAL, "plan dtype differs from the batch's");
-  if (p->structure != kGeneral)
-    return set_error(QW_EUNSUPPORTED, "batched walks need plans on the general CSR path (layout QW_LAYOUT_CSR)");
+  if (!(p->structure == kGeneral || (p->kind == QW_CTQW && p->structure == kEll)))
+    return set_error(QW_EUNSUPPORTED,
+                     "batched walks need plans on the general CSR path (layout QW_LAYOUT_CSR) or CTQW plans on the ELL path");
   if (work_bytes < p->work_bytes) return set_error(QW_ENOMEM, "workspace too small for the plan");
   if (steps < 0) return set_error(QW_EINVAL, "negative steps");
   if (p->n == 0) return set_error(QW_EINVAL, "empty graph");
@@ -323,6 +333,8 @@ int qw_batch_set_slot(qw_batch *b, int32_t slot, const qw_plan *p, void *d_psi, 
   w.units = steps * w.K;
   w.rp = p->view.rp;
   w.col = p->view.col;
+  w.ell_d = p->structure == kEll ? p->view.ell_d : 0;
+  w.pad0 = 0;
   w.rev = p->view.rev;
   w.markbits = p->view.markbits;
   w.psi = d_psi;

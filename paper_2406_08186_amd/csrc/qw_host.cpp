@@ -139,8 +139,15 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (n < 0 || n >= (int64_t{1} << 31)) return fail(QW_EINVAL, "vertex count %lld out of range", (long long)n);
   if (w->kind != QW_COINED && w->kind != QW_CTQW) return fail(QW_EINVAL, "bad walk kind %d", w->kind);
   if (w->dtype != QW_C64 && w->dtype != QW_C128) return fail(QW_EINVAL, "bad dtype %d", w->dtype);
-  if (w->layout < QW_LAYOUT_AUTO || w->layout > QW_LAYOUT_STRUCTURED)
+  if (w->layout < QW_LAYOUT_AUTO || w->layout > QW_LAYOUT_DENSE)
     return fail(QW_EINVAL, "bad layout %d", w->layout);
+  if (w->layout == QW_LAYOUT_DENSE) {
+    if (w->kind != QW_CTQW) return fail(QW_EUNSUPPORTED, "the dense layout is for continuous-time walks");
+    if (w->columns < 0 || w->columns > kMaxDenseColumns)
+      return fail(QW_EINVAL, "columns %d out of range (1..%d)", w->columns, kMaxDenseColumns);
+  } else if (w->columns > 1 || w->columns < 0) {
+    return fail(QW_EINVAL, "columns > 1 needs the dense layout");
+  }
   if (w->kind == QW_COINED && w->coin != QW_GROVER && w->coin != QW_HADAMARD)
     return fail(QW_EINVAL, "bad coin %d", w->coin);
   if (w->n_marked < 0 || (w->n_marked > 0 && !w->marked)) return fail(QW_EINVAL, "bad marked list");
@@ -245,7 +252,13 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   const bool small_fits = p->kind == QW_COINED
                               ? coined_small_lds(c128, static_cast<int>(n), static_cast<int>(na)) <= kSmallLdsBytes
                               : ctqw_small_lds(c128, static_cast<int>(n), static_cast<int>(na)) <= kSmallLdsBytes;
-  if (p->layout == QW_LAYOUT_AUTO && small_fits && n > 0) {
+  if (p->layout == QW_LAYOUT_DENSE) {
+    structure = kDense;
+    p->columns = std::max(1, w->columns);
+    p->ld = static_cast<int32_t>((n + kDenseK - 1) / kDenseK * kDenseK);
+    p->rows_pad = static_cast<size_t>((n + kDenseRows - 1) / kDenseRows * kDenseRows);
+    p->dense_bytes = p->rows_pad * static_cast<size_t>(p->ld) * (c128 ? 8 : 4);
+  } else if (p->layout == QW_LAYOUT_AUTO && small_fits && n > 0) {
     structure = kSmall;
   } else if (p->layout != QW_LAYOUT_CSR && n > 0) {
     int32_t a = 0, b = 0;
@@ -260,6 +273,9 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
       structure = kTorus;
       p->dims[0] = a;
       p->dims[1] = b;
+    } else if (p->kind == QW_CTQW && maxd >= 1 && maxd <= kMaxEllDegree && na == static_cast<int64_t>(maxd) * n) {
+      structure = kEll;  // every vertex has degree maxd
+      p->dims[0] = maxd;
     }
   }
   p->structure = structure;
@@ -269,7 +285,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   p->has_rev = coined && (structure == kGeneral || structure == kSmall);
   p->has_tiles = coined && structure == kGeneral;
   p->has_perm = coined && (structure == kCycle || structure == kTorus || structure == kHypercube);
-  p->has_col = !coined && (structure == kGeneral || structure == kSmall);
+  p->has_col = !coined && (structure == kGeneral || structure == kSmall || structure == kEll || structure == kDense);
 
   std::vector<int32_t> tiles;
   if (p->has_tiles) {
@@ -324,10 +340,20 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   p->off_bits = section(sizeof(uint32_t) * bits.size());
   p->off_mlist = section(sizeof(int32_t) * std::max<size_t>(mlist.size(), 1));
   p->image.assign(off, 0);
+  if (structure == kDense) p->off_dense = align256(off);
   std::vector<int32_t> rp32(static_cast<size_t>(n) + 1);
   for (int64_t v = 0; v <= n; ++v) rp32[v] = static_cast<int32_t>(rp[v]);
   put(p->image, p->off_rp, rp32.data(), rp32.size());
-  if (p->has_col) put(p->image, p->off_col, col, static_cast<size_t>(na));
+  if (p->has_col && structure == kEll) {
+    // column-major: entry (j, v) = j-th neighbour of v in row order
+    std::vector<int32_t> colT(static_cast<size_t>(na));
+    const int64_t d = p->dims[0];
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t j = 0; j < d; ++j) colT[static_cast<size_t>(j) * n + v] = col[rp[v] + j];
+    put(p->image, p->off_col, colT.data(), colT.size());
+  } else if (p->has_col) {
+    put(p->image, p->off_col, col, static_cast<size_t>(na));
+  }
   if (p->has_rev) put(p->image, p->off_rev, rev.data(), rev.size());
   if (p->has_tiles) put(p->image, p->off_tiles, tiles.data(), tiles.size());
   if (p->has_perm) put(p->image, p->off_perm, perm.data(), perm.size());
@@ -336,12 +362,13 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
 
   // ---- workspace
   const size_t es = c128 ? 16 : 8;
-  const int64_t len = coined ? na : n;
+  const int64_t len = coined ? na : n * p->columns;
   p->state_bytes = es * static_cast<size_t>(len);
   GraphView probe;
   probe.n = static_cast<int32_t>(n);
   probe.structure = structure;
   probe.group = p->group;
+  probe.columns = p->columns;
   const size_t partials = static_cast<size_t>(std::max(readout_partials(probe), ctqw_stage_partials(probe))) + 1;
   size_t w_off = 0;
   auto wsec = [&](size_t bytes) {
@@ -351,7 +378,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   };
   wsec(p->state_bytes);                    // buffer 0 at offset 0
   p->off_w1 = wsec(p->state_bytes);        // buffer 1
-  p->off_pscratch = wsec(sizeof(double) * static_cast<size_t>(n));
+  p->off_pscratch = wsec(sizeof(double) * static_cast<size_t>(n) * p->columns);
   p->off_partials = wsec(sizeof(double) * partials);
   p->work_bytes = w_off;
   return ok();
@@ -439,6 +466,18 @@ int evolve_ctqw(const qw_plan *p, void *psi, unsigned char *work, int64_t steps,
   }
   if (steps == 0) return readout_only(p, psi, ro, s);
   void *w0 = work, *w1 = work + p->off_w1;
+  if (p->structure == kDense) {
+    for (int64_t i = 0; i < steps; ++i) {
+      const void *yin = psi;
+      for (int k = K; k >= 1; --k) {
+        void *yout = (k == 1) ? (K == 1 ? w0 : psi) : (((K - k) & 1) ? w1 : w0);
+        QW_TRY(dense_stage(c128, g, yin, psi, yout, beta[k - 1], s), "dense Horner stage kernel");
+        yin = yout;
+      }
+      if (K == 1) QW_TRY(copy_state(c128, p->n * p->columns, w0, psi, s), "state copy kernel");
+    }
+    return readout_only(p, psi, ro, s);
+  }
   bool fused_done = false;
   for (int64_t i = 0; i < steps; ++i) {
     const void *yin = psi;
@@ -533,13 +572,17 @@ int qw_plan_get_info(const qw_plan *p, qw_plan_info *info) {
   info->graph_bytes = p->image.size();
   info->state_bytes = p->state_bytes;
   info->work_bytes = p->work_bytes;
+  info->columns = p->columns;
+  info->state_len = p->kind == QW_COINED ? p->n_arcs : p->n * p->columns;
+  if (p->structure == kDense) info->graph_bytes = p->off_dense + p->dense_bytes;
   return ok();
 }
 
 int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) {
   if (!p || !d_graph) return fail(QW_EINVAL, "null plan or graph buffer");
-  if (graph_bytes < p->image.size())
-    return fail(QW_ENOMEM, "graph buffer of %zu bytes, plan needs %zu", graph_bytes, p->image.size());
+  const size_t need = p->structure == kDense ? p->off_dense + p->dense_bytes : p->image.size();
+  if (graph_bytes < need)
+    return fail(QW_ENOMEM, "graph buffer of %zu bytes, plan needs %zu", graph_bytes, need);
   if (reinterpret_cast<uintptr_t>(d_graph) % 256 != 0) return fail(QW_EINVAL, "graph buffer not 256-byte aligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
   QW_TRY(hipMemcpyAsync(d_graph, p->image.data(), p->image.size(), hipMemcpyHostToDevice, s), "graph upload");
@@ -557,11 +600,18 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
   g.group = p->group;
   g.rp = reinterpret_cast<const int32_t *>(base + p->off_rp);
   if (p->has_col) g.col = reinterpret_cast<const int32_t *>(base + p->off_col);
+  if (p->structure == kEll) g.ell_d = p->dims[0];
   if (p->has_rev) g.rev = reinterpret_cast<const int32_t *>(base + p->off_rev);
   if (p->has_tiles) g.tiles = reinterpret_cast<const int32_t *>(base + p->off_tiles);
   if (p->has_perm) g.perm = reinterpret_cast<const int32_t *>(base + p->off_perm);
   g.markbits = reinterpret_cast<const uint32_t *>(base + p->off_bits);
   g.marklist = reinterpret_cast<const int32_t *>(base + p->off_mlist);
+  g.columns = p->columns;
+  if (p->structure == kDense) {
+    g.ld = p->ld;
+    g.dense = base + p->off_dense;
+    QW_TRY(dense_fill(p->dtype == QW_C128, g, p->gamma, p->rows_pad, s), "dense H fill kernels");
+  }
   return ok();
 }
 

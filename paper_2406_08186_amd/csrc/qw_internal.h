@@ -21,7 +21,13 @@ constexpr size_t kSmallLdsBytes = 60 * 1024;  // dynamic LDS, leaves room for st
 // Largest hypercube dimension the structured kernels handle.
 constexpr int kMaxHypercubeDim = 30;
 
-enum Structure : int32_t { kGeneral = 0, kCycle = 1, kTorus = 2, kHypercube = 3, kSmall = 4 };
+enum Structure : int32_t { kGeneral = 0, kCycle = 1, kTorus = 2, kHypercube = 3, kSmall = 4, kEll = 5, kDense = 6 };
+// Dense-H GEMM tiles: rows of H per workgroup, k per LDS chunk.
+constexpr int kDenseRows = 64;
+constexpr int kDenseK = 16;
+constexpr int kMaxDenseColumns = 128;
+// Largest degree of the ELL (regular-graph) CTQW layout.
+constexpr int kMaxEllDegree = 64;
 
 // Device view of a plan's graph tables (pointers into the caller's buffer).
 struct GraphView {
@@ -33,7 +39,11 @@ struct GraphView {
   int32_t n_tiles = 0;
   int32_t group = 1;           // CTQW CSR: lanes per row
   const int32_t *rp = nullptr;      // n+1
-  const int32_t *col = nullptr;     // n_arcs (CTQW general/small)
+  const int32_t *col = nullptr;     // n_arcs (CTQW general/small: CSR order; ELL: col[j*n + v])
+  int32_t ell_d = 0;                // ELL degree
+  int32_t columns = 1;              // dense: walks sharing H
+  int32_t ld = 0;                   // dense: leading dimension of H (multiple of kDenseK)
+  void *dense = nullptr;            // dense: H, rows padded to kDenseRows, FP64 or FP32
   const int32_t *rev = nullptr;     // n_arcs (coined general/small)
   const int32_t *tiles = nullptr;   // n_tiles+1 (coined general)
   const int32_t *perm = nullptr;    // n_arcs (coined structured: slot-major -> CSR position)
@@ -86,6 +96,12 @@ hipError_t ctqw_stage(bool c128, const GraphView &g, const void *y, const void *
 hipError_t vertex_prob(bool c128, const GraphView &g, const void *psi, const Readout &ro,
                        hipStream_t s);
 
+// Dense H: expand the CSR into H (zero fill then scatter of -gamma and the
+// marked diagonal), and one Horner stage y_out = psi + (-i c) H y_in on MFMA.
+hipError_t dense_fill(bool c128, const GraphView &g, double gamma, size_t rows_pad, hipStream_t s);
+hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void *psi, void *out, double c,
+                       hipStream_t s);
+
 // Sum of `count` partials -> *norm; sum over the marked list of p -> *pmarked.
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s);
 
@@ -107,7 +123,9 @@ struct WalkSlot {
   int64_t L0;        // global launch index at which the walk starts
   int64_t units;     // launches it needs: steps * K (CTQW) or steps (coined)
   const int32_t *rp;
-  const int32_t *col;     // CTQW
+  const int32_t *col;     // CTQW (CSR order, or column-major when ell_d > 0)
+  int32_t ell_d;          // CTQW: regular degree of the ELL layout, 0 = CSR
+  int32_t pad0;
   const int32_t *rev;     // coined
   const uint32_t *markbits;
   void *psi;

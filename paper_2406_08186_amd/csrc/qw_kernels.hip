@@ -16,6 +16,8 @@
 // y_out = psi + i (alpha sum_u y_u + beta [v in M] y_v), alpha = gamma dt/k,
 // beta = dt/k.
 
+#include <algorithm>
+
 #include "qw_internal.h"
 
 namespace qwk {
@@ -88,14 +90,15 @@ __device__ double block_sum(double x, double *red) {
 
 // ---- readout tail: partial norms ---------------------------------------------
 __global__ __launch_bounds__(256) void k_finish(const double *partials, int count, const double *p,
-                                                const int32_t *marklist, int n_marked,
+                                                const int32_t *marklist, int n_marked, int columns,
                                                 double *norm, double *pmarked) {
   __shared__ double red[16];
   double acc = 0.0;
   for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partials[i];
   double tot = block_sum(acc, red);
   double pm = 0.0;
-  for (int i = threadIdx.x; i < n_marked; i += blockDim.x) pm += p[marklist[i]];
+  for (int i = threadIdx.x; i < n_marked; i += blockDim.x)
+    for (int b = 0; b < columns; ++b) pm += p[static_cast<int64_t>(marklist[i]) * columns + b];
   double ptot = block_sum(pm, red);
   if (threadIdx.x == 0) {
     if (norm) *norm = tot;
@@ -357,6 +360,79 @@ __global__ __launch_bounds__(kBlock) void k_prob_vertex(const T *__restrict__ ps
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// Sum of y over a row's neighbours, in arc order a = lo..hi-1.  A row of up to
+// 8 arcs issues all its index loads, then all its gathers, before the first
+// add, so a lane keeps up to 8 independent loads in flight instead of a chain
+// of dependent ones; longer rows go 4 arcs at a time.  The summation order is
+// the same in every branch, so results do not depend on which one runs.
+template <typename T>
+__device__ __forceinline__ double2 gather_sum(const T *__restrict__ y, const int32_t *__restrict__ col, int lo,
+                                              int hi) {
+  const int d = hi - lo;
+  double2 s = make_double2(0.0, 0.0);
+  if (d <= 8) {
+    int c[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < d) c[j] = col[lo + j];
+    T x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < d) x[j] = y[c[j]];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < d) s = add(s, cvt(x[j]));
+  } else {
+    int a = lo;
+    for (; a + 4 <= hi; a += 4) {
+      const int c0 = col[a], c1 = col[a + 1], c2 = col[a + 2], c3 = col[a + 3];
+      const T x0 = y[c0], x1 = y[c1], x2 = y[c2], x3 = y[c3];
+      s = add(s, cvt(x0));
+      s = add(s, cvt(x1));
+      s = add(s, cvt(x2));
+      s = add(s, cvt(x3));
+    }
+    for (; a < hi; ++a) s = add(s, cvt(y[col[a]]));
+  }
+  return s;
+}
+
+// Same sum for the column-major neighbour table of a d-regular graph:
+// neighbour j of v at colT[j*n + v], so the index loads of a wavefront are
+// contiguous and no row pointer is read.  Order j = 0..d-1 is row order.
+template <typename T>
+__device__ __forceinline__ double2 ell_gather_sum(const T *__restrict__ y, const int32_t *__restrict__ colT,
+                                                  int n, int d, int v) {
+  double2 s = make_double2(0.0, 0.0);
+  if (d <= 8) {
+    int c[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < d) c[j] = colT[static_cast<int64_t>(j) * n + v];
+    T x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < d) x[j] = y[c[j]];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < d) s = add(s, cvt(x[j]));
+  } else {
+    int j = 0;
+    for (; j + 4 <= d; j += 4) {
+      const int64_t b = static_cast<int64_t>(j) * n + v;
+      const int c0 = colT[b], c1 = colT[b + n], c2 = colT[b + 2 * static_cast<int64_t>(n)],
+                c3 = colT[b + 3 * static_cast<int64_t>(n)];
+      const T x0 = y[c0], x1 = y[c1], x2 = y[c2], x3 = y[c3];
+      s = add(s, cvt(x0));
+      s = add(s, cvt(x1));
+      s = add(s, cvt(x2));
+      s = add(s, cvt(x3));
+    }
+    for (; j < d; ++j) s = add(s, cvt(y[colT[static_cast<int64_t>(j) * n + v]]));
+  }
+  return s;
+}
+
 // ---- CTQW: one Horner stage ---------------------------------------------------
 // y_out = psi + i (alpha sum_{u~v} y_u + beta [v in M] y_v)
 __device__ __forceinline__ double2 horner_out(double2 psi, double2 nsum, double2 yv, bool mk,
@@ -381,10 +457,16 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_csr(GraphView g, const T *__res
   double sx = 0.0, sy = 0.0;
   if (row < g.n) {
     const int lo = g.rp[row], hi = g.rp[row + 1];
-    for (int a = lo + lane; a < hi; a += G) {
-      double2 x = ld(y, g.col[a]);
-      sx += x.x;
-      sy += x.y;
+    if (G == 1) {
+      const double2 t = gather_sum(y, g.col, lo, hi);
+      sx = t.x;
+      sy = t.y;
+    } else {
+      for (int a = lo + lane; a < hi; a += G) {
+        double2 x = ld(y, g.col[a]);
+        sx += x.x;
+        sy += x.y;
+      }
     }
   }
 #pragma unroll
@@ -402,6 +484,32 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_csr(GraphView g, const T *__res
       T stored = pack<T>(r);
       pv = abs2(cvt(stored));
       p[row] = pv;
+    }
+  }
+  if (PROB) {
+    double tot = block_sum(pv, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+  }
+}
+
+// Regular graphs: ELL stage, one thread per row, column-major neighbour table.
+template <typename T, bool PROB>
+__global__ __launch_bounds__(kBlock) void k_ctqw_ell(GraphView g, const T *__restrict__ y, const T *psi,
+                                                     T *out, double alpha, double beta, double *p,
+                                                     double *partials) {
+  __shared__ double red[16];
+  const int n = g.n;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double pv = 0.0;
+  if (v < n) {
+    const double2 s = ell_gather_sum(y, g.col, n, g.ell_d, v);
+    const bool mk = marked(g.markbits, v);
+    const double2 yv = mk ? ld(y, v) : make_double2(0.0, 0.0);
+    const double2 r = horner_out(ld(psi, v), s, yv, mk, alpha, beta);
+    st(out, v, r);
+    if (PROB) {
+      pv = abs2(cvt(pack<T>(r)));
+      p[v] = pv;
     }
   }
   if (PROB) {
@@ -526,9 +634,54 @@ __device__ void batch_ctqw_tile(const WalkSlot &w, const TileEntry &te, int64_t 
   const T *yin = (k == K) ? psi : static_cast<const T *>(((K - k - 1) & 1) ? w.w1 : w.w0);
   T *yout = (k == 1) ? static_cast<T *>(w.psi) : static_cast<T *>(((K - k) & 1) ? w.w1 : w.w0);
   const double alpha = w.alpha[k - 1], beta = w.beta[k - 1];
+  if (w.ell_d > 0 && w.ell_d <= 8) {
+    // regular graph: two rows per lane, every index load and then every gather
+    // of both rows issued before the first add (row r1 clamped to a valid row
+    // when it is past the tile; its result is then discarded)
+    const int d = w.ell_d, n = w.n;
+    for (int r0 = te.begin + threadIdx.x; r0 < te.end; r0 += 2 * blockDim.x) {
+      const int r1raw = r0 + blockDim.x;
+      const bool h1 = r1raw < te.end;
+      const int r1 = h1 ? r1raw : r0;
+      int c0[8], c1[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < d) {
+          c0[j] = w.col[static_cast<int64_t>(j) * n + r0];
+          c1[j] = w.col[static_cast<int64_t>(j) * n + r1];
+        }
+      const double2 p0 = ld(psi, r0), p1 = ld(psi, r1);
+      const bool m0 = marked(w.markbits, r0), m1 = marked(w.markbits, r1);
+      T x0[8], x1[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < d) {
+          x0[j] = yin[c0[j]];
+          x1[j] = yin[c1[j]];
+        }
+      double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < d) {
+          s0 = add(s0, cvt(x0[j]));
+          s1 = add(s1, cvt(x1[j]));
+        }
+      const double2 yv0 = m0 ? ld(yin, r0) : make_double2(0.0, 0.0);
+      const double2 yv1 = m1 ? ld(yin, r1) : make_double2(0.0, 0.0);
+      const T o0 = pack<T>(horner_out(p0, s0, yv0, m0, alpha, beta));
+      const T o1 = pack<T>(horner_out(p1, s1, yv1, m1, alpha, beta));
+      yout[r0] = o0;
+      if (h1) yout[r1] = o1;
+      if (k == 1 && w.hist) {
+        if (m0) atomicAdd(&w.hist[step], abs2(cvt(o0)));
+        if (h1 && m1) atomicAdd(&w.hist[step], abs2(cvt(o1)));
+      }
+    }
+    return;
+  }
   for (int row = te.begin + threadIdx.x; row < te.end; row += blockDim.x) {
-    double2 sum = make_double2(0.0, 0.0);
-    for (int a = w.rp[row]; a < w.rp[row + 1]; ++a) sum = add(sum, ld(yin, w.col[a]));
+    const double2 sum = w.ell_d > 0 ? ell_gather_sum(yin, w.col, w.n, w.ell_d, row)
+                                    : gather_sum(yin, w.col, w.rp[row], w.rp[row + 1]);
     const bool mk = marked(w.markbits, row);
     const double2 yv = mk ? ld(yin, row) : make_double2(0.0, 0.0);
     const double2 r = horner_out(ld(psi, row), sum, yv, mk, alpha, beta);
@@ -592,16 +745,148 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
     __syncthreads();
   }
   if (probe) return;
+  // Launch ticket: the last workgroup to finish advances L.  Only atomicity
+  // is needed -- every workgroup read L before taking its ticket, and the next
+  // launch reads it after the kernel boundary -- so no fence is issued (an
+  // agent-scope fence would write back the L2 once per workgroup).
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned int prev = atomicAdd(&ctl->done, 1u);
     if (prev == gridDim.x - 1) {
       atomicExch(&ctl->done, 0u);
       atomicAdd(&ctl->L, 1ull);
-      __threadfence();
     }
   }
+}
+
+// ---- dense H on the matrix cores -------------------------------------------------
+// H (n x n real, rows padded to kDenseRows, leading dimension ld) times the
+// real view of the state block Y (n x 2C: each complex column b is the real
+// columns 2b, 2b+1).  Workgroup = 4 wavefronts, 64 rows of H; each wave owns
+// 16 rows and all NT*16 real columns as NT accumulator tiles of the
+// 16x16x4 MFMA.  H and Y chunks of kDenseK values of k are staged in LDS.
+// Epilogue: with z = (H y)_v = a + i b, y_out = psi + c (b - i a): real
+// column 2b takes +c * (its odd partner), column 2b+1 takes -c * (its even
+// partner); partners sit in neighbouring lanes.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+// Result layout of the 16x16x4 forms (lane l, register r, column l % 16):
+// the FP64 form holds row l/16 + 4r, the FP32 form row 4(l/16) + r.
+template <> struct Mfma<double> {
+  using acc = md4;
+  static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+  static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  using acc = mf4;
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+  static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename R, int NT>
+__global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, int ld, int n, int c2,
+                                                     const R *__restrict__ yin, const R *psi, R *out,
+                                                     double c) {
+  using M = Mfma<R>;
+  constexpr int NC = NT * 16;
+  __shared__ R hs[kDenseRows][kDenseK + 1];
+  __shared__ R xs[kDenseK][NC];
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int row0 = blockIdx.x * kDenseRows;
+  typename M::acc acc[NT];
+  double wide[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = M::zero();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) wide[t][r] = 0.0;
+  }
+  int chunk = 0;
+  for (int k0 = 0; k0 < n; k0 += kDenseK, ++chunk) {
+    for (int e = threadIdx.x; e < kDenseRows * kDenseK; e += blockDim.x) {
+      const int i = e / kDenseK, j = e % kDenseK;
+      hs[i][j] = H[static_cast<int64_t>(row0 + i) * ld + k0 + j];
+    }
+    for (int e = threadIdx.x; e < kDenseK * NC; e += blockDim.x) {
+      const int i = e / NC, j = e % NC;
+      R v = R(0);
+      if (k0 + i < n && j < c2) v = yin[static_cast<int64_t>(k0 + i) * c2 + j];
+      xs[i][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kDenseK; kk += 4) {
+      const R a = hs[wave * 16 + (l & 15)][kk + (l >> 4)];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = M::mma(a, xs[kk + (l >> 4)][t * 16 + (l & 15)], acc[t]);
+    }
+    __syncthreads();
+    if (sizeof(R) == 4 && (chunk & 15) == 15) {  // FP32 products: fold into FP64 every 256 k
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wide[t][r] += static_cast<double>(acc[t][r]);
+        acc[t] = M::zero();
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double z = wide[t][r] + static_cast<double>(acc[t][r]);
+      const double zp = __shfl_xor(z, 1, 64);
+      const int row = row0 + wave * 16 + M::row(l, r);
+      const int col = t * 16 + (l & 15);
+      if (row < n && col < c2) {
+        const int64_t idx = static_cast<int64_t>(row) * c2 + col;
+        const double ps = static_cast<double>(psi[idx]);
+        out[idx] = static_cast<R>((col & 1) ? ps - c * zp : ps + c * zp);
+      }
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_dense_zero(R *H, int64_t total) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    H[i] = R(0);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_dense_scatter(GraphView g, R *H, double gamma) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.n) return;
+  R *row = H + static_cast<int64_t>(v) * g.ld;
+  for (int a = g.rp[v]; a < g.rp[v + 1]; ++a) row[g.col[a]] = static_cast<R>(-gamma);
+  if (marked(g.markbits, v)) row[v] = R(-1);
+}
+
+template <typename R, int NT>
+void launch_dense(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
+  const dim3 grid((g.n + kDenseRows - 1) / kDenseRows);
+  hipLaunchKernelGGL((k_dense_stage<R, NT>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld, g.n,
+                     2 * g.columns, static_cast<const R *>(y), static_cast<const R *>(psi), static_cast<R *>(out),
+                     c);
+}
+
+template <typename R>
+void launch_dense_nt(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
+  const int c2 = 2 * g.columns;
+  if (c2 <= 16) launch_dense<R, 1>(g, y, psi, out, c, s);
+  else if (c2 <= 32) launch_dense<R, 2>(g, y, psi, out, c, s);
+  else if (c2 <= 64) launch_dense<R, 4>(g, y, psi, out, c, s);
+  else if (c2 <= 128) launch_dense<R, 8>(g, y, psi, out, c, s);
+  else launch_dense<R, 16>(g, y, psi, out, c, s);
 }
 
 inline int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
@@ -692,6 +977,10 @@ hipError_t launch_ctqw_stage(const GraphView &g, const T *y, const T *psi, T *ou
         hipLaunchKernelGGL((k_ctqw_struct<T, kHypercube, PROB>), grid, dim3(kBlock), 0, s, g, y, psi,
                            out, c.alpha, c.beta, p, partials);
         break;
+      case kEll:
+        hipLaunchKernelGGL((k_ctqw_ell<T, PROB>), grid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta, p,
+                           partials);
+        break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -778,7 +1067,9 @@ hipError_t copy_state(bool c128, int64_t len, const void *in, void *out, hipStre
   return hipGetLastError();
 }
 
-int readout_partials(const GraphView &g) { return blocks_for(g.n, kBlock); }
+int readout_partials(const GraphView &g) {
+  return blocks_for(g.structure == kDense ? static_cast<int64_t>(g.n) * g.columns : g.n, kBlock);
+}
 
 int ctqw_stage_partials(const GraphView &g) {
   const int64_t lanes = g.structure == kGeneral ? static_cast<int64_t>(g.n) * g.group : g.n;
@@ -823,13 +1114,14 @@ hipError_t ctqw_stage(bool c128, const GraphView &g, const void *y, const void *
 
 hipError_t vertex_prob(bool c128, const GraphView &g, const void *psi, const Readout &ro, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  const dim3 grid(blocks_for(g.n, kBlock));
+  const int len = g.structure == kDense ? g.n * g.columns : g.n;
+  const dim3 grid(blocks_for(len, kBlock));
   if (c128)
     hipLaunchKernelGGL(k_prob_vertex<double2>, grid, dim3(kBlock), 0, s, static_cast<const double2 *>(psi),
-                       g.n, ro.p_out(), ro.partials);
+                       len, ro.p_out(), ro.partials);
   else
     hipLaunchKernelGGL(k_prob_vertex<float2>, grid, dim3(kBlock), 0, s, static_cast<const float2 *>(psi),
-                       g.n, ro.p_out(), ro.partials);
+                       len, ro.p_out(), ro.partials);
   return hipGetLastError();
 }
 
@@ -843,10 +1135,32 @@ hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const Ti
   return hipGetLastError();
 }
 
+hipError_t dense_fill(bool c128, const GraphView &g, double gamma, size_t rows_pad, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(rows_pad) * g.ld;
+  const dim3 zgrid(static_cast<unsigned>(std::min<int64_t>((total + kBlock - 1) / kBlock, 8192)));
+  const dim3 sgrid(blocks_for(g.n, kBlock));
+  if (c128) {
+    hipLaunchKernelGGL(k_dense_zero<double>, zgrid, dim3(kBlock), 0, s, static_cast<double *>(g.dense), total);
+    if (g.n) hipLaunchKernelGGL(k_dense_scatter<double>, sgrid, dim3(kBlock), 0, s, g, static_cast<double *>(g.dense), gamma);
+  } else {
+    hipLaunchKernelGGL(k_dense_zero<float>, zgrid, dim3(kBlock), 0, s, static_cast<float *>(g.dense), total);
+    if (g.n) hipLaunchKernelGGL(k_dense_scatter<float>, sgrid, dim3(kBlock), 0, s, g, static_cast<float *>(g.dense), gamma);
+  }
+  return hipGetLastError();
+}
+
+hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void *psi, void *out, double c,
+                       hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  if (c128) launch_dense_nt<double>(g, y, psi, out, c, s);
+  else launch_dense_nt<float>(g, y, psi, out, c, s);
+  return hipGetLastError();
+}
+
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s) {
   if (!ro.norm && !ro.pmarked) return hipSuccess;
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, ro.partials, count, ro.p_out(), g.marklist,
-                     g.n_marked, ro.norm, ro.pmarked);
+                     g.n_marked, g.structure == kDense ? g.columns : 1, ro.norm, ro.pmarked);
   return hipGetLastError();
 }
 

@@ -21,6 +21,11 @@ struct qw_plan {
   int32_t n_marked = 0;
   int32_t n_tiles = 0;
   int32_t group = 1;
+  // dense layout: walks per state, leading dimension and padded rows of H,
+  // and where H sits in the device graph buffer (after the uploaded image)
+  int32_t columns = 1;
+  int32_t ld = 0;
+  size_t rows_pad = 0, off_dense = 0, dense_bytes = 0;
   // host image of the device graph buffer, and section offsets into it
   std::vector<unsigned char> image;
   size_t off_rp = 0, off_col = 0, off_rev = 0, off_tiles = 0, off_perm = 0, off_bits = 0, off_mlist = 0;

@@ -50,11 +50,13 @@ def _from_rows(n: int, heads: np.ndarray, tails: np.ndarray, name: str,
     tails = np.asarray(tails, dtype=np.int64)
     heads = np.asarray(heads, dtype=np.int64)
     if sort_rows:
-        order = np.lexsort((heads, tails))
+        keys = tails * np.int64(max(n, 1)) + heads
+        keys.sort()
+        t, h = np.divmod(keys, np.int64(max(n, 1)))
     else:
         order = np.argsort(tails, kind="stable")
-    t = tails[order]
-    h = heads[order]
+        t = tails[order]
+        h = heads[order]
     counts = np.bincount(t, minlength=n).astype(np.int64)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
@@ -120,10 +122,14 @@ def hypercube(dim: int) -> Graph:
 
 def complete(n: int) -> Graph:
     """Complete graph K_n, rows sorted."""
-    v = np.arange(n, dtype=np.int64)
-    tails = np.repeat(v, n - 1)
-    heads = np.concatenate([np.delete(v, i) for i in range(n)]) if n > 1 else v[:0]
-    return _from_rows(n, heads, tails, f"complete{n}")
+    if n < 2:
+        return Graph(n=n, row_ptr=np.zeros(n + 1, np.int64), col=np.zeros(0, np.int32),
+                     name=f"complete{n}")
+    tails = np.repeat(np.arange(n, dtype=np.int64), n - 1)
+    heads = np.tile(np.arange(n - 1, dtype=np.int64), n)
+    heads += heads >= tails  # skip the diagonal: row v lists 0..v-1, v+1..n-1
+    row_ptr = np.arange(0, n * (n - 1) + 1, n - 1, dtype=np.int64)
+    return Graph(n=n, row_ptr=row_ptr, col=heads.astype(np.int32), name=f"complete{n}")
 
 
 def random_regular(n: int, d: int, seed: int) -> Graph:
@@ -149,23 +155,34 @@ def random_regular(n: int, d: int, seed: int) -> Graph:
     raise RuntimeError("could not draw a connected random regular graph")
 
 
-def _edge_keys(e: np.ndarray, n_hint: int) -> np.ndarray:
-    return e[:, 0] * np.int64(n_hint) + e[:, 1]
-
-
 def _switch_to_simple(e: np.ndarray, rng) -> np.ndarray:
-    """Remove loops and repeated edges by degree-preserving switches."""
+    """Remove loops and repeated edges by degree-preserving switches.
+
+    A bad edge (a, b) and a random edge (c, d) become (a, c), (b, d) (or
+    (a, d), (b, c)) when neither new edge is a loop or already present.
+    """
     m = e.shape[0]
-    n_hint = int(e.max()) + 1
-    for _sweep in range(10000):
-        keys = _edge_keys(e, n_hint)
-        _, first, counts = np.unique(keys, return_index=True, return_counts=True)
-        dup = np.ones(m, dtype=bool)
-        dup[first] = False
+    n_hint = np.int64(int(e.max()) + 1)
+    for _sweep in range(1000):
+        keys = e[:, 0] * n_hint + e[:, 1]
+        order = np.argsort(keys, kind="stable")
+        sk = keys[order]
+        dup = np.zeros(m, dtype=bool)
+        dup[order[1:][sk[1:] == sk[:-1]]] = True
         bad = np.flatnonzero((e[:, 0] == e[:, 1]) | dup)
         if bad.size == 0:
             return e
-        present = set(keys.tolist())
+        extra = set()   # keys created during this sweep
+        removed = set()
+
+        def present(k):
+            if k in extra:
+                return True
+            if k in removed:
+                return False
+            i = np.searchsorted(sk, k)
+            return i < sk.size and sk[i] == k
+
         for i in bad.tolist():
             for _try in range(100):
                 j = int(rng.integers(m))
@@ -179,18 +196,20 @@ def _switch_to_simple(e: np.ndarray, rng) -> np.ndarray:
                 n2 = (min(b, dd), max(b, dd))
                 if n1[0] == n1[1] or n2[0] == n2[1] or n1 == n2:
                     continue
-                k1 = n1[0] * n_hint + n1[1]
-                k2 = n2[0] * n_hint + n2[1]
-                if k1 in present or k2 in present:
+                k1 = n1[0] * int(n_hint) + n1[1]
+                k2 = n2[0] * int(n_hint) + n2[1]
+                if present(k1) or present(k2):
                     continue
-                present.discard(int(keys[i]))
-                present.discard(int(keys[j]))
-                present.add(k1)
-                present.add(k2)
+                for k_old in (a * int(n_hint) + b if a <= b else b * int(n_hint) + a,
+                              min(c, dd) * int(n_hint) + max(c, dd)):
+                    extra.discard(k_old)
+                    removed.add(k_old)
+                extra.add(k1)
+                extra.add(k2)
+                removed.discard(k1)
+                removed.discard(k2)
                 e[i] = n1
                 e[j] = n2
-                keys[i] = k1
-                keys[j] = k2
                 break
     raise RuntimeError("edge switching did not converge")
 

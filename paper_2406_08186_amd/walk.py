@@ -18,7 +18,8 @@ from .inputs import Graph, arc_index
 
 _DT = {"c64": L.QW_C64, "c128": L.QW_C128}
 _TORCH_DT = {"c64": torch.complex64, "c128": torch.complex128}
-_LAYOUT = {"auto": L.QW_LAYOUT_AUTO, "csr": L.QW_LAYOUT_CSR, "structured": L.QW_LAYOUT_STRUCTURED}
+_LAYOUT = {"auto": L.QW_LAYOUT_AUTO, "csr": L.QW_LAYOUT_CSR, "structured": L.QW_LAYOUT_STRUCTURED,
+           "dense": L.QW_LAYOUT_DENSE}
 
 
 def _stream_ptr(stream, device) -> int:
@@ -30,14 +31,16 @@ class Plan:
     """A validated walk on one graph with its device tables uploaded.
 
     kind: "coined" or "ctqw"; coin: "grover" or "hadamard"; dtype: "c64" or
-    "c128"; layout: "auto", "csr" or "structured".  CTQW takes gamma, dt and
-    either taylor_order or (trunc_tol, horizon_steps).
+    "c128"; layout: "auto", "csr", "structured" or "dense".  CTQW takes gamma, dt
+    and either taylor_order or (trunc_tol, horizon_steps); the dense layout takes
+    `columns` walks sharing H (state n x columns, vertex-major).
     """
 
     def __init__(self, graph: Graph, kind: str = "coined", *, coin: str = "grover",
                  dtype: str = "c128", layout: str = "auto", gamma: float = 0.0, dt: float = 0.0,
                  taylor_order: int = 0, trunc_tol: float = 0.0, horizon_steps: int = 0,
-                 marked: Sequence[int] = (), device=None, stream=None):
+                 marked: Sequence[int] = (), columns: int = 0, device=None, stream=None,
+                 upload: bool = True):
         self.graph = graph
         self.kind = kind
         self.dtype = dtype
@@ -56,16 +59,31 @@ class Plan:
             taylor_order=int(taylor_order), trunc_tol=float(trunc_tol),
             horizon_steps=int(horizon_steps),
             marked=self._marked.ctypes.data_as(C.POINTER(C.c_int32)) if self._marked.size else None,
-            n_marked=int(self._marked.size))
+            n_marked=int(self._marked.size), columns=int(columns))
         self._plan = L.qw_plan_create(csr, desc)
         self.info = L.qw_plan_get_info(self._plan)
         self.structure = L.STRUCTURES[self.info.structure]
+        self.d_graph = None
+        if upload:
+            self.upload(stream)
+
+    @property
+    def device_bytes(self) -> int:
+        """Device memory this plan needs once uploaded: tables, workspace, one state."""
+        return int(self.info.graph_bytes + self.info.work_bytes + self.info.state_bytes)
+
+    def upload(self, stream=None) -> None:
+        """Allocate the device tables and workspace (torch) and upload (second phase)."""
         self.d_graph = torch.empty(max(self.info.graph_bytes, 256), dtype=torch.uint8, device=self.device)
         self.work = torch.empty(max(self.info.work_bytes, 256), dtype=torch.uint8, device=self.device)
-        self._p = torch.empty(max(graph.n, 1), dtype=torch.float64, device=self.device)
+        self._p = torch.empty(max(self.p_len, 1), dtype=torch.float64, device=self.device)
         self._scal = torch.zeros(2, dtype=torch.float64, device=self.device)
         L.qw_plan_upload(self._plan, self.d_graph.data_ptr(), self.d_graph.numel(),
                          _stream_ptr(stream, self.device))
+
+    def release_device(self) -> None:
+        """Drop the device buffers (the plan must not be used on the device afterwards)."""
+        self.d_graph = self.work = self._p = self._scal = None
 
     # -- lifetime
     def close(self) -> None:
@@ -83,6 +101,11 @@ class Plan:
     @property
     def state_len(self) -> int:
         return int(self.info.state_len)
+
+    @property
+    def p_len(self) -> int:
+        """Length of the probability readout: n, or n * columns for the dense layout."""
+        return int(self.graph.n * max(1, self.info.columns))
 
     def state(self, psi0) -> torch.Tensor:
         """Device copy of psi0 in this plan's precision."""
@@ -105,7 +128,7 @@ class Plan:
             p, scal = self._p, self._scal
             L.qw_evolve(self._plan, psi.data_ptr(), self.work.data_ptr(), self.work.numel(), int(steps),
                         p.data_ptr(), scal.data_ptr(), scal.data_ptr() + 8, sp)
-            return p[:self.graph.n], scal[0], scal[1]
+            return p[:self.p_len], scal[0], scal[1]
         L.qw_evolve(self._plan, psi.data_ptr(), self.work.data_ptr(), self.work.numel(), int(steps),
                     None, None, None, sp)
         return None
@@ -113,12 +136,12 @@ class Plan:
     def probabilities(self, psi: torch.Tensor, stream=None):
         """(p, norm, p_marked) of a state, FP64, on device."""
         self._check(psi)
-        p = torch.empty(max(self.graph.n, 1), dtype=torch.float64, device=self.device)
+        p = torch.empty(max(self.p_len, 1), dtype=torch.float64, device=self.device)
         scal = torch.zeros(2, dtype=torch.float64, device=self.device)
         L.qw_probabilities(self._plan, psi.data_ptr(), p.data_ptr(), scal.data_ptr(),
                            scal.data_ptr() + 8, self.work.data_ptr(), self.work.numel(),
                            _stream_ptr(stream, self.device))
-        return p[:self.graph.n], scal[0], scal[1]
+        return p[:self.p_len], scal[0], scal[1]
 
 
 class Batch:

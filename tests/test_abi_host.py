@@ -118,7 +118,10 @@ def test_evolve_before_upload_is_state_error():
     (I.cycle(5000), 0, L.QW_LAYOUT_AUTO, "cycle"),
     (I.cycle_sorted(5000), 1, L.QW_LAYOUT_AUTO, "cycle"),
     (I.random_regular(3000, 4, 1), 0, L.QW_LAYOUT_AUTO, "general"),
-    (I.random_regular(3000, 4, 1), 1, L.QW_LAYOUT_STRUCTURED, "general"),
+    (I.random_regular(3000, 4, 1), 1, L.QW_LAYOUT_STRUCTURED, "ell"),
+    (I.random_regular(3000, 4, 1), 1, L.QW_LAYOUT_AUTO, "ell"),
+    (I.random_regular(3000, 4, 1), 1, L.QW_LAYOUT_CSR, "general"),
+    (I.erdos_renyi(3000, 0.002, 2), 1, L.QW_LAYOUT_AUTO, "general"),
 ])
 def test_path_choice(g, kind, layout, expect):
     kw = dict(kind=kind, coin=0, dtype=1, layout=layout)
@@ -204,3 +207,22 @@ def test_batch_host_side():
     assert lib.qw_batch_remaining(b, 9, C.byref(r)) == L.QW_EINVAL
     L.qw_batch_destroy(b)
     assert lib.qw_batch_destroy(None) == L.QW_OK
+
+
+def test_dense_layout_plans():
+    g = I.complete(50)
+    p = _create(g, kind=1, dtype=1, layout=L.QW_LAYOUT_DENSE, gamma=0.02, dt=0.3, taylor_order=10,
+                columns=8)
+    info = L.qw_plan_get_info(p)
+    assert L.STRUCTURES[info.structure] == "dense" and info.columns == 8
+    assert info.state_len == 50 * 8 and info.state_bytes == 16 * 400
+    assert info.graph_bytes >= 64 * 64 * 8  # H rows padded to 64, ld to 16
+    L.qw_plan_destroy(p)
+    assert _code(lambda: _create(g, kind=0, dtype=1, layout=L.QW_LAYOUT_DENSE)) == L.QW_EUNSUPPORTED
+    assert _code(lambda: _create(g, kind=1, dtype=1, gamma=0.1, dt=0.1, taylor_order=4,
+                                 columns=2)) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=1, dtype=1, layout=L.QW_LAYOUT_DENSE, gamma=0.1, dt=0.1,
+                                 taylor_order=4, columns=129)) == L.QW_EINVAL
+    c = I.complete(7)
+    assert c.n_arcs == 42 and all(sorted(c.row(v).tolist()) == [w for w in range(7) if w != v]
+                                  for v in range(7))

@@ -21,8 +21,13 @@ def _gpu():
 def _walks(dtype):
     """(graph, kind, params, steps) of a ragged mix."""
     return [
-        (I.random_regular(500, 3, seed=1), "ctqw", dict(gamma=1 / 3, dt=0.3, taylor_order=14, marked=[7]), 9),
+        (I.random_regular(500, 3, seed=1), "ctqw", dict(gamma=1 / 3, dt=0.3, taylor_order=14, marked=[7],
+                                                       layout="structured"), 9),
         (I.random_regular(1200, 5, seed=2), "ctqw", dict(gamma=0.2, dt=0.5, taylor_order=16, marked=[0]), 5),
+        (I.random_regular(3001 + 1, 7, seed=12), "ctqw", dict(gamma=1 / 7, dt=0.2, taylor_order=12, marked=[5],
+                                                             layout="structured"), 6),
+        (I.random_regular(700, 12, seed=13), "ctqw", dict(gamma=1 / 12, dt=0.2, taylor_order=10, marked=[9],
+                                                         layout="structured"), 4),
         (I.random_regular(2000, 8, seed=3), "ctqw", dict(gamma=0.125, dt=0.4, taylor_order=12, marked=[1999]), 12),
         (I.erdos_renyi(1500, 6 / 1499, seed=4), "ctqw", dict(gamma=0.2, dt=0.25, taylor_order=10, marked=[3]), 7),
         (I.cycle(300), "coined", dict(coin="hadamard"), 31),
@@ -34,7 +39,9 @@ def _walks(dtype):
 
 def _plan(g, kind, params, dtype):
     from paper_2406_08186_amd.walk import Plan
-    return Plan(g, kind, dtype=dtype, layout="csr", **params)
+    params = dict(params)
+    layout = params.pop("layout", "csr")
+    return Plan(g, kind, dtype=dtype, layout=layout, **params)
 
 
 def _psi0(pl, seed):
@@ -79,6 +86,7 @@ def test_batch_alone_vs_mix_and_oracle(dtype):
         assert torch.equal(alone[1], mixed[i][1])
         g, kind, params, _ = walks[i]
         if kind == "ctqw":
+            assert pl.structure == ("ell" if params.get("layout") == "structured" else "general")
             ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps, gamma=params["gamma"], dt=params["dt"],
                                      K=params["taylor_order"], marked=params["marked"])
             pref = oracle.vertex_prob(ref)
@@ -107,22 +115,22 @@ def test_batch_continuous_join_and_schedules():
     dtype = "c64"
     walks = _walks(dtype)
     pls = [_plan(g, kind, params, dtype) for g, kind, params, _ in walks]
-    late = 5
+    late = 7
     ref = _run_batch([(pls[late], _psi0(pls[late], 7), walks[late][3])], dtype)[0]
     b = Batch(capacity=8, max_tiles=8192, dtype=dtype)
     keep = []
-    for slot in (0, 1, 4):
-        psi = pls[slot].state(_psi0(pls[slot], 50 + slot))
+    for slot, wi in enumerate((0, 1, 6)):
+        psi = pls[wi].state(_psi0(pls[wi], 50 + wi))
         keep.append(psi)
-        b.set_slot(slot, pls[slot], psi, walks[slot][3])
+        b.set_slot(slot, pls[wi], psi, walks[wi][3])
     b.commit()
     b.run(23)  # replay path (>= 16) plus single launches
     psi = pls[late].state(_psi0(pls[late], 7))
-    b.set_slot(6, pls[late], psi, walks[late][3])
+    b.set_slot(5, pls[late], psi, walks[late][3])
     b.commit()
-    assert b.remaining(6) == walks[late][3]
+    assert b.remaining(5) == walks[late][3]
     b.run_to_completion()
-    b.readout(6)
+    b.readout(5)
     torch.cuda.synchronize()
     assert torch.equal(psi, ref[0])
     for sched in ((256, False), (4096, True)):
