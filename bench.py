@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--dtypes", default="c64,c128")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
-    ap.add_argument("--workload", default="grid", choices=["grid", "batch", "serve", "dense"],
+    ap.add_argument("--workload", default="grid",
+                    choices=["grid", "batch", "serve", "dense", "hypercube", "cycle"],
                     help="grid: the 1024^2 CTQW (default); batch: many CTQW searches on random "
                          "regular graphs in one batch; serve: the Poisson job stream")
     ap.add_argument("--batch-walks", type=int, default=4096)
@@ -94,8 +95,8 @@ def timed_passes(plan, psi, steps, warmup, spp):
 
 
 def stage_launch_ms(plan, psi, reps=20):
-    """Average duration of one Horner-stage launch: HIP events around
-    single-step evolves (20 stage launches each) on the launch stream."""
+    """Average duration of one launch of the stage kernel: HIP events around
+    single-step evolves (K / block_depth launches each) on the launch stream."""
     import torch
     plan.evolve(psi, 1)
     torch.cuda.synchronize()
@@ -105,7 +106,7 @@ def stage_launch_ms(plan, psi, reps=20):
         plan.evolve(psi, 1)
     b.record()
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / (reps * K_ORDER)
+    return a.elapsed_time(b) / (reps * (K_ORDER // max(1, plan.info.block_depth)))
 
 
 def pct(sorted_vals, q):
@@ -152,6 +153,12 @@ def main():
     if args.workload == "dense":
         run_dense(args)
         return
+    if args.workload == "hypercube":
+        run_hypercube(args)
+        return
+    if args.workload == "cycle":
+        run_cycle(args)
+        return
     spp = args.steps_per_pass
     dtypes = args.dtypes.split(",")
     import numpy as np
@@ -173,10 +180,14 @@ def main():
         state = psi.cpu().numpy().astype(np.complex128)
         launch_ms = stage_launch_ms(pl, pl.state(psi0))
         es = 8 if dtype == "c64" else 16
-        bytes_per_launch = 3 * es * g.n  # read y, read psi, write y' (gathers ideally cached)
+        # algorithmic bytes of one row-stage of the matrix-free grid stencil: read y,
+        # read psi, write y' (3 S); one launch runs block_depth stages of every row
+        depth = int(pl.info.block_depth)
+        bytes_per_launch = depth * 3 * es * g.n
         res[dtype] = dict(plan=pl, wall=wall, per=per, norm=float(norm), state=state,
                           total_steps=total_steps, launch_ms=launch_ms,
-                          bytes_per_launch=bytes_per_launch, structure=pl.structure)
+                          bytes_per_launch=bytes_per_launch, structure=pl.structure,
+                        depth=depth)
         del psi
     t_final = res[dtypes[0]]["total_steps"] * DT
     ref1 = cf.cycle_ctqw(L_SIDE, GAMMA, t_final, L_SIDE // 2)
@@ -212,7 +223,7 @@ def main():
         "config": {"workload": "ctqw_torus_1024x1024_gamma0.25_K20_dt0.1_1000steps",
                    "n": g.n, "arcs": g.n_arcs, "gamma": GAMMA, "dt": DT, "taylor_order": K_ORDER,
                    "steps_per_pass": spp, "start_vertex": v0,
-                   "path": r64["structure"], "parallelism": "single-gpu"},
+                   "path": r64["structure"], "stages_per_launch": r64["depth"], "parallelism": "single-gpu"},
         "arc_spmv_per_s": rate(r64) * K_ORDER,
         "p50_ms": pct(r64["per"], 50), "p99_ms": pct(r64["per"], 99),
         "c128": {"value": rate(r128), "ms_per_step": r128["wall"] / args.steps * 1e3,
@@ -224,7 +235,9 @@ def main():
         "l2_c64_vs_closed_form": l2_64,
         "l2_c64_vs_c128": l2_64_128,
         "norm_drift_c64": abs(r64["norm"] - 1.0),
-        "roofline": {"bound": "hbm", "kernel": "k_ctqw_struct<float2,TORUS> (one Horner stage)",
+        "roofline": {"bound": "hbm",
+                     "kernel": (f"k_ctqw_torus_tb<float2,32,64,{r64['depth']}> ({r64['depth']} Horner stages per launch)"
+                                if r64["depth"] > 1 else "k_ctqw_struct<float2,TORUS> (one Horner stage)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": r64["bytes_per_launch"],
@@ -490,6 +503,95 @@ def run_dense(args):
         del psi
     print(json.dumps({"workload": f"dense_complete_{n}", "dtype": args.dense_dtype, "taylor_order": 16,
                       "points": out}), flush=True)
+
+
+# ---------------------------------------------------------------- hypercube search
+
+def run_hypercube(args):
+    """Coined Grover search on the dimension-20 hypercube (2^20 vertices,
+    20 * 2^20 arcs), coin -I at vertex 0, uniform arc state, ceil((pi/2)
+    sqrt(N ln N)) = 5989 steps; complex64 and complex128, checked against the
+    symmetric-subspace closed form."""
+    import numpy as np
+    import torch
+
+    from oracle import closed_forms as cf
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Plan
+    dim = 20
+    n = 1 << dim
+    steps = math.ceil(math.pi / 2 * math.sqrt(n * math.log(n)))
+    g = I.hypercube(dim)
+    o, _, _ = cf.hypercube_search_reduced(dim, steps)
+    ref = cf.hypercube_search_state(dim, steps, g.row_ptr, g.col)
+    res = {}
+    for dtype in ("c64", "c128"):
+        pl = Plan(g, "coined", dtype=dtype, marked=[0])
+        psi0 = np.full(g.n_arcs, 1 / math.sqrt(g.n_arcs), dtype=np.complex128)
+        psi = pl.state(psi0)
+        pl.evolve(psi, 2)
+        torch.cuda.synchronize()
+        psi = pl.state(psi0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record()
+        p, norm, pm = pl.evolve(psi, steps, readout=True)
+        b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = a.elapsed_time(b)
+        es = 8 if dtype == "c64" else 16
+        got = psi.cpu().numpy().astype(np.complex128)
+        res[dtype] = {"value": g.n_arcs * steps / (ms * 1e-3), "ms": ms, "wall_s": wall,
+                      "step_us": ms * 1e3 / steps,
+                      "step_gbs": 2 * es * g.n_arcs / (ms * 1e-3 / steps) / 1e9,
+                      "frac": 2 * es * g.n_arcs / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS,
+                      "p_marked": float(pm), "p_marked_ref": float(abs(o[0]) ** 2),
+                      "l2_vs_closed_form": float(np.linalg.norm(got - ref)), "norm": float(norm),
+                      "path": pl.structure}
+        del psi
+        pl.close()
+    print(json.dumps({"workload": "coined_search_hypercube20", "steps": steps, "arcs": g.n_arcs,
+                      "unit": "arc-steps/s", "roofline_bytes_per_arc_step": "2S (read + write, slot-major)",
+                      **{k: v for k, v in res.items()}}), flush=True)
+
+
+# ---------------------------------------------------------------- 64-cycle latency
+
+def run_cycle(args):
+    """The 64-cycle Hadamard walk from (|0,0> + i|0,1>)/sqrt2, 100 steps, complex128,
+    with the FP64 readout: one call runs the whole walk in one workgroup's LDS.
+    Reports the per-call latency distribution (host clock around a synchronised call,
+    and HIP events on the stream)."""
+    import numpy as np
+    import torch
+
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Plan
+    g, psi0 = I.cycle_hadamard_state(64)
+    pl = Plan(g, "coined", coin="hadamard", dtype="c128")
+    psi = pl.state(psi0)
+    for _ in range(50):
+        psi.copy_(pl.state(psi0))
+        pl.evolve(psi, 100, readout=True)
+    torch.cuda.synchronize()
+    host, dev = [], []
+    reps = 1000
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record()
+        pl.evolve(psi, 100, readout=True)
+        b.record()
+        b.synchronize()
+        host.append((time.perf_counter() - t0) * 1e3)
+        dev.append(a.elapsed_time(b))
+    host.sort()
+    dev.sort()
+    print(json.dumps({"workload": "coined_hadamard_cycle64_100steps", "dtype": "c128", "path": pl.structure,
+                      "calls": reps, "host_p50_ms": pct(host, 50), "host_p99_ms": pct(host, 99),
+                      "device_p50_ms": pct(dev, 50), "device_p99_ms": pct(dev, 99),
+                      "arc_steps_per_s_p50": g.n_arcs * 100 / (pct(dev, 50) * 1e-3)}), flush=True)
 
 
 if __name__ == "__main__":

@@ -146,6 +146,8 @@ typedef struct qw_plan_info {
   size_t state_bytes;      /* bytes of one state vector                       */
   size_t work_bytes;       /* device workspace qw_evolve/qw_probabilities need*/
   int32_t columns;         /* walks per state (dense layout), else 1          */
+  int32_t block_depth;     /* CTQW on a torus: Horner stages per launch (> 1
+                              when temporal blocking in LDS applies), else 1  */
 } qw_plan_info;
 
 /* Validate the graph and the walk, precompute the host-side tables (reverse

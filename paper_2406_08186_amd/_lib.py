@@ -50,7 +50,7 @@ class QwPlanInfo(C.Structure):
                 ("dims", C.c_int32 * 2), ("max_degree", C.c_int32), ("taylor_order", C.c_int32),
                 ("dt", C.c_double), ("h_norm_bound", C.c_double), ("trunc_bound", C.c_double),
                 ("graph_bytes", C.c_size_t), ("state_bytes", C.c_size_t), ("work_bytes", C.c_size_t),
-                ("columns", C.c_int32)]
+                ("columns", C.c_int32), ("block_depth", C.c_int32)]
 
 
 class QwError(RuntimeError):

@@ -378,8 +378,23 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   };
   wsec(p->state_bytes);                    // buffer 0 at offset 0
   p->off_w1 = wsec(p->state_bytes);        // buffer 1
+  if (!coined && structure == kTorus) {
+    GraphView tv;
+    tv.structure = structure;
+    tv.dims[0] = p->dims[0];
+    tv.dims[1] = p->dims[1];
+    p->block_depth = torus_block_depth(c128, tv, p->K);
+    if (p->block_depth > 1) p->off_w2 = wsec(p->state_bytes);  // buffer 2: the other psi
+  }
   p->off_pscratch = wsec(sizeof(double) * static_cast<size_t>(n) * p->columns);
   p->off_partials = wsec(sizeof(double) * partials);
+  if (structure == kDense) {
+    GraphView dv;
+    dv.n = static_cast<int32_t>(n);
+    dv.columns = p->columns;
+    const int sp = dense_splits(dv);
+    if (sp > 1) p->off_dpartial = wsec(sizeof(double) * static_cast<size_t>(sp) * n * 2 * p->columns);
+  }
   p->work_bytes = w_off;
   return ok();
 }
@@ -466,12 +481,37 @@ int evolve_ctqw(const qw_plan *p, void *psi, unsigned char *work, int64_t steps,
   }
   if (steps == 0) return readout_only(p, psi, ro, s);
   void *w0 = work, *w1 = work + p->off_w1;
+  if (p->block_depth > 1) {
+    // temporal blocking: K/S launches per step, each S stages in LDS; psi
+    // alternates between the caller's buffer and buffer 2, y between 0 and 1
+    std::vector<double> a64(64, 0.0), b64(64, 0.0);
+    for (int k = 0; k < K; ++k) {
+      a64[k] = alpha[k];
+      b64[k] = beta[k];
+    }
+    const int S = p->block_depth, per = K / S;
+    void *pc = psi, *pa = work + p->off_w2;
+    void *ybuf[2] = {w0, w1};
+    for (int64_t i = 0; i < steps; ++i) {
+      for (int j = 0; j < per; ++j) {
+        const void *yin = (j == 0) ? pc : ybuf[(j - 1) & 1];
+        void *out = (j == per - 1) ? pa : ybuf[j & 1];
+        QW_TRY(torus_block_stages(c128, g, S, pc, yin, out, K - j * S, a64.data(), b64.data(), s),
+               "grid CTQW blocked stages kernel");
+      }
+      std::swap(pc, pa);
+    }
+    if (pc != psi) QW_TRY(copy_state(c128, p->n, pc, psi, s), "state copy kernel");
+    return readout_only(p, psi, ro, s);
+  }
   if (p->structure == kDense) {
+    GraphView gd = g;
+    gd.dense_partial = p->off_dpartial ? reinterpret_cast<double *>(work + p->off_dpartial) : nullptr;
     for (int64_t i = 0; i < steps; ++i) {
       const void *yin = psi;
       for (int k = K; k >= 1; --k) {
         void *yout = (k == 1) ? (K == 1 ? w0 : psi) : (((K - k) & 1) ? w1 : w0);
-        QW_TRY(dense_stage(c128, g, yin, psi, yout, beta[k - 1], s), "dense Horner stage kernel");
+        QW_TRY(dense_stage(c128, gd, yin, psi, yout, beta[k - 1], s), "dense Horner stage kernel");
         yin = yout;
       }
       if (K == 1) QW_TRY(copy_state(c128, p->n * p->columns, w0, psi, s), "state copy kernel");
@@ -573,6 +613,7 @@ int qw_plan_get_info(const qw_plan *p, qw_plan_info *info) {
   info->state_bytes = p->state_bytes;
   info->work_bytes = p->work_bytes;
   info->columns = p->columns;
+  info->block_depth = p->block_depth;
   info->state_len = p->kind == QW_COINED ? p->n_arcs : p->n * p->columns;
   if (p->structure == kDense) info->graph_bytes = p->off_dense + p->dense_bytes;
   return ok();

@@ -26,6 +26,7 @@ enum Structure : int32_t { kGeneral = 0, kCycle = 1, kTorus = 2, kHypercube = 3,
 constexpr int kDenseRows = 64;
 constexpr int kDenseK = 16;
 constexpr int kMaxDenseColumns = 128;
+constexpr int kMaxDenseSplits = 8;
 // Largest degree of the ELL (regular-graph) CTQW layout.
 constexpr int kMaxEllDegree = 64;
 
@@ -44,6 +45,7 @@ struct GraphView {
   int32_t columns = 1;              // dense: walks sharing H
   int32_t ld = 0;                   // dense: leading dimension of H (multiple of kDenseK)
   void *dense = nullptr;            // dense: H, rows padded to kDenseRows, FP64 or FP32
+  double *dense_partial = nullptr;  // dense: split-k partial products (workspace)
   const int32_t *rev = nullptr;     // n_arcs (coined general/small)
   const int32_t *tiles = nullptr;   // n_tiles+1 (coined general)
   const int32_t *perm = nullptr;    // n_arcs (coined structured: slot-major -> CSR position)
@@ -99,8 +101,18 @@ hipError_t vertex_prob(bool c128, const GraphView &g, const void *psi, const Rea
 // Dense H: expand the CSR into H (zero fill then scatter of -gamma and the
 // marked diagonal), and one Horner stage y_out = psi + (-i c) H y_in on MFMA.
 hipError_t dense_fill(bool c128, const GraphView &g, double gamma, size_t rows_pad, hipStream_t s);
+// Number of k ranges the dense stage splits into (1 = no split; partials then unused).
+int dense_splits(const GraphView &g);
 hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void *psi, void *out, double c,
                        hipStream_t s);
+
+// Grid CTQW with temporal blocking: depth S (stages per launch, dividing K;
+// 1 = not applicable), and S stages k = kfirst..kfirst-S+1 of one time step
+// from (P, Yin) to Out (Yin may equal P at the first stage of a step).
+// alpha/beta hold 64 entries (stage k at [k-1]).
+int torus_block_depth(bool c128, const GraphView &g, int K);
+hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *P, const void *Yin, void *Out,
+                              int kfirst, const double *alpha, const double *beta, hipStream_t s);
 
 // Sum of `count` partials -> *norm; sum over the marked list of p -> *pmarked.
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s);

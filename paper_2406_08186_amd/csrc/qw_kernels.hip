@@ -554,12 +554,87 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_struct(GraphView g, const T *__
   }
 }
 
-// CTQW small graphs: every stage of every step in one workgroup, vectors in LDS.
 struct Coefs {
   double alpha[64];
   double beta[64];
 };
 
+// ---- grid CTQW with temporal blocking ------------------------------------------
+// S consecutive Horner stages k = kfirst .. kfirst-S+1 of one time step in one
+// launch.  Workgroup = one TR x TC tile of the l1 x l2 torus plus a halo of S
+// cells on every side, held in LDS: psi (unchanged inside a step), and y in
+// two ping-pong buffers.  Stage s updates the cells at distance >= s+1 from
+// the tile edge, so after S stages exactly the core is valid and is written
+// out.  Local cell (i, j) is global ((r0+i) mod l1, (c0+j) mod l2), so the
+// periodic wrap is handled at load time and the stencil in LDS is plain.
+template <int TR, int TC, int S>
+struct TbShape {
+  static constexpr int H = TR + 2 * S;
+  static constexpr int W = TC + 2 * S;
+  static constexpr int CELLS = H * W;
+};
+
+template <typename T, int TR, int TC, int S>
+__global__ __launch_bounds__(512) void k_ctqw_torus_tb(GraphView g, const T *__restrict__ P,
+                                                       const T *__restrict__ Yin, T *__restrict__ Out,
+                                                       int kfirst, Coefs c) {
+  using Sh = TbShape<TR, TC, S>;
+  constexpr int H = Sh::H, W = Sh::W;
+  __shared__ T ps[Sh::CELLS];
+  __shared__ T ya[Sh::CELLS];
+  __shared__ T yb[Sh::CELLS];
+  const int l1 = g.dims[0], l2 = g.dims[1];
+  const int tiles_c = l2 / TC;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int r0 = (b / tiles_c) * TR - S, c0 = (b % tiles_c) * TC - S;
+  const bool y_is_p = (Yin == P);
+  for (int e = threadIdx.x; e < Sh::CELLS; e += blockDim.x) {
+    const int i = e / W, j = e - (e / W) * W;
+    int gr = r0 + i, gc = c0 + j;
+    gr += (gr < 0) ? l1 : 0;
+    gr -= (gr >= l1) ? l1 : 0;
+    gc += (gc < 0) ? l2 : 0;
+    gc -= (gc >= l2) ? l2 : 0;
+    const int v = gr * l2 + gc;
+    const T pv = P[v];
+    ps[e] = pv;
+    ya[e] = y_is_p ? pv : Yin[v];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+    const int k = kfirst - st;
+    const double alpha = c.alpha[k - 1], beta = c.beta[k - 1];
+    const T *src = (st & 1) ? yb : ya;
+    T *dst = (st & 1) ? ya : yb;
+    const int lo = st + 1, rh = H - 2 * lo, rw = W - 2 * lo;  // region [lo, H-lo) x [lo, W-lo)
+    for (int e = threadIdx.x; e < rh * rw; e += blockDim.x) {
+      const int i = lo + e / rw, j = lo + (e - (e / rw) * rw);
+      const int q = i * W + j;
+      double2 sum = cvt(src[q - W]);
+      sum = add(sum, cvt(src[q + W]));
+      sum = add(sum, cvt(src[q - 1]));
+      sum = add(sum, cvt(src[q + 1]));
+      int gr = r0 + i, gc = c0 + j;
+      gr += (gr < 0) ? l1 : 0;
+      gr -= (gr >= l1) ? l1 : 0;
+      gc += (gc < 0) ? l2 : 0;
+      gc -= (gc >= l2) ? l2 : 0;
+      const bool mk = marked(g.markbits, gr * l2 + gc);
+      const double2 yv = mk ? cvt(src[q]) : make_double2(0.0, 0.0);
+      dst[q] = pack<T>(horner_out(cvt(ps[q]), sum, yv, mk, alpha, beta));
+    }
+    __syncthreads();
+  }
+  const T *fin = (S & 1) ? yb : ya;
+  for (int e = threadIdx.x; e < TR * TC; e += blockDim.x) {
+    const int i = S + e / TC, j = S + (e - (e / TC) * TC);
+    const int gr = r0 + i, gc = c0 + j;  // core cells never wrap
+    Out[gr * l2 + gc] = fin[i * W + j];
+  }
+}
+
+// CTQW small graphs: every stage of every step in one workgroup, vectors in LDS.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_ctqw_small(GraphView g, T *psi, Coefs c, int K,
                                                      int64_t steps, Readout ro) {
@@ -794,13 +869,16 @@ template <> struct Mfma<float> {
 template <typename R, int NT>
 __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, int ld, int n, int c2,
                                                      const R *__restrict__ yin, const R *psi, R *out,
-                                                     double c) {
+                                                     double c, int ksplit, double *partial) {
   using M = Mfma<R>;
   constexpr int NC = NT * 16;
   __shared__ R hs[kDenseRows][kDenseK + 1];
   __shared__ R xs[kDenseK][NC];
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int row0 = blockIdx.x * kDenseRows;
+  const int rblocks = (n + kDenseRows - 1) / kDenseRows;
+  const int split = blockIdx.x / rblocks;            // k range of this workgroup
+  const int row0 = (blockIdx.x - split * rblocks) * kDenseRows;
+  const int kbeg = split * ksplit, kend = min(n, kbeg + ksplit);
   typename M::acc acc[NT];
   double wide[NT][4];
 #pragma unroll
@@ -810,7 +888,7 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
     for (int r = 0; r < 4; ++r) wide[t][r] = 0.0;
   }
   int chunk = 0;
-  for (int k0 = 0; k0 < n; k0 += kDenseK, ++chunk) {
+  for (int k0 = kbeg; k0 < kend; k0 += kDenseK, ++chunk) {
     for (int e = threadIdx.x; e < kDenseRows * kDenseK; e += blockDim.x) {
       const int i = e / kDenseK, j = e % kDenseK;
       hs[i][j] = H[static_cast<int64_t>(row0 + i) * ld + k0 + j];
@@ -818,7 +896,7 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
     for (int e = threadIdx.x; e < kDenseK * NC; e += blockDim.x) {
       const int i = e / NC, j = e % NC;
       R v = R(0);
-      if (k0 + i < n && j < c2) v = yin[static_cast<int64_t>(k0 + i) * c2 + j];
+      if (k0 + i < kend && j < c2) v = yin[static_cast<int64_t>(k0 + i) * c2 + j];
       xs[i][j] = v;
     }
     __syncthreads();
@@ -846,6 +924,10 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
       const double zp = __shfl_xor(z, 1, 64);
       const int row = row0 + wave * 16 + M::row(l, r);
       const int col = t * 16 + (l & 15);
+      if (partial) {  // split k: hand the raw product to the reduction kernel
+        if (row < n && col < c2) partial[(static_cast<int64_t>(split) * n + row) * c2 + col] = z;
+        continue;
+      }
       if (row < n && col < c2) {
         const int64_t idx = static_cast<int64_t>(row) * c2 + col;
         const double ps = static_cast<double>(psi[idx]);
@@ -853,6 +935,103 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
       }
     }
   }
+}
+
+// Few walks (NT = 1, 2: HBM-bound on H): 16 rows per workgroup, so the grid
+// has n/16 workgroups, and the 4 wavefronts take interleaved k-chunks of the
+// same 16 rows; their accumulators are summed in LDS in wave order (fixed).
+// Every operand comes straight from global memory: the A fragment of an MFMA
+// is 16 rows x 4 consecutive k of H (rows padded with zeros up to ld), the B
+// fragment 4 rows x 16 real columns of Y (small and cache-resident; guarded
+// past n and past 2C).  No LDS is shared between waves inside the k loop, so
+// waves with different trip counts never wait for each other.
+template <typename R, int NT>
+__global__ __launch_bounds__(256) void k_dense_stage_sk(const R *__restrict__ H, int ld, int n, int c2,
+                                                        const R *__restrict__ yin, const R *psi, R *out,
+                                                        double c) {
+  using M = Mfma<R>;
+  constexpr int KC = 16;  // k per wave per chunk
+  __shared__ double red[4][NT][4][64];
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int row0 = blockIdx.x * 16;
+  typename M::acc acc[NT];
+  double wide[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = M::zero();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) wide[t][r] = 0.0;
+  }
+  const R *hrow = H + static_cast<int64_t>(row0 + (l & 15)) * ld;
+  int chunk = 0;
+  for (int kb = wave * KC; kb < n; kb += 4 * KC, ++chunk) {
+    R a[KC / 4];
+    R b[KC / 4][NT];
+#pragma unroll
+    for (int q = 0; q < KC / 4; ++q) {
+      const int k = kb + 4 * q + (l >> 4);
+      a[q] = hrow[k];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int j = t * 16 + (l & 15);
+        b[q][t] = (k < n && j < c2) ? yin[static_cast<int64_t>(k) * c2 + j] : R(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KC / 4; ++q) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = M::mma(a[q], b[q][t], acc[t]);
+    }
+    if (sizeof(R) == 4 && (chunk & 3) == 3) {  // FP32 products: fold into FP64 every 256 k of this wave
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wide[t][r] += static_cast<double>(acc[t][r]);
+        acc[t] = M::zero();
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wave][t][r][l] = wide[t][r] + static_cast<double>(acc[t][r]);
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double z = ((red[0][t][r][l] + red[1][t][r][l]) + red[2][t][r][l]) + red[3][t][r][l];
+        const double zp = __shfl_xor(z, 1, 64);
+        const int row = row0 + M::row(l, r);
+        const int col = t * 16 + (l & 15);
+        if (row < n && col < c2) {
+          const int64_t idx = static_cast<int64_t>(row) * c2 + col;
+          const double ps = static_cast<double>(psi[idx]);
+          out[idx] = static_cast<R>((col & 1) ? ps - c * zp : ps + c * zp);
+        }
+      }
+    }
+  }
+}
+
+// Split-k epilogue: z = sum of the partial products in split order (fixed),
+// then y_out = psi + c (b - i a) for z = a + i b.  One thread per complex entry.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_dense_reduce(const double *__restrict__ partial, int splits, int n,
+                                                         int c2, const R *psi, R *out, double c) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;  // complex index
+  const int64_t total = static_cast<int64_t>(n) * (c2 / 2);
+  if (e >= total) return;
+  double a = 0.0, b = 0.0;
+  for (int sp = 0; sp < splits; ++sp) {
+    const double *ps = partial + static_cast<int64_t>(sp) * n * c2 + 2 * e;
+    a += ps[0];
+    b += ps[1];
+  }
+  const double pr = static_cast<double>(psi[2 * e]), pi = static_cast<double>(psi[2 * e + 1]);
+  out[2 * e] = static_cast<R>(pr + c * b);
+  out[2 * e + 1] = static_cast<R>(pi - c * a);
 }
 
 template <typename R>
@@ -873,17 +1052,35 @@ __global__ __launch_bounds__(kBlock) void k_dense_scatter(GraphView g, R *H, dou
 
 template <typename R, int NT>
 void launch_dense(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
-  const dim3 grid((g.n + kDenseRows - 1) / kDenseRows);
+  const int rblocks = (g.n + kDenseRows - 1) / kDenseRows;
+  const int splits = dense_splits(g);
+  const int ksplit = ((g.n + splits - 1) / splits + kDenseK - 1) / kDenseK * kDenseK;
+  const int used = (g.n + ksplit - 1) / ksplit;  // splits that own at least one k
+  const dim3 grid(rblocks * used);
+  double *partial = used > 1 ? g.dense_partial : nullptr;
   hipLaunchKernelGGL((k_dense_stage<R, NT>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld, g.n,
                      2 * g.columns, static_cast<const R *>(y), static_cast<const R *>(psi), static_cast<R *>(out),
-                     c);
+                     c, ksplit, partial);
+  if (partial) {
+    const int64_t total = static_cast<int64_t>(g.n) * g.columns;
+    hipLaunchKernelGGL(k_dense_reduce<R>, dim3(blocks_for(total, kBlock)), dim3(kBlock), 0, s, partial, used,
+                       g.n, 2 * g.columns, static_cast<const R *>(psi), static_cast<R *>(out), c);
+  }
+}
+
+template <typename R, int NT>
+void launch_dense_sk(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
+  const dim3 grid((g.n + 15) / 16);
+  hipLaunchKernelGGL((k_dense_stage_sk<R, NT>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld,
+                     g.n, 2 * g.columns, static_cast<const R *>(y), static_cast<const R *>(psi),
+                     static_cast<R *>(out), c);
 }
 
 template <typename R>
 void launch_dense_nt(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
   const int c2 = 2 * g.columns;
-  if (c2 <= 16) launch_dense<R, 1>(g, y, psi, out, c, s);
-  else if (c2 <= 32) launch_dense<R, 2>(g, y, psi, out, c, s);
+  if (c2 <= 16) launch_dense_sk<R, 1>(g, y, psi, out, c, s);
+  else if (c2 <= 32) launch_dense_sk<R, 2>(g, y, psi, out, c, s);
   else if (c2 <= 64) launch_dense<R, 4>(g, y, psi, out, c, s);
   else if (c2 <= 128) launch_dense<R, 8>(g, y, psi, out, c, s);
   else launch_dense<R, 16>(g, y, psi, out, c, s);
@@ -1135,6 +1332,15 @@ hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const Ti
   return hipGetLastError();
 }
 
+int dense_splits(const GraphView &g) {
+  if (2 * g.columns <= 32) return 1;  // the 16-row kernel fills the device itself
+  const int rblocks = (g.n + kDenseRows - 1) / kDenseRows;
+  int sp = (512 + rblocks - 1) / rblocks;
+  sp = std::min(sp, kMaxDenseSplits);
+  sp = std::min(sp, std::max(1, g.n / (4 * kDenseK)));
+  return std::max(sp, 1);
+}
+
 hipError_t dense_fill(bool c128, const GraphView &g, double gamma, size_t rows_pad, hipStream_t s) {
   const int64_t total = static_cast<int64_t>(rows_pad) * g.ld;
   const dim3 zgrid(static_cast<unsigned>(std::min<int64_t>((total + kBlock - 1) / kBlock, 8192)));
@@ -1155,6 +1361,50 @@ hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void 
   if (c128) launch_dense_nt<double>(g, y, psi, out, c, s);
   else launch_dense_nt<float>(g, y, psi, out, c, s);
   return hipGetLastError();
+}
+
+int torus_block_depth(bool c128, const GraphView &g, int K) {
+  if (g.structure != kTorus) return 1;
+  const int tr = c128 ? 32 : 32, tc = c128 ? 32 : 64;
+  const int l1 = g.dims[0], l2 = g.dims[1];
+  if (l1 % tr || l2 % tc || l1 <= 5 || l2 <= 5) return 1;
+  for (int S : {5, 4, 3, 2})
+    if (K % S == 0) return S;
+  return 1;
+}
+
+template <typename T, int TR, int TC, int S>
+hipError_t launch_tb(const GraphView &g, const void *P, const void *Yin, void *Out, int kfirst, const Coefs &c,
+                     hipStream_t s) {
+  const dim3 grid((g.dims[0] / TR) * (g.dims[1] / TC));
+  hipLaunchKernelGGL((k_ctqw_torus_tb<T, TR, TC, S>), grid, dim3(512), 0, s, g, static_cast<const T *>(P),
+                     static_cast<const T *>(Yin), static_cast<T *>(Out), kfirst, c);
+  return hipGetLastError();
+}
+
+hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *P, const void *Yin, void *Out,
+                              int kfirst, const double *alpha, const double *beta, hipStream_t s) {
+  Coefs c;
+  for (int k = 0; k < 64; ++k) {
+    c.alpha[k] = alpha[k];
+    c.beta[k] = beta[k];
+  }
+  if (c128) {
+    switch (S) {
+      case 5: return launch_tb<double2, 32, 32, 5>(g, P, Yin, Out, kfirst, c, s);
+      case 4: return launch_tb<double2, 32, 32, 4>(g, P, Yin, Out, kfirst, c, s);
+      case 3: return launch_tb<double2, 32, 32, 3>(g, P, Yin, Out, kfirst, c, s);
+      case 2: return launch_tb<double2, 32, 32, 2>(g, P, Yin, Out, kfirst, c, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (S) {
+    case 5: return launch_tb<float2, 32, 64, 5>(g, P, Yin, Out, kfirst, c, s);
+    case 4: return launch_tb<float2, 32, 64, 4>(g, P, Yin, Out, kfirst, c, s);
+    case 3: return launch_tb<float2, 32, 64, 3>(g, P, Yin, Out, kfirst, c, s);
+    case 2: return launch_tb<float2, 32, 64, 2>(g, P, Yin, Out, kfirst, c, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s) {

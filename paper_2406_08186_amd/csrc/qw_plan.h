@@ -25,7 +25,7 @@ struct qw_plan {
   // and where H sits in the device graph buffer (after the uploaded image)
   int32_t columns = 1;
   int32_t ld = 0;
-  size_t rows_pad = 0, off_dense = 0, dense_bytes = 0;
+  size_t rows_pad = 0, off_dense = 0, dense_bytes = 0, off_dpartial = 0;
   // host image of the device graph buffer, and section offsets into it
   std::vector<unsigned char> image;
   size_t off_rp = 0, off_col = 0, off_rev = 0, off_tiles = 0, off_perm = 0, off_bits = 0, off_mlist = 0;
@@ -34,7 +34,8 @@ struct qw_plan {
   unsigned char *d_graph = nullptr;
   qwk::GraphView view;
   // workspace layout
-  size_t state_bytes = 0, off_w1 = 0, off_pscratch = 0, off_partials = 0, work_bytes = 0;
+  size_t state_bytes = 0, off_w1 = 0, off_w2 = 0, off_pscratch = 0, off_partials = 0, work_bytes = 0;
+  int32_t block_depth = 1;  // grid CTQW: Horner stages per launch (temporal blocking)
 };
 
 namespace qwk {

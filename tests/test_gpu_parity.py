@@ -173,6 +173,33 @@ def test_ctqw_orders(K, layout):
     assert np.abs(got - ref).max() < C128_TOL
 
 
+@pytest.mark.parametrize("l1,l2,K,dtype,depth", [
+    (64, 64, 20, "c64", 5), (64, 128, 12, "c64", 4), (96, 64, 9, "c64", 3), (32, 64, 14, "c64", 2),
+    (64, 64, 7, "c64", 1), (96, 32, 20, "c128", 5), (32, 64, 8, "c128", 4), (64, 96, 6, "c128", 3),
+    (32, 32, 10, "c128", 5),
+])
+def test_ctqw_torus_blocked(l1, l2, K, dtype, depth):
+    """Temporal blocking (S stages per launch in LDS), tiles wrapping small tori,
+    marked vertices on tile edges and corners."""
+    from paper_2406_08186_amd.walk import Plan
+    g = I.torus(l1, l2)
+    marked = [0, 31, 32 * l2 + 63 % l2, g.n - 1]
+    marked = sorted(set(m for m in marked if m < g.n))
+    psi0 = I.random_state(g.n, seed=l1 + l2 + K)
+    ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 7, gamma=0.25, dt=0.07, K=K, marked=marked)
+    pl = Plan(g, "ctqw", dtype=dtype, gamma=0.25, dt=0.07, taylor_order=K, marked=marked, layout="structured")
+    assert pl.structure == "torus" and pl.info.block_depth == depth
+    psi = pl.state(psi0)
+    p, norm, pm = pl.evolve(psi, 7, readout=True)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy().astype(np.complex128)
+    if dtype == "c128":
+        assert np.abs(got - ref).max() < C128_TOL
+    else:
+        assert np.linalg.norm(got - ref) < 1e-5
+    assert abs(float(pm) - (np.abs(ref[marked]) ** 2).sum()) < (1e-12 if dtype == "c128" else 1e-6)
+
+
 def test_zero_steps_is_readout_only():
     g = GRAPHS["rr"]
     psi0 = I.random_state(g.n_arcs, seed=3)
