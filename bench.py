@@ -32,6 +32,10 @@ DT = 0.1
 K_ORDER = 20
 STEPS_PER_PASS = 1000
 METRIC = "arc-steps/s (c64 batched vs c128 plain, L2 err<=1e-4); p50/p99 latency"
+# HBM bytes per launch of the grid kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (scaled by a 256 MiB copy: x2.00 / x1.00); profiles/ctqw_torus1024_blocked.md.  Valid
+# only for the kernel version named here; None for any other.
+MEASURED_TRAFFIC = {"k_ctqw_torus_tb<float2,32,64,5>": (7834.8 * 2 + 8192.0) * 1024}
 
 
 def parse():
@@ -63,6 +67,9 @@ def parse():
     ap.add_argument("--dense-n", type=int, default=15000)
     ap.add_argument("--dense-columns", default="1,8,32,128")
     ap.add_argument("--dense-dtype", default="c128")
+    ap.add_argument("--hypercube-steps", type=int, default=0,
+                    help="override the step count (profiling runs); 0 = ceil((pi/2) sqrt(N ln N))")
+    ap.add_argument("--hypercube-dtypes", default="c64,c128")
     return ap.parse_args()
 
 
@@ -207,6 +214,8 @@ def main():
 
     r64, r128 = res["c64"], res["c128"]
     achieved = r64["bytes_per_launch"] / (r64["launch_ms"] * 1e-3) / 1e9
+    kname = (f"k_ctqw_torus_tb<float2,32,64,{r64['depth']}>" if r64["depth"] > 1
+             else "k_ctqw_struct<float2,TORUS>")
     line = {
         "metric": METRIC,
         "value": rate(r64),
@@ -236,10 +245,10 @@ def main():
         "l2_c64_vs_c128": l2_64_128,
         "norm_drift_c64": abs(r64["norm"] - 1.0),
         "roofline": {"bound": "hbm",
-                     "kernel": (f"k_ctqw_torus_tb<float2,32,64,{r64['depth']}> ({r64['depth']} Horner stages per launch)"
-                                if r64["depth"] > 1 else "k_ctqw_struct<float2,TORUS> (one Horner stage)"),
+                     "kernel": kname + (f" ({r64['depth']} Horner stages per launch)" if r64["depth"] > 1
+                                        else " (one Horner stage)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(kname),
                      "bytes_per_launch": r64["bytes_per_launch"],
                      "launch_ms": r64["launch_ms"]},
     }
@@ -273,8 +282,11 @@ def run_batch(args):
     from paper_2406_08186_amd import inputs as I
     specs = I.batch_regular_specs(args.batch_walks, seed=args.batch_seed)
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(min(args.workers, os.cpu_count() or 1)) as pool:
-        csrs = pool.map(_gen_regular, specs, chunksize=4)
+    if args.workers <= 1:  # serial (e.g. under a profiler, which should not see forked workers)
+        csrs = [_gen_regular(sp) for sp in specs]
+    else:
+        with mp.get_context("fork").Pool(min(args.workers, os.cpu_count() or 1)) as pool:
+            csrs = pool.map(_gen_regular, specs, chunksize=4)
     gen_s = time.perf_counter() - t0
     print(f"[batch] generated {len(specs)} graphs in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
@@ -297,11 +309,13 @@ def run_batch(args):
                     taylor_order=K, marked=[sp["marked"]], upload=False)
 
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(args.workers) as ex:
+    with ThreadPoolExecutor(max(1, args.workers)) as ex:
         plans = list(ex.map(mk, range(len(specs))))
     plan_s = time.perf_counter() - t0
     total_rows = sum(g.n for g in graphs)
-    max_tiles = total_rows // 256 + 16 * len(graphs) + 64
+    # tiles at 256 rows each, plus the XCD padding (8 lists, each at most the mean plus the
+    # largest walk's tiles under longest-first placement)
+    max_tiles = total_rows // 256 + len(graphs) + 8 * (max(g.n for g in graphs) // 256 + 1) + 64
     batch = Batch(capacity=len(plans), max_tiles=max_tiles, dtype="c64")
     states, hists = [], []
     for i, pl in enumerate(plans):
@@ -394,8 +408,11 @@ def run_serve(args):
     import numpy as np
     t0 = time.perf_counter()
     tasks = [(i, 1000 + i, args.serve_max_arcs, args.serve_max_steps) for i in range(args.serve_jobs)]
-    with mp.get_context("fork").Pool(min(args.workers, os.cpu_count() or 1)) as pool:
-        base_jobs = pool.map(_gen_job, tasks)
+    if args.workers <= 1:
+        base_jobs = [_gen_job(t) for t in tasks]
+    else:
+        with mp.get_context("fork").Pool(min(args.workers, os.cpu_count() or 1)) as pool:
+            base_jobs = pool.map(_gen_job, tasks)
     print(f"[serve] generated {len(base_jobs)} jobs in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     import torch
@@ -520,12 +537,12 @@ def run_hypercube(args):
     from paper_2406_08186_amd.walk import Plan
     dim = 20
     n = 1 << dim
-    steps = math.ceil(math.pi / 2 * math.sqrt(n * math.log(n)))
+    steps = args.hypercube_steps or math.ceil(math.pi / 2 * math.sqrt(n * math.log(n)))
     g = I.hypercube(dim)
     o, _, _ = cf.hypercube_search_reduced(dim, steps)
     ref = cf.hypercube_search_state(dim, steps, g.row_ptr, g.col)
     res = {}
-    for dtype in ("c64", "c128"):
+    for dtype in args.hypercube_dtypes.split(","):
         pl = Plan(g, "coined", dtype=dtype, marked=[0])
         psi0 = np.full(g.n_arcs, 1 / math.sqrt(g.n_arcs), dtype=np.complex128)
         psi = pl.state(psi0)

@@ -43,7 +43,13 @@ def build(verbose: bool = False) -> str:
         cmd = [cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.PIPE)
+        res = subprocess.run(cmd, stderr=subprocess.PIPE, text=True)
+        noise = "is not a recognized feature for this target"
+        msgs = "\n".join(line for line in res.stderr.splitlines() if noise not in line)
+        if res.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{msgs}")
+        if verbose and msgs.strip():
+            print(msgs, flush=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]

@@ -506,6 +506,10 @@ int qw_batch_autotune(qw_batch *b, int32_t reps, void *stream, int32_t *rows_per
       b->rows_per_tile = r;
       b->xcd_aware = xi != 0;
       st = build_table(b);
+      if (st == QW_ENOMEM) {  // this schedule's tile table does not fit max_tiles: skip it
+        st = QW_OK;
+        continue;
+      }
       if (st == QW_OK) st = upload_tables(b, s);
       if (st != QW_OK) break;
       hipError_t e = launch_one(b, s);
@@ -532,6 +536,7 @@ int qw_batch_autotune(qw_batch *b, int32_t reps, void *stream, int32_t *rows_per
   (void)hipEventDestroy(e1);
   if (st != QW_OK) return st;
   if (st2 != QW_OK) return st2;
+  if (best > 1e299) return set_error(QW_ENOMEM, "no candidate schedule fits max_tiles");
   b->rows_per_tile = best_r;
   b->xcd_aware = best_x != 0;
   st = build_table(b);

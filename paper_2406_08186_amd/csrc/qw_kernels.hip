@@ -25,6 +25,8 @@ namespace {
 
 constexpr double kInvSqrt2 = 0.70710678118654752440;
 
+inline int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
+
 // ---- storage <-> FP64 -------------------------------------------------------
 __device__ __forceinline__ double2 ld(const float2 *p, int64_t i) {
   float2 v = p[i];
@@ -583,11 +585,16 @@ __global__ __launch_bounds__(512) void k_ctqw_torus_tb(GraphView g, const T *__r
   __shared__ T ps[Sh::CELLS];
   __shared__ T ya[Sh::CELLS];
   __shared__ T yb[Sh::CELLS];
+  __shared__ unsigned char mk_cell[Sh::CELLS];  // marked flag of each local cell
+  __shared__ int any_marked;
   const int l1 = g.dims[0], l2 = g.dims[1];
   const int tiles_c = l2 / TC;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int r0 = (b / tiles_c) * TR - S, c0 = (b % tiles_c) * TC - S;
   const bool y_is_p = (Yin == P);
+  if (threadIdx.x == 0) any_marked = 0;
+  __syncthreads();
+  int mine = 0;
   for (int e = threadIdx.x; e < Sh::CELLS; e += blockDim.x) {
     const int i = e / W, j = e - (e / W) * W;
     int gr = r0 + i, gc = c0 + j;
@@ -599,8 +606,13 @@ __global__ __launch_bounds__(512) void k_ctqw_torus_tb(GraphView g, const T *__r
     const T pv = P[v];
     ps[e] = pv;
     ya[e] = y_is_p ? pv : Yin[v];
+    const bool m = marked(g.markbits, v);
+    mk_cell[e] = m;
+    mine |= m;
   }
+  if (mine) atomicOr(&any_marked, 1);
   __syncthreads();
+  const bool tile_marked = any_marked != 0;
 #pragma unroll
   for (int st = 0; st < S; ++st) {
     const int k = kfirst - st;
@@ -615,12 +627,7 @@ __global__ __launch_bounds__(512) void k_ctqw_torus_tb(GraphView g, const T *__r
       sum = add(sum, cvt(src[q + W]));
       sum = add(sum, cvt(src[q - 1]));
       sum = add(sum, cvt(src[q + 1]));
-      int gr = r0 + i, gc = c0 + j;
-      gr += (gr < 0) ? l1 : 0;
-      gr -= (gr >= l1) ? l1 : 0;
-      gc += (gc < 0) ? l2 : 0;
-      gc -= (gc >= l2) ? l2 : 0;
-      const bool mk = marked(g.markbits, gr * l2 + gc);
+      const bool mk = tile_marked && mk_cell[q];
       const double2 yv = mk ? cvt(src[q]) : make_double2(0.0, 0.0);
       dst[q] = pack<T>(horner_out(cvt(ps[q]), sum, yv, mk, alpha, beta));
     }
@@ -1086,7 +1093,6 @@ void launch_dense_nt(const GraphView &g, const void *y, const void *psi, void *o
   else launch_dense<R, 16>(g, y, psi, out, c, s);
 }
 
-inline int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
 
 template <typename T> hipError_t launch_coined_small(const GraphView &g, void *psi, int hadamard,
                                                      int64_t steps, const Readout &ro, hipStream_t s) {
