@@ -35,13 +35,15 @@ METRIC = "arc-steps/s (c64 batched vs c128 plain, L2 err<=1e-4); p50/p99 latency
 # HBM bytes per launch of the grid kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (scaled by a 256 MiB copy: x2.00 / x1.00); profiles/ctqw_torus1024_blocked.md.  Valid
 # only for the kernel version named here; None for any other.
-MEASURED_TRAFFIC = {"k_ctqw_torus_tb<float2,32,64,5>": (7834.8 * 2 + 8192.0) * 1024}
+MEASURED_TRAFFIC = {"k_ctqw_torus_tb<float2,32,64,5>": (7834.2 * 2 + 8192.0) * 1024}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--grid-side", type=int, default=L_SIDE,
+                    help="side of the periodic grid (default 1024; 4096 gives an HBM-resident variant)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -128,17 +130,18 @@ def cpu_baseline(g, v0, seconds):
     import oracle
     from paper_2406_08186_amd import inputs as I
     psi = I.ket_vertex(g.n, v0)
+    psi = oracle.ctqw_evolve(g.row_ptr, g.col, psi, 2, gamma=GAMMA, dt=DT, K=K_ORDER)  # warm-up
+    n_more, chunk = 0, 25
     t0 = time.perf_counter()
-    psi = oracle.ctqw_evolve(g.row_ptr, g.col, psi, 1, gamma=GAMMA, dt=DT, K=K_ORDER)
-    t1 = time.perf_counter() - t0
-    n_more = max(1, int(seconds / max(t1, 1e-6)) - 1)
-    t0 = time.perf_counter()
-    psi = oracle.ctqw_evolve(g.row_ptr, g.col, psi, n_more, gamma=GAMMA, dt=DT, K=K_ORDER)
+    while time.perf_counter() - t0 < seconds:
+        psi = oracle.ctqw_evolve(g.row_ptr, g.col, psi, chunk, gamma=GAMMA, dt=DT, K=K_ORDER)
+        n_more += chunk
     el = time.perf_counter() - t0
     return {"value": g.n_arcs * n_more / el, "unit": "arc-steps/s", "cores": oracle.max_threads(),
             "kind": "oracle",
-            "sample": f"{n_more} of the {STEPS_PER_PASS} time steps of one pass on the same "
-                      f"{L_SIDE}x{L_SIDE} grid (FP64 power-form Taylor, K={K_ORDER})",
+            "sample": f"{n_more} time steps (dt={DT}) of the same walk from the same start vertex on the "
+                      f"same {g.name} grid, run as oracle calls of {chunk} steps for about {seconds:g} s "
+                      f"(FP64 power-form Taylor, K={K_ORDER})",
             "seconds": el}
 
 
@@ -175,8 +178,9 @@ def main():
     from paper_2406_08186_amd import inputs as I
     from paper_2406_08186_amd.walk import Plan
 
-    g = I.torus(L_SIDE, L_SIDE)
-    v0 = (L_SIDE // 2) * L_SIDE + L_SIDE // 2
+    side = args.grid_side
+    g = I.torus(side, side)
+    v0 = (side // 2) * side + side // 2
     psi0 = I.ket_vertex(g.n, v0)
     res = {}
     for dtype in dtypes:
@@ -197,7 +201,7 @@ def main():
                         depth=depth)
         del psi
     t_final = res[dtypes[0]]["total_steps"] * DT
-    ref1 = cf.cycle_ctqw(L_SIDE, GAMMA, t_final, L_SIDE // 2)
+    ref1 = cf.cycle_ctqw(side, GAMMA, t_final, side // 2)
     ref = np.outer(ref1, ref1).reshape(-1)
     for r in res.values():
         r["l2"] = float(np.linalg.norm(r["state"] - ref))
@@ -216,6 +220,10 @@ def main():
     achieved = r64["bytes_per_launch"] / (r64["launch_ms"] * 1e-3) / 1e9
     kname = (f"k_ctqw_torus_tb<float2,32,64,{r64['depth']}>" if r64["depth"] > 1
              else "k_ctqw_struct<float2,TORUS>")
+    # counters were taken on the 1024 x 1024 grid; per launch they scale with the rows
+    traffic = MEASURED_TRAFFIC.get(kname)
+    if traffic is not None:
+        traffic *= g.n / (L_SIDE * L_SIDE)
     line = {
         "metric": METRIC,
         "value": rate(r64),
@@ -229,7 +237,8 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "ctqw_torus_1024x1024_gamma0.25_K20_dt0.1_1000steps",
+        "config": {"workload": f"ctqw_torus_{side}x{side}_gamma0.25_K20_dt0.1_{spp}steps"
+                               + ("" if side == L_SIDE else "_supplementary"),
                    "n": g.n, "arcs": g.n_arcs, "gamma": GAMMA, "dt": DT, "taylor_order": K_ORDER,
                    "steps_per_pass": spp, "start_vertex": v0,
                    "path": r64["structure"], "stages_per_launch": r64["depth"], "parallelism": "single-gpu"},
@@ -248,9 +257,14 @@ def main():
                      "kernel": kname + (f" ({r64['depth']} Horner stages per launch)" if r64["depth"] > 1
                                         else " (one Horner stage)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get(kname),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": r64["bytes_per_launch"],
-                     "launch_ms": r64["launch_ms"]},
+                     "launch_ms": r64["launch_ms"],
+                     "dram_gbs": None if traffic is None else traffic / (r64["launch_ms"] * 1e-3) / 1e9,
+                     "note": ("achieved counts the per-stage model bytes (read y, read psi, write y per "
+                              "row and stage) of every stage the launch runs; with several stages per "
+                              "launch on an LDS tile the DRAM traffic is a fraction of that, so frac can "
+                              "pass 1; dram_gbs is the measured traffic over the launch time")},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, v0, args.cpu_seconds)

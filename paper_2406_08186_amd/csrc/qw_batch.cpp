@@ -59,6 +59,8 @@ struct qw_batch {
   std::vector<TileEntry> table;
   int32_t n_tiles = 0;
   uint64_t L_host = 0;
+  std::vector<char> needs_perm_in;  // structured coined slots staged since the last commit
+  bool has_struct = false;          // any structured coined slot in the table (two kernels per unit)
   // device binding
   unsigned char *d_buf = nullptr;
   size_t off_ctl = 0, off_slots = 0, off_coefs = 0, off_tiles = 0, off_ntiles = 0, bytes = 0;
@@ -145,12 +147,27 @@ int build_table(qw_batch *b) {
       for (int64_t r = 0; r < p->n; r += R)
         it.tiles.push_back({s, static_cast<int32_t>(r), static_cast<int32_t>(std::min<int64_t>(p->n, r + R)), 0});
       it.load = p->n_arcs + 3 * p->n;
+    } else if (w.structure != kGeneral) {
+      const int R = b->rows_per_tile;
+      for (int64_t v = 0; v < p->n; v += R)
+        it.tiles.push_back({s, static_cast<int32_t>(v), static_cast<int32_t>(std::min<int64_t>(p->n, v + R)), 0});
+      it.load = 2 * p->n_arcs;
     } else {
       const std::vector<int32_t> t = plan_tiles(p);
       for (int32_t i = 0; i + 1 < static_cast<int32_t>(t.size()); ++i) it.tiles.push_back({s, t[i], t[i + 1], 0});
       it.load = 2 * p->n_arcs;
     }
     items.push_back(std::move(it));
+  }
+  bool has_struct = false;
+  for (int s = 0; s < b->capacity; ++s)
+    has_struct |= b->slots[s].kind == QW_COINED && b->slots[s].structure != kGeneral;
+  if (has_struct != b->has_struct) {
+    b->has_struct = has_struct;
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);  // the launch unit changed: re-captured at the next run
+      b->exec = nullptr;
+    }
   }
   std::vector<TileEntry> table;
   if (b->xcd_aware) {
@@ -219,6 +236,11 @@ int set_probe(qw_batch *b, unsigned int on, hipStream_t s) {
 }
 
 hipError_t launch_one(qw_batch *b, hipStream_t s) {
+  if (b->has_struct) {
+    const hipError_t e =
+        batch_struct(b->dtype == QW_C128, b->ctl(), b->dslots(), b->dtiles(), b->dntiles(), b->grid, s);
+    if (e != hipSuccess) return e;
+  }
   return batch_stage(b->dtype == QW_C128, b->ctl(), b->dslots(), b->dtiles(), b->dntiles(), b->grid, s);
 }
 
@@ -247,6 +269,7 @@ int qw_batch_create(int32_t capacity, int32_t max_tiles, int32_t dtype, qw_batch
     for (auto &w : b->slots) w.kind = -1;
     b->plans.assign(capacity, nullptr);
     b->steps.assign(capacity, 0);
+    b->needs_perm_in.assign(capacity, 0);
     b->coefs.assign(static_cast<size_t>(capacity) * kCoefStride, 0.0);
     b->grid = std::min(kMaxGrid, b->max_tiles);
     layout(b);
@@ -318,9 +341,12 @@ int qw_batch_set_slot(qw_batch *b, int32_t slot, const qw_plan *p, void *d_psi, 
   if (!p || !d_psi || !d_work) return set_error(QW_EINVAL, "null plan, state or workspace");
   if (!p->d_graph) return set_error(QW_ESTATE, "plan not uploaded");
   if (p->dtype != b->dtype) return set_error(QW_EINVAL, "plan dtype differs from the batch's");
-  if (!(p->structure == kGeneral || (p->kind == QW_CTQW && p->structure == kEll)))
+  const bool coined_struct = p->kind == QW_COINED &&
+                             (p->structure == kCycle || p->structure == kTorus || p->structure == kHypercube);
+  if (!(p->structure == kGeneral || (p->kind == QW_CTQW && p->structure == kEll) || coined_struct))
     return set_error(QW_EUNSUPPORTED,
-                     "batched walks need plans on the general CSR path (layout QW_LAYOUT_CSR) or CTQW plans on the ELL path");
+                     "batched walks need CSR plans, CTQW plans on the ELL path, or coined plans on a "
+                     "cycle, torus or hypercube path");
   if (work_bytes < p->work_bytes) return set_error(QW_ENOMEM, "workspace too small for the plan");
   if (steps < 0) return set_error(QW_EINVAL, "negative steps");
   if (p->n == 0) return set_error(QW_EINVAL, "empty graph");
@@ -335,6 +361,10 @@ int qw_batch_set_slot(qw_batch *b, int32_t slot, const qw_plan *p, void *d_psi, 
   w.col = p->view.col;
   w.ell_d = p->structure == kEll ? p->view.ell_d : 0;
   w.pad0 = 0;
+  w.structure = coined_struct ? p->structure : kGeneral;
+  w.sdims[0] = p->dims[0];
+  w.sdims[1] = p->dims[1];
+  w.pad1 = 0;
   w.rev = p->view.rev;
   w.markbits = p->view.markbits;
   w.psi = d_psi;
@@ -364,6 +394,7 @@ int qw_batch_set_slot(qw_batch *b, int32_t slot, const qw_plan *p, void *d_psi, 
   b->slots[slot] = w;
   b->plans[slot] = p;
   b->steps[slot] = steps;
+  b->needs_perm_in[slot] = coined_struct;
   return clear_error();
 }
 
@@ -374,6 +405,7 @@ int qw_batch_clear_slot(qw_batch *b, int32_t slot) {
   b->slots[slot].kind = -1;
   b->plans[slot] = nullptr;
   b->steps[slot] = 0;
+  b->needs_perm_in[slot] = 0;
   return clear_error();
 }
 
@@ -382,7 +414,15 @@ int qw_batch_commit(qw_batch *b, void *stream) {
   if (st != QW_OK) return st;
   st = build_table(b);
   if (st != QW_OK) return st;
-  st = upload_tables(b, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < b->capacity; ++i) {
+    if (!b->needs_perm_in[i]) continue;
+    const qw_plan *p = b->plans[i];
+    QW_TRY(coined_perm_in(b->dtype == QW_C128, p->view, b->slots[i].psi, b->slots[i].w0, s),
+           "layout permutation kernel");
+    b->needs_perm_in[i] = 0;
+  }
+  st = upload_tables(b, s);
   return st == QW_OK ? clear_error() : st;
 }
 
@@ -448,6 +488,12 @@ int qw_batch_readout(qw_batch *b, int32_t slot, double *d_p, double *d_norm, dou
   const WalkSlot &w = b->slots[slot];
   const qw_plan *p = b->plans[slot];
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (w.kind == QW_COINED && w.structure != kGeneral) {
+    // slot-major state: units alternate w0 -> w1 -> w0, so it ends in w1 after an odd count
+    const void *fin = (b->steps[slot] & 1) ? w.w1 : w.w0;
+    st = plan_struct_out(p, fin, w.psi, static_cast<unsigned char *>(w.w0), d_p, d_norm, d_pmarked, s);
+    return st == QW_OK ? clear_error() : st;
+  }
   if (w.kind == QW_COINED && (b->steps[slot] & 1))
     QW_TRY(copy_state(b->dtype == QW_C128, p->n_arcs, w.w0, w.psi, s), "state copy kernel");
   st = plan_readout(p, w.psi, static_cast<unsigned char *>(w.w0), d_p, d_norm, d_pmarked, s);

@@ -326,6 +326,44 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     p->group = avg <= 6 ? 1 : avg <= 12 ? 2 : avg <= 24 ? 4 : avg <= 48 ? 8 : avg <= 96 ? 16 : avg <= 192 ? 32 : 64;
   }
 
+  // grid CTQW: stages per launch and, per strip of the blocked kernel, whether
+  // a marked vertex lies in its window (halo included)
+  std::vector<uint8_t> tmark;
+  if (!coined && structure == kTorus) {
+    GraphView tv;
+    tv.structure = structure;
+    tv.dims[0] = p->dims[0];
+    tv.dims[1] = p->dims[1];
+    p->block_depth = torus_block_depth(c128, tv, p->K);
+    if (p->block_depth > 1) {
+      const StripGrid sg = torus_strips(c128, p->dims[0], p->dims[1], p->block_depth);
+      const int l1 = p->dims[0], l2 = p->dims[1], S = sg.halo;
+      tmark.assign(static_cast<size_t>(sg.count()), 0);
+      const double cost = static_cast<double>(mlist.size()) * (sg.tiles_r + sg.tiles_c);
+      if (cost > 5e7) {
+        std::fill(tmark.begin(), tmark.end(), 1);  // dense marked set: every strip takes the marked path
+      } else {
+        std::vector<int> rows_hit, cols_hit;
+        for (int32_t v : mlist) {
+          const int gr = v / l2, gc = v % l2;
+          rows_hit.clear();
+          cols_hit.clear();
+          for (int t = 0; t < sg.tiles_r; ++t) {
+            const int lo = ((std::min(t * sg.rows, l1 - sg.rows) - S) % l1 + l1) % l1;
+            if ((gr - lo + l1) % l1 < sg.rows + 2 * S) rows_hit.push_back(t);
+          }
+          for (int t = 0; t < sg.tiles_c; ++t) {
+            const int lo = ((std::min(t * sg.core, l2 - sg.core) - S) % l2 + l2) % l2;
+            if ((gc - lo + l2) % l2 < sg.width) cols_hit.push_back(t);
+          }
+          for (int a : rows_hit)
+            for (int b : cols_hit) tmark[static_cast<size_t>(a) * sg.tiles_c + b] = 1;
+        }
+      }
+      p->has_tmark = true;
+    }
+  }
+
   size_t off = 0;
   auto section = [&](size_t bytes) {
     const size_t o = off;
@@ -339,6 +377,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (p->has_perm) p->off_perm = section(sizeof(int32_t) * na);
   p->off_bits = section(sizeof(uint32_t) * bits.size());
   p->off_mlist = section(sizeof(int32_t) * std::max<size_t>(mlist.size(), 1));
+  if (p->has_tmark) p->off_tmark = section(tmark.size());
   p->image.assign(off, 0);
   if (structure == kDense) p->off_dense = align256(off);
   std::vector<int32_t> rp32(static_cast<size_t>(n) + 1);
@@ -359,6 +398,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (p->has_perm) put(p->image, p->off_perm, perm.data(), perm.size());
   put(p->image, p->off_bits, bits.data(), bits.size());
   put(p->image, p->off_mlist, mlist.data(), mlist.size());
+  if (p->has_tmark) put(p->image, p->off_tmark, tmark.data(), tmark.size());
 
   // ---- workspace
   const size_t es = c128 ? 16 : 8;
@@ -378,14 +418,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   };
   wsec(p->state_bytes);                    // buffer 0 at offset 0
   p->off_w1 = wsec(p->state_bytes);        // buffer 1
-  if (!coined && structure == kTorus) {
-    GraphView tv;
-    tv.structure = structure;
-    tv.dims[0] = p->dims[0];
-    tv.dims[1] = p->dims[1];
-    p->block_depth = torus_block_depth(c128, tv, p->K);
-    if (p->block_depth > 1) p->off_w2 = wsec(p->state_bytes);  // buffer 2: the other psi
-  }
+  if (p->block_depth > 1) p->off_w2 = wsec(p->state_bytes);  // buffer 2: the other psi
   p->off_pscratch = wsec(sizeof(double) * static_cast<size_t>(n) * p->columns);
   p->off_partials = wsec(sizeof(double) * partials);
   if (structure == kDense) {
@@ -559,6 +592,14 @@ int plan_readout(const qw_plan *p, const void *psi, unsigned char *work, double 
   return readout_only(p, psi, ro, s);
 }
 
+int plan_struct_out(const qw_plan *p, const void *internal, void *psi, unsigned char *work, double *d_p,
+                    double *d_norm, double *d_pmarked, hipStream_t s) {
+  const Readout ro = make_readout(p, work, d_p, d_norm, d_pmarked);
+  QW_TRY(coined_perm_out(p->dtype == QW_C128, p->view, internal, psi, ro, s), "layout permutation kernel");
+  if (ro.any()) QW_TRY(finish_readout(p->view, readout_partials(p->view), ro, s), "readout reduction kernel");
+  return QW_OK;
+}
+
 }  // namespace qwk
 
 // =============================== C ABI =======================================
@@ -647,6 +688,7 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
   if (p->has_perm) g.perm = reinterpret_cast<const int32_t *>(base + p->off_perm);
   g.markbits = reinterpret_cast<const uint32_t *>(base + p->off_bits);
   g.marklist = reinterpret_cast<const int32_t *>(base + p->off_mlist);
+  if (p->has_tmark) g.tmark = reinterpret_cast<const uint8_t *>(base + p->off_tmark);
   g.columns = p->columns;
   if (p->structure == kDense) {
     g.ld = p->ld;

@@ -30,6 +30,40 @@ constexpr int kMaxDenseSplits = 8;
 // Largest degree of the ELL (regular-graph) CTQW layout.
 constexpr int kMaxEllDegree = 64;
 
+// Grid CTQW strips (register-resident temporal blocking): one wavefront holds
+// rows x (64 * cols-per-lane) cells plus a halo of S (the stages per launch).
+#ifndef QW_STRIP_ROWS_C64
+#define QW_STRIP_ROWS_C64 8
+#endif
+#ifndef QW_STRIP_CPL_C64
+#define QW_STRIP_CPL_C64 1
+#endif
+#ifndef QW_STRIP_ROWS_C128
+#define QW_STRIP_ROWS_C128 8
+#endif
+#ifndef QW_STRIP_CPL_C128
+#define QW_STRIP_CPL_C128 1
+#endif
+#ifndef QW_STRIP_WAVES_EU
+#define QW_STRIP_WAVES_EU 2  // register budget: wavefronts per SIMD the strip kernel is compiled for
+#endif
+constexpr int kStripRows64 = QW_STRIP_ROWS_C64;
+constexpr int kStripCpl64 = QW_STRIP_CPL_C64;
+constexpr int kStripRows128 = QW_STRIP_ROWS_C128;
+constexpr int kStripCpl128 = QW_STRIP_CPL_C128;
+constexpr int kStripWaves = 4;  // wavefronts (strips) per workgroup
+
+// Strip decomposition of an l1 x l2 grid for S stages per launch.
+struct StripGrid {
+  int rows = 0;     // core rows per strip
+  int width = 0;    // columns a wavefront holds (64 * cols-per-lane)
+  int core = 0;     // core columns = width - 2S
+  int halo = 0;     // S
+  int tiles_r = 0;  // strips along the rows (last one clamped to the grid edge)
+  int tiles_c = 0;
+  int64_t count() const { return static_cast<int64_t>(tiles_r) * tiles_c; }
+};
+
 // Device view of a plan's graph tables (pointers into the caller's buffer).
 struct GraphView {
   int32_t n = 0;
@@ -51,6 +85,7 @@ struct GraphView {
   const int32_t *perm = nullptr;    // n_arcs (coined structured: slot-major -> CSR position)
   const uint32_t *markbits = nullptr;  // ceil(n/32)
   const int32_t *marklist = nullptr;   // n_marked
+  const uint8_t *tmark = nullptr;      // grid CTQW strips: 1 if a marked vertex lies in the strip's window
 };
 
 // Readout request: any pointer may be null.  `pscratch` (n doubles) and
@@ -111,6 +146,7 @@ hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void 
 // from (P, Yin) to Out (Yin may equal P at the first stage of a step).
 // alpha/beta hold 64 entries (stage k at [k-1]).
 int torus_block_depth(bool c128, const GraphView &g, int K);
+StripGrid torus_strips(bool c128, int l1, int l2, int S);
 hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *P, const void *Yin, void *Out,
                               int kfirst, const double *alpha, const double *beta, hipStream_t s);
 
@@ -146,6 +182,10 @@ struct WalkSlot {
   const double *alpha;    // K entries, stage k at [k-1]
   const double *beta;
   double *hist;           // CTQW: p_marked after each step (caller-zeroed), may be null
+  int32_t structure;      // coined: kGeneral (CSR tiles, state in psi/w0) or kCycle/kTorus/
+                          // kHypercube (slot-major state in w0/w1, see k_batch_struct)
+  int32_t sdims[2];       // structured coined: {n, 0} / {l1, l2} / {dim, 0}
+  int32_t pad1;
 };
 
 // A unit of work of a batched launch: rows (CTQW) or vertices (coined) [begin, end) of a slot.
@@ -158,6 +198,10 @@ struct TileEntry {
 
 hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
                        const int32_t *n_tiles, int grid, hipStream_t s);
+// The structured coined tiles of a batched launch (run before batch_stage in
+// each launch unit; reads the launch counter, does not advance it).
+hipError_t batch_struct(bool c128, const BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
+                        const int32_t *n_tiles, int grid, hipStream_t s);
 
 // Number of partial sums the readout kernels (one thread per vertex) write.
 int readout_partials(const GraphView &g);

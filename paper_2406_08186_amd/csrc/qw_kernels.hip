@@ -561,83 +561,163 @@ struct Coefs {
   double beta[64];
 };
 
-// ---- grid CTQW with temporal blocking ------------------------------------------
-// S consecutive Horner stages k = kfirst .. kfirst-S+1 of one time step in one
-// launch.  Workgroup = one TR x TC tile of the l1 x l2 torus plus a halo of S
-// cells on every side, held in LDS: psi (unchanged inside a step), and y in
-// two ping-pong buffers.  Stage s updates the cells at distance >= s+1 from
-// the tile edge, so after S stages exactly the core is valid and is written
-// out.  Local cell (i, j) is global ((r0+i) mod l1, (c0+j) mod l2), so the
-// periodic wrap is handled at load time and the stencil in LDS is plain.
-template <int TR, int TC, int S>
-struct TbShape {
-  static constexpr int H = TR + 2 * S;
-  static constexpr int W = TC + 2 * S;
-  static constexpr int CELLS = H * W;
-};
+// ---- grid CTQW, register-resident temporal blocking ---------------------------------
+// One wavefront owns a strip of the l1 x l2 torus: H = R + 2S rows by
+// W = 64 * CPL columns (CPL adjacent columns per lane), read once from memory
+// into registers.  S Horner stages then run in registers: the rows above and
+// below a cell are in the same lane, the columns beside it in the same lane or
+// in the neighbouring lane, fetched with a one-lane wavefront shift (DPP).  A
+// stage updates rows 1 .. H-2 of what is still valid, so the row halo shrinks
+// by one per stage; the wavefront's outermost lanes read zeros through the
+// shift, so the column halo shrinks by one per stage too.  After S stages the
+// core R x (W - 2S) cells are exact and are written out.  Strips at the end of
+// a row or column are clamped to the grid edge and overlap their neighbour;
+// both compute the overlap with the same operations, so the duplicate stores
+// write equal values.  No LDS, no barriers; values stay FP64 between the
+// stages of one launch and are rounded once when stored.
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ void opaque(float2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+__device__ __forceinline__ void opaque(double2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+constexpr int kFromLower = 0x138;  // wave_shr:1, lane i receives lane i-1 (lane 0 receives 0)
+constexpr int kFromUpper = 0x130;  // wave_shl:1, lane i receives lane i+1 (lane 63 receives 0)
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double2 lane_shift(double2 v) {
+  return make_double2(lane_shift<CTRL>(v.x), lane_shift<CTRL>(v.y));
+}
+template <int CTRL>
+__device__ __forceinline__ float2 lane_shift(float2 v) {
+  return make_float2(lane_shift<CTRL>(v.x), lane_shift<CTRL>(v.y));
+}
 
-template <typename T, int TR, int TC, int S>
-__global__ __launch_bounds__(512) void k_ctqw_torus_tb(GraphView g, const T *__restrict__ P,
-                                                       const T *__restrict__ Yin, T *__restrict__ Out,
-                                                       int kfirst, Coefs c) {
-  using Sh = TbShape<TR, TC, S>;
-  constexpr int H = Sh::H, W = Sh::W;
-  __shared__ T ps[Sh::CELLS];
-  __shared__ T ya[Sh::CELLS];
-  __shared__ T yb[Sh::CELLS];
-  __shared__ unsigned char mk_cell[Sh::CELLS];  // marked flag of each local cell
-  __shared__ int any_marked;
-  const int l1 = g.dims[0], l2 = g.dims[1];
-  const int tiles_c = l2 / TC;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int r0 = (b / tiles_c) * TR - S, c0 = (b % tiles_c) * TC - S;
-  const bool y_is_p = (Yin == P);
-  if (threadIdx.x == 0) any_marked = 0;
-  __syncthreads();
-  int mine = 0;
-  for (int e = threadIdx.x; e < Sh::CELLS; e += blockDim.x) {
-    const int i = e / W, j = e - (e / W) * W;
-    int gr = r0 + i, gc = c0 + j;
-    gr += (gr < 0) ? l1 : 0;
-    gr -= (gr >= l1) ? l1 : 0;
-    gc += (gc < 0) ? l2 : 0;
-    gc -= (gc >= l2) ? l2 : 0;
-    const int v = gr * l2 + gc;
-    const T pv = P[v];
-    ps[e] = pv;
-    ya[e] = y_is_p ? pv : Yin[v];
-    const bool m = marked(g.markbits, v);
-    mk_cell[e] = m;
-    mine |= m;
-  }
-  if (mine) atomicOr(&any_marked, 1);
-  __syncthreads();
-  const bool tile_marked = any_marked != 0;
+template <typename T, int R, int S, int CPL, bool MARK>
+__device__ __forceinline__ void strip_stages(T (&y)[R + 2 * S][CPL], const T (&ps)[R + 2 * S - 2][CPL], uint64_t mk,
+                                             int kfirst, const Coefs &c) {
+  constexpr int H = R + 2 * S;
+  // opaque to the optimiser: keeps the two instances of this routine (marked
+  // strip or not) from sharing hoisted work, which would hold the first stage's
+  // partial sums for every row in registers at once
+#pragma unroll
+  for (int r = 0; r < H; ++r)
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) opaque(y[r][q]);
 #pragma unroll
   for (int st = 0; st < S; ++st) {
-    const int k = kfirst - st;
-    const double alpha = c.alpha[k - 1], beta = c.beta[k - 1];
-    const T *src = (st & 1) ? yb : ya;
-    T *dst = (st & 1) ? ya : yb;
-    const int lo = st + 1, rh = H - 2 * lo, rw = W - 2 * lo;  // region [lo, H-lo) x [lo, W-lo)
-    for (int e = threadIdx.x; e < rh * rw; e += blockDim.x) {
-      const int i = lo + e / rw, j = lo + (e - (e / rw) * rw);
-      const int q = i * W + j;
-      double2 sum = cvt(src[q - W]);
-      sum = add(sum, cvt(src[q + W]));
-      sum = add(sum, cvt(src[q - 1]));
-      sum = add(sum, cvt(src[q + 1]));
-      const bool mk = tile_marked && mk_cell[q];
-      const double2 yv = mk ? cvt(src[q]) : make_double2(0.0, 0.0);
-      dst[q] = pack<T>(horner_out(cvt(ps[q]), sum, yv, mk, alpha, beta));
+    const double alpha = c.alpha[kfirst - st - 1], beta = c.beta[kfirst - st - 1];
+    T prev[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) prev[q] = y[st][q];
+#pragma unroll
+    for (int r = st + 1; r < H - st - 1; ++r) {
+      T old[CPL];
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) old[q] = y[r][q];
+      const T lower = lane_shift<kFromLower>(old[CPL - 1]);
+      const T upper = lane_shift<kFromUpper>(old[0]);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        double2 sum = add(cvt(prev[q]), cvt(y[r + 1][q]));
+        sum = add(sum, cvt(q == 0 ? lower : old[q - 1]));
+        sum = add(sum, cvt(q == CPL - 1 ? upper : old[q + 1]));
+        const bool m = MARK && ((mk >> (r * CPL + q)) & 1u);
+        y[r][q] = pack<T>(horner_out(cvt(ps[r - 1][q]), sum, cvt(old[q]), m, alpha, beta));
+      }
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) prev[q] = old[q];
     }
-    __syncthreads();
   }
-  const T *fin = (S & 1) ? yb : ya;
-  for (int e = threadIdx.x; e < TR * TC; e += blockDim.x) {
-    const int i = S + e / TC, j = S + (e - (e / TC) * TC);
-    const int gr = r0 + i, gc = c0 + j;  // core cells never wrap
-    Out[gr * l2 + gc] = fin[i * W + j];
+}
+
+template <typename T, int R, int S, int CPL>
+__global__ __launch_bounds__(64 * kStripWaves) __attribute__((amdgpu_waves_per_eu(QW_STRIP_WAVES_EU))) void k_ctqw_torus_strip(GraphView g, const T *__restrict__ P,
+                                                                       const T *__restrict__ Yin,
+                                                                       T *__restrict__ Out, int kfirst, Coefs c) {
+  constexpr int H = R + 2 * S, W = 64 * CPL, CORE = W - 2 * S;
+  static_assert(H * CPL <= 64, "marked mask holds one bit per cell");
+  const int l1 = g.dims[0], l2 = g.dims[1];
+  const int tiles_c = (l2 + CORE - 1) / CORE, tiles_r = (l1 + R - 1) / R;
+  // the wavefront index is uniform; say so, so that the strip geometry lives in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * kStripWaves + wv;
+  if (tile >= tiles_r * tiles_c) return;  // whole wavefront
+  const int lane = threadIdx.x & 63;
+  const int tr = tile / tiles_c, tc = tile - tr * tiles_c;
+  int rb = min(tr * R, l1 - R) - S, cb = min(tc * CORE, l2 - CORE) - S;
+  rb += rb < 0 ? l1 : 0;
+  cb += cb < 0 ? l2 : 0;
+  // per lane: column byte offsets within a row (the row base is uniform, so the
+  // loads and stores take a scalar base plus a 32-bit lane offset)
+  int gcol[CPL];
+  unsigned boff[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int x = cb + lane * CPL + q;  // < 2 l2 since W <= l2
+    gcol[q] = x >= l2 ? x - l2 : x;
+    boff[q] = static_cast<unsigned>(gcol[q]) * static_cast<unsigned>(sizeof(T));
+  }
+  auto at = [](const T *row, unsigned off) -> T {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + off);
+  };
+  T y[H][CPL];       // y of the current stage, stored precision (as the per-stage kernel stores it)
+  T ps[H - 2][CPL];  // psi of rows 1 .. H-2, the rows a stage can update
+  auto row_of = [&](int r) {
+    const int gr = rb + r;  // < 2 l1 since H <= l1
+    return static_cast<size_t>(gr >= l1 ? gr - l1 : gr) * l2;
+  };
+  if (Yin == P) {  // first launch of a step: y = psi
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      const T *prow = P + row_of(r);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const T pv = at(prow, boff[q]);
+        if (r >= 1 && r <= H - 2) ps[r - 1][q] = pv;
+        y[r][q] = pv;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      const T *prow = P + row_of(r), *yrow = Yin + row_of(r);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        if (r >= 1 && r <= H - 2) ps[r - 1][q] = at(prow, boff[q]);
+        y[r][q] = at(yrow, boff[q]);
+      }
+    }
+  }
+  uint64_t mk = 0;
+  const bool strip_marked = g.tmark[tile] != 0;
+  if (strip_marked) {
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int v = static_cast<int>(row_of(r)) + gcol[q];
+        if ((g.markbits[v >> 5] >> (v & 31)) & 1u) mk |= 1ull << (r * CPL + q);
+      }
+    }
+    strip_stages<T, R, S, CPL, true>(y, ps, mk, kfirst, c);
+  } else {
+    strip_stages<T, R, S, CPL, false>(y, ps, 0, kfirst, c);
+  }
+#pragma unroll
+  for (int r = S; r < S + R; ++r) {
+    char *orow = reinterpret_cast<char *>(Out + row_of(r));
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int local = lane * CPL + q;
+      if (local >= S && local < W - S) *reinterpret_cast<T *>(orow + boff[q]) = y[r][q];
+    }
   }
 }
 
@@ -804,6 +884,67 @@ __device__ void batch_coined_tile(const WalkSlot &w, const TileEntry &te, int64_
   for (int i = threadIdx.x; i < na; i += blockDim.x) out[w.rev[ab + i]] = s[i];
 }
 
+// Structured coined walks of a batch: slot-major state ping-ponging between
+// w0 (even units) and w1; one thread per vertex of the tile, the same
+// arithmetic as k_coined_struct.
+template <typename T, int KIND, int D>
+__device__ __forceinline__ void batch_struct_vertices(const WalkSlot &w, const TileEntry &te, int64_t u) {
+  const T *in = static_cast<const T *>((u & 1) ? w.w1 : w.w0);
+  T *out = static_cast<T *>((u & 1) ? w.w0 : w.w1);
+  const int n = w.n, l2 = w.sdims[1];
+  const int d = (KIND == kHypercube) ? w.sdims[0] : D;
+  for (int v = te.begin + threadIdx.x; v < te.end; v += blockDim.x) {
+    T x[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) x[j] = in[static_cast<int64_t>(j) * n + v];
+    if (marked(w.markbits, v)) {
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (j < d) x[j] = pack<T>(scale(cvt(x[j]), -1.0));
+    } else if (KIND == kCycle && w.hadamard) {
+      const double2 x0 = cvt(x[0]), x1 = cvt(x[1]);
+      x[0] = pack<T>(scale(add(x0, x1), kInvSqrt2));
+      x[1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+    } else {
+      double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (j < d) sum = add(sum, cvt(x[j]));
+      const double2 m = grover_mean(sum, d);
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (j < d) x[j] = pack<T>(sub(add(m, m), cvt(x[j])));
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) out[static_cast<int64_t>(rev_slot<KIND>(j)) * n + head_of<KIND>(v, j, n, l2)] = x[j];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_batch_struct(const BatchCtl *ctl, const WalkSlot *slots,
+                                                               const TileEntry *tiles, const int32_t *n_tiles) {
+  const int64_t L = static_cast<int64_t>(ctl->L);
+  const int nt = *n_tiles;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const TileEntry te = tiles[t];
+    if (te.slot < 0) continue;
+    const WalkSlot &w = slots[te.slot];
+    if (w.kind != 0 || w.structure == kGeneral) continue;
+    const int64_t u = L - w.L0;
+    if (u < 0 || u >= w.units) continue;
+    switch (w.structure) {
+      case kCycle: batch_struct_vertices<T, kCycle, 2>(w, te, u); break;
+      case kTorus: batch_struct_vertices<T, kTorus, 4>(w, te, u); break;
+      default:
+        if (w.sdims[0] <= 16) batch_struct_vertices<T, kHypercube, 16>(w, te, u);
+        else batch_struct_vertices<T, kHypercube, 32>(w, te, u);
+        break;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, const WalkSlot *slots,
                                                               const TileEntry *tiles,
@@ -821,8 +962,10 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
     if (u < 0 || u >= w.units) continue;
     if (w.kind == 1) {
       batch_ctqw_tile<T>(w, te, u);
-    } else {
+    } else if (w.structure == kGeneral) {
       batch_coined_tile<T>(w, te, u, s);
+    } else {
+      continue;  // structured coined tiles belong to k_batch_struct
     }
     __syncthreads();
   }
@@ -879,8 +1022,12 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
                                                      double c, int ksplit, double *partial) {
   using M = Mfma<R>;
   constexpr int NC = NT * 16;
-  __shared__ R hs[kDenseRows][kDenseK + 1];
-  __shared__ R xs[kDenseK][NC];
+  constexpr int HPT = kDenseRows * kDenseK / 256;  // H values each thread stages per chunk
+  constexpr int XPT = kDenseK * NC / 256;          // Y values each thread stages per chunk
+  // double-buffered LDS: chunk c is read from buffer c & 1 while the global
+  // loads of chunk c+1 are in flight in registers
+  __shared__ R hs[2][kDenseRows][kDenseK + 1];
+  __shared__ R xs[2][kDenseK][NC];
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int rblocks = (n + kDenseRows - 1) / kDenseRows;
   const int split = blockIdx.x / rblocks;            // k range of this workgroup
@@ -894,26 +1041,43 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
 #pragma unroll
     for (int r = 0; r < 4; ++r) wide[t][r] = 0.0;
   }
+  R hreg[HPT], xreg[XPT];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int e = threadIdx.x + q * 256, i = e / kDenseK, j = e % kDenseK;
+      hreg[q] = H[static_cast<int64_t>(row0 + i) * ld + k0 + j];  // rows padded, k0 + j < ld
+    }
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int e = threadIdx.x + q * 256, i = e / NC, j = e % NC;
+      xreg[q] = (k0 + i < kend && j < c2) ? yin[static_cast<int64_t>(k0 + i) * c2 + j] : R(0);
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
   int chunk = 0;
   for (int k0 = kbeg; k0 < kend; k0 += kDenseK, ++chunk) {
-    for (int e = threadIdx.x; e < kDenseRows * kDenseK; e += blockDim.x) {
-      const int i = e / kDenseK, j = e % kDenseK;
-      hs[i][j] = H[static_cast<int64_t>(row0 + i) * ld + k0 + j];
+    const int buf = chunk & 1;
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int e = threadIdx.x + q * 256;
+      hs[buf][e / kDenseK][e % kDenseK] = hreg[q];
     }
-    for (int e = threadIdx.x; e < kDenseK * NC; e += blockDim.x) {
-      const int i = e / NC, j = e % NC;
-      R v = R(0);
-      if (k0 + i < kend && j < c2) v = yin[static_cast<int64_t>(k0 + i) * c2 + j];
-      xs[i][j] = v;
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int e = threadIdx.x + q * 256;
+      xs[buf][e / NC][e % NC] = xreg[q];
     }
+    // one barrier per chunk: a wave passing it has finished its MMAs of chunk-1, so the
+    // buffer written next iteration (chunk+1 & 1 = chunk-1 & 1) is free
     __syncthreads();
+    if (k0 + kDenseK < kend) fetch(k0 + kDenseK);
 #pragma unroll
     for (int kk = 0; kk < kDenseK; kk += 4) {
-      const R a = hs[wave * 16 + (l & 15)][kk + (l >> 4)];
+      const R a = hs[buf][wave * 16 + (l & 15)][kk + (l >> 4)];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = M::mma(a, xs[kk + (l >> 4)][t * 16 + (l & 15)], acc[t]);
+      for (int t = 0; t < NT; ++t) acc[t] = M::mma(a, xs[buf][kk + (l >> 4)][t * 16 + (l & 15)], acc[t]);
     }
-    __syncthreads();
     if (sizeof(R) == 4 && (chunk & 15) == 15) {  // FP32 products: fold into FP64 every 256 k
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -952,12 +1116,13 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
 // fragment 4 rows x 16 real columns of Y (small and cache-resident; guarded
 // past n and past 2C).  No LDS is shared between waves inside the k loop, so
 // waves with different trip counts never wait for each other.
-template <typename R, int NT>
+template <typename R, int NT, int KC>
 __global__ __launch_bounds__(256) void k_dense_stage_sk(const R *__restrict__ H, int ld, int n, int c2,
                                                         const R *__restrict__ yin, const R *psi, R *out,
                                                         double c) {
   using M = Mfma<R>;
-  constexpr int KC = 16;  // k per wave per chunk
+  static_assert(KC % 16 == 0 && 256 % KC == 0, "k per wave per chunk: a multiple of 16 dividing 256");
+  constexpr int FOLD = 256 / KC;  // FP32 products fold into FP64 every 256 k of a wave
   __shared__ double red[4][NT][4][64];
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int row0 = blockIdx.x * 16;
@@ -977,7 +1142,7 @@ __global__ __launch_bounds__(256) void k_dense_stage_sk(const R *__restrict__ H,
 #pragma unroll
     for (int q = 0; q < KC / 4; ++q) {
       const int k = kb + 4 * q + (l >> 4);
-      a[q] = hrow[k];
+      a[q] = (k < ld) ? hrow[k] : R(0);  // H columns past ld do not exist (KC may exceed 16)
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int j = t * 16 + (l & 15);
@@ -989,7 +1154,7 @@ __global__ __launch_bounds__(256) void k_dense_stage_sk(const R *__restrict__ H,
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t] = M::mma(a[q], b[q][t], acc[t]);
     }
-    if (sizeof(R) == 4 && (chunk & 3) == 3) {  // FP32 products: fold into FP64 every 256 k of this wave
+    if (sizeof(R) == 4 && (chunk % FOLD) == FOLD - 1) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -1077,8 +1242,9 @@ void launch_dense(const GraphView &g, const void *y, const void *psi, void *out,
 
 template <typename R, int NT>
 void launch_dense_sk(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
+  constexpr int KC = NT == 1 ? 64 : 32;
   const dim3 grid((g.n + 15) / 16);
-  hipLaunchKernelGGL((k_dense_stage_sk<R, NT>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld,
+  hipLaunchKernelGGL((k_dense_stage_sk<R, NT, KC>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld,
                      g.n, 2 * g.columns, static_cast<const R *>(y), static_cast<const R *>(psi),
                      static_cast<R *>(out), c);
 }
@@ -1369,22 +1535,34 @@ hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void 
   return hipGetLastError();
 }
 
+StripGrid torus_strips(bool c128, int l1, int l2, int S) {
+  StripGrid sg;
+  sg.rows = c128 ? kStripRows128 : kStripRows64;
+  sg.width = 64 * (c128 ? kStripCpl128 : kStripCpl64);
+  sg.core = sg.width - 2 * S;
+  sg.halo = S;
+  // a strip's rows and columns must be distinct grid rows and columns
+  if (S < 2 || l1 < sg.rows + 2 * S || l2 < sg.width) return StripGrid{};
+  sg.tiles_r = (l1 + sg.rows - 1) / sg.rows;
+  sg.tiles_c = (l2 + sg.core - 1) / sg.core;
+  return sg;
+}
+
 int torus_block_depth(bool c128, const GraphView &g, int K) {
   if (g.structure != kTorus) return 1;
-  const int tr = c128 ? 32 : 32, tc = c128 ? 32 : 64;
-  const int l1 = g.dims[0], l2 = g.dims[1];
-  if (l1 % tr || l2 % tc || l1 <= 5 || l2 <= 5) return 1;
   for (int S : {5, 4, 3, 2})
-    if (K % S == 0) return S;
+    if (K % S == 0 && torus_strips(c128, g.dims[0], g.dims[1], S).count() > 0) return S;
   return 1;
 }
 
-template <typename T, int TR, int TC, int S>
-hipError_t launch_tb(const GraphView &g, const void *P, const void *Yin, void *Out, int kfirst, const Coefs &c,
-                     hipStream_t s) {
-  const dim3 grid((g.dims[0] / TR) * (g.dims[1] / TC));
-  hipLaunchKernelGGL((k_ctqw_torus_tb<T, TR, TC, S>), grid, dim3(512), 0, s, g, static_cast<const T *>(P),
-                     static_cast<const T *>(Yin), static_cast<T *>(Out), kfirst, c);
+template <typename T, int R, int S, int CPL>
+hipError_t launch_strips(const GraphView &g, const void *P, const void *Yin, void *Out, int kfirst, const Coefs &c,
+                         hipStream_t s) {
+  const StripGrid sg = torus_strips(sizeof(T) == 16, g.dims[0], g.dims[1], S);
+  if (sg.count() == 0 || sg.rows != R || sg.width != 64 * CPL || !g.tmark) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((sg.count() + kStripWaves - 1) / kStripWaves));
+  hipLaunchKernelGGL((k_ctqw_torus_strip<T, R, S, CPL>), grid, dim3(64 * kStripWaves), 0, s, g,
+                     static_cast<const T *>(P), static_cast<const T *>(Yin), static_cast<T *>(Out), kfirst, c);
   return hipGetLastError();
 }
 
@@ -1395,22 +1573,33 @@ hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *
     c.alpha[k] = alpha[k];
     c.beta[k] = beta[k];
   }
+  constexpr int R64 = kStripRows64, C64 = kStripCpl64, R128 = kStripRows128, C128 = kStripCpl128;
   if (c128) {
     switch (S) {
-      case 5: return launch_tb<double2, 32, 32, 5>(g, P, Yin, Out, kfirst, c, s);
-      case 4: return launch_tb<double2, 32, 32, 4>(g, P, Yin, Out, kfirst, c, s);
-      case 3: return launch_tb<double2, 32, 32, 3>(g, P, Yin, Out, kfirst, c, s);
-      case 2: return launch_tb<double2, 32, 32, 2>(g, P, Yin, Out, kfirst, c, s);
+      case 5: return launch_strips<double2, R128, 5, C128>(g, P, Yin, Out, kfirst, c, s);
+      case 4: return launch_strips<double2, R128, 4, C128>(g, P, Yin, Out, kfirst, c, s);
+      case 3: return launch_strips<double2, R128, 3, C128>(g, P, Yin, Out, kfirst, c, s);
+      case 2: return launch_strips<double2, R128, 2, C128>(g, P, Yin, Out, kfirst, c, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (S) {
-    case 5: return launch_tb<float2, 32, 64, 5>(g, P, Yin, Out, kfirst, c, s);
-    case 4: return launch_tb<float2, 32, 64, 4>(g, P, Yin, Out, kfirst, c, s);
-    case 3: return launch_tb<float2, 32, 64, 3>(g, P, Yin, Out, kfirst, c, s);
-    case 2: return launch_tb<float2, 32, 64, 2>(g, P, Yin, Out, kfirst, c, s);
+    case 5: return launch_strips<float2, R64, 5, C64>(g, P, Yin, Out, kfirst, c, s);
+    case 4: return launch_strips<float2, R64, 4, C64>(g, P, Yin, Out, kfirst, c, s);
+    case 3: return launch_strips<float2, R64, 3, C64>(g, P, Yin, Out, kfirst, c, s);
+    case 2: return launch_strips<float2, R64, 2, C64>(g, P, Yin, Out, kfirst, c, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t batch_struct(bool c128, const BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
+                        const int32_t *n_tiles, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (c128)
+    hipLaunchKernelGGL(k_batch_struct<double2>, dim3(grid), dim3(kTileThreads), 0, s, ctl, slots, tiles, n_tiles);
+  else
+    hipLaunchKernelGGL(k_batch_struct<float2>, dim3(grid), dim3(kTileThreads), 0, s, ctl, slots, tiles, n_tiles);
+  return hipGetLastError();
 }
 
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s) {

@@ -29,7 +29,8 @@ struct qw_plan {
   // host image of the device graph buffer, and section offsets into it
   std::vector<unsigned char> image;
   size_t off_rp = 0, off_col = 0, off_rev = 0, off_tiles = 0, off_perm = 0, off_bits = 0, off_mlist = 0;
-  bool has_col = false, has_rev = false, has_tiles = false, has_perm = false;
+  size_t off_tmark = 0;  // grid CTQW strips: marked-window flag per strip
+  bool has_col = false, has_rev = false, has_tiles = false, has_perm = false, has_tmark = false;
   // device binding
   unsigned char *d_graph = nullptr;
   qwk::GraphView view;
@@ -44,4 +45,7 @@ int set_error(int code, const char *fmt, ...);
 int clear_error();
 int plan_readout(const qw_plan *p, const void *psi, unsigned char *work, double *d_p, double *d_norm,
                  double *d_pmarked, hipStream_t s);
+// Structured coined plans: slot-major `internal` -> boundary-order psi, with the readout fused.
+int plan_struct_out(const qw_plan *p, const void *internal, void *psi, unsigned char *work, double *d_p,
+                    double *d_norm, double *d_pmarked, hipStream_t s);
 }  // namespace qwk

@@ -140,8 +140,12 @@ class WalkServer:
         from .walk import Plan
         job.status = "building"
 
+        # coined jobs on cycles, grids and hypercubes take the index-free slot-major path;
+        # everything else the CSR path (both run inside the batch)
+        layout = "structured" if job.kind == "coined" else "csr"
+
         def build():
-            return Plan(job.graph, job.kind, dtype=self.dtype, layout="csr", device=self.device,
+            return Plan(job.graph, job.kind, dtype=self.dtype, layout=layout, device=self.device,
                         upload=False, **job.params)
 
         self.building.append((job, self.pool.submit(build)))

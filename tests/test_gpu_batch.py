@@ -205,3 +205,45 @@ def test_batch_errors():
         b.commit()
     assert e.value.code == L.QW_ENOMEM
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_structured_coined(dtype):
+    """Coined walks on slot-major (index-free) plans inside a batch, mixed with CSR and
+    ELL walks: bitwise equal alone and in the mix, equal to the oracle."""
+    walks = [
+        (I.hypercube(10), "coined", dict(coin="grover", marked=[0], layout="structured"), 21),
+        (I.torus(24, 30), "coined", dict(coin="grover", marked=[5, 700], layout="structured"), 16),
+        (I.cycle(301), "coined", dict(coin="hadamard", layout="structured"), 33),
+        (I.hypercube(6), "coined", dict(coin="grover", layout="structured"), 8),
+        (I.erdos_renyi(900, 8 / 899, seed=5), "coined", dict(coin="grover", marked=[2]), 11),
+        (I.random_regular(1000, 5, seed=8), "ctqw", dict(gamma=0.2, dt=0.3, taylor_order=12, marked=[4],
+                                                        layout="structured"), 6),
+    ]
+    print(f"[case] batch structured coined {dtype}", flush=True)
+    entries = []
+    for i, (g, kind, params, steps) in enumerate(walks):
+        pl = _plan(g, kind, params, dtype)
+        entries.append((pl, _psi0(pl, 300 + i), steps))
+    assert [e[0].structure for e in entries[:4]] == ["hypercube", "torus", "cycle", "hypercube"]
+    mixed = _run_batch(entries, dtype)
+    for i, (pl, psi0, steps) in enumerate(entries):
+        alone = _run_batch([(pl, psi0, steps)], dtype)[0]
+        assert torch.equal(alone[0], mixed[i][0]), i
+        assert torch.equal(alone[1], mixed[i][1]), i
+        g, kind, params, _ = walks[i]
+        if kind == "coined":
+            ref = oracle.coined_evolve(g.row_ptr, g.col, psi0, steps,
+                                       coin=oracle.HADAMARD if params["coin"] == "hadamard" else oracle.GROVER,
+                                       marked=params.get("marked", ()))
+            pref = oracle.coined_prob(g.row_ptr, g.col, ref)
+        else:
+            ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps, gamma=params["gamma"], dt=params["dt"],
+                                     K=params["taylor_order"], marked=params["marked"])
+            pref = oracle.vertex_prob(ref)
+        got = mixed[i][0].cpu().numpy().astype(np.complex128)
+        if dtype == "c128":
+            assert np.abs(got - ref).max() < 1e-12, i
+            assert np.abs(mixed[i][1].cpu().numpy() - pref).max() < 1e-12, i
+        else:
+            assert np.linalg.norm(got - ref) < 1e-5, i

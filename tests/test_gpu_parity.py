@@ -175,15 +175,17 @@ def test_ctqw_orders(K, layout):
 
 @pytest.mark.parametrize("l1,l2,K,dtype,depth", [
     (64, 64, 20, "c64", 5), (64, 128, 12, "c64", 4), (96, 64, 9, "c64", 3), (32, 64, 14, "c64", 2),
-    (64, 64, 7, "c64", 1), (96, 32, 20, "c128", 5), (32, 64, 8, "c128", 4), (64, 96, 6, "c128", 3),
-    (32, 32, 10, "c128", 5),
+    (64, 64, 7, "c64", 1), (18, 100, 20, "c64", 5), (37, 201, 10, "c64", 5), (96, 32, 20, "c128", 1),
+    (32, 64, 8, "c128", 4), (64, 96, 6, "c128", 3), (17, 65, 15, "c128", 3), (50, 130, 20, "c128", 5),
 ])
 def test_ctqw_torus_blocked(l1, l2, K, dtype, depth):
-    """Temporal blocking (S stages per launch in LDS), tiles wrapping small tori,
-    marked vertices on tile edges and corners."""
+    """Temporal blocking (S stages per launch on register-resident strips):
+    strips clamped at ragged grid edges, windows that wrap the torus, the
+    smallest grids a strip fits, marked vertices on strip edges and corners,
+    and grids too narrow to block (one stage per launch)."""
     from paper_2406_08186_amd.walk import Plan
     g = I.torus(l1, l2)
-    marked = [0, 31, 32 * l2 + 63 % l2, g.n - 1]
+    marked = [0, 31, 32 * l2 + 63 % l2, 8 * l2 + 53, 13 * l2 + 54, g.n - 1]
     marked = sorted(set(m for m in marked if m < g.n))
     psi0 = I.random_state(g.n, seed=l1 + l2 + K)
     ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 7, gamma=0.25, dt=0.07, K=K, marked=marked)

@@ -38,7 +38,8 @@ def test_served_results_equal_alone():
                      if a is not b and a.admitted_at < b.admitted_at < a.finished_at)
     assert overlapped > 0, "no job joined while another was running"
     for j in done:
-        plan = Plan(j.graph, j.kind, dtype="c64", layout="csr", **j.params)
+        plan = Plan(j.graph, j.kind, dtype="c64", layout="structured" if j.kind == "coined" else "csr",
+                    **j.params)
         b = Batch(capacity=1, max_tiles=1 << 14, dtype="c64")
         psi = plan.state(j.psi0)
         b.set_slot(0, plan, psi, j.steps)
