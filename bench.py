@@ -32,10 +32,11 @@ DT = 0.1
 K_ORDER = 20
 STEPS_PER_PASS = 1000
 METRIC = "arc-steps/s (c64 batched vs c128 plain, L2 err<=1e-4); p50/p99 latency"
-# HBM bytes per launch of the grid kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
-# (scaled by a 256 MiB copy: x2.00 / x1.00); profiles/ctqw_torus1024_blocked.md.  Valid
-# only for the kernel version named here; None for any other.
-MEASURED_TRAFFIC = {"k_ctqw_torus_tb<float2,32,64,5>": (7834.2 * 2 + 8192.0) * 1024}
+# HBM bytes per launch of the grid kernel (1024 x 1024, c64, averaged over the
+# four launches of a time step) measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by a 256 MiB copy (x2.00 / x1.00); profiles/ctqw_torus1024_sweep.md.
+# Valid only for the kernel version named here; None for any other.
+MEASURED_TRAFFIC = {"k_ctqw_torus_sweep<float2,5>": ((4569.5 + 3 * 9002.6) / 4 * 2 + 8194.5) * 1024}
 
 
 def parse():
@@ -218,7 +219,7 @@ def main():
 
     r64, r128 = res["c64"], res["c128"]
     achieved = r64["bytes_per_launch"] / (r64["launch_ms"] * 1e-3) / 1e9
-    kname = (f"k_ctqw_torus_tb<float2,32,64,{r64['depth']}>" if r64["depth"] > 1
+    kname = (f"k_ctqw_torus_sweep<float2,{r64['depth']}>" if r64["depth"] > 1
              else "k_ctqw_struct<float2,TORUS>")
     # counters were taken on the 1024 x 1024 grid; per launch they scale with the rows
     traffic = MEASURED_TRAFFIC.get(kname)
@@ -261,10 +262,11 @@ def main():
                      "bytes_per_launch": r64["bytes_per_launch"],
                      "launch_ms": r64["launch_ms"],
                      "dram_gbs": None if traffic is None else traffic / (r64["launch_ms"] * 1e-3) / 1e9,
+                     "dram_frac": None if traffic is None else traffic / (r64["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "note": ("achieved counts the per-stage model bytes (read y, read psi, write y per "
                               "row and stage) of every stage the launch runs; with several stages per "
-                              "launch on an LDS tile the DRAM traffic is a fraction of that, so frac can "
-                              "pass 1; dram_gbs is the measured traffic over the launch time")},
+                              "launch kept in registers the DRAM traffic is a fraction of that, so frac "
+                              "can pass 1; dram_gbs is the measured traffic over the launch time")},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, v0, args.cpu_seconds)

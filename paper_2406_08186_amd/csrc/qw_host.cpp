@@ -338,6 +338,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     if (p->block_depth > 1) {
       const StripGrid sg = torus_strips(c128, p->dims[0], p->dims[1], p->block_depth);
       const int l1 = p->dims[0], l2 = p->dims[1], S = sg.halo;
+      p->strip_rows = sg.rows;
       tmark.assign(static_cast<size_t>(sg.count()), 0);
       const double cost = static_cast<double>(mlist.size()) * (sg.tiles_r + sg.tiles_c);
       if (cost > 5e7) {
@@ -689,6 +690,7 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
   g.markbits = reinterpret_cast<const uint32_t *>(base + p->off_bits);
   g.marklist = reinterpret_cast<const int32_t *>(base + p->off_mlist);
   if (p->has_tmark) g.tmark = reinterpret_cast<const uint8_t *>(base + p->off_tmark);
+  g.strip_rows = p->strip_rows;
   g.columns = p->columns;
   if (p->structure == kDense) {
     g.ld = p->ld;

@@ -52,6 +52,16 @@ constexpr int kStripCpl64 = QW_STRIP_CPL_C64;
 constexpr int kStripRows128 = QW_STRIP_ROWS_C128;
 constexpr int kStripCpl128 = QW_STRIP_CPL_C128;
 constexpr int kStripWaves = 4;  // wavefronts (strips) per workgroup
+#ifndef QW_GRID_SWEEP
+#define QW_GRID_SWEEP 1  // 1: streaming sweep kernel, 0: fixed-height register strips
+#endif
+#ifndef QW_SWEEP_WAVES_PER_SIMD
+#define QW_SWEEP_WAVES_PER_SIMD 1
+#endif
+#ifndef QW_SWEEP_MIN_ROWS_PER_STAGE
+#define QW_SWEEP_MIN_ROWS_PER_STAGE 4
+#endif
+constexpr int kSimds = 256 * 4;  // MI355X: 256 compute units of 4 SIMDs
 
 // Strip decomposition of an l1 x l2 grid for S stages per launch.
 struct StripGrid {
@@ -86,6 +96,7 @@ struct GraphView {
   const uint32_t *markbits = nullptr;  // ceil(n/32)
   const int32_t *marklist = nullptr;   // n_marked
   const uint8_t *tmark = nullptr;      // grid CTQW strips: 1 if a marked vertex lies in the strip's window
+  int32_t strip_rows = 0;              // grid CTQW strips: core rows per strip
 };
 
 // Readout request: any pointer may be null.  `pscratch` (n doubles) and

@@ -17,6 +17,7 @@
 // beta = dt/k.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "qw_internal.h"
 
@@ -719,6 +720,144 @@ __global__ __launch_bounds__(64 * kStripWaves) __attribute__((amdgpu_waves_per_e
       if (local >= S && local < W - S) *reinterpret_cast<T *>(orow + boff[q]) = y[r][q];
     }
   }
+}
+
+// ---- grid CTQW, streaming temporal blocking ----------------------------------------
+// One wavefront sweeps a strip of the l1 x l2 torus from top to bottom: 64
+// columns (core 64 - 2S) by R core rows plus S halo rows above and below.  At
+// sweep position t the window row t arrives (y and psi, fetched one body of
+// kSweepRing rows ahead), and stage s = 1 .. S computes its value of window
+// row t - s from stage s-1's rows t-s-1, t-s, t-s+1: each stage keeps only its
+// last three rows, so the registers hold O(S) rows however tall the strip is,
+// and the loads stream in while earlier rows compute.  Row neighbours beside a
+// cell come from the adjacent lanes through one-lane wavefront shifts; the
+// outermost lanes read zeros, so the valid columns shrink by one per stage and
+// the core 64 - 2S lanes are exact after S stages.  Stage s starts at t = 2s,
+// where its rows become exact, and the last stage stores each core row as soon
+// as it is computed.  A stage's rows are rounded to the storage type, as the
+// one-stage kernel rounds its output, and the neighbours are summed in that
+// kernel's order.  Strips at the grid's right and bottom edges are
+// clamped and overlap their neighbour; duplicate stores write equal values.
+constexpr int kSweepRing = 6;  // rows per unrolled body; holds psi for S <= 5 stages
+
+__device__ __forceinline__ constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
+
+template <typename T, int S, bool YP, bool MARK>
+__device__ __forceinline__ void sweep_strip(const GraphView &g, const T *__restrict__ P, const T *__restrict__ Yin,
+                                            T *__restrict__ Out, int kfirst, const Coefs &c, int R, int rb,
+                                            int lane, int gcol, unsigned boff) {
+  constexpr int RING = kSweepRing, W = 64;
+  static_assert(S >= 2 && S < RING, "psi ring holds rows t-S .. t");
+  const int l1 = g.dims[0], l2 = g.dims[1];
+  const int n_in = R + 2 * S;
+  auto row_off = [&](int t) -> size_t {
+    const int gr = rb + t;  // < 2 l1 since n_in <= l1
+    return static_cast<size_t>(gr >= l1 ? gr - l1 : gr) * l2;
+  };
+  auto at = [](const T *row, unsigned off) -> T {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + off);
+  };
+  // rows of the next body, fetched while the current one computes (rows past
+  // the strip's end re-read its last row and are never used)
+  T ny[RING], np[RING];
+  uint32_t nmw[RING], nms[RING];  // marked-set word and bit position of each row's cell
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int i = 0; i < RING; ++i) {
+      const size_t o = row_off(min(t0 + i, n_in - 1));
+      np[i] = at(P + o, boff);
+      ny[i] = YP ? np[i] : at(Yin + o, boff);
+      if (MARK) {
+        const int v = static_cast<int>(o) + gcol;
+        nmw[i] = g.markbits[v >> 5];
+        nms[i] = static_cast<uint32_t>(v & 31);
+      }
+    }
+  };
+  T yv[S][3];       // stage s-1 (s = 1 .. S) rows, slot = window row mod 3
+  T pr[RING];       // psi, slot = window row mod RING
+  uint32_t mr = 0;  // bit k: window row t - k is marked
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) yv[s][j] = T{};
+#pragma unroll
+  for (int j = 0; j < RING; ++j) pr[j] = T{};
+
+  // one body: window rows t0 .. t0 + RING - 1.  FULL: every row exists and
+  // every stage is past its warm-up, so the body has no branches.
+  auto body = [&](int t0, auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    T cy[RING], cp[RING];
+    uint32_t cmw[RING], cms[RING];
+#pragma unroll
+    for (int i = 0; i < RING; ++i) {
+      cy[i] = ny[i];
+      cp[i] = np[i];
+      if (MARK) {
+        cmw[i] = nmw[i];
+        cms[i] = nms[i];
+      }
+    }
+    if (t0 + RING < n_in) fetch(t0 + RING);
+#pragma unroll
+    for (int i = 0; i < RING; ++i) {
+      const int t = t0 + i;  // t0 is a multiple of RING, so every ring slot below is static
+      if (!FULL && t >= n_in) break;
+      yv[0][i % 3] = cy[i];
+      pr[i] = cp[i];
+      if (MARK) mr = (mr << 1) | ((cmw[i] >> cms[i]) & 1u);
+#pragma unroll
+      for (int st = 1; st <= S; ++st) {
+        if (!FULL && t < 2 * st) break;  // window rows above stage st's exact region
+        const T up = yv[st - 1][pmod(i - st - 1, 3)];
+        const T self = yv[st - 1][pmod(i - st, 3)];
+        const T dn = yv[st - 1][pmod(i - st + 1, 3)];
+        const T left = lane_shift<kFromLower>(self), right = lane_shift<kFromUpper>(self);
+        // the one-stage kernel's order: right, left, below, above
+        double2 sum = add(cvt(right), cvt(left));
+        sum = add(sum, cvt(dn));
+        sum = add(sum, cvt(up));
+        const bool m = MARK && ((mr >> st) & 1u);
+        const T val = pack<T>(horner_out(cvt(pr[pmod(i - st, RING)]), sum, cvt(self), m, c.alpha[kfirst - st],
+                                         c.beta[kfirst - st]));
+        if (st < S) {
+          yv[st][pmod(i - st, 3)] = val;
+        } else if (lane >= S && lane < W - S) {
+          *reinterpret_cast<T *>(reinterpret_cast<char *>(Out + row_off(t - S)) + boff) = val;
+        }
+      }
+    }
+  };
+  fetch(0);
+  int t0 = 0;
+  for (; t0 < 2 * S; t0 += RING) body(t0, std::false_type{});
+  for (; t0 + RING <= n_in; t0 += RING) body(t0, std::true_type{});
+  if (t0 < n_in) body(t0, std::false_type{});
+}
+
+template <typename T, int S, bool YP>
+__global__ __launch_bounds__(64 * kStripWaves) void k_ctqw_torus_sweep(GraphView g, const T *__restrict__ P,
+                                                                       const T *__restrict__ Yin,
+                                                                       T *__restrict__ Out, int kfirst, Coefs c) {
+  constexpr int CORE = 64 - 2 * S;
+  const int l1 = g.dims[0], l2 = g.dims[1], R = g.strip_rows;
+  const int tiles_c = (l2 + CORE - 1) / CORE, tiles_r = (l1 + R - 1) / R;
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * kStripWaves + wv;
+  if (tile >= tiles_r * tiles_c) return;  // whole wavefront
+  const int lane = threadIdx.x & 63;
+  const int tr = tile / tiles_c, tc = tile - tr * tiles_c;
+  int rb = min(tr * R, l1 - R) - S, cb = min(tc * CORE, l2 - CORE) - S;
+  rb += rb < 0 ? l1 : 0;
+  cb += cb < 0 ? l2 : 0;
+  int gcol = cb + lane;  // < 2 l2 since 64 <= l2
+  gcol -= gcol >= l2 ? l2 : 0;
+  const unsigned boff = static_cast<unsigned>(gcol) * static_cast<unsigned>(sizeof(T));
+  if (g.tmark[tile])
+    sweep_strip<T, S, YP, true>(g, P, Yin, Out, kfirst, c, R, rb, lane, gcol, boff);
+  else
+    sweep_strip<T, S, YP, false>(g, P, Yin, Out, kfirst, c, R, rb, lane, gcol, boff);
 }
 
 // CTQW small graphs: every stage of every step in one workgroup, vectors in LDS.
@@ -1537,6 +1676,22 @@ hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void 
 
 StripGrid torus_strips(bool c128, int l1, int l2, int S) {
   StripGrid sg;
+#if QW_GRID_SWEEP
+  (void)c128;
+  if (S < 2 || S >= kSweepRing || l2 < 64) return StripGrid{};
+  sg.width = 64;
+  sg.core = 64 - 2 * S;
+  sg.halo = S;
+  sg.tiles_c = (l2 + sg.core - 1) / sg.core;
+  // strips as tall as possible while every SIMD still gets its wavefronts, but
+  // at least 4S rows so the halo rows stay a minor share of a strip's work
+  const int want_r = std::max(1, kSimds * QW_SWEEP_WAVES_PER_SIMD / sg.tiles_c);
+  int rows = std::max((l1 + want_r - 1) / want_r, QW_SWEEP_MIN_ROWS_PER_STAGE * S);
+  rows = std::min(rows, l1 - 2 * S);  // a strip's window rows must be distinct grid rows
+  if (rows < 1) return StripGrid{};
+  sg.rows = rows;
+  sg.tiles_r = (l1 + rows - 1) / rows;
+#else
   sg.rows = c128 ? kStripRows128 : kStripRows64;
   sg.width = 64 * (c128 ? kStripCpl128 : kStripCpl64);
   sg.core = sg.width - 2 * S;
@@ -1545,6 +1700,7 @@ StripGrid torus_strips(bool c128, int l1, int l2, int S) {
   if (S < 2 || l1 < sg.rows + 2 * S || l2 < sg.width) return StripGrid{};
   sg.tiles_r = (l1 + sg.rows - 1) / sg.rows;
   sg.tiles_c = (l2 + sg.core - 1) / sg.core;
+#endif
   return sg;
 }
 
@@ -1566,6 +1722,20 @@ hipError_t launch_strips(const GraphView &g, const void *P, const void *Yin, voi
   return hipGetLastError();
 }
 
+template <typename T, int S>
+hipError_t launch_sweep(const GraphView &g, const void *P, const void *Yin, void *Out, int kfirst, const Coefs &c,
+                        hipStream_t s) {
+  const StripGrid sg = torus_strips(sizeof(T) == 16, g.dims[0], g.dims[1], S);
+  if (sg.count() == 0 || sg.rows != g.strip_rows || !g.tmark) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((sg.count() + kStripWaves - 1) / kStripWaves)), block(64 * kStripWaves);
+  const T *p = static_cast<const T *>(P), *y = static_cast<const T *>(Yin);
+  if (Yin == P)
+    hipLaunchKernelGGL((k_ctqw_torus_sweep<T, S, true>), grid, block, 0, s, g, p, y, static_cast<T *>(Out), kfirst, c);
+  else
+    hipLaunchKernelGGL((k_ctqw_torus_sweep<T, S, false>), grid, block, 0, s, g, p, y, static_cast<T *>(Out), kfirst, c);
+  return hipGetLastError();
+}
+
 hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *P, const void *Yin, void *Out,
                               int kfirst, const double *alpha, const double *beta, hipStream_t s) {
   Coefs c;
@@ -1573,6 +1743,24 @@ hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *
     c.alpha[k] = alpha[k];
     c.beta[k] = beta[k];
   }
+#if QW_GRID_SWEEP
+  if (c128) {
+    switch (S) {
+      case 5: return launch_sweep<double2, 5>(g, P, Yin, Out, kfirst, c, s);
+      case 4: return launch_sweep<double2, 4>(g, P, Yin, Out, kfirst, c, s);
+      case 3: return launch_sweep<double2, 3>(g, P, Yin, Out, kfirst, c, s);
+      case 2: return launch_sweep<double2, 2>(g, P, Yin, Out, kfirst, c, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (S) {
+    case 5: return launch_sweep<float2, 5>(g, P, Yin, Out, kfirst, c, s);
+    case 4: return launch_sweep<float2, 4>(g, P, Yin, Out, kfirst, c, s);
+    case 3: return launch_sweep<float2, 3>(g, P, Yin, Out, kfirst, c, s);
+    case 2: return launch_sweep<float2, 2>(g, P, Yin, Out, kfirst, c, s);
+    default: return hipErrorInvalidValue;
+  }
+#else
   constexpr int R64 = kStripRows64, C64 = kStripCpl64, R128 = kStripRows128, C128 = kStripCpl128;
   if (c128) {
     switch (S) {
@@ -1590,6 +1778,7 @@ hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *
     case 2: return launch_strips<float2, R64, 2, C64>(g, P, Yin, Out, kfirst, c, s);
     default: return hipErrorInvalidValue;
   }
+#endif
 }
 
 hipError_t batch_struct(bool c128, const BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,

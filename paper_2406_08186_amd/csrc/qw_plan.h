@@ -36,6 +36,7 @@ struct qw_plan {
   qwk::GraphView view;
   // workspace layout
   size_t state_bytes = 0, off_w1 = 0, off_w2 = 0, off_pscratch = 0, off_partials = 0, work_bytes = 0;
+  int32_t strip_rows = 0;   // grid CTQW blocked kernel: core rows per strip
   int32_t block_depth = 1;  // grid CTQW: Horner stages per launch (temporal blocking)
 };
 

@@ -176,7 +176,8 @@ def test_ctqw_orders(K, layout):
 @pytest.mark.parametrize("l1,l2,K,dtype,depth", [
     (64, 64, 20, "c64", 5), (64, 128, 12, "c64", 4), (96, 64, 9, "c64", 3), (32, 64, 14, "c64", 2),
     (64, 64, 7, "c64", 1), (18, 100, 20, "c64", 5), (37, 201, 10, "c64", 5), (96, 32, 20, "c128", 1),
-    (32, 64, 8, "c128", 4), (64, 96, 6, "c128", 3), (17, 65, 15, "c128", 3), (50, 130, 20, "c128", 5),
+    (32, 64, 8, "c128", 4), (64, 96, 6, "c128", 3), (17, 65, 15, "c128", 5), (50, 130, 20, "c128", 5),
+    (300, 64, 20, "c64", 5), (257, 130, 8, "c128", 4),
 ])
 def test_ctqw_torus_blocked(l1, l2, K, dtype, depth):
     """Temporal blocking (S stages per launch on register-resident strips):
