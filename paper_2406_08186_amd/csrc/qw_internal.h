@@ -30,43 +30,18 @@ constexpr int kMaxDenseSplits = 8;
 // Largest degree of the ELL (regular-graph) CTQW layout.
 constexpr int kMaxEllDegree = 64;
 
-// Grid CTQW strips (register-resident temporal blocking): one wavefront holds
-// rows x (64 * cols-per-lane) cells plus a halo of S (the stages per launch).
-#ifndef QW_STRIP_ROWS_C64
-#define QW_STRIP_ROWS_C64 8
-#endif
-#ifndef QW_STRIP_CPL_C64
-#define QW_STRIP_CPL_C64 1
-#endif
-#ifndef QW_STRIP_ROWS_C128
-#define QW_STRIP_ROWS_C128 8
-#endif
-#ifndef QW_STRIP_CPL_C128
-#define QW_STRIP_CPL_C128 1
-#endif
-#ifndef QW_STRIP_WAVES_EU
-#define QW_STRIP_WAVES_EU 2  // register budget: wavefronts per SIMD the strip kernel is compiled for
-#endif
-constexpr int kStripRows64 = QW_STRIP_ROWS_C64;
-constexpr int kStripCpl64 = QW_STRIP_CPL_C64;
-constexpr int kStripRows128 = QW_STRIP_ROWS_C128;
-constexpr int kStripCpl128 = QW_STRIP_CPL_C128;
+// Grid CTQW strips (streaming temporal blocking): one wavefront sweeps a strip
+// of 64 columns; strips are sized so each SIMD gets kSweepWavesPerSimd of them,
+// with at least kSweepMinRowsPerStage * S core rows.
 constexpr int kStripWaves = 4;  // wavefronts (strips) per workgroup
-#ifndef QW_GRID_SWEEP
-#define QW_GRID_SWEEP 1  // 1: streaming sweep kernel, 0: fixed-height register strips
-#endif
-#ifndef QW_SWEEP_WAVES_PER_SIMD
-#define QW_SWEEP_WAVES_PER_SIMD 1
-#endif
-#ifndef QW_SWEEP_MIN_ROWS_PER_STAGE
-#define QW_SWEEP_MIN_ROWS_PER_STAGE 4
-#endif
 constexpr int kSimds = 256 * 4;  // MI355X: 256 compute units of 4 SIMDs
+constexpr int kSweepWavesPerSimd = 1;
+constexpr int kSweepMinRowsPerStage = 4;
 
 // Strip decomposition of an l1 x l2 grid for S stages per launch.
 struct StripGrid {
   int rows = 0;     // core rows per strip
-  int width = 0;    // columns a wavefront holds (64 * cols-per-lane)
+  int width = 0;    // columns a wavefront holds
   int core = 0;     // core columns = width - 2S
   int halo = 0;     // S
   int tiles_r = 0;  // strips along the rows (last one clamped to the grid edge)

@@ -562,20 +562,7 @@ struct Coefs {
   double beta[64];
 };
 
-// ---- grid CTQW, register-resident temporal blocking ---------------------------------
-// One wavefront owns a strip of the l1 x l2 torus: H = R + 2S rows by
-// W = 64 * CPL columns (CPL adjacent columns per lane), read once from memory
-// into registers.  S Horner stages then run in registers: the rows above and
-// below a cell are in the same lane, the columns beside it in the same lane or
-// in the neighbouring lane, fetched with a one-lane wavefront shift (DPP).  A
-// stage updates rows 1 .. H-2 of what is still valid, so the row halo shrinks
-// by one per stage; the wavefront's outermost lanes read zeros through the
-// shift, so the column halo shrinks by one per stage too.  After S stages the
-// core R x (W - 2S) cells are exact and are written out.  Strips at the end of
-// a row or column are clamped to the grid edge and overlap their neighbour;
-// both compute the overlap with the same operations, so the duplicate stores
-// write equal values.  No LDS, no barriers; values stay FP64 between the
-// stages of one launch and are rounded once when stored.
+// ---- one-lane wavefront shifts ---------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ double lane_shift(double x) {
   const long long b = __double_as_longlong(x);
@@ -583,8 +570,6 @@ __device__ __forceinline__ double lane_shift(double x) {
   const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
-__device__ __forceinline__ void opaque(float2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
-__device__ __forceinline__ void opaque(double2 &v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 constexpr int kFromLower = 0x138;  // wave_shr:1, lane i receives lane i-1 (lane 0 receives 0)
 constexpr int kFromUpper = 0x130;  // wave_shl:1, lane i receives lane i+1 (lane 63 receives 0)
 template <int CTRL>
@@ -598,128 +583,6 @@ __device__ __forceinline__ double2 lane_shift(double2 v) {
 template <int CTRL>
 __device__ __forceinline__ float2 lane_shift(float2 v) {
   return make_float2(lane_shift<CTRL>(v.x), lane_shift<CTRL>(v.y));
-}
-
-template <typename T, int R, int S, int CPL, bool MARK>
-__device__ __forceinline__ void strip_stages(T (&y)[R + 2 * S][CPL], const T (&ps)[R + 2 * S - 2][CPL], uint64_t mk,
-                                             int kfirst, const Coefs &c) {
-  constexpr int H = R + 2 * S;
-  // opaque to the optimiser: keeps the two instances of this routine (marked
-  // strip or not) from sharing hoisted work, which would hold the first stage's
-  // partial sums for every row in registers at once
-#pragma unroll
-  for (int r = 0; r < H; ++r)
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) opaque(y[r][q]);
-#pragma unroll
-  for (int st = 0; st < S; ++st) {
-    const double alpha = c.alpha[kfirst - st - 1], beta = c.beta[kfirst - st - 1];
-    T prev[CPL];
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) prev[q] = y[st][q];
-#pragma unroll
-    for (int r = st + 1; r < H - st - 1; ++r) {
-      T old[CPL];
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) old[q] = y[r][q];
-      const T lower = lane_shift<kFromLower>(old[CPL - 1]);
-      const T upper = lane_shift<kFromUpper>(old[0]);
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        double2 sum = add(cvt(prev[q]), cvt(y[r + 1][q]));
-        sum = add(sum, cvt(q == 0 ? lower : old[q - 1]));
-        sum = add(sum, cvt(q == CPL - 1 ? upper : old[q + 1]));
-        const bool m = MARK && ((mk >> (r * CPL + q)) & 1u);
-        y[r][q] = pack<T>(horner_out(cvt(ps[r - 1][q]), sum, cvt(old[q]), m, alpha, beta));
-      }
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) prev[q] = old[q];
-    }
-  }
-}
-
-template <typename T, int R, int S, int CPL>
-__global__ __launch_bounds__(64 * kStripWaves) __attribute__((amdgpu_waves_per_eu(QW_STRIP_WAVES_EU))) void k_ctqw_torus_strip(GraphView g, const T *__restrict__ P,
-                                                                       const T *__restrict__ Yin,
-                                                                       T *__restrict__ Out, int kfirst, Coefs c) {
-  constexpr int H = R + 2 * S, W = 64 * CPL, CORE = W - 2 * S;
-  static_assert(H * CPL <= 64, "marked mask holds one bit per cell");
-  const int l1 = g.dims[0], l2 = g.dims[1];
-  const int tiles_c = (l2 + CORE - 1) / CORE, tiles_r = (l1 + R - 1) / R;
-  // the wavefront index is uniform; say so, so that the strip geometry lives in scalar registers
-  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-  const int tile = xcd_remap(blockIdx.x, gridDim.x) * kStripWaves + wv;
-  if (tile >= tiles_r * tiles_c) return;  // whole wavefront
-  const int lane = threadIdx.x & 63;
-  const int tr = tile / tiles_c, tc = tile - tr * tiles_c;
-  int rb = min(tr * R, l1 - R) - S, cb = min(tc * CORE, l2 - CORE) - S;
-  rb += rb < 0 ? l1 : 0;
-  cb += cb < 0 ? l2 : 0;
-  // per lane: column byte offsets within a row (the row base is uniform, so the
-  // loads and stores take a scalar base plus a 32-bit lane offset)
-  int gcol[CPL];
-  unsigned boff[CPL];
-#pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    const int x = cb + lane * CPL + q;  // < 2 l2 since W <= l2
-    gcol[q] = x >= l2 ? x - l2 : x;
-    boff[q] = static_cast<unsigned>(gcol[q]) * static_cast<unsigned>(sizeof(T));
-  }
-  auto at = [](const T *row, unsigned off) -> T {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + off);
-  };
-  T y[H][CPL];       // y of the current stage, stored precision (as the per-stage kernel stores it)
-  T ps[H - 2][CPL];  // psi of rows 1 .. H-2, the rows a stage can update
-  auto row_of = [&](int r) {
-    const int gr = rb + r;  // < 2 l1 since H <= l1
-    return static_cast<size_t>(gr >= l1 ? gr - l1 : gr) * l2;
-  };
-  if (Yin == P) {  // first launch of a step: y = psi
-#pragma unroll
-    for (int r = 0; r < H; ++r) {
-      const T *prow = P + row_of(r);
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        const T pv = at(prow, boff[q]);
-        if (r >= 1 && r <= H - 2) ps[r - 1][q] = pv;
-        y[r][q] = pv;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < H; ++r) {
-      const T *prow = P + row_of(r), *yrow = Yin + row_of(r);
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        if (r >= 1 && r <= H - 2) ps[r - 1][q] = at(prow, boff[q]);
-        y[r][q] = at(yrow, boff[q]);
-      }
-    }
-  }
-  uint64_t mk = 0;
-  const bool strip_marked = g.tmark[tile] != 0;
-  if (strip_marked) {
-#pragma unroll
-    for (int r = 0; r < H; ++r) {
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        const int v = static_cast<int>(row_of(r)) + gcol[q];
-        if ((g.markbits[v >> 5] >> (v & 31)) & 1u) mk |= 1ull << (r * CPL + q);
-      }
-    }
-    strip_stages<T, R, S, CPL, true>(y, ps, mk, kfirst, c);
-  } else {
-    strip_stages<T, R, S, CPL, false>(y, ps, 0, kfirst, c);
-  }
-#pragma unroll
-  for (int r = S; r < S + R; ++r) {
-    char *orow = reinterpret_cast<char *>(Out + row_of(r));
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-      const int local = lane * CPL + q;
-      if (local >= S && local < W - S) *reinterpret_cast<T *>(orow + boff[q]) = y[r][q];
-    }
-  }
 }
 
 // ---- grid CTQW, streaming temporal blocking ----------------------------------------
@@ -1675,9 +1538,8 @@ hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void 
 }
 
 StripGrid torus_strips(bool c128, int l1, int l2, int S) {
-  StripGrid sg;
-#if QW_GRID_SWEEP
   (void)c128;
+  StripGrid sg;
   if (S < 2 || S >= kSweepRing || l2 < 64) return StripGrid{};
   sg.width = 64;
   sg.core = 64 - 2 * S;
@@ -1685,22 +1547,12 @@ StripGrid torus_strips(bool c128, int l1, int l2, int S) {
   sg.tiles_c = (l2 + sg.core - 1) / sg.core;
   // strips as tall as possible while every SIMD still gets its wavefronts, but
   // at least 4S rows so the halo rows stay a minor share of a strip's work
-  const int want_r = std::max(1, kSimds * QW_SWEEP_WAVES_PER_SIMD / sg.tiles_c);
-  int rows = std::max((l1 + want_r - 1) / want_r, QW_SWEEP_MIN_ROWS_PER_STAGE * S);
+  const int want_r = std::max(1, kSimds * kSweepWavesPerSimd / sg.tiles_c);
+  int rows = std::max((l1 + want_r - 1) / want_r, kSweepMinRowsPerStage * S);
   rows = std::min(rows, l1 - 2 * S);  // a strip's window rows must be distinct grid rows
   if (rows < 1) return StripGrid{};
   sg.rows = rows;
   sg.tiles_r = (l1 + rows - 1) / rows;
-#else
-  sg.rows = c128 ? kStripRows128 : kStripRows64;
-  sg.width = 64 * (c128 ? kStripCpl128 : kStripCpl64);
-  sg.core = sg.width - 2 * S;
-  sg.halo = S;
-  // a strip's rows and columns must be distinct grid rows and columns
-  if (S < 2 || l1 < sg.rows + 2 * S || l2 < sg.width) return StripGrid{};
-  sg.tiles_r = (l1 + sg.rows - 1) / sg.rows;
-  sg.tiles_c = (l2 + sg.core - 1) / sg.core;
-#endif
   return sg;
 }
 
@@ -1709,17 +1561,6 @@ int torus_block_depth(bool c128, const GraphView &g, int K) {
   for (int S : {5, 4, 3, 2})
     if (K % S == 0 && torus_strips(c128, g.dims[0], g.dims[1], S).count() > 0) return S;
   return 1;
-}
-
-template <typename T, int R, int S, int CPL>
-hipError_t launch_strips(const GraphView &g, const void *P, const void *Yin, void *Out, int kfirst, const Coefs &c,
-                         hipStream_t s) {
-  const StripGrid sg = torus_strips(sizeof(T) == 16, g.dims[0], g.dims[1], S);
-  if (sg.count() == 0 || sg.rows != R || sg.width != 64 * CPL || !g.tmark) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>((sg.count() + kStripWaves - 1) / kStripWaves));
-  hipLaunchKernelGGL((k_ctqw_torus_strip<T, R, S, CPL>), grid, dim3(64 * kStripWaves), 0, s, g,
-                     static_cast<const T *>(P), static_cast<const T *>(Yin), static_cast<T *>(Out), kfirst, c);
-  return hipGetLastError();
 }
 
 template <typename T, int S>
@@ -1743,7 +1584,6 @@ hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *
     c.alpha[k] = alpha[k];
     c.beta[k] = beta[k];
   }
-#if QW_GRID_SWEEP
   if (c128) {
     switch (S) {
       case 5: return launch_sweep<double2, 5>(g, P, Yin, Out, kfirst, c, s);
@@ -1760,25 +1600,6 @@ hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *
     case 2: return launch_sweep<float2, 2>(g, P, Yin, Out, kfirst, c, s);
     default: return hipErrorInvalidValue;
   }
-#else
-  constexpr int R64 = kStripRows64, C64 = kStripCpl64, R128 = kStripRows128, C128 = kStripCpl128;
-  if (c128) {
-    switch (S) {
-      case 5: return launch_strips<double2, R128, 5, C128>(g, P, Yin, Out, kfirst, c, s);
-      case 4: return launch_strips<double2, R128, 4, C128>(g, P, Yin, Out, kfirst, c, s);
-      case 3: return launch_strips<double2, R128, 3, C128>(g, P, Yin, Out, kfirst, c, s);
-      case 2: return launch_strips<double2, R128, 2, C128>(g, P, Yin, Out, kfirst, c, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (S) {
-    case 5: return launch_strips<float2, R64, 5, C64>(g, P, Yin, Out, kfirst, c, s);
-    case 4: return launch_strips<float2, R64, 4, C64>(g, P, Yin, Out, kfirst, c, s);
-    case 3: return launch_strips<float2, R64, 3, C64>(g, P, Yin, Out, kfirst, c, s);
-    case 2: return launch_strips<float2, R64, 2, C64>(g, P, Yin, Out, kfirst, c, s);
-    default: return hipErrorInvalidValue;
-  }
-#endif
 }
 
 hipError_t batch_struct(bool c128, const BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
