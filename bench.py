@@ -66,6 +66,11 @@ def parse():
                     help="arrival rates as fractions of the measured saturated capacity")
     ap.add_argument("--serve-max-arcs", type=float, default=4e6)
     ap.add_argument("--serve-max-steps", type=int, default=5000)
+    ap.add_argument("--serve-solo-arcs", type=float, default=2 ** 19,
+                    help="jobs with at least this many arcs run in a solo lane")
+    ap.add_argument("--serve-batch-arcs", type=float, default=2 ** 21,
+                    help="cap on the arcs in the batch lane (0: none)")
+    ap.add_argument("--serve-solo-slots", type=int, default=1, help="solo lanes running at once")
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--dense-n", type=int, default=15000)
     ap.add_argument("--dense-columns", default="1,8,32,128")
@@ -416,8 +421,9 @@ def _gen_job(args_tuple):
 
 
 def run_serve(args):
-    """Poisson stream of mixed coined / CTQW jobs served with continuous batching,
-    against the plain one-job-at-a-time form on the same GPU."""
+    """Poisson stream of mixed coined / CTQW jobs served (continuous batch for
+    small jobs, solo lane for large ones), against the plain one-job-at-a-time
+    form on the same GPU with the same arrivals."""
     import copy
     import multiprocessing as mp
 
@@ -441,55 +447,76 @@ def run_serve(args):
     def fresh():
         return [copy.copy(j) for j in base_jobs]
 
-    # saturated capacity: every job at t = 0
-    jobs = fresh()
-    for j in jobs:
-        j.arrival = 0.0
-    srv = WalkServer(capacity=64, chunk=64, dtype="c64", workers=args.workers)
-    t1 = time.perf_counter()
-    done = serve_stream(srv, jobs, time_limit=900)
-    sat_s = time.perf_counter() - t1
-    srv.close()
-    cap_jobs_s = len(done) / sat_s
-    cap_rate = arc_work(done) / sat_s
-    print(f"[serve] saturated: {len(done)} jobs in {sat_s:.1f} s", file=sys.stderr, flush=True)
-    results = []
-    rng = np.random.default_rng(7)
-    for frac in [float(x) for x in args.serve_rates.split(",")]:
-        lam = frac * cap_jobs_s
-        jobs = fresh()
-        for j, a in zip(jobs, poisson_arrivals(len(jobs), lam, rng)):
-            j.arrival = float(a)
-        srv = WalkServer(capacity=64, chunk=64, dtype="c64", workers=args.workers)
+    def served(jobs):
+        srv = WalkServer(capacity=64, chunk=64, dtype="c64", workers=args.workers,
+                         solo_arcs=int(args.serve_solo_arcs), solo_slots=args.serve_solo_slots,
+                         batch_arcs=int(args.serve_batch_arcs) if args.serve_batch_arcs > 0 else None)
         t1 = time.perf_counter()
         done = serve_stream(srv, jobs, time_limit=900)
         el = time.perf_counter() - t1
         srv.close()
-        st = latency_stats(done)
-        results.append({"load": frac, "rate_jobs_per_s": lam, "arc_steps_per_s": arc_work(done) / el,
-                        **st, "cycles": srv.cycles})
-        print(f"[serve] load {frac}: p50 {st['p50_s']:.3f} s p99 {st['p99_s']:.3f} s", file=sys.stderr,
-              flush=True)
-    # plain form at the first load
-    lam = float(args.serve_rates.split(",")[0]) * cap_jobs_s
+        return done, el, srv.cycles
+
+    def plain(jobs):
+        t1 = time.perf_counter()
+        serve_sequential(jobs, time_limit=1800)
+        return jobs, time.perf_counter() - t1
+
+    # warm-up (kernel loading, graph capture): a few jobs, untimed
+    warm = fresh()[:8]
+    for j in warm:
+        j.arrival = 0.0
+    served(warm)
+    # saturated capacity: every job at t = 0
     jobs = fresh()
-    for j, a in zip(jobs, poisson_arrivals(len(jobs), lam, np.random.default_rng(7))):
-        j.arrival = float(a)
-    t1 = time.perf_counter()
-    serve_sequential(jobs, time_limit=1800)
-    el = time.perf_counter() - t1
-    plain = {"load": float(args.serve_rates.split(",")[0]), "arc_steps_per_s": arc_work(jobs) / el,
-             **latency_stats(jobs)}
+    for j in jobs:
+        j.arrival = 0.0
+    done, sat_s, _ = served(jobs)
+    cap_jobs_s = len(done) / sat_s
+    cap_rate = arc_work(done) / sat_s
+    print(f"[serve] saturated: {len(done)} jobs in {sat_s:.1f} s", file=sys.stderr, flush=True)
+    jobs = fresh()
+    for j in jobs:
+        j.arrival = 0.0
+    pdone, psat_s = plain(jobs)
+    plain_sat = {"jobs_per_s": len(pdone) / psat_s, "arc_steps_per_s": arc_work(pdone) / psat_s}
+    print(f"[serve] plain saturated: {len(pdone)} jobs in {psat_s:.1f} s", file=sys.stderr, flush=True)
+    results = []
+    for k, frac in enumerate(float(x) for x in args.serve_rates.split(",")):
+        lam = frac * cap_jobs_s
+        arrivals = poisson_arrivals(len(base_jobs), lam, np.random.default_rng(7 + k))
+        jobs = fresh()
+        for j, a in zip(jobs, arrivals):
+            j.arrival = float(a)
+        done, el, cycles = served(jobs)
+        st = latency_stats(done)
+        jobs = fresh()
+        for j, a in zip(jobs, arrivals):
+            j.arrival = float(a)
+        pdone, pel = plain(jobs)
+        pst = latency_stats(pdone)
+
+        def tail(js):  # the five slowest jobs: latency, lane, kind, arcs, steps
+            return [[round(j.latency, 3), j.lane, j.kind, j.arcs, j.steps]
+                    for j in sorted(js, key=lambda j: -j.latency)[:5]]
+        results.append({"load": frac, "rate_jobs_per_s": lam, "arc_steps_per_s": arc_work(done) / el,
+                        **st, "cycles": cycles, "slowest": tail(done),
+                        "plain": {"arc_steps_per_s": arc_work(pdone) / pel, **pst, "slowest": tail(pdone)}})
+        print(f"[serve] load {frac}: p50 {st['p50_s']:.3f} s p99 {st['p99_s']:.3f} s; plain p50 "
+              f"{pst['p50_s']:.3f} s p99 {pst['p99_s']:.3f} s", file=sys.stderr, flush=True)
     line = {
         "metric": METRIC, "value": cap_rate, "unit": "arc-steps/s", "n_gpus": 1, "steps": 1,
         "warmup": 0, "ms_per_step": sat_s * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"serve_{len(base_jobs)}_mixed_jobs", "jobs": len(base_jobs),
                    "arcs_range": [1e3, args.serve_max_arcs], "steps_range": [100, args.serve_max_steps],
-                   "slots": 64, "chunk": 64, "parallelism": "single-gpu"},
+                   "slots": 64, "chunk": 64, "solo_lane_arcs": int(args.serve_solo_arcs),
+                   "batch_arcs_cap": int(args.serve_batch_arcs), "solo_lanes": args.serve_solo_slots,
+                   "parallelism": "single-gpu"},
         "saturated_jobs_per_s": cap_jobs_s,
+        "plain_saturated": plain_sat,
+        "speedup_saturated_vs_plain": cap_rate / plain_sat["arc_steps_per_s"],
         "loads": results,
-        "plain_sequential": plain,
     }
     print(json.dumps(line), flush=True)
 

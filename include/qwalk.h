@@ -147,7 +147,7 @@ typedef struct qw_plan_info {
   size_t work_bytes;       /* device workspace qw_evolve/qw_probabilities need*/
   int32_t columns;         /* walks per state (dense layout), else 1          */
   int32_t block_depth;     /* CTQW on a torus: Horner stages per launch (> 1
-                              when temporal blocking in LDS applies), else 1  */
+                              when temporal blocking applies), else 1         */
 } qw_plan_info;
 
 /* Validate the graph and the walk, precompute the host-side tables (reverse
@@ -197,6 +197,28 @@ int qw_evolve(const qw_plan *plan, void *d_psi, void *d_work, size_t work_bytes,
  * bitwise reproducible for a given plan.  Errors as qw_evolve. */
 int qw_probabilities(const qw_plan *plan, const void *d_psi, double *d_p, double *d_norm,
                      double *d_pmarked, void *d_work, size_t work_bytes, void *stream);
+
+/* ---- many small walks in one launch ------------------------------------- */
+/* Advance `count` independent walks by steps[i] steps each (Sec. 3.1 for
+ * CTQW, Sec. 3.2 for coined walks) in a single launch, one workgroup per
+ * walk: each walk runs whole in its workgroup's LDS, with the arithmetic and
+ * order of qw_evolve on the same plan, so results are bitwise those of
+ * qw_evolve(plans[i], d_psi[i], ..., steps[i]).  Every plan must be uploaded,
+ * share one dtype and have taken the one-workgroup path (info.structure ==
+ * QW_STRUCT_SMALL, which QW_LAYOUT_AUTO picks for graphs whose vectors fit in
+ * LDS); the walks may differ in kind, graph and step count.  plans, d_psi
+ * and steps are host arrays of count entries; d_psi[i] is the device state of
+ * walk i, read and written in place; no readout is produced (call
+ * qw_probabilities afterwards).  d_desc: caller-owned device buffer of at
+ * least qw_small_many_desc_bytes(count) bytes that must stay allocated until
+ * the launch has run; the call returns once the walk descriptors are staged
+ * for the copy into it, and is otherwise asynchronous on `stream`.  count = 0
+ * does nothing.  Errors: QW_EINVAL (null arrays, negative steps or count,
+ * mixed dtypes, a plan not on the one-workgroup path), QW_ENOMEM (d_desc too
+ * small), QW_ESTATE (a plan not uploaded), QW_EDEVICE. */
+size_t qw_small_many_desc_bytes(int32_t count);
+int qw_small_many(const qw_plan *const *plans, void *const *d_psi, const int64_t *steps, int32_t count,
+                  void *d_desc, size_t desc_bytes, void *stream);
 
 /* ---- batched walks ------------------------------------------------------ */
 /* A batch advances many walks (of different graphs, sizes, kinds and step

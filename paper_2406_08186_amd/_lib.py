@@ -25,7 +25,8 @@ QW_LAYOUT_AUTO, QW_LAYOUT_CSR, QW_LAYOUT_STRUCTURED, QW_LAYOUT_DENSE = 0, 1, 2, 
 STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small", 5: "ell", 6: "dense"}
 
 EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upload", "qw_evolve",
-           "qw_probabilities", "qw_taylor_order", "qw_taylor_plan", "qw_taylor_tail_bound",
+           "qw_probabilities", "qw_small_many_desc_bytes", "qw_small_many",
+           "qw_taylor_order", "qw_taylor_plan", "qw_taylor_tail_bound",
            "qw_last_error", "qw_version",
            "qw_batch_create", "qw_batch_destroy", "qw_batch_device_bytes", "qw_batch_bind",
            "qw_batch_set_slot", "qw_batch_clear_slot", "qw_batch_commit", "qw_batch_run",
@@ -76,6 +77,10 @@ def lib():
         L.qw_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
         L.qw_evolve.argtypes = [vp, vp, vp, C.c_size_t, C.c_int64, vp, vp, vp, vp]
         L.qw_probabilities.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.qw_small_many_desc_bytes.argtypes = [C.c_int32]
+        L.qw_small_many_desc_bytes.restype = C.c_size_t
+        L.qw_small_many.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32, vp,
+                                    C.c_size_t, vp]
         L.qw_taylor_order.argtypes = [C.c_double, C.c_int64, C.c_double, C.POINTER(C.c_int32)]
         L.qw_taylor_plan.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int32),
                                      dp, C.POINTER(C.c_int64)]
@@ -99,7 +104,7 @@ def lib():
         L.qw_last_error.restype = C.c_char_p
         L.qw_version.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("qw_taylor_tail_bound", "qw_last_error", "qw_version"):
+            if name not in ("qw_taylor_tail_bound", "qw_last_error", "qw_version", "qw_small_many_desc_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -142,6 +147,20 @@ def qw_probabilities(plan, d_psi: int, d_p, d_norm, d_pmarked, d_work: int, work
                      stream: int) -> None:
     check(lib().qw_probabilities(plan, d_psi, d_p, d_norm, d_pmarked, d_work, work_bytes, stream),
           "qw_probabilities")
+
+
+def qw_small_many_desc_bytes(count: int) -> int:
+    return int(lib().qw_small_many_desc_bytes(count))
+
+
+def qw_small_many(plans, d_psi, steps, d_desc: int, desc_bytes: int, stream: int) -> None:
+    n = len(plans)
+    if len(d_psi) != n or len(steps) != n:
+        raise ValueError("plans, states and step counts must have the same length")
+    P = (C.c_void_p * max(n, 1))(*[p.value if isinstance(p, C.c_void_p) else p for p in plans])
+    S = (C.c_void_p * max(n, 1))(*d_psi)
+    T = (C.c_int64 * max(n, 1))(*[int(x) for x in steps])
+    check(lib().qw_small_many(P, S, T, n, d_desc, desc_bytes, stream), "qw_small_many")
 
 
 def qw_taylor_order(rho: float, steps: int, tol: float) -> int:

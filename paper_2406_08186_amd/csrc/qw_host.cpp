@@ -516,8 +516,8 @@ int evolve_ctqw(const qw_plan *p, void *psi, unsigned char *work, int64_t steps,
   if (steps == 0) return readout_only(p, psi, ro, s);
   void *w0 = work, *w1 = work + p->off_w1;
   if (p->block_depth > 1) {
-    // temporal blocking: K/S launches per step, each S stages in LDS; psi
-    // alternates between the caller's buffer and buffer 2, y between 0 and 1
+    // temporal blocking: K/S launches per step, each S stages in registers;
+    // psi alternates between the caller's buffer and buffer 2, y between 0 and 1
     std::vector<double> a64(64, 0.0), b64(64, 0.0);
     for (int k = 0; k < K; ++k) {
       a64[k] = alpha[k];
@@ -726,6 +726,62 @@ int qw_probabilities(const qw_plan *p, const void *d_psi, double *d_p, double *d
   const Readout ro = make_readout(p, work, d_p, d_norm, d_pmarked);
   st = readout_only(p, d_psi, ro, static_cast<hipStream_t>(stream));
   return st == QW_OK ? ok() : st;
+}
+
+size_t qw_small_many_desc_bytes(int32_t count) {
+  return count > 0 ? sizeof(SmallWalk) * static_cast<size_t>(count) : 0;
+}
+
+int qw_small_many(const qw_plan *const *plans, void *const *d_psi, const int64_t *steps, int32_t count,
+                  void *d_desc, size_t desc_bytes, void *stream) {
+  if (count < 0) return fail(QW_EINVAL, "negative walk count");
+  if (count == 0) return ok();
+  if (!plans || !d_psi || !steps) return fail(QW_EINVAL, "null walk arrays");
+  if (!d_desc) return fail(QW_EINVAL, "null descriptor buffer");
+  if (desc_bytes < qw_small_many_desc_bytes(count))
+    return fail(QW_ENOMEM, "descriptor buffer of %zu bytes, %d walks need %zu", desc_bytes, count,
+                qw_small_many_desc_bytes(count));
+  std::vector<SmallWalk> walks;
+  try {
+    walks.resize(static_cast<size_t>(count));
+  } catch (const std::bad_alloc &) {
+    return fail(QW_ENOMEM, "host allocation");
+  }
+  const int dtype = plans[0] ? plans[0]->dtype : QW_C64;
+  size_t lds = 0;
+  int threads = 64;
+  for (int32_t i = 0; i < count; ++i) {
+    const qw_plan *p = plans[i];
+    int st = check_bound(p);
+    if (st != QW_OK) return st;
+    if (p->dtype != dtype) return fail(QW_EINVAL, "walk %d: all walks must share one dtype", i);
+    if (p->structure != kSmall) return fail(QW_EINVAL, "walk %d: plan is not on the one-workgroup path", i);
+    if (steps[i] < 0) return fail(QW_EINVAL, "walk %d: negative step count", i);
+    if (!d_psi[i] && p->state_bytes) return fail(QW_EINVAL, "walk %d: null state", i);
+    const bool c128 = p->dtype == QW_C128, coined = p->kind == QW_COINED;
+    const int n = static_cast<int>(p->n), na = static_cast<int>(p->n_arcs);
+    lds = std::max(lds, coined ? coined_small_lds(c128, n, na) : ctqw_small_lds(c128, n, na));
+    const int want = coined ? na : n;
+    while (threads < 1024 && threads < want) threads *= 2;
+    SmallWalk &w = walks[static_cast<size_t>(i)];
+    w.g = p->view;
+    w.psi = d_psi[i];
+    w.coined = coined;
+    w.hadamard = p->coin == QW_HADAMARD;
+    w.K = p->K;
+    w.steps = steps[i];
+    for (int k = 1; k <= p->K && !coined; ++k) {
+      w.beta[k - 1] = p->dt / k;
+      w.alpha[k - 1] = p->gamma * p->dt / k;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t bytes = qw_small_many_desc_bytes(count);
+  hipError_t e = hipMemcpyAsync(d_desc, walks.data(), bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(QW_EDEVICE, "descriptor copy: %s", hipGetErrorString(e));
+  e = small_many(dtype == QW_C128, static_cast<const SmallWalk *>(d_desc), count, lds, threads, s);
+  if (e != hipSuccess) return fail(QW_EDEVICE, "many-small-walks kernel: %s", hipGetErrorString(e));
+  return ok();
 }
 
 int qw_taylor_order(double rho, int64_t steps, double tol, int32_t *K) {

@@ -17,7 +17,7 @@ constexpr int kTileMaxVerts = 1024;
 // Threads per workgroup of the elementwise/stencil kernels.
 constexpr int kBlock = 256;
 // LDS budget of the one-workgroup whole-walk kernels.
-constexpr size_t kSmallLdsBytes = 60 * 1024;  // dynamic LDS, leaves room for static
+constexpr size_t kSmallLdsBytes = 156 * 1024;  // dynamic LDS of the one-workgroup path (of 160 KiB)
 // Largest hypercube dimension the structured kernels handle.
 constexpr int kMaxHypercubeDim = 30;
 
@@ -74,6 +74,19 @@ struct GraphView {
   int32_t strip_rows = 0;              // grid CTQW strips: core rows per strip
 };
 
+// One walk of a many-small-walks launch (the whole walk in one workgroup's LDS).
+struct SmallWalk {
+  GraphView g;
+  void *psi = nullptr;
+  int32_t coined = 0;
+  int32_t hadamard = 0;
+  int32_t K = 0;
+  int32_t pad = 0;
+  int64_t steps = 0;
+  double alpha[64] = {};  // CTQW stage coefficients gamma dt / k, dt / k
+  double beta[64] = {};
+};
+
 // Readout request: any pointer may be null.  `pscratch` (n doubles) and
 // `partials` (enough for the launch) come from the workspace.
 struct Readout {
@@ -111,6 +124,7 @@ hipError_t copy_state(bool c128, int64_t len, const void *in, void *out, hipStre
 hipError_t coined_prob_csr(bool c128, const GraphView &g, const void *psi, const Readout &ro,
                            hipStream_t s);
 
+hipError_t small_many(bool c128, const SmallWalk *d_walks, int count, size_t lds, int threads, hipStream_t s);
 hipError_t ctqw_small(bool c128, const GraphView &g, void *psi, const double *alpha,
                       const double *beta, int K, int64_t steps, const Readout &ro, hipStream_t s);
 size_t ctqw_small_lds(bool c128, int n, int n_arcs);

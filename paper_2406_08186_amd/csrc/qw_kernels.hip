@@ -111,10 +111,8 @@ __global__ __launch_bounds__(256) void k_finish(const double *partials, int coun
 
 // ---- coined: whole walk in one workgroup's LDS -------------------------------
 template <typename T>
-__global__ __launch_bounds__(1024) void k_coined_small(GraphView g, T *psi, int hadamard,
-                                                       int64_t steps, Readout ro) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[16];
+__device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int64_t steps, const Readout &ro,
+                                  unsigned char *smem, double *red) {
   const int n = g.n, na = g.n_arcs;
   T *a = reinterpret_cast<T *>(smem);
   T *b = a + na;
@@ -171,6 +169,14 @@ __global__ __launch_bounds__(1024) void k_coined_small(GraphView g, T *psi, int 
       if (ro.pmarked) *ro.pmarked = ptot;
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coined_small(GraphView g, T *psi, int hadamard,
+                                                       int64_t steps, Readout ro) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  coined_small_walk<T>(g, psi, hadamard, steps, ro, smem, red);
 }
 
 // ---- coined: general CSR, one LDS tile of whole vertex blocks per workgroup --
@@ -725,10 +731,8 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_ctqw_torus_sweep(GraphView
 
 // CTQW small graphs: every stage of every step in one workgroup, vectors in LDS.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_ctqw_small(GraphView g, T *psi, Coefs c, int K,
-                                                     int64_t steps, Readout ro) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[16];
+__device__ void ctqw_small_walk(const GraphView &g, T *psi, const double *alpha, const double *beta, int K,
+                                int64_t steps, const Readout &ro, unsigned char *smem, double *red) {
   const int n = g.n, na = g.n_arcs;
   T *ps = reinterpret_cast<T *>(smem);
   T *ya = ps + n;
@@ -750,7 +754,7 @@ __global__ __launch_bounds__(1024) void k_ctqw_small(GraphView g, T *psi, Coefs 
         for (int a = srp[v]; a < srp[v + 1]; ++a) sum = add(sum, cvt(yin[scol[a]]));
         const bool mk = marked(g.markbits, v);
         double2 yv = mk ? cvt(yin[v]) : make_double2(0.0, 0.0);
-        double2 r = horner_out(cvt(ps[v]), sum, yv, mk, c.alpha[k - 1], c.beta[k - 1]);
+        double2 r = horner_out(cvt(ps[v]), sum, yv, mk, alpha[k - 1], beta[k - 1]);
         yout[v] = pack<T>(r);
       }
       __syncthreads();
@@ -780,6 +784,28 @@ __global__ __launch_bounds__(1024) void k_ctqw_small(GraphView g, T *psi, Coefs 
       if (ro.pmarked) *ro.pmarked = ptot;
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_ctqw_small(GraphView g, T *psi, Coefs c, int K,
+                                                     int64_t steps, Readout ro) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  ctqw_small_walk<T>(g, psi, c.alpha, c.beta, K, steps, ro, smem, red);
+}
+
+// Many independent small walks in one launch: workgroup b runs walk b whole,
+// its vectors in LDS, exactly as the one-walk kernels above do.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_small_many(const SmallWalk *__restrict__ walks) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  const SmallWalk &w = walks[blockIdx.x];
+  const Readout none;
+  if (w.coined)
+    coined_small_walk<T>(w.g, static_cast<T *>(w.psi), w.hadamard, w.steps, none, smem, red);
+  else
+    ctqw_small_walk<T>(w.g, static_cast<T *>(w.psi), w.alpha, w.beta, w.K, w.steps, none, smem, red);
 }
 
 // ---- batched launch over many walks -------------------------------------------
@@ -1262,9 +1288,18 @@ void launch_dense_nt(const GraphView &g, const void *y, const void *psi, void *o
 }
 
 
+// A kernel launched with more than 64 KiB of dynamic LDS must be allowed it
+// first (on the current device).
+template <typename F> hipError_t allow_lds(F *kernel, size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(kSmallLdsBytes));
+}
+
 template <typename T> hipError_t launch_coined_small(const GraphView &g, void *psi, int hadamard,
                                                      int64_t steps, const Readout &ro, hipStream_t s) {
   size_t lds = coined_small_lds(sizeof(T) == 16, g.n, g.n_arcs);
+  if (hipError_t e = allow_lds(&k_coined_small<T>, lds); e != hipSuccess) return e;
   int threads = 64;
   while (threads < 1024 && threads < g.n_arcs) threads *= 2;
   hipLaunchKernelGGL(k_coined_small<T>, dim3(1), dim3(threads), lds, s, g, static_cast<T *>(psi),
@@ -1281,10 +1316,18 @@ template <typename T> hipError_t launch_ctqw_small(const GraphView &g, void *psi
     c.beta[k] = k < K ? beta[k] : 0.0;
   }
   size_t lds = ctqw_small_lds(sizeof(T) == 16, g.n, g.n_arcs);
+  if (hipError_t e = allow_lds(&k_ctqw_small<T>, lds); e != hipSuccess) return e;
   int threads = 64;
   while (threads < 1024 && threads < g.n) threads *= 2;
   hipLaunchKernelGGL(k_ctqw_small<T>, dim3(1), dim3(threads), lds, s, g, static_cast<T *>(psi), c, K,
                      steps, ro);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_small_many(const SmallWalk *d_walks, int count, size_t lds, int threads, hipStream_t s) {
+  if (hipError_t e = allow_lds(&k_small_many<T>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_small_many<T>, dim3(count), dim3(threads), lds, s, d_walks);
   return hipGetLastError();
 }
 
@@ -1370,6 +1413,12 @@ size_t coined_small_lds(bool c128, int n, int n_arcs) {
 size_t ctqw_small_lds(bool c128, int n, int n_arcs) {
   const size_t es = c128 ? 16 : 8;
   return 3 * es * static_cast<size_t>(n) + 4 * (static_cast<size_t>(n) + 1 + n_arcs);
+}
+
+hipError_t small_many(bool c128, const SmallWalk *d_walks, int count, size_t lds, int threads, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  return c128 ? launch_small_many<double2>(d_walks, count, lds, threads, s)
+              : launch_small_many<float2>(d_walks, count, lds, threads, s);
 }
 
 hipError_t coined_small(bool c128, const GraphView &g, void *psi, int hadamard, int64_t steps,

@@ -3,15 +3,24 @@
 Jobs (a graph, a walk, an initial state and a step count) arrive over time.
 Host-side plan building (validation, reverse arcs, Taylor order) runs in a
 thread pool; the admission controller admits jobs first-come-first-served
-when a batch slot is free and the job's device footprint (graph tables +
-workspace + state) fits the HBM budget.  Admitted jobs join the running
-batch between chunks of launches, their states stay resident until they
-finish, and every chunk advances every active job, so jobs that arrive while
-others are on the GPU overlap with them.  Finished jobs are read out (FP64
-probabilities) and their memory and slot are released.
+while the job's device footprint (graph tables + workspace + state) fits the
+HBM budget.  Three lanes share the GPU on their own streams:
 
-A walk's arithmetic in a batch does not depend on the other slots, so each
-result is the same alone and in the mix.
+* the small lane runs jobs whose graphs fit one workgroup's LDS whole: a
+  group of them goes out in one launch (qw_small_many), one workgroup per
+  job, every step of every job inside that launch;
+* the batch lane holds the mid-size jobs in one continuous batch: admitted
+  jobs join between chunks of launches, their states stay resident until they
+  finish, and every chunk advances every job in the batch; a cap on the arcs
+  in the batch bounds the time of a launch;
+* the solo lane runs jobs large enough to fill the GPU on their own, one at
+  a time in arrival order, in chunks of steps on the single-walk path.
+
+The lanes are polled independently, so a small job never waits for a large
+job's launches, and a large job does not slow every launch of the batch.
+Finished jobs are read out (FP64 probabilities) and their memory and slot
+are released.  A walk's arithmetic does not depend on the other jobs, so
+each result is the same alone and served.
 """
 from __future__ import annotations
 
@@ -38,6 +47,7 @@ class Job:
     steps: int
     arrival: float = 0.0          # seconds after the server's start
     # filled in by the server
+    lane: str = "batch"           # "small", "batch" or "solo"
     footprint: int = 0
     slot: int = -1
     admitted_at: float = math.nan
@@ -47,7 +57,7 @@ class Job:
 
     @property
     def arcs(self) -> int:
-        return int(self.graph.n_arcs)
+        return int(self.graph.n_arcs) if self.graph is not None else 0
 
     @property
     def latency(self) -> float:
@@ -55,15 +65,28 @@ class Job:
 
 
 class AdmissionController:
-    """FCFS admission by free slot and device-memory budget (host logic only)."""
+    """FCFS admission by device-memory budget (host logic only).
 
-    def __init__(self, capacity: int, budget_bytes: int):
+    Batch-lane jobs also need a free batch slot; solo-lane jobs run up to
+    `solo_slots` at a time; small-lane jobs go out in groups.  Each lane keeps
+    its own FCFS queue; all draw on one budget.
+    """
+
+    def __init__(self, capacity: int, budget_bytes: int, batch_arcs: int | None = None,
+                 solo_slots: int = 1):
         self.capacity = capacity
+        self.solo_slots = solo_slots
         self.budget = int(budget_bytes)
+        self.batch_arcs = batch_arcs    # cap on the arcs one batch launch advances (None: none)
+        self.arcs_running = 0
         self.used = 0
         self.free_slots = list(range(capacity - 1, -1, -1))
-        self.queue: deque[Job] = deque()
-        self.running: dict[int, Job] = {}
+        self.queue: deque[Job] = deque()        # batch lane
+        self.solo_queue: deque[Job] = deque()   # solo lane
+        self.small_queue: deque[Job] = deque()  # small lane
+        self.small: list[Job] = []              # running small-lane jobs
+        self.running: dict[int, Job] = {}       # batch slot -> job
+        self.solo: list[Job] = []               # running solo-lane jobs
 
     def offer(self, job: Job) -> bool:
         """Queue a job whose footprint is known; reject it if it can never fit."""
@@ -71,45 +94,96 @@ class AdmissionController:
             job.status = "rejected"
             return False
         job.status = "queued"
-        self.queue.append(job)
+        {"solo": self.solo_queue, "small": self.small_queue}.get(job.lane, self.queue).append(job)
         return True
 
     def admit(self) -> list[Job]:
-        """Pop queued jobs in arrival order while a slot and the budget allow."""
+        """Pop batch-lane jobs in arrival order while a slot and the budget allow."""
         out = []
         while self.queue and self.free_slots and self.queue[0].footprint <= self.budget - self.used:
+            head = self.queue[0]
+            if (self.batch_arcs is not None and self.running
+                    and self.arcs_running + head.arcs > self.batch_arcs):
+                break  # the launch would grow past its arc cap: wait for running jobs to finish
             job = self.queue.popleft()
             job.slot = self.free_slots.pop()
             job.status = "running"
             self.used += job.footprint
+            self.arcs_running += job.arcs
             self.running[job.slot] = job
             out.append(job)
         return out
 
+    def admit_solo(self) -> Optional[Job]:
+        """Pop the next solo-lane job if a solo slot is free and the budget allows."""
+        if (len(self.solo) < self.solo_slots and self.solo_queue
+                and self.solo_queue[0].footprint <= self.budget - self.used):
+            job = self.solo_queue.popleft()
+            job.status = "running"
+            self.used += job.footprint
+            self.solo.append(job)
+            return job
+        return None
+
+    def admit_small(self, limit: int) -> list[Job]:
+        """Pop up to `limit` small-lane jobs in arrival order while the budget allows."""
+        out = []
+        while (len(out) < limit and self.small_queue
+               and self.small_queue[0].footprint <= self.budget - self.used):
+            job = self.small_queue.popleft()
+            job.status = "running"
+            self.used += job.footprint
+            self.small.append(job)
+            out.append(job)
+        return out
+
     def release(self, job: Job) -> None:
-        if self.running.get(job.slot) is not job:
-            raise ValueError("job is not running")
-        del self.running[job.slot]
+        if job.lane == "small":
+            if job not in self.small:
+                raise ValueError("job is not running")
+            self.small.remove(job)
+        elif job.lane == "solo":
+            if job not in self.solo:
+                raise ValueError("job is not running")
+            self.solo.remove(job)
+        else:
+            if self.running.get(job.slot) is not job:
+                raise ValueError("job is not running")
+            del self.running[job.slot]
+            self.free_slots.append(job.slot)
+            self.arcs_running -= job.arcs
+            job.slot = -1
         self.used -= job.footprint
-        self.free_slots.append(job.slot)
-        job.slot = -1
 
     def cancel(self, job: Job) -> bool:
         """Drop a queued job; running jobs are cancelled by the server."""
-        try:
-            self.queue.remove(job)
-        except ValueError:
-            return False
-        job.status = "cancelled"
-        return True
+        for q in (self.queue, self.solo_queue, self.small_queue):
+            try:
+                q.remove(job)
+            except ValueError:
+                continue
+            job.status = "cancelled"
+            return True
+        return False
+
+    def busy(self) -> bool:
+        return bool(self.queue or self.solo_queue or self.small_queue or self.running or self.solo
+                    or self.small)
 
 
 class WalkServer:
-    """Serve walk jobs with continuous batching on one GPU (complex64 by default)."""
+    """Serve walk jobs on one GPU (complex64 by default): groups of whole-walk
+    launches for jobs that fit one workgroup (up to `small_group` per launch, on
+    `small_streams` streams), a continuous batch for mid-size jobs, and
+    `solo_slots` solo lanes for jobs of at least `solo_arcs` arcs.
+    The batch admits jobs while their arcs total at most `batch_arcs`, which
+    bounds the time of one batch launch and so the latency of every job in it."""
 
     def __init__(self, capacity: int = 64, budget_bytes: int | None = None, chunk: int = 64,
                  dtype: str = "c64", max_tiles: int = 1 << 18, workers: int = 4, device=None,
-                 keep_states: bool = False):
+                 keep_states: bool = False, solo_arcs: int = 1 << 19, solo_chunk: int = 64,
+                 batch_arcs: int | None = 1 << 21, solo_slots: int = 1, small_group: int = 16,
+                 small_streams: int = 3):
         import torch
 
         from .walk import Batch
@@ -120,9 +194,17 @@ class WalkServer:
             budget_bytes = int(0.5 * free)
         self.dtype = dtype
         self.chunk = chunk
+        self.solo_arcs = solo_arcs
+        self.solo_chunk = solo_chunk
         self.keep_states = keep_states
-        self.batch = Batch(capacity, max_tiles, dtype, device=self.device)
-        self.adm = AdmissionController(capacity, budget_bytes)
+        self.s_batch = torch.cuda.Stream(self.device)
+        self.small_group = small_group
+        # small-lane launches in flight: [jobs, stream, event, descriptor buffer]
+        self.small_lanes = [[[], torch.cuda.Stream(self.device), None, None] for _ in range(small_streams)]
+        # one stream per solo lane: [job, stream, event after its last chunk, steps left]
+        self.solo_lanes = [[None, torch.cuda.Stream(self.device), None, 0] for _ in range(solo_slots)]
+        self.batch = Batch(capacity, max_tiles, dtype, device=self.device, stream=self.s_batch)
+        self.adm = AdmissionController(capacity, budget_bytes, batch_arcs, solo_slots)
         self.pool = ThreadPoolExecutor(max_workers=workers)
         self.building: list[tuple[Job, Future]] = []
         self.live: dict[int, tuple] = {}
@@ -130,23 +212,34 @@ class WalkServer:
         self.t0 = time.perf_counter()
         self.cycles = 0
         self._cancel: set[int] = set()
+        self._batch_ev = None       # event after the batch lane's last chunk
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
 
     # -- intake ------------------------------------------------------------
     def submit(self, job: Job) -> None:
-        """Accept a job now: its host-side plan is built in the background."""
+        """Accept a job now: its host-side plan is built in the background, and
+        the plan's path picks the lane."""
         from .walk import Plan
         job.status = "building"
-
-        # coined jobs on cycles, grids and hypercubes take the index-free slot-major path;
-        # everything else the CSR path (both run inside the batch)
-        layout = "structured" if job.kind == "coined" else "csr"
+        solo = job.arcs >= self.solo_arcs
 
         def build():
-            return Plan(job.graph, job.kind, dtype=self.dtype, layout=layout, device=self.device,
+            # alone, the plan picks its fastest path; a graph that fits one
+            # workgroup goes to the small lane, the rest of the mid-size jobs
+            # to the batch (coined walks on cycles, grids and hypercubes in the
+            # index-free slot-major layout, everything else on CSR)
+            plan = Plan(job.graph, job.kind, dtype=self.dtype, layout="auto", device=self.device,
                         upload=False, **job.params)
+            if solo:
+                return plan, "solo"
+            if plan.structure == "small":
+                return plan, "small"
+            plan.close()
+            layout = "structured" if job.kind == "coined" else "csr"
+            return Plan(job.graph, job.kind, dtype=self.dtype, layout=layout, device=self.device,
+                        upload=False, **job.params), "batch"
 
         self.building.append((job, self.pool.submit(build)))
 
@@ -158,7 +251,7 @@ class WalkServer:
         still = []
         for job, fut in self.building:
             if fut.done():
-                plan = fut.result()
+                plan, job.lane = fut.result()
                 job.footprint = plan.device_bytes
                 if self.adm.offer(job):
                     self.live[job.job_id] = (plan, None)
@@ -170,63 +263,138 @@ class WalkServer:
                 still.append((job, fut))
         self.building = still
 
+    def _upload(self, job: Job, stream):
+        """Device tables and state of an admitted job (later launches on a lane's
+        stream wait for this upload on torch's current stream)."""
+        plan, _ = self.live[job.job_id]
+        plan.upload()
+        psi = plan.state(job.psi0)
+        self.live[job.job_id] = (plan, psi)
+        job.admitted_at = self.now()
+        return plan, psi
+
     # -- one scheduling cycle -------------------------------------------------
     def cycle(self) -> int:
-        """Admit, run one chunk, reap.  Returns the number of launches run."""
+        """Poll both lanes once; returns the number of launches or steps enqueued."""
         self._collect_built()
+        work = self._small_lane() + self._batch_lane() + self._solo_lane()
+        self.cycles += 1
+        return work
+
+    def _batch_lane(self) -> int:
+        if self._batch_ev is not None and not self._batch_ev.query():
+            return 0
+        self._batch_ev = None
         changed = False
         for job in list(self.adm.running.values()):
             if job.job_id in self._cancel:
                 self._cancel.discard(job.job_id)
                 self._finish(job, cancelled=True)
                 changed = True
+            elif self.batch.remaining(job.slot) == 0:
+                self._finish(job)
+                changed = True
         for job in self.adm.admit():
-            plan, _ = self.live[job.job_id]
-            plan.upload()
-            psi = plan.state(job.psi0)
+            plan, psi = self._upload(job, self.s_batch)
             self.batch.set_slot(job.slot, plan, psi, job.steps)
-            self.live[job.job_id] = (plan, psi)
-            job.admitted_at = self.now()
             changed = True
         if changed:
-            self.batch.commit()
-        active = list(self.adm.running.values())
-        if not active:
-            return 0
-        rem = [self.batch.remaining(j.slot) for j in active]
-        pending = [r for r in rem if r > 0]
+            self.batch.commit(stream=self.s_batch)
+        pending = [r for r in (self.batch.remaining(j.slot) for j in self.adm.running.values()) if r > 0]
         n = min(self.chunk, min(pending)) if pending else 0
-        if n:
-            self.batch.run(n)
-        self.torch.cuda.synchronize(self.device)
-        self.cycles += 1
-        for job in active:
-            if self.batch.remaining(job.slot) == 0:
-                self._finish(job)
+        if n or changed:
+            if n:
+                self.batch.run(n, stream=self.s_batch)
+            self._batch_ev = self.torch.cuda.Event()
+            self._batch_ev.record(self.s_batch)
         return n
 
-    def _finish(self, job: Job, cancelled: bool = False) -> None:
+    def _small_lane(self) -> int:
+        from .walk import evolve_many
+        work = 0
+        for lane in self.small_lanes:
+            jobs, stream, ev, _ = lane
+            if ev is not None and not ev.query():
+                continue
+            for job in jobs:
+                self._cancel.discard(job.job_id)
+                self._finish(job, stream=stream)
+            lane[0], lane[2], lane[3] = [], None, None
+            jobs = self.adm.admit_small(self.small_group)
+            if not jobs:
+                continue
+            plans, states = [], []
+            for job in jobs:
+                plan, psi = self._upload(job, stream)
+                plans.append(plan)
+                states.append(psi)
+            lane[3] = evolve_many(plans, states, [j.steps for j in jobs], stream=stream)
+            lane[0] = jobs
+            lane[2] = self.torch.cuda.Event()
+            lane[2].record(stream)
+            work += len(jobs)
+        return work
+
+    def _solo_lane(self) -> int:
+        work = 0
+        for lane in self.solo_lanes:
+            job, stream, ev, left = lane
+            if ev is not None and not ev.query():
+                continue
+            lane[2] = None
+            if job is not None and (job.job_id in self._cancel or left == 0):
+                cancelled = job.job_id in self._cancel
+                self._cancel.discard(job.job_id)
+                self._finish(job, cancelled=cancelled, stream=stream)
+                job = lane[0] = None
+            if job is None:
+                job = self.adm.admit_solo()
+                if job is None:
+                    continue
+                self._upload(job, stream)
+                lane[0], left = job, job.steps
+            plan, psi = self.live[job.job_id]
+            k = min(self.solo_chunk, left)
+            if k:
+                plan.evolve(psi, k, stream=stream)
+            lane[3] = left - k
+            lane[2] = self.torch.cuda.Event()
+            lane[2].record(stream)
+            work += k
+        return work
+
+    def _finish(self, job: Job, cancelled: bool = False, stream=None) -> None:
         plan, psi = self.live.pop(job.job_id)
+        stream = stream if stream is not None else self.s_batch
         if not cancelled:
-            p, norm, pm = self.batch.readout(job.slot)
+            if job.lane == "small":
+                p, norm, pm = plan.probabilities(psi, stream=stream)
+            elif job.lane == "solo":
+                p, norm, pm = plan.evolve(psi, 0, readout=True, stream=stream)
+            else:
+                p, norm, pm = self.batch.readout(job.slot, stream=stream)
+            stream.synchronize()
             job.result = {"norm": float(norm), "p_marked": float(pm),
                           "p": p.cpu().numpy() if self.keep_states else None,
                           "psi": psi.cpu().numpy() if self.keep_states else None}
             job.status = "done"
         else:
+            stream.synchronize()
             job.status = "cancelled"
         job.finished_at = self.now()
-        self.batch.clear_slot(job.slot)
+        if job.lane == "batch":
+            self.batch.clear_slot(job.slot)
         self.adm.release(job)
         plan.release_device()
         plan.close()
         self.done.append(job)
 
     def busy(self) -> bool:
-        return bool(self.building or self.adm.queue or self.adm.running)
+        return bool(self.building or self.adm.busy())
 
     def close(self) -> None:
         self.pool.shutdown(wait=True)
+        self.torch.cuda.synchronize(self.device)
         self.batch.close()
 
 
@@ -240,13 +408,13 @@ def serve_stream(server: WalkServer, jobs: list[Job], time_limit: float = 600.0)
             raise TimeoutError("serving stream exceeded its time limit")
         while pending and pending[0].arrival <= t:
             server.submit(pending.popleft())
-        if server.cycle() == 0 and not server.adm.running:
-            time.sleep(0.0005)
+        if server.cycle() == 0:
+            time.sleep(0.0002)
     return server.done
 
 
 def serve_sequential(jobs: list[Job], dtype: str = "c64", device=None, time_limit: float = 600.0):
-    """The plain form: one job at a time, in arrival order, on the single-walk path."""
+    """The plain form: one job at a time, in arrival order, each on its fastest single-walk path."""
     import torch
 
     from .walk import Plan
@@ -255,7 +423,7 @@ def serve_sequential(jobs: list[Job], dtype: str = "c64", device=None, time_limi
     for job in sorted(jobs, key=lambda j: j.arrival):
         while time.perf_counter() - t0 < job.arrival:
             time.sleep(0.0005)
-        plan = Plan(job.graph, job.kind, dtype=dtype, layout="csr", device=dev, **job.params)
+        plan = Plan(job.graph, job.kind, dtype=dtype, layout="auto", device=dev, **job.params)
         psi = plan.state(job.psi0)
         p, norm, pm = plan.evolve(psi, job.steps, readout=True)
         torch.cuda.synchronize(dev)

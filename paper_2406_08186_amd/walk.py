@@ -23,8 +23,14 @@ _LAYOUT = {"auto": L.QW_LAYOUT_AUTO, "csr": L.QW_LAYOUT_CSR, "structured": L.QW_
 
 
 def _stream_ptr(stream, device) -> int:
-    s = stream if stream is not None else torch.cuda.current_stream(device)
-    return int(s.cuda_stream)
+    """Handle of the stream to launch on (default: torch's current stream).  A
+    different stream first waits for the current one, so buffers that torch
+    allocated or filled there are ready before the launch reads or writes them."""
+    cur = torch.cuda.current_stream(device)
+    if stream is None or stream.cuda_stream == cur.cuda_stream:
+        return int(cur.cuda_stream)
+    stream.wait_stream(cur)
+    return int(stream.cuda_stream)
 
 
 class Plan:
@@ -142,6 +148,23 @@ class Plan:
                            scal.data_ptr() + 8, self.work.data_ptr(), self.work.numel(),
                            _stream_ptr(stream, self.device))
         return p[:self.p_len], scal[0], scal[1]
+
+
+def evolve_many(plans: Sequence["Plan"], states: Sequence[torch.Tensor], steps: Sequence[int],
+                stream=None) -> torch.Tensor:
+    """Advance many small walks (plans on the one-workgroup path, one dtype) by
+    their step counts in one launch (qw_small_many).  Returns the device buffer
+    holding the walk descriptors; keep it until the launch has run."""
+    if not (len(plans) == len(states) == len(steps)):
+        raise ValueError("plans, states and step counts must have the same length")
+    for pl, psi in zip(plans, states):
+        pl._check(psi)
+    dev = plans[0].device if plans else torch.device("cuda", 0)
+    nbytes = L.qw_small_many_desc_bytes(len(plans))
+    desc = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    L.qw_small_many([pl._plan for pl in plans], [psi.data_ptr() for psi in states], list(steps),
+                    desc.data_ptr(), desc.numel(), _stream_ptr(stream, dev))
+    return desc
 
 
 class Batch:

@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 def test_library_exports_every_declared_symbol():
     text = open(HEADER).read()
-    declared = set(re.findall(r"^\s*(?:int|double|const char \*)\s*(qw_\w+)\s*\(", text, re.M))
+    declared = set(re.findall(r"^\s*(?:int|double|size_t|const char \*)\s*(qw_\w+)\s*\(", text, re.M))
     assert len(declared) >= 11
     lib = L.lib()
     for name in declared:
@@ -113,7 +113,8 @@ def test_evolve_before_upload_is_state_error():
     (I.hypercube(3), 0, L.QW_LAYOUT_STRUCTURED, "hypercube"),
     (I.hypercube(10), 0, L.QW_LAYOUT_CSR, "general"),
     (I.torus(40, 30), 0, L.QW_LAYOUT_AUTO, "torus"),
-    (I.torus(40, 30), 1, L.QW_LAYOUT_AUTO, "torus"),
+    (I.torus(40, 30), 1, L.QW_LAYOUT_AUTO, "small"),      # 1200 vertices fit one workgroup's LDS
+    (I.torus(100, 80), 1, L.QW_LAYOUT_AUTO, "torus"),
     (I.torus(3, 3), 1, L.QW_LAYOUT_STRUCTURED, "torus"),
     (I.cycle(5000), 0, L.QW_LAYOUT_AUTO, "cycle"),
     (I.cycle_sorted(5000), 1, L.QW_LAYOUT_AUTO, "cycle"),
@@ -135,7 +136,7 @@ def test_path_choice(g, kind, layout, expect):
     assert info.state_bytes == 16 * info.state_len
     assert info.work_bytes >= 2 * info.state_bytes and info.graph_bytes > 0
     if expect == "torus":
-        assert tuple(info.dims) == (40, 30) or tuple(info.dims) == (3, 3)
+        assert tuple(info.dims) in ((40, 30), (3, 3), (100, 80))
     L.qw_plan_destroy(p)
 
 
@@ -226,3 +227,25 @@ def test_dense_layout_plans():
     c = I.complete(7)
     assert c.n_arcs == 42 and all(sorted(c.row(v).tolist()) == [w for w in range(7) if w != v]
                                   for v in range(7))
+
+
+def test_small_many_host_validation():
+    """qw_small_many's argument checks run before any device work."""
+    assert L.qw_small_many_desc_bytes(0) == 0 and L.qw_small_many_desc_bytes(-3) == 0
+    one = L.qw_small_many_desc_bytes(1)
+    assert one > 0 and L.qw_small_many_desc_bytes(10) == 10 * one
+    L.qw_small_many([], [], [], 0, 0, 0)                      # nothing to do
+    p = _create(I.cycle(64), kind=0, coin=0, dtype=1)
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "small"
+    with pytest.raises(L.QwError) as e:                      # not uploaded
+        L.qw_small_many([p], [1 << 20], [3], 1 << 20, one, 0)
+    assert e.value.code == L.QW_ESTATE
+    with pytest.raises(L.QwError) as e:                      # descriptor buffer too small
+        L.qw_small_many([p], [1 << 20], [3], 1 << 20, one - 1, 0)
+    assert e.value.code == L.QW_ENOMEM
+    with pytest.raises(L.QwError) as e:                      # null descriptor buffer
+        L.qw_small_many([p], [1 << 20], [3], 0, one, 0)
+    assert e.value.code == L.QW_EINVAL
+    code = L.lib().qw_small_many(None, None, None, -1, None, 0, None)
+    assert code == L.QW_EINVAL
+    L.qw_plan_destroy(p)

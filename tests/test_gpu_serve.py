@@ -1,7 +1,8 @@
-"""GPU test of the serving loop: each job's result is the same alone and in the
-mix (bitwise against a one-slot batch, to rounding against the plain path),
-jobs arriving while others run overlap with them, and the device budget is
-respected."""
+"""GPU test of the serving loop: each job's result is the same alone and
+served (bitwise: batch-lane jobs against a one-slot batch, small- and
+solo-lane jobs against one uninterrupted evolve of the same plan; to rounding
+against the plain CSR path), jobs arriving while others run overlap with
+them, and the device budget is respected."""
 import numpy as np
 import pytest
 import torch
@@ -11,47 +12,67 @@ from paper_2406_08186_amd.serve import WalkServer, make_job, serve_stream
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_alone():
+@pytest.mark.parametrize("solo_arcs", [1 << 40, 20000])
+def test_served_results_equal_alone(solo_arcs):
     from paper_2406_08186_amd.walk import Batch, Plan
     rng = np.random.default_rng(11)
     jobs = [make_job(i, rng, arc_range=(1e3, 6e4), steps_range=(20, 120)) for i in range(14)]
     for i, j in enumerate(jobs):
-        j.arrival = 0.01 * i
-    print(f"[case] serve {len(jobs)} jobs", flush=True)
+        j.arrival = 0.002 * i
+    print(f"[case] serve {len(jobs)} jobs, solo lane from {solo_arcs} arcs", flush=True)
     budget = 64 * 2**20
     srv = WalkServer(capacity=6, budget_bytes=budget, chunk=16, dtype="c64", max_tiles=1 << 14,
-                     keep_states=True)
+                     keep_states=True, solo_arcs=solo_arcs, solo_chunk=16)
     peak = [0]
-    orig = srv.adm.admit
+    orig_admit, orig_solo = srv.adm.admit, srv.adm.admit_solo
 
-    def admit_and_track():
-        out = orig()
+    def track(fn):
+        def wrapped():
+            out = fn()
+            peak[0] = max(peak[0], srv.adm.used)
+            return out
+        return wrapped
+
+    orig_small = srv.adm.admit_small
+
+    def track_small(limit):
+        out = orig_small(limit)
         peak[0] = max(peak[0], srv.adm.used)
         return out
 
-    srv.adm.admit = admit_and_track
+    srv.adm.admit, srv.adm.admit_solo = track(orig_admit), track(orig_solo)
+    srv.adm.admit_small = track_small
     done = serve_stream(srv, jobs, time_limit=300)
     srv.close()
     assert len(done) == len(jobs) and all(j.status == "done" for j in done)
     assert peak[0] <= budget
+    lanes = {j.lane for j in done}
+    assert lanes == ({"small", "batch"} if solo_arcs > 1e6 else {"small", "batch", "solo"})
     overlapped = sum(1 for a in done for b in done
                      if a is not b and a.admitted_at < b.admitted_at < a.finished_at)
     assert overlapped > 0, "no job joined while another was running"
     for j in done:
-        plan = Plan(j.graph, j.kind, dtype="c64", layout="structured" if j.kind == "coined" else "csr",
-                    **j.params)
-        b = Batch(capacity=1, max_tiles=1 << 14, dtype="c64")
-        psi = plan.state(j.psi0)
-        b.set_slot(0, plan, psi, j.steps)
-        b.commit()
-        b.run_to_completion()
-        b.readout(0)
+        if j.lane in ("solo", "small"):
+            plan = Plan(j.graph, j.kind, dtype="c64", layout="auto", **j.params)
+            psi = plan.state(j.psi0)
+            plan.evolve(psi, j.steps)
+        else:
+            plan = Plan(j.graph, j.kind, dtype="c64", layout="structured" if j.kind == "coined" else "csr",
+                        **j.params)
+            b = Batch(capacity=1, max_tiles=1 << 14, dtype="c64")
+            psi = plan.state(j.psi0)
+            b.set_slot(0, plan, psi, j.steps)
+            b.commit()
+            b.run_to_completion()
+            b.readout(0)
+            torch.cuda.synchronize()
+            b.close()
         torch.cuda.synchronize()
         alone = psi.cpu().numpy()
-        assert np.array_equal(alone, j.result["psi"]), f"job {j.job_id} differs alone vs in the mix"
-        plain = plan.state(j.psi0)
-        plan.evolve(plain, j.steps)
+        assert np.array_equal(alone, j.result["psi"]), f"job {j.job_id} ({j.lane}) differs alone vs served"
+        ref = Plan(j.graph, j.kind, dtype="c64", layout="csr", **j.params)
+        plain = ref.state(j.psi0)
+        ref.evolve(plain, j.steps)
         torch.cuda.synchronize()
         assert np.abs(plain.cpu().numpy() - j.result["psi"]).max() < 1e-5
         assert abs(j.result["norm"] - 1.0) < 1e-5
-        b.close()

@@ -71,3 +71,32 @@ def test_job_stream_recipe():
         assert abs(np.linalg.norm(j.psi0) - 1) < 1e-12
     t = poisson_arrivals(1000, 4.0, np.random.default_rng(1))
     assert np.all(np.diff(t) > 0) and abs(1000 / t[-1] - 4.0) < 0.5
+
+
+def test_batch_arc_cap_and_solo_lane():
+    a = AdmissionController(capacity=8, budget_bytes=1000, batch_arcs=100)
+    jobs = [_job(i, 10) for i in range(4)]
+    for j, arcs in zip(jobs, [60, 30, 20, 5]):
+        j.graph = type("G", (), {"n_arcs": arcs})()
+        assert a.offer(j)
+    assert [j.job_id for j in a.admit()] == [0, 1]    # 60 + 30; 20 would pass the cap of 100
+    assert a.arcs_running == 90
+    a.release(jobs[0])
+    assert [j.job_id for j in a.admit()] == [2, 3]
+    assert a.arcs_running == 55
+    big = _job(9, 10)
+    big.graph = type("G", (), {"n_arcs": 500})()
+    big.lane = "solo"
+    assert a.offer(big) and list(a.solo_queue) == [big]
+    assert a.admit_solo() is big and a.admit_solo() is None   # one solo slot by default
+    assert a.used == 30 + 10
+    a.release(big)
+    assert a.solo == [] and a.used == 30
+    b = AdmissionController(capacity=1, budget_bytes=100, solo_slots=2)
+    s = [_job(20 + i, 30) for i in range(3)]
+    for j in s:
+        j.lane = "solo"
+        b.offer(j)
+    assert b.admit_solo() is s[0] and b.admit_solo() is s[1] and b.admit_solo() is None
+    b.release(s[0])
+    assert b.admit_solo() is s[2] and b.used == 60
