@@ -603,9 +603,9 @@ __device__ __forceinline__ float2 lane_shift(float2 v) {
 // outermost lanes read zeros, so the valid columns shrink by one per stage and
 // the core 64 - 2S lanes are exact after S stages.  Stage s starts at t = 2s,
 // where its rows become exact, and the last stage stores each core row as soon
-// as it is computed.  A stage's rows are rounded to the storage type, as the
-// one-stage kernel rounds its output, and the neighbours are summed in that
-// kernel's order.  Strips at the grid's right and bottom edges are
+// as it is computed.  Values stay FP64 across the stages of a launch and are
+// rounded to the storage type once, when stored; the neighbours are summed in
+// the one-stage kernel's order.  Strips at the grid's right and bottom edges are
 // clamped and overlap their neighbour; duplicate stores write equal values.
 constexpr int kSweepRing = 6;  // rows per unrolled body; holds psi for S <= 5 stages
 
@@ -643,15 +643,15 @@ __device__ __forceinline__ void sweep_strip(const GraphView &g, const T *__restr
       }
     }
   };
-  T yv[S][3];       // stage s-1 (s = 1 .. S) rows, slot = window row mod 3
-  T pr[RING];       // psi, slot = window row mod RING
-  uint32_t mr = 0;  // bit k: window row t - k is marked
+  double2 yv[S][3];  // stage s-1 (s = 1 .. S) rows, slot = window row mod 3
+  double2 pr[RING];  // psi, slot = window row mod RING
+  uint32_t mr = 0;   // bit k: window row t - k is marked
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) yv[s][j] = T{};
+    for (int j = 0; j < 3; ++j) yv[s][j] = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int j = 0; j < RING; ++j) pr[j] = T{};
+  for (int j = 0; j < RING; ++j) pr[j] = make_double2(0.0, 0.0);
 
   // one body: window rows t0 .. t0 + RING - 1.  FULL: every row exists and
   // every stage is past its warm-up, so the body has no branches.
@@ -673,27 +673,27 @@ __device__ __forceinline__ void sweep_strip(const GraphView &g, const T *__restr
     for (int i = 0; i < RING; ++i) {
       const int t = t0 + i;  // t0 is a multiple of RING, so every ring slot below is static
       if (!FULL && t >= n_in) break;
-      yv[0][i % 3] = cy[i];
-      pr[i] = cp[i];
+      yv[0][i % 3] = cvt(cy[i]);
+      pr[i] = cvt(cp[i]);
       if (MARK) mr = (mr << 1) | ((cmw[i] >> cms[i]) & 1u);
 #pragma unroll
       for (int st = 1; st <= S; ++st) {
         if (!FULL && t < 2 * st) break;  // window rows above stage st's exact region
-        const T up = yv[st - 1][pmod(i - st - 1, 3)];
-        const T self = yv[st - 1][pmod(i - st, 3)];
-        const T dn = yv[st - 1][pmod(i - st + 1, 3)];
-        const T left = lane_shift<kFromLower>(self), right = lane_shift<kFromUpper>(self);
+        const double2 up = yv[st - 1][pmod(i - st - 1, 3)];
+        const double2 self = yv[st - 1][pmod(i - st, 3)];
+        const double2 dn = yv[st - 1][pmod(i - st + 1, 3)];
+        const double2 left = lane_shift<kFromLower>(self), right = lane_shift<kFromUpper>(self);
         // the one-stage kernel's order: right, left, below, above
-        double2 sum = add(cvt(right), cvt(left));
-        sum = add(sum, cvt(dn));
-        sum = add(sum, cvt(up));
+        double2 sum = add(right, left);
+        sum = add(sum, dn);
+        sum = add(sum, up);
         const bool m = MARK && ((mr >> st) & 1u);
-        const T val = pack<T>(horner_out(cvt(pr[pmod(i - st, RING)]), sum, cvt(self), m, c.alpha[kfirst - st],
-                                         c.beta[kfirst - st]));
+        const double2 val = horner_out(pr[pmod(i - st, RING)], sum, self, m, c.alpha[kfirst - st],
+                                       c.beta[kfirst - st]);
         if (st < S) {
           yv[st][pmod(i - st, 3)] = val;
         } else if (lane >= S && lane < W - S) {
-          *reinterpret_cast<T *>(reinterpret_cast<char *>(Out + row_off(t - S)) + boff) = val;
+          *reinterpret_cast<T *>(reinterpret_cast<char *>(Out + row_off(t - S)) + boff) = pack<T>(val);
         }
       }
     }
@@ -1587,17 +1587,22 @@ hipError_t dense_stage(bool c128, const GraphView &g, const void *y, const void 
 }
 
 StripGrid torus_strips(bool c128, int l1, int l2, int S) {
-  (void)c128;
   StripGrid sg;
   if (S < 2 || S >= kSweepRing || l2 < 64) return StripGrid{};
   sg.width = 64;
   sg.core = 64 - 2 * S;
   sg.halo = S;
   sg.tiles_c = (l2 + sg.core - 1) / sg.core;
-  // strips as tall as possible while every SIMD still gets its wavefronts, but
-  // at least 4S rows so the halo rows stay a minor share of a strip's work
-  const int want_r = std::max(1, kSimds * kSweepWavesPerSimd / sg.tiles_c);
-  int rows = std::max((l1 + want_r - 1) / want_r, kSweepMinRowsPerStage * S);
+  // strips as tall as possible while every SIMD still gets its wavefronts
+  // (complex64: two per SIMD where the strips stay at least 8S rows tall, so a
+  // second wavefront hides latency at little halo cost; else one; complex128,
+  // bound by memory, one), and never below 4S rows, so the halo rows stay a
+  // minor share of a strip's work
+  auto rows_for = [&](int waves_per_simd) {
+    const int want_r = std::max(1, kSimds * waves_per_simd / sg.tiles_c);
+    return (l1 + want_r - 1) / want_r;
+  };
+  int rows = !c128 && rows_for(2) >= 8 * S ? rows_for(2) : std::max(rows_for(1), kSweepMinRowsPerStage * S);
   rows = std::min(rows, l1 - 2 * S);  // a strip's window rows must be distinct grid rows
   if (rows < 1) return StripGrid{};
   sg.rows = rows;
