@@ -36,7 +36,7 @@ METRIC = "arc-steps/s (c64 batched vs c128 plain, L2 err<=1e-4); p50/p99 latency
 # four launches of a time step) measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by a 256 MiB copy (x2.00 / x1.00); profiles/ctqw_torus1024_sweep.md.
 # Valid only for the kernel version named here; None for any other.
-MEASURED_TRAFFIC = {"k_ctqw_torus_sweep<float2,5>": ((4569.5 + 3 * 9002.6) / 4 * 2 + 8194.5) * 1024}
+MEASURED_TRAFFIC = {"k_ctqw_torus_sweep<float2,5>": ((4576.5 + 3 * 8995.1) / 4 * 2 + 8194.5) * 1024}
 
 
 def parse():
