@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--workload", default="grid",
-                    choices=["grid", "batch", "serve", "dense", "hypercube", "cycle"],
+                    choices=["grid", "batch", "serve", "dense", "hypercube", "cycle", "snapshots"],
                     help="grid: the 1024^2 CTQW (default); batch: many CTQW searches on random "
                          "regular graphs in one batch; serve: the Poisson job stream")
     ap.add_argument("--batch-walks", type=int, default=4096)
@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--dense-n", type=int, default=15000)
     ap.add_argument("--dense-columns", default="1,8,32,128")
     ap.add_argument("--dense-dtype", default="c128")
+    ap.add_argument("--snap-every", type=int, default=10, help="snapshots workload: steps between snapshots")
+    ap.add_argument("--hypercube-layout", default="auto", choices=["auto", "csr"],
+                    help="auto: index-free slot-major kernel; csr: the general CSR coined path")
     ap.add_argument("--hypercube-steps", type=int, default=0,
                     help="override the step count (profiling runs); 0 = ceil((pi/2) sqrt(N ln N))")
     ap.add_argument("--hypercube-dtypes", default="c64,c128")
@@ -174,6 +177,9 @@ def main():
         return
     if args.workload == "cycle":
         run_cycle(args)
+        return
+    if args.workload == "snapshots":
+        run_snapshots(args)
         return
     spp = args.steps_per_pass
     dtypes = args.dtypes.split(",")
@@ -586,7 +592,7 @@ def run_hypercube(args):
     ref = cf.hypercube_search_state(dim, steps, g.row_ptr, g.col)
     res = {}
     for dtype in args.hypercube_dtypes.split(","):
-        pl = Plan(g, "coined", dtype=dtype, marked=[0])
+        pl = Plan(g, "coined", dtype=dtype, marked=[0], layout=args.hypercube_layout)
         psi0 = np.full(g.n_arcs, 1 / math.sqrt(g.n_arcs), dtype=np.complex128)
         psi = pl.state(psi0)
         pl.evolve(psi, 2)
@@ -601,19 +607,93 @@ def run_hypercube(args):
         wall = time.perf_counter() - t0
         ms = a.elapsed_time(b)
         es = 8 if dtype == "c64" else 16
+        # algorithmic bytes per arc-step: read and write the state (2S); the
+        # general CSR path also reads rev (4 B) and row_ptr (4/d B)
+        per_arc = 2 * es + (0 if pl.structure == "hypercube" else 4 + 4 / dim)
         got = psi.cpu().numpy().astype(np.complex128)
         res[dtype] = {"value": g.n_arcs * steps / (ms * 1e-3), "ms": ms, "wall_s": wall,
-                      "step_us": ms * 1e3 / steps,
-                      "step_gbs": 2 * es * g.n_arcs / (ms * 1e-3 / steps) / 1e9,
-                      "frac": 2 * es * g.n_arcs / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS,
+                      "step_us": ms * 1e3 / steps, "bytes_per_arc_step": per_arc,
+                      "step_gbs": per_arc * g.n_arcs / (ms * 1e-3 / steps) / 1e9,
+                      "frac": per_arc * g.n_arcs / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS,
                       "p_marked": float(pm), "p_marked_ref": float(abs(o[0]) ** 2),
                       "l2_vs_closed_form": float(np.linalg.norm(got - ref)), "norm": float(norm),
                       "path": pl.structure}
         del psi
         pl.close()
     print(json.dumps({"workload": "coined_search_hypercube20", "steps": steps, "arcs": g.n_arcs,
-                      "unit": "arc-steps/s", "roofline_bytes_per_arc_step": "2S (read + write, slot-major)",
+                      "unit": "arc-steps/s", "layout": args.hypercube_layout,
                       **{k: v for k, v in res.items()}}), flush=True)
+
+
+# ---------------------------------------------------------------- streamed snapshots
+
+def run_snapshots(args):
+    """The 1024 x 1024 grid CTQW pass (1000 steps, complex64) with a snapshot
+    every --snap-every steps brought to host memory: compute alone, the naive
+    form (evolve, then a synchronous copy per snapshot), and the streamed form
+    (device ring + pinned host buffers, copies on a second stream), for states
+    and for FP64 distributions."""
+    import numpy as np
+    import torch
+
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Plan, stream_snapshots
+    g = I.torus(L_SIDE, L_SIDE)
+    v0 = (L_SIDE // 2) * L_SIDE + L_SIDE // 2
+    psi0 = I.ket_vertex(g.n, v0)
+    pl = Plan(g, "ctqw", dtype="c64", gamma=GAMMA, dt=DT, taylor_order=K_ORDER)
+    every = args.snap_every
+    snaps = list(range(every, STEPS_PER_PASS + 1, every))
+
+    def timed(fn):
+        psi = pl.state(psi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn(psi)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out, psi
+
+    def compute(psi):
+        pl.evolve(psi, STEPS_PER_PASS)
+
+    def naive(psi):
+        out, at = [], 0
+        for k in snaps:
+            pl.evolve(psi, k - at)
+            at = k
+            out.append(psi.cpu().numpy())
+        return out
+
+    pinned_s = [torch.empty(g.n, dtype=torch.complex64, pin_memory=True) for _ in snaps]
+    pinned_p = [torch.empty(g.n, dtype=torch.float64, pin_memory=True) for _ in snaps]
+    timed(compute)                                  # warm-up
+    t_comp, _, ref = timed(compute)
+    t_naive, out_n, _ = timed(naive)
+    t_state, out_s, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "state", host=pinned_s))
+    t_prob, out_p, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "probability", host=pinned_p))
+    # the copy engine's rate alone: the same device-to-pinned copies, nothing else running
+    src = pl.state(psi0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h in pinned_s:
+        h.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t_d2h = time.perf_counter() - t0
+    same = all(np.array_equal(a, b) for a, b in zip(out_n, out_s))
+    final_ok = np.array_equal(out_s[-1], ref.cpu().numpy())
+    mb_state = len(snaps) * g.n * 8 / 1e6
+    mb_prob = len(snaps) * g.n * 8 / 1e6
+    print(json.dumps({
+        "workload": f"ctqw_torus_{L_SIDE}x{L_SIDE}_c64_{STEPS_PER_PASS}steps_snapshot_every_{every}",
+        "snapshots": len(snaps), "compute_only_ms": t_comp * 1e3,
+        "naive_states_ms": t_naive * 1e3, "streamed_states_ms": t_state * 1e3,
+        "streamed_probabilities_ms": t_prob * 1e3,
+        "streamed_overhead_vs_compute": t_state / t_comp - 1.0,
+        "naive_overhead_vs_compute": t_naive / t_comp - 1.0,
+        "states_MB": mb_state, "probabilities_MB": mb_prob,
+        "streamed_states_GBps": mb_state / 1e3 / t_state, "d2h_alone_GBps": mb_state / 1e3 / t_d2h,
+        "streamed_equals_naive": same, "final_equals_unsnapshotted": final_ok,
+        "arc_steps_per_s_streamed": g.n_arcs * STEPS_PER_PASS / t_state}), flush=True)
 
 
 # ---------------------------------------------------------------- 64-cycle latency

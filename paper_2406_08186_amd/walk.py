@@ -253,6 +253,61 @@ def _steps_of(rng) -> list[int]:
     return list(range(*rng))
 
 
+def stream_snapshots(plan: Plan, psi: torch.Tensor, steps: Sequence[int], kind: str = "state",
+                     ring: int = 3, host: Sequence[torch.Tensor] | None = None) -> list[np.ndarray]:
+    """Evolve psi in place through the step indices `steps` (increasing, from the
+    state's current step 0) and return, for each, the state (kind "state") or
+    its FP64 vertex probabilities (kind "probability") in host memory.
+
+    Each snapshot is produced on torch's current stream into one of `ring`
+    device slots (a copy of the state, or the qw_probabilities readout) and
+    copied to pinned host memory on a second stream while the walk moves on;
+    a slot is reused only after its copy has finished.  The snapshots equal
+    those of evolve calls stopped at each step (the same kernels run).  `host`
+    may supply the pinned destination tensors (one per step) for reuse."""
+    if kind not in ("state", "probability"):
+        raise ValueError("kind is 'state' or 'probability'")
+    steps = list(steps)
+    if any(b <= a for a, b in zip(steps, steps[1:])) or (steps and steps[0] < 0):
+        raise ValueError("steps must be increasing and non-negative")
+    plan._check(psi)
+    dev = plan.device
+    cs = torch.cuda.current_stream(dev)
+    xs = torch.cuda.Stream(dev)
+    shape, dt = (psi.shape, psi.dtype) if kind == "state" else ((plan.p_len,), torch.float64)
+    if host is None:
+        host = [torch.empty(shape, dtype=dt, pin_memory=True) for _ in steps]
+    elif len(host) != len(steps) or any(h.shape != shape or h.dtype != dt or not h.is_pinned() for h in host):
+        raise ValueError("host buffers must be pinned, one per step, of the snapshot's shape and dtype")
+    if kind == "state":
+        slots = [torch.empty_like(psi) for _ in range(ring)]
+    else:
+        slots = [torch.empty(max(plan.p_len, 1), dtype=torch.float64, device=dev) for _ in range(ring)]
+        scal = torch.empty(2, dtype=torch.float64, device=dev)
+    free = [None] * ring
+    at = 0
+    for j, k in enumerate(steps):
+        plan.evolve(psi, k - at, stream=cs)
+        at = k
+        slot = j % ring
+        if free[slot] is not None:
+            cs.wait_event(free[slot])
+        if kind == "state":
+            slots[slot].copy_(psi)
+        else:
+            L.qw_probabilities(plan._plan, psi.data_ptr(), slots[slot].data_ptr(), scal.data_ptr(), None,
+                               plan.work.data_ptr(), plan.work.numel(), int(cs.cuda_stream))
+        ready = torch.cuda.Event()
+        ready.record(cs)
+        xs.wait_event(ready)
+        with torch.cuda.stream(xs):
+            host[j].copy_(slots[slot][:host[j].numel()], non_blocking=True)
+        free[slot] = torch.cuda.Event()
+        free[slot].record(xs)
+    xs.synchronize()
+    return [h.numpy() for h in host]
+
+
 class _Walk:
     plan: Plan
 
@@ -272,6 +327,13 @@ class _Walk:
 
     def probability_distribution(self, states: Iterable[torch.Tensor]) -> list[torch.Tensor]:
         return [self.plan.probabilities(s)[0].clone() for s in states]
+
+    def simulate_host(self, range=1, state=None, kind: str = "state") -> list[np.ndarray]:
+        """simulate() streamed to host memory: states (or, with kind
+        "probability", FP64 distributions) at the step indices of range(...),
+        copied out on a second stream while the walk continues."""
+        psi = self.plan.state(state)
+        return stream_snapshots(self.plan, psi, _steps_of(range), kind)
 
 
 class Coined(_Walk):
