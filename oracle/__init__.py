@@ -71,6 +71,8 @@ def _load():
         lib.orc_reverse_arcs.restype = C.c_int
         lib.orc_coined_evolve.argtypes = [C.c_int64, i64p, i32p, i64p, C.c_int, u8p, dp, C.c_int64]
         lib.orc_coined_evolve.restype = C.c_int
+        lib.orc_coined_evolve_general.argtypes = [C.c_int64, i64p, i64p, dp, C.c_int64, u8p, dp, C.c_int64]
+        lib.orc_coined_evolve_general.restype = C.c_int
         lib.orc_coined_prob.argtypes = [C.c_int64, i64p, i32p, dp, dp]
         lib.orc_coined_prob.restype = None
         lib.orc_ctqw_evolve.argtypes = [C.c_int64, i64p, i32p, C.c_double, u8p, C.c_double,
@@ -155,6 +157,88 @@ def coined_evolve(row_ptr, col, psi0, steps: int, coin: int = GROVER, marked=Non
                                    _ptr(buf, C.c_double), int(steps))
     if st == -3:
         raise ValueError("Hadamard coin needs degree 2 at every unmarked vertex")
+    if st != 0:
+        raise RuntimeError(f"oracle coined evolve failed ({st})")
+    return psi
+
+
+def fourier_coin(d: int) -> np.ndarray:
+    """The d x d Fourier coin, F[j][k] = exp(2 pi i j k / d) / sqrt(d) (Sec. 3.2)."""
+    j = np.arange(d)
+    return np.exp(2j * np.pi * np.outer(j, j) / d) / np.sqrt(d)
+
+
+def persistent_successor(row_ptr, col, dims) -> np.ndarray:
+    """For each arc v -> w of a cycle (dims = (n,)) or a periodic l1 x l2 grid
+    (dims = (l1, l2), vertex r*l2 + c), the index of the arc w -> u that keeps
+    the direction: u = w + (w - v) in lattice coordinates, taken modulo the
+    sides.  The persistent shift sends the amplitude of arc v -> w there."""
+    rp, cl = _csr(row_ptr, col)
+    n = rp.size - 1
+    dims = tuple(int(x) for x in dims)
+    if dims == (n,):
+        coords = np.arange(n)[:, None]
+    elif len(dims) == 2 and dims[0] * dims[1] == n:
+        v = np.arange(n)
+        coords = np.stack([v // dims[1], v % dims[1]], axis=1)
+    else:
+        raise ValueError("dims must be (n,) for a cycle or (l1, l2) with l1 * l2 = n")
+    side = np.array(dims)
+    tails = np.repeat(np.arange(n), np.diff(rp))
+    step = (coords[cl] - coords[tails]) % side        # displacement w - v, modulo the sides
+    ahead = (coords[cl] + step) % side                # u = w + (w - v)
+    u = ahead[:, 0] if len(dims) == 1 else ahead[:, 0] * dims[1] + ahead[:, 1]
+    succ = np.empty(cl.size, dtype=np.int64)
+    for a in range(cl.size):                          # the arc w -> u in row w
+        w = int(cl[a])
+        row = cl[rp[w]:rp[w + 1]]
+        hit = np.nonzero(row == u[a])[0]
+        if hit.size != 1:
+            raise ValueError(f"arc {a}: no unique arc {w} -> {int(u[a])}")
+        succ[a] = rp[w] + int(hit[0])
+    return succ
+
+
+def coined_evolve_general(row_ptr, col, psi0, steps: int, coin="grover", shift: str = "flipflop",
+                          dims=None, marked=None) -> np.ndarray:
+    """(S C)^steps psi0 with coin "grover", "hadamard", "fourier" or a d x d
+    matrix (applied in each row's order, the coin basis; marked vertices take
+    -I), and shift "flipflop" (S|v,w> = |w,v>) or "persistent" (the arc
+    straight ahead on a cycle or periodic grid given by dims)."""
+    rp, cl = _csr(row_ptr, col)
+    n = rp.size - 1
+    if shift == "flipflop":
+        dest = reverse_arcs(rp, cl)
+    elif shift == "persistent":
+        dest = persistent_successor(rp, cl, dims)
+    else:
+        raise ValueError("shift is 'flipflop' or 'persistent'")
+    if dest.size == 0:
+        dest = np.zeros(1, np.int64)
+    degs = np.diff(rp)
+    d = int(degs.max()) if degs.size else 0
+    if isinstance(coin, str) and coin == "grover":
+        mat = None
+    elif isinstance(coin, str) and coin == "hadamard":
+        mat = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2)
+    elif isinstance(coin, str) and coin == "fourier":
+        mat = fourier_coin(d)
+    else:
+        mat = np.asarray(coin, dtype=np.complex128)
+        if mat.ndim != 2 or mat.shape[0] != mat.shape[1]:
+            raise ValueError("coin matrix must be square")
+    psi = np.ascontiguousarray(np.array(psi0, dtype=np.complex128, copy=True))
+    if psi.size != cl.size:
+        raise ValueError("state length must equal the arc count")
+    m = _marked_bytes(n, marked)
+    buf = psi.view(np.float64) if psi.size else np.zeros(2, np.float64)
+    mbuf = None if mat is None else np.ascontiguousarray(mat, dtype=np.complex128).view(np.float64)
+    st = _load().orc_coined_evolve_general(n, _ptr(rp, C.c_int64), _ptr(np.ascontiguousarray(dest), C.c_int64),
+                                           None if mbuf is None else _ptr(mbuf, C.c_double),
+                                           0 if mat is None else mat.shape[0], _ptr(m, C.c_uint8),
+                                           _ptr(buf, C.c_double), int(steps))
+    if st == -3:
+        raise ValueError("the coin matrix's size differs from a vertex degree")
     if st != 0:
         raise RuntimeError(f"oracle coined evolve failed ({st})")
     return psi

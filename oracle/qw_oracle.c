@@ -171,6 +171,54 @@ int orc_coined_evolve(int64_t n, const int64_t *row_ptr, const int32_t *col,
   return 0;
 }
 
+/*
+ * Coined evolution with any coin and shift (Sec. 3.2): psi <- (S C)^steps psi,
+ * in place.  coin_mat: NULL for the Grover coin, else an interleaved complex
+ * d x d matrix (row-major) applied to every unmarked vertex of degree
+ * coin_dim, in the order of its row (the coin basis); marked vertices take
+ * -I.  dest[a]: the arc that receives phi_a -- the reverse arc for the
+ * flip-flop shift, the arc straight ahead for the persistent shift; it must
+ * be a permutation of the arcs.  Returns 0, -3 if a vertex with arcs, not
+ * marked, has a degree other than coin_dim, -4 on allocation failure.
+ */
+int orc_coined_evolve_general(int64_t n, const int64_t *row_ptr, const int64_t *dest,
+                              const double *coin_mat, int64_t coin_dim, const uint8_t *marked,
+                              double *psi_io, int64_t steps) {
+  int64_t n_arcs = row_ptr[n];
+  if (coin_mat) {
+    for (int64_t v = 0; v < n; ++v) {
+      int64_t d = row_ptr[v + 1] - row_ptr[v];
+      int mk = marked ? marked[v] : 0;
+      if (!mk && d != 0 && d != coin_dim) return -3;
+    }
+  }
+  const cplx *cm = (const cplx *)coin_mat;
+  cplx *psi = (cplx *)psi_io;
+  cplx *phi = (cplx *)malloc(sizeof(cplx) * (size_t)(n_arcs > 0 ? n_arcs : 1));
+  if (!phi) return -4;
+  for (int64_t s = 0; s < steps; ++s) {
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(orc_max_threads())
+    for (int64_t v = 0; v < n; ++v) {
+      int64_t lo = row_ptr[v], hi = row_ptr[v + 1];
+      int mk = marked ? marked[v] : 0;
+      if (!cm || mk) {
+        coin_block(ORC_GROVER, mk, lo, hi, psi, phi);
+        continue;
+      }
+      /* phi_j = sum_k C[j][k] psi_k over the vertex's arcs in row order */
+      for (int64_t j = 0; j < hi - lo; ++j) {
+        cplx acc = 0.0;
+        for (int64_t k = 0; k < hi - lo; ++k) acc += cm[j * coin_dim + k] * psi[lo + k];
+        phi[lo + j] = acc;
+      }
+    }
+#pragma omp parallel for schedule(static) num_threads(orc_max_threads())
+    for (int64_t a = 0; a < n_arcs; ++a) psi[dest[a]] = phi[a];
+  }
+  free(phi);
+  return 0;
+}
+
 /* Coined vertex probability p_v = sum over arcs with tail v of |psi_a|^2. */
 void orc_coined_prob(int64_t n, const int64_t *row_ptr, const int32_t *col,
                      const double *psi_in, double *p) {

@@ -107,6 +107,21 @@ def torus(l1: int, l2: int) -> Graph:
                  name=f"torus{l1}x{l2}")
 
 
+def torus_directed(l1: int, l2: int) -> Graph:
+    """Periodic l1 x l2 grid (vertex r*l2 + c) with every row in direction
+    order: c+1, c-1, r+1, r-1 (wrapping) -- the coin basis of position-coin
+    notation on a grid."""
+    if l1 < 3 or l2 < 3:
+        raise ValueError("sides must be at least 3")
+    v = np.arange(l1 * l2, dtype=np.int64)
+    r, c = v // l2, v % l2
+    heads = np.stack([r * l2 + (c + 1) % l2, r * l2 + (c - 1) % l2,
+                      ((r + 1) % l1) * l2 + c, ((r - 1) % l1) * l2 + c], axis=1)
+    row_ptr = np.arange(0, 4 * l1 * l2 + 1, 4, dtype=np.int64)
+    return Graph(n=l1 * l2, row_ptr=row_ptr, col=heads.reshape(-1).astype(np.int32),
+                 name=f"torus{l1}x{l2}d")
+
+
 def hypercube(dim: int) -> Graph:
     """Hypercube Q_dim: v ~ v xor 2^j, rows sorted."""
     if dim < 1:
