@@ -671,7 +671,10 @@ def run_snapshots(args):
     t_naive, out_n, _ = timed(naive)
     t_state, out_s, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "state", host=pinned_s))
     t_prob, out_p, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "probability", host=pinned_p))
-    # the copy engine's rate alone: the same device-to-pinned copies, nothing else running
+    same = all(np.array_equal(a, b) for a, b in zip(out_n, out_s))
+    final_ok = np.array_equal(out_s[-1], ref.cpu().numpy())
+    # the copy engine's rate alone: the same device-to-pinned copies, nothing
+    # else running (this overwrites the pinned buffers, so it comes last)
     src = pl.state(psi0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -679,8 +682,6 @@ def run_snapshots(args):
         h.copy_(src, non_blocking=True)
     torch.cuda.synchronize()
     t_d2h = time.perf_counter() - t0
-    same = all(np.array_equal(a, b) for a, b in zip(out_n, out_s))
-    final_ok = np.array_equal(out_s[-1], ref.cpu().numpy())
     mb_state = len(snaps) * g.n * 8 / 1e6
     mb_prob = len(snaps) * g.n * 8 / 1e6
     print(json.dumps({

@@ -59,8 +59,22 @@ extern "C" {
 #define QW_COINED 0
 #define QW_CTQW 1
 
+/* Coins (Sec. 3.2).  GROVER: (2/d) J - I on each vertex's arcs.  HADAMARD:
+ * (1/sqrt 2)[[1, 1], [1, -1]] (degree 2 only).  FOURIER: F[j][k] =
+ * exp(2 pi i j k / d) / sqrt(d).  MATRIX: the caller's d x d matrix.  Marked
+ * vertices take -I whatever the coin.  HADAMARD, FOURIER and MATRIX act on
+ * the coin basis, which is the order of the vertex's row in the CSR. */
 #define QW_GROVER 0
 #define QW_HADAMARD 1
+#define QW_FOURIER 2
+#define QW_MATRIX 3
+
+/* Shifts (Sec. 3.2).  FLIPFLOP: S|v,w> = |w,v>.  PERSISTENT (the lattice
+ * shift of position-coin notation): the walker keeps its direction, S maps
+ * the arc v -> w to the arc w -> u with u = w + (w - v) on a cycle or a
+ * periodic 2-D grid. */
+#define QW_FLIPFLOP 0
+#define QW_PERSISTENT 1
 
 #define QW_C64 0  /* complex64 state, FP64 reductions */
 #define QW_C128 1 /* complex128 state                 */
@@ -110,7 +124,8 @@ typedef struct qw_csr {
 /* ---- walk description --------------------------------------------------- */
 typedef struct qw_walk_desc {
   int32_t kind;         /* QW_COINED or QW_CTQW                                */
-  int32_t coin;         /* coined: QW_GROVER or QW_HADAMARD (degree 2 only)    */
+  int32_t coin;         /* coined: QW_GROVER, QW_HADAMARD (degree 2 only),
+                           QW_FOURIER or QW_MATRIX                             */
   int32_t dtype;        /* QW_C64 or QW_C128                                   */
   int32_t layout;       /* QW_LAYOUT_AUTO or QW_LAYOUT_CSR                     */
   double gamma;         /* CTQW: gamma > 0 (Sec. 3.1)                          */
@@ -126,7 +141,18 @@ typedef struct qw_walk_desc {
   int64_t n_marked;
   int32_t columns;      /* QW_LAYOUT_DENSE: walks sharing H, 1..128 (0 = 1);
                            other layouts: must be 0 or 1                      */
+  int32_t shift;        /* coined: QW_FLIPFLOP or QW_PERSISTENT                */
+  int32_t coin_dim;     /* coined, QW_MATRIX: d, the degree of every vertex    */
+  const double *coin_matrix; /* coined, QW_MATRIX: host double[2 d d], row-major
+                           interleaved complex C[j][k], copied at creation and
+                           used as given (not checked for unitarity)          */
 } qw_walk_desc;
+/* FOURIER and MATRIX coins and the PERSISTENT shift run on the index-free
+ * lattice kernels only: the graph must be a cycle (rows ordered v+1, v-1) or
+ * a periodic l1 x l2 grid, l1, l2 >= 3, vertex v = r*l2 + c (rows ordered
+ * c+1, c-1, r+1, r-1, wrapping), and the layout AUTO or STRUCTURED; a
+ * PERSISTENT shift with the GROVER coin accepts the rows in any order.
+ * Otherwise QW_EUNSUPPORTED.  Such walks cannot join a batch. */
 
 typedef struct qw_plan qw_plan;
 

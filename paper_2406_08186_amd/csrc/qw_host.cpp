@@ -90,7 +90,8 @@ bool is_cycle(int64_t n, const std::vector<int64_t> &rp, const int32_t *col, boo
   return true;
 }
 
-bool is_torus(int64_t n, const std::vector<int64_t> &rp, const int32_t *col, int32_t *l1o, int32_t *l2o) {
+bool is_torus(int64_t n, const std::vector<int64_t> &rp, const int32_t *col, int32_t *l1o, int32_t *l2o,
+              bool ordered = false) {
   if (n < 9 || rp[1] - rp[0] != 4) return false;
   int64_t s[4];
   for (int i = 0; i < 4; ++i) s[i] = col[rp[0] + i];
@@ -106,8 +107,10 @@ bool is_torus(int64_t n, const std::vector<int64_t> &rp, const int32_t *col, int
                        ((r + l1 - 1) % l1) * l2 + c};
     int64_t got[4];
     for (int i = 0; i < 4; ++i) got[i] = col[rp[v] + i];
-    std::sort(want, want + 4);
-    std::sort(got, got + 4);
+    if (!ordered) {  // any order; else exactly c+1, c-1, r+1, r-1
+      std::sort(want, want + 4);
+      std::sort(got, got + 4);
+    }
     if (!std::equal(want, want + 4, got)) return false;
   }
   *l1o = static_cast<int32_t>(l1);
@@ -148,12 +151,17 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   } else if (w->columns > 1 || w->columns < 0) {
     return fail(QW_EINVAL, "columns > 1 needs the dense layout");
   }
-  if (w->kind == QW_COINED && w->coin != QW_GROVER && w->coin != QW_HADAMARD)
+  if (w->kind == QW_COINED && (w->coin < QW_GROVER || w->coin > QW_MATRIX))
     return fail(QW_EINVAL, "bad coin %d", w->coin);
+  if (w->kind == QW_COINED && w->shift != QW_FLIPFLOP && w->shift != QW_PERSISTENT)
+    return fail(QW_EINVAL, "bad shift %d", w->shift);
+  if (w->kind == QW_COINED && w->coin == QW_MATRIX && (!w->coin_matrix || w->coin_dim < 1))
+    return fail(QW_EINVAL, "the matrix coin needs coin_matrix and coin_dim >= 1");
   if (w->n_marked < 0 || (w->n_marked > 0 && !w->marked)) return fail(QW_EINVAL, "bad marked list");
   if (n > 0 && (!g->row_ptr)) return fail(QW_EINVAL, "null row_ptr");
   p->kind = w->kind;
   p->coin = w->kind == QW_COINED ? w->coin : QW_GROVER;
+  p->shift = w->kind == QW_COINED ? w->shift : QW_FLIPFLOP;
   p->dtype = w->dtype;
   p->layout = w->layout;
   p->n = n;
@@ -258,6 +266,39 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     p->ld = static_cast<int32_t>((n + kDenseK - 1) / kDenseK * kDenseK);
     p->rows_pad = static_cast<size_t>((n + kDenseRows - 1) / kDenseRows * kDenseRows);
     p->dense_bytes = p->rows_pad * static_cast<size_t>(p->ld) * (c128 ? 8 : 4);
+  } else if (p->lattice()) {
+    // Fourier / matrix coins and the persistent shift: lattice kernels only,
+    // rows in direction order unless the coin is Grover (order-invariant)
+    if (p->layout != QW_LAYOUT_AUTO && p->layout != QW_LAYOUT_STRUCTURED)
+      return fail(QW_EUNSUPPORTED, "Fourier and matrix coins and the persistent shift need the structured layout");
+    int32_t a = 0, b = 0;
+    const bool ordered = p->coin != QW_GROVER;
+    if (n > 0 && is_cycle(n, rp, col, ordered)) {
+      structure = kCycle;
+      p->dims[0] = static_cast<int32_t>(n);
+    } else if (n > 0 && is_torus(n, rp, col, &a, &b, ordered)) {
+      structure = kTorus;
+      p->dims[0] = a;
+      p->dims[1] = b;
+    } else {
+      return fail(QW_EUNSUPPORTED, "Fourier and matrix coins and the persistent shift need a cycle (rows v+1, v-1) "
+                                   "or a periodic grid (rows c+1, c-1, r+1, r-1)");
+    }
+    const int d = structure == kCycle ? 2 : 4;
+    if (p->coin == QW_MATRIX) {
+      if (w->coin_dim != d)
+        return fail(QW_EUNSUPPORTED, "matrix coin of size %d on a lattice of degree %d", w->coin_dim, d);
+      p->coin_mat.assign(w->coin_matrix, w->coin_matrix + 2 * d * d);
+    } else if (p->coin == QW_FOURIER) {
+      p->coin_mat.resize(static_cast<size_t>(2 * d * d));
+      const double pi = 3.14159265358979323846;
+      for (int j = 0; j < d; ++j)
+        for (int k = 0; k < d; ++k) {
+          const int m = (j * k) % d;  // exact phase index
+          p->coin_mat[2 * (j * d + k)] = std::cos(2 * pi * m / d) / std::sqrt(static_cast<double>(d));
+          p->coin_mat[2 * (j * d + k) + 1] = std::sin(2 * pi * m / d) / std::sqrt(static_cast<double>(d));
+        }
+    }
   } else if (p->layout == QW_LAYOUT_AUTO && small_fits && n > 0) {
     structure = kSmall;
   } else if (p->layout != QW_LAYOUT_CSR && n > 0) {
@@ -379,6 +420,8 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   p->off_bits = section(sizeof(uint32_t) * bits.size());
   p->off_mlist = section(sizeof(int32_t) * std::max<size_t>(mlist.size(), 1));
   if (p->has_tmark) p->off_tmark = section(tmark.size());
+  p->has_coin = !p->coin_mat.empty();
+  if (p->has_coin) p->off_coin = section(sizeof(double) * p->coin_mat.size());
   p->image.assign(off, 0);
   if (structure == kDense) p->off_dense = align256(off);
   std::vector<int32_t> rp32(static_cast<size_t>(n) + 1);
@@ -400,6 +443,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   put(p->image, p->off_bits, bits.data(), bits.size());
   put(p->image, p->off_mlist, mlist.data(), mlist.size());
   if (p->has_tmark) put(p->image, p->off_tmark, tmark.data(), tmark.size());
+  if (p->has_coin) put(p->image, p->off_coin, p->coin_mat.data(), p->coin_mat.size());
 
   // ---- workspace
   const size_t es = c128 ? 16 : 8;
@@ -691,6 +735,8 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
   g.marklist = reinterpret_cast<const int32_t *>(base + p->off_mlist);
   if (p->has_tmark) g.tmark = reinterpret_cast<const uint8_t *>(base + p->off_tmark);
   g.strip_rows = p->strip_rows;
+  g.persistent = p->shift == QW_PERSISTENT;
+  if (p->has_coin) g.coin = reinterpret_cast<const double *>(base + p->off_coin);
   g.columns = p->columns;
   if (p->structure == kDense) {
     g.ld = p->ld;

@@ -71,6 +71,8 @@ struct GraphView {
   const int32_t *marklist = nullptr;   // n_marked
   const uint8_t *tmark = nullptr;      // grid CTQW strips: 1 if a marked vertex lies in the strip's window
   int32_t strip_rows = 0;              // grid CTQW strips: core rows per strip
+  int32_t persistent = 0;              // coined on a lattice: persistent shift
+  const double *coin = nullptr;        // coined on a lattice: d x d complex coin (row-major), else null
 };
 
 // One walk of a many-small-walks launch (the whole walk in one workgroup's LDS).

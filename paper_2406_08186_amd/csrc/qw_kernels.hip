@@ -286,6 +286,23 @@ __global__ __launch_bounds__(kBlock) void k_coined_struct(GraphView g, const T *
     double2 x0 = cvt(x[0]), x1 = cvt(x[1]);
     x[0] = pack<T>(scale(add(x0, x1), kInvSqrt2));
     x[1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+  } else if (KIND != kHypercube && g.coin) {
+    // d x d coin on the slots, which are the rows' (direction) order here:
+    // phi_j = sum_k C[j][k] x_k, FP64, with the entries read uniformly
+    double2 xin[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xin[k] = cvt(x[k]);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double cr = g.coin[2 * (j * D + k)], ci = g.coin[2 * (j * D + k) + 1];
+        re += cr * xin[k].x - ci * xin[k].y;
+        im += cr * xin[k].y + ci * xin[k].x;
+      }
+      x[j] = pack<T>(make_double2(re, im));
+    }
   } else {
     double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
@@ -296,9 +313,12 @@ __global__ __launch_bounds__(kBlock) void k_coined_struct(GraphView g, const T *
     for (int j = 0; j < D; ++j)
       if (j < d) x[j] = pack<T>(sub(add(m, m), cvt(x[j])));
   }
+  // flip-flop: the amplitude moves to the reverse arc's slot at the head;
+  // persistent (lattices): it keeps its direction slot
+  const bool keep = KIND != kHypercube && g.persistent;
 #pragma unroll
   for (int j = 0; j < D; ++j)
-    if (j < d) out[static_cast<int64_t>(rev_slot<KIND>(j)) * n + head_of<KIND>(v, j, n, l2)] = x[j];
+    if (j < d) out[static_cast<int64_t>(keep ? j : rev_slot<KIND>(j)) * n + head_of<KIND>(v, j, n, l2)] = x[j];
 }
 
 // internal[i] = psi[perm[i]]
@@ -444,14 +464,19 @@ __device__ __forceinline__ double2 ell_gather_sum(const T *__restrict__ y, const
 
 // ---- CTQW: one Horner stage ---------------------------------------------------
 // y_out = psi + i (alpha sum_{u~v} y_u + beta [v in M] y_v)
+// psi + i (alpha nsum + beta [marked] yv).  The unmarked part is one fused
+// multiply-add per component and the marked term a second one, so an
+// unmarked cell gets the same bits whether or not the code path allows a
+// marked term (overlapping grid strips of the two kinds store equal values).
 __device__ __forceinline__ double2 horner_out(double2 psi, double2 nsum, double2 yv, bool mk,
                                               double alpha, double beta) {
-  double tx = alpha * nsum.x, ty = alpha * nsum.y;
+  double re = __fma_rn(-alpha, nsum.y, psi.x);
+  double im = __fma_rn(alpha, nsum.x, psi.y);
   if (mk) {
-    tx += beta * yv.x;
-    ty += beta * yv.y;
+    re = __fma_rn(-beta, yv.y, re);
+    im = __fma_rn(beta, yv.x, im);
   }
-  return make_double2(psi.x - ty, psi.y + tx);
+  return make_double2(re, im);
 }
 
 // General CSR, G lanes per row (G in 1..64, power of two), lane sums strided

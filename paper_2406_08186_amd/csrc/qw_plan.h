@@ -12,6 +12,9 @@
 struct qw_plan {
   // walk description
   int32_t kind = QW_COINED, coin = QW_GROVER, dtype = QW_C128, layout = QW_LAYOUT_AUTO;
+  int32_t shift = QW_FLIPFLOP;
+  std::vector<double> coin_mat;  // Fourier / matrix coin: interleaved complex d x d, row-major
+  bool lattice() const { return shift == QW_PERSISTENT || coin == QW_FOURIER || coin == QW_MATRIX; }
   int32_t structure = qwk::kGeneral;
   int64_t n = 0, n_arcs = 0;
   int32_t dims[2] = {0, 0};
@@ -30,6 +33,8 @@ struct qw_plan {
   std::vector<unsigned char> image;
   size_t off_rp = 0, off_col = 0, off_rev = 0, off_tiles = 0, off_perm = 0, off_bits = 0, off_mlist = 0;
   size_t off_tmark = 0;  // grid CTQW strips: marked-window flag per strip
+  size_t off_coin = 0;   // Fourier / matrix coin
+  bool has_coin = false;
   bool has_col = false, has_rev = false, has_tiles = false, has_perm = false, has_tmark = false;
   // device binding
   unsigned char *d_graph = nullptr;

@@ -36,13 +36,14 @@ def _stream_ptr(stream, device) -> int:
 class Plan:
     """A validated walk on one graph with its device tables uploaded.
 
-    kind: "coined" or "ctqw"; coin: "grover" or "hadamard"; dtype: "c64" or
-    "c128"; layout: "auto", "csr", "structured" or "dense".  CTQW takes gamma, dt
-    and either taylor_order or (trunc_tol, horizon_steps); the dense layout takes
+    kind: "coined" or "ctqw"; coin: "grover", "hadamard", "fourier" or a d x d
+    complex matrix; shift: "flipflop" or "persistent"; dtype: "c64" or "c128";
+    layout: "auto", "csr", "structured" or "dense".  CTQW takes gamma, dt and
+    either taylor_order or (trunc_tol, horizon_steps); the dense layout takes
     `columns` walks sharing H (state n x columns, vertex-major).
     """
 
-    def __init__(self, graph: Graph, kind: str = "coined", *, coin: str = "grover",
+    def __init__(self, graph: Graph, kind: str = "coined", *, coin="grover", shift: str = "flipflop",
                  dtype: str = "c128", layout: str = "auto", gamma: float = 0.0, dt: float = 0.0,
                  taylor_order: int = 0, trunc_tol: float = 0.0, horizon_steps: int = 0,
                  marked: Sequence[int] = (), columns: int = 0, device=None, stream=None,
@@ -56,16 +57,28 @@ class Plan:
         if self._col.size == 0:
             self._col = np.zeros(1, dtype=np.int32)
         self._marked = np.ascontiguousarray(np.asarray(list(marked), dtype=np.int32))
+        if isinstance(coin, str):
+            coin_id = {"grover": L.QW_GROVER, "hadamard": L.QW_HADAMARD, "fourier": L.QW_FOURIER}[coin]
+            self._coin = None
+        else:
+            coin_id = L.QW_MATRIX
+            self._coin = np.ascontiguousarray(np.asarray(coin, dtype=np.complex128))
+            if self._coin.ndim != 2 or self._coin.shape[0] != self._coin.shape[1]:
+                raise ValueError("a coin matrix must be square")
         csr = L.QwCsr(graph.n, self._rp.ctypes.data_as(C.POINTER(C.c_int64)),
                       self._col.ctypes.data_as(C.POINTER(C.c_int32)))
         desc = L.QwWalkDesc(
             kind=L.QW_COINED if kind == "coined" else L.QW_CTQW,
-            coin=L.QW_HADAMARD if coin == "hadamard" else L.QW_GROVER,
+            coin=coin_id,
             dtype=_DT[dtype], layout=_LAYOUT[layout], gamma=float(gamma), dt=float(dt),
             taylor_order=int(taylor_order), trunc_tol=float(trunc_tol),
             horizon_steps=int(horizon_steps),
             marked=self._marked.ctypes.data_as(C.POINTER(C.c_int32)) if self._marked.size else None,
-            n_marked=int(self._marked.size), columns=int(columns))
+            n_marked=int(self._marked.size), columns=int(columns),
+            shift={"flipflop": L.QW_FLIPFLOP, "persistent": L.QW_PERSISTENT}[shift],
+            coin_dim=0 if self._coin is None else int(self._coin.shape[0]),
+            coin_matrix=None if self._coin is None else self._coin.view(np.float64).ctypes.data_as(
+                C.POINTER(C.c_double)))
         self._plan = L.qw_plan_create(csr, desc)
         self.info = L.qw_plan_get_info(self._plan)
         self.structure = L.STRUCTURES[self.info.structure]
@@ -337,15 +350,15 @@ class _Walk:
 
 
 class Coined(_Walk):
-    """Coined walk U = S C with the flip-flop shift (Sec. 3.2)."""
+    """Coined walk U = S C (Sec. 3.2): flip-flop shift on any graph, or the
+    persistent shift on cycles and periodic grids; Grover, Hadamard, Fourier or
+    a caller's coin matrix."""
 
-    def __init__(self, graph: Graph, shift: str = "flipflop", coin: str = "grover",
+    def __init__(self, graph: Graph, shift: str = "flipflop", coin="grover",
                  marked: Sequence[int] = (), dtype: str = "c128", layout: str = "auto", device=None):
-        if shift != "flipflop":
-            raise NotImplementedError("only the flip-flop shift is implemented")
         self.graph = graph
-        self.plan = Plan(graph, "coined", coin=coin, dtype=dtype, layout=layout, marked=marked,
-                         device=device)
+        self.plan = Plan(graph, "coined", coin=coin, shift=shift, dtype=dtype, layout=layout,
+                         marked=marked, device=device)
 
     def ket(self, v: int, w: int) -> np.ndarray:
         psi = np.zeros(self.graph.n_arcs, dtype=np.complex128)

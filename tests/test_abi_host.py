@@ -249,3 +249,35 @@ def test_small_many_host_validation():
     code = L.lib().qw_small_many(None, None, None, -1, None, 0, None)
     assert code == L.QW_EINVAL
     L.qw_plan_destroy(p)
+
+
+def test_lattice_coins_and_persistent_shift_validation():
+    """Fourier / matrix coins and the persistent shift: lattice kernels only."""
+    eye4 = np.ascontiguousarray(np.eye(4, dtype=np.complex128))
+    m4 = eye4.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+    # Grover + persistent: any row order; Fourier needs direction order
+    p = _create(I.torus(5, 6), kind=0, coin=L.QW_GROVER, dtype=1, shift=L.QW_PERSISTENT)
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "torus"
+    L.qw_plan_destroy(p)
+    assert _code(lambda: _create(I.torus(5, 6), kind=0, coin=L.QW_FOURIER, dtype=1)) == L.QW_EUNSUPPORTED
+    p = _create(I.torus_directed(5, 6), kind=0, coin=L.QW_FOURIER, dtype=1)
+    info = L.qw_plan_get_info(p)
+    assert L.STRUCTURES[info.structure] == "torus" and tuple(info.dims) == (5, 6)
+    L.qw_plan_destroy(p)
+    p = _create(I.torus_directed(5, 6), kind=0, coin=L.QW_MATRIX, dtype=1, coin_dim=4, coin_matrix=m4,
+                shift=L.QW_PERSISTENT)
+    L.qw_plan_destroy(p)
+    p = _create(I.cycle(40), kind=0, coin=L.QW_FOURIER, dtype=0, shift=L.QW_PERSISTENT)
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "cycle"   # not the one-workgroup path
+    L.qw_plan_destroy(p)
+    # wrong matrix size, null matrix, non-lattice graphs, CSR layout, bad enums
+    assert _code(lambda: _create(I.cycle(40), kind=0, coin=L.QW_MATRIX, dtype=1, coin_dim=4,
+                                 coin_matrix=m4)) == L.QW_EUNSUPPORTED
+    assert _code(lambda: _create(I.cycle(40), kind=0, coin=L.QW_MATRIX, dtype=1, coin_dim=2)) == L.QW_EINVAL
+    assert _code(lambda: _create(I.hypercube(5), kind=0, coin=L.QW_GROVER, dtype=1,
+                                 shift=L.QW_PERSISTENT)) == L.QW_EUNSUPPORTED
+    assert _code(lambda: _create(I.random_regular(50, 4, 1), kind=0, coin=L.QW_FOURIER, dtype=1)) == L.QW_EUNSUPPORTED
+    assert _code(lambda: _create(I.torus_directed(5, 6), kind=0, coin=L.QW_FOURIER, dtype=1,
+                                 layout=L.QW_LAYOUT_CSR)) == L.QW_EUNSUPPORTED
+    assert _code(lambda: _create(I.cycle(40), kind=0, coin=7, dtype=1)) == L.QW_EINVAL
+    assert _code(lambda: _create(I.cycle(40), kind=0, coin=0, dtype=1, shift=5)) == L.QW_EINVAL
