@@ -73,6 +73,8 @@ def _load():
         lib.orc_coined_evolve.restype = C.c_int
         lib.orc_coined_evolve_general.argtypes = [C.c_int64, i64p, i64p, dp, C.c_int64, u8p, dp, C.c_int64]
         lib.orc_coined_evolve_general.restype = C.c_int
+        lib.orc_szegedy_evolve.argtypes = [C.c_int64, i64p, i64p, dp, u8p, dp, C.c_int64]
+        lib.orc_szegedy_evolve.restype = C.c_int
         lib.orc_coined_prob.argtypes = [C.c_int64, i64p, i32p, dp, dp]
         lib.orc_coined_prob.restype = None
         lib.orc_ctqw_evolve.argtypes = [C.c_int64, i64p, i32p, C.c_double, u8p, C.c_double,
@@ -241,6 +243,31 @@ def coined_evolve_general(row_ptr, col, psi0, steps: int, coin="grover", shift: 
         raise ValueError("the coin matrix's size differs from a vertex degree")
     if st != 0:
         raise RuntimeError(f"oracle coined evolve failed ({st})")
+    return psi
+
+
+def szegedy_evolve(row_ptr, col, psi0, steps: int, p_arc, marked=None) -> np.ndarray:
+    """Szegedy walk (S (2 Pi - I))^steps psi0 on the arc basis for the
+    transition probabilities p_arc (one per arc in CSR order, P[tail][head];
+    each row sums to 1); marked vertices take -I."""
+    rp, cl = _csr(row_ptr, col)
+    n = rp.size - 1
+    p_arc = np.asarray(p_arc, dtype=np.float64)
+    if p_arc.size != cl.size or np.any(p_arc < 0):
+        raise ValueError("one non-negative transition probability per arc")
+    rev = reverse_arcs(rp, cl)
+    if rev.size == 0:
+        rev = np.zeros(1, np.int64)
+    sq = np.ascontiguousarray(np.sqrt(p_arc)) if p_arc.size else np.zeros(1)
+    psi = np.ascontiguousarray(np.array(psi0, dtype=np.complex128, copy=True))
+    if psi.size != cl.size:
+        raise ValueError("state length must equal the arc count")
+    m = _marked_bytes(n, marked)
+    buf = psi.view(np.float64) if psi.size else np.zeros(2, np.float64)
+    st = _load().orc_szegedy_evolve(n, _ptr(rp, C.c_int64), _ptr(rev, C.c_int64), _ptr(sq, C.c_double),
+                                    _ptr(m, C.c_uint8), _ptr(buf, C.c_double), int(steps))
+    if st != 0:
+        raise RuntimeError(f"oracle Szegedy evolve failed ({st})")
     return psi
 
 

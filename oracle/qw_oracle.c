@@ -219,6 +219,42 @@ int orc_coined_evolve_general(int64_t n, const int64_t *row_ptr, const int64_t *
   return 0;
 }
 
+/*
+ * Szegedy walk (the paper's frontend future work, Sec. 5), on the arc basis:
+ * psi <- (S (2 Pi - I))^steps psi with Pi = sum_x |alpha_x><alpha_x|,
+ * alpha_x = sum_y sqrt(P_xy) |x,y>, and S the flip-flop swap.  The
+ * reflection is written as its matrix elements, <a| 2 Pi - I |b> =
+ * 2 sqrt(P_a) sqrt(P_b) - delta_ab for arcs a, b of the same tail.  sqrt_p:
+ * double per arc (CSR order).  Marked vertices take -I.
+ */
+int orc_szegedy_evolve(int64_t n, const int64_t *row_ptr, const int64_t *rev, const double *sqrt_p,
+                       const uint8_t *marked, double *psi_io, int64_t steps) {
+  int64_t n_arcs = row_ptr[n];
+  cplx *psi = (cplx *)psi_io;
+  cplx *phi = (cplx *)malloc(sizeof(cplx) * (size_t)(n_arcs > 0 ? n_arcs : 1));
+  if (!phi) return -4;
+  for (int64_t s = 0; s < steps; ++s) {
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(orc_max_threads())
+    for (int64_t v = 0; v < n; ++v) {
+      int64_t lo = row_ptr[v], hi = row_ptr[v + 1];
+      if (marked && marked[v]) {
+        for (int64_t a = lo; a < hi; ++a) phi[a] = -psi[a];
+        continue;
+      }
+      for (int64_t out = lo; out < hi; ++out) {
+        cplx acc = 0.0;
+        for (int64_t in = lo; in < hi; ++in)
+          acc += (2.0 * sqrt_p[out] * sqrt_p[in] - (in == out ? 1.0 : 0.0)) * psi[in];
+        phi[out] = acc;
+      }
+    }
+#pragma omp parallel for schedule(static) num_threads(orc_max_threads())
+    for (int64_t a = 0; a < n_arcs; ++a) psi[a] = phi[rev[a]];
+  }
+  free(phi);
+  return 0;
+}
+
 /* Coined vertex probability p_v = sum over arcs with tail v of |psi_a|^2. */
 void orc_coined_prob(int64_t n, const int64_t *row_ptr, const int32_t *col,
                      const double *psi_in, double *p) {
