@@ -61,13 +61,18 @@ extern "C" {
 
 /* Coins (Sec. 3.2).  GROVER: (2/d) J - I on each vertex's arcs.  HADAMARD:
  * (1/sqrt 2)[[1, 1], [1, -1]] (degree 2 only).  FOURIER: F[j][k] =
- * exp(2 pi i j k / d) / sqrt(d).  MATRIX: the caller's d x d matrix.  Marked
- * vertices take -I whatever the coin.  HADAMARD, FOURIER and MATRIX act on
- * the coin basis, which is the order of the vertex's row in the CSR. */
+ * exp(2 pi i j k / d) / sqrt(d).  MATRIX: the caller's d x d matrix.
+ * SZEGEDY: the reflection 2|alpha_x><alpha_x| - I with alpha_x = sum_y
+ * sqrt(P_xy) |x,y>, which with the flip-flop shift is Szegedy's walk for the
+ * transition matrix P (the paper's future work, Sec. 5; GROVER is the case
+ * P_xy = 1/d_x).  Marked vertices take -I whatever the coin.  HADAMARD,
+ * FOURIER and MATRIX act on the coin basis, which is the order of the
+ * vertex's row in the CSR. */
 #define QW_GROVER 0
 #define QW_HADAMARD 1
 #define QW_FOURIER 2
 #define QW_MATRIX 3
+#define QW_SZEGEDY 4
 
 /* Shifts (Sec. 3.2).  FLIPFLOP: S|v,w> = |w,v>.  PERSISTENT (the lattice
  * shift of position-coin notation): the walker keeps its direction, S maps
@@ -125,7 +130,7 @@ typedef struct qw_csr {
 typedef struct qw_walk_desc {
   int32_t kind;         /* QW_COINED or QW_CTQW                                */
   int32_t coin;         /* coined: QW_GROVER, QW_HADAMARD (degree 2 only),
-                           QW_FOURIER or QW_MATRIX                             */
+                           QW_FOURIER, QW_MATRIX or QW_SZEGEDY                 */
   int32_t dtype;        /* QW_C64 or QW_C128                                   */
   int32_t layout;       /* QW_LAYOUT_AUTO or QW_LAYOUT_CSR                     */
   double gamma;         /* CTQW: gamma > 0 (Sec. 3.1)                          */
@@ -146,13 +151,19 @@ typedef struct qw_walk_desc {
   const double *coin_matrix; /* coined, QW_MATRIX: host double[2 d d], row-major
                            interleaved complex C[j][k], copied at creation and
                            used as given (not checked for unitarity)          */
+  const double *transition; /* coined, QW_SZEGEDY: host double[n_arcs], P of each
+                           arc (tail -> head) in CSR order, >= 0, every row
+                           of a vertex with arcs summing to 1 within 1e-12;
+                           copied at creation                                 */
 } qw_walk_desc;
 /* FOURIER and MATRIX coins and the PERSISTENT shift run on the index-free
  * lattice kernels only: the graph must be a cycle (rows ordered v+1, v-1) or
  * a periodic l1 x l2 grid, l1, l2 >= 3, vertex v = r*l2 + c (rows ordered
  * c+1, c-1, r+1, r-1, wrapping), and the layout AUTO or STRUCTURED; a
  * PERSISTENT shift with the GROVER coin accepts the rows in any order.
- * Otherwise QW_EUNSUPPORTED.  Such walks cannot join a batch. */
+ * Otherwise QW_EUNSUPPORTED.  Such walks cannot join a batch.  The SZEGEDY
+ * coin runs on the one-workgroup and general CSR paths (any graph, flip-flop
+ * shift) and cannot join a batch either. */
 
 typedef struct qw_plan qw_plan;
 

@@ -19,7 +19,7 @@ QW_OK, QW_EINVAL, QW_EGRAPH, QW_EUNSUPPORTED, QW_ENOMEM, QW_EDEVICE, QW_ESTATE =
 ERRORS = {1: "QW_EINVAL", 2: "QW_EGRAPH", 3: "QW_EUNSUPPORTED", 4: "QW_ENOMEM", 5: "QW_EDEVICE",
           6: "QW_ESTATE"}
 QW_COINED, QW_CTQW = 0, 1
-QW_GROVER, QW_HADAMARD, QW_FOURIER, QW_MATRIX = 0, 1, 2, 3
+QW_GROVER, QW_HADAMARD, QW_FOURIER, QW_MATRIX, QW_SZEGEDY = 0, 1, 2, 3, 4
 QW_FLIPFLOP, QW_PERSISTENT = 0, 1
 QW_C64, QW_C128 = 0, 1
 QW_LAYOUT_AUTO, QW_LAYOUT_CSR, QW_LAYOUT_STRUCTURED, QW_LAYOUT_DENSE = 0, 1, 2, 3
@@ -44,7 +44,8 @@ class QwWalkDesc(C.Structure):
                 ("gamma", C.c_double), ("dt", C.c_double), ("taylor_order", C.c_int32),
                 ("trunc_tol", C.c_double), ("horizon_steps", C.c_int64),
                 ("marked", C.POINTER(C.c_int32)), ("n_marked", C.c_int64), ("columns", C.c_int32),
-                ("shift", C.c_int32), ("coin_dim", C.c_int32), ("coin_matrix", C.POINTER(C.c_double))]
+                ("shift", C.c_int32), ("coin_dim", C.c_int32), ("coin_matrix", C.POINTER(C.c_double)),
+                ("transition", C.POINTER(C.c_double))]
 
 
 class QwPlanInfo(C.Structure):

@@ -347,8 +347,9 @@ int qw_batch_set_slot(qw_batch *b, int32_t slot, const qw_plan *p, void *d_psi, 
     return set_error(QW_EUNSUPPORTED,
                      "batched walks need CSR plans, CTQW plans on the ELL path, or coined plans on a "
                      "cycle, torus or hypercube path");
-  if (p->lattice())
-    return set_error(QW_EUNSUPPORTED, "Fourier and matrix coins and the persistent shift cannot join a batch");
+  if (p->lattice() || p->coin == QW_SZEGEDY)
+    return set_error(QW_EUNSUPPORTED,
+                     "Fourier, matrix and Szegedy coins and the persistent shift cannot join a batch");
   if (work_bytes < p->work_bytes) return set_error(QW_ENOMEM, "workspace too small for the plan");
   if (steps < 0) return set_error(QW_EINVAL, "negative steps");
   if (p->n == 0) return set_error(QW_EINVAL, "empty graph");

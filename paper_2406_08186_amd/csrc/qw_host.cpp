@@ -151,12 +151,14 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   } else if (w->columns > 1 || w->columns < 0) {
     return fail(QW_EINVAL, "columns > 1 needs the dense layout");
   }
-  if (w->kind == QW_COINED && (w->coin < QW_GROVER || w->coin > QW_MATRIX))
+  if (w->kind == QW_COINED && (w->coin < QW_GROVER || w->coin > QW_SZEGEDY))
     return fail(QW_EINVAL, "bad coin %d", w->coin);
   if (w->kind == QW_COINED && w->shift != QW_FLIPFLOP && w->shift != QW_PERSISTENT)
     return fail(QW_EINVAL, "bad shift %d", w->shift);
   if (w->kind == QW_COINED && w->coin == QW_MATRIX && (!w->coin_matrix || w->coin_dim < 1))
     return fail(QW_EINVAL, "the matrix coin needs coin_matrix and coin_dim >= 1");
+  if (w->kind == QW_COINED && w->coin == QW_SZEGEDY && w->shift != QW_FLIPFLOP)
+    return fail(QW_EUNSUPPORTED, "the Szegedy coin takes the flip-flop shift");
   if (w->n_marked < 0 || (w->n_marked > 0 && !w->marked)) return fail(QW_EINVAL, "bad marked list");
   if (n > 0 && (!g->row_ptr)) return fail(QW_EINVAL, "null row_ptr");
   p->kind = w->kind;
@@ -220,6 +222,23 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     mlist[i] = m;
   }
   p->n_marked = static_cast<int32_t>(w->n_marked);
+
+  // ---- Szegedy transition probabilities
+  if (p->kind == QW_COINED && p->coin == QW_SZEGEDY) {
+    if (na > 0 && !w->transition) return fail(QW_EINVAL, "the Szegedy coin needs transition probabilities");
+    p->sqrt_p.resize(static_cast<size_t>(na));
+    for (int64_t v = 0; v < n; ++v) {
+      double row = 0.0;
+      for (int64_t a = rp[v]; a < rp[v + 1]; ++a) {
+        const double x = w->transition[a];
+        if (!(x >= 0.0) || !std::isfinite(x)) return fail(QW_EINVAL, "transition probability of arc %lld is not >= 0", (long long)a);
+        row += x;
+        p->sqrt_p[static_cast<size_t>(a)] = std::sqrt(x);
+      }
+      if (rp[v + 1] > rp[v] && std::fabs(row - 1.0) > 1e-12)
+        return fail(QW_EINVAL, "transition probabilities of vertex %lld sum to %.17g", (long long)v, row);
+    }
+  }
 
   // ---- walk parameters
   if (p->kind == QW_COINED && p->coin == QW_HADAMARD) {
@@ -301,7 +320,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     }
   } else if (p->layout == QW_LAYOUT_AUTO && small_fits && n > 0) {
     structure = kSmall;
-  } else if (p->layout != QW_LAYOUT_CSR && n > 0) {
+  } else if (p->layout != QW_LAYOUT_CSR && n > 0 && !(p->kind == QW_COINED && p->coin == QW_SZEGEDY)) {
     int32_t a = 0, b = 0;
     const bool ordered = p->kind == QW_COINED && p->coin == QW_HADAMARD;
     if (!ordered && is_hypercube(n, rp, col, &a)) {
@@ -422,6 +441,8 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (p->has_tmark) p->off_tmark = section(tmark.size());
   p->has_coin = !p->coin_mat.empty();
   if (p->has_coin) p->off_coin = section(sizeof(double) * p->coin_mat.size());
+  p->has_sqrtp = p->kind == QW_COINED && p->coin == QW_SZEGEDY;
+  if (p->has_sqrtp) p->off_sqrtp = section(sizeof(double) * p->sqrt_p.size());
   p->image.assign(off, 0);
   if (structure == kDense) p->off_dense = align256(off);
   std::vector<int32_t> rp32(static_cast<size_t>(n) + 1);
@@ -444,6 +465,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   put(p->image, p->off_mlist, mlist.data(), mlist.size());
   if (p->has_tmark) put(p->image, p->off_tmark, tmark.data(), tmark.size());
   if (p->has_coin) put(p->image, p->off_coin, p->coin_mat.data(), p->coin_mat.size());
+  if (p->has_sqrtp) put(p->image, p->off_sqrtp, p->sqrt_p.data(), p->sqrt_p.size());
 
   // ---- workspace
   const size_t es = c128 ? 16 : 8;
@@ -737,6 +759,7 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
   g.strip_rows = p->strip_rows;
   g.persistent = p->shift == QW_PERSISTENT;
   if (p->has_coin) g.coin = reinterpret_cast<const double *>(base + p->off_coin);
+  if (p->has_sqrtp) g.sqrtp = reinterpret_cast<const double *>(base + p->off_sqrtp);
   g.columns = p->columns;
   if (p->structure == kDense) {
     g.ld = p->ld;

@@ -73,6 +73,7 @@ struct GraphView {
   int32_t strip_rows = 0;              // grid CTQW strips: core rows per strip
   int32_t persistent = 0;              // coined on a lattice: persistent shift
   const double *coin = nullptr;        // coined on a lattice: d x d complex coin (row-major), else null
+  const double *sqrtp = nullptr;       // Szegedy coin: sqrt(P) per arc, else null
 };
 
 // One walk of a many-small-walks launch (the whole walk in one workgroup's LDS).

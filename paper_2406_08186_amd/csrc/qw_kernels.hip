@@ -134,6 +134,11 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
         double2 x0 = cvt(a[lo]), x1 = cvt(a[lo + 1]);
         a[lo] = pack<T>(scale(add(x0, x1), kInvSqrt2));
         a[lo + 1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+      } else if (g.sqrtp) {
+        const double *wt = g.sqrtp + g.rp[v];  // Szegedy: 2 w_a <w, x> - x_a
+        double2 sum = make_double2(0.0, 0.0);
+        for (int i = lo; i < hi; ++i) sum = add(sum, scale(cvt(a[i]), wt[i - lo]));
+        for (int i = lo; i < hi; ++i) a[i] = pack<T>(sub(scale(sum, 2.0 * wt[i - lo]), cvt(a[i])));
       } else {
         double2 sum = make_double2(0.0, 0.0);
         for (int i = lo; i < hi; ++i) sum = add(sum, cvt(a[i]));
@@ -204,6 +209,11 @@ __global__ __launch_bounds__(kTileThreads) void k_coined_tile(GraphView g, const
         double2 x0 = cvt(s[lo]), x1 = cvt(s[lo + 1]);
         s[lo] = pack<T>(scale(add(x0, x1), kInvSqrt2));
         s[lo + 1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+      } else if (g.sqrtp) {
+        const double *wt = g.sqrtp + ab;  // Szegedy: 2 w_a <w, x> - x_a
+        double2 sum = make_double2(0.0, 0.0);
+        for (int i = lo; i < hi; ++i) sum = add(sum, scale(cvt(s[i]), wt[i]));
+        for (int i = lo; i < hi; ++i) s[i] = pack<T>(sub(scale(sum, 2.0 * wt[i]), cvt(s[i])));
       } else {
         double2 sum = make_double2(0.0, 0.0);
         for (int i = lo; i < hi; ++i) sum = add(sum, cvt(s[i]));
@@ -222,16 +232,18 @@ __global__ __launch_bounds__(kTileThreads) void k_coined_tile(GraphView g, const
       double sx = 0.0, sy = 0.0;
       for (int i = ab + threadIdx.x; i < ae; i += blockDim.x) {
         double2 x = ld(in, i);
-        sx += x.x;
-        sy += x.y;
+        const double wt = g.sqrtp ? g.sqrtp[i] : 1.0;
+        sx += wt * x.x;
+        sy += wt * x.y;
       }
       sx = block_sum(sx, red);
       sy = block_sum(sy, red);
-      m = grover_mean(make_double2(sx, sy), na);
+      m = g.sqrtp ? make_double2(sx, sy) : grover_mean(make_double2(sx, sy), na);
     }
     for (int i = ab + threadIdx.x; i < ae; i += blockDim.x) {
       double2 x = ld(in, i);
-      double2 phi = mk ? scale(x, -1.0) : sub(add(m, m), x);
+      double2 phi = mk ? scale(x, -1.0)
+                       : (g.sqrtp ? sub(scale(m, 2.0 * g.sqrtp[i]), x) : sub(add(m, m), x));
       st(out, g.rev[i], phi);
     }
   }

@@ -15,6 +15,7 @@ struct qw_plan {
   int32_t shift = QW_FLIPFLOP;
   std::vector<double> coin_mat;  // Fourier / matrix coin: interleaved complex d x d, row-major
   bool lattice() const { return shift == QW_PERSISTENT || coin == QW_FOURIER || coin == QW_MATRIX; }
+  std::vector<double> sqrt_p;  // Szegedy coin: sqrt(P) per arc
   int32_t structure = qwk::kGeneral;
   int64_t n = 0, n_arcs = 0;
   int32_t dims[2] = {0, 0};
@@ -35,6 +36,8 @@ struct qw_plan {
   size_t off_tmark = 0;  // grid CTQW strips: marked-window flag per strip
   size_t off_coin = 0;   // Fourier / matrix coin
   bool has_coin = false;
+  size_t off_sqrtp = 0;  // Szegedy coin weights
+  bool has_sqrtp = false;
   bool has_col = false, has_rev = false, has_tiles = false, has_perm = false, has_tmark = false;
   // device binding
   unsigned char *d_graph = nullptr;

@@ -36,8 +36,9 @@ def _stream_ptr(stream, device) -> int:
 class Plan:
     """A validated walk on one graph with its device tables uploaded.
 
-    kind: "coined" or "ctqw"; coin: "grover", "hadamard", "fourier" or a d x d
-    complex matrix; shift: "flipflop" or "persistent"; dtype: "c64" or "c128";
+    kind: "coined" or "ctqw"; coin: "grover", "hadamard", "fourier", "szegedy"
+    (with `transition`, P per arc in CSR order) or a d x d complex matrix;
+    shift: "flipflop" or "persistent"; dtype: "c64" or "c128";
     layout: "auto", "csr", "structured" or "dense".  CTQW takes gamma, dt and
     either taylor_order or (trunc_tol, horizon_steps); the dense layout takes
     `columns` walks sharing H (state n x columns, vertex-major).
@@ -47,7 +48,7 @@ class Plan:
                  dtype: str = "c128", layout: str = "auto", gamma: float = 0.0, dt: float = 0.0,
                  taylor_order: int = 0, trunc_tol: float = 0.0, horizon_steps: int = 0,
                  marked: Sequence[int] = (), columns: int = 0, device=None, stream=None,
-                 upload: bool = True):
+                 upload: bool = True, transition=None):
         self.graph = graph
         self.kind = kind
         self.dtype = dtype
@@ -57,9 +58,15 @@ class Plan:
         if self._col.size == 0:
             self._col = np.zeros(1, dtype=np.int32)
         self._marked = np.ascontiguousarray(np.asarray(list(marked), dtype=np.int32))
+        self._trans = None
         if isinstance(coin, str):
-            coin_id = {"grover": L.QW_GROVER, "hadamard": L.QW_HADAMARD, "fourier": L.QW_FOURIER}[coin]
+            coin_id = {"grover": L.QW_GROVER, "hadamard": L.QW_HADAMARD, "fourier": L.QW_FOURIER,
+                       "szegedy": L.QW_SZEGEDY}[coin]
             self._coin = None
+            if coin == "szegedy":
+                if transition is None:
+                    raise ValueError("the Szegedy coin needs transition (P per arc, CSR order)")
+                self._trans = np.ascontiguousarray(np.asarray(transition, dtype=np.float64))
         else:
             coin_id = L.QW_MATRIX
             self._coin = np.ascontiguousarray(np.asarray(coin, dtype=np.complex128))
@@ -78,7 +85,8 @@ class Plan:
             shift={"flipflop": L.QW_FLIPFLOP, "persistent": L.QW_PERSISTENT}[shift],
             coin_dim=0 if self._coin is None else int(self._coin.shape[0]),
             coin_matrix=None if self._coin is None else self._coin.view(np.float64).ctypes.data_as(
-                C.POINTER(C.c_double)))
+                C.POINTER(C.c_double)),
+            transition=None if self._trans is None else self._trans.ctypes.data_as(C.POINTER(C.c_double)))
         self._plan = L.qw_plan_create(csr, desc)
         self.info = L.qw_plan_get_info(self._plan)
         self.structure = L.STRUCTURES[self.info.structure]
@@ -351,14 +359,16 @@ class _Walk:
 
 class Coined(_Walk):
     """Coined walk U = S C (Sec. 3.2): flip-flop shift on any graph, or the
-    persistent shift on cycles and periodic grids; Grover, Hadamard, Fourier or
-    a caller's coin matrix."""
+    persistent shift on cycles and periodic grids; Grover, Hadamard, Fourier, a
+    caller's coin matrix, or Szegedy's reflection for a transition matrix P
+    (Szegedy's walk, Sec. 5)."""
 
     def __init__(self, graph: Graph, shift: str = "flipflop", coin="grover",
-                 marked: Sequence[int] = (), dtype: str = "c128", layout: str = "auto", device=None):
+                 marked: Sequence[int] = (), dtype: str = "c128", layout: str = "auto", device=None,
+                 transition=None):
         self.graph = graph
         self.plan = Plan(graph, "coined", coin=coin, shift=shift, dtype=dtype, layout=layout,
-                         marked=marked, device=device)
+                         marked=marked, device=device, transition=transition)
 
     def ket(self, v: int, w: int) -> np.ndarray:
         psi = np.zeros(self.graph.n_arcs, dtype=np.complex128)

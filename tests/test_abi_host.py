@@ -281,3 +281,25 @@ def test_lattice_coins_and_persistent_shift_validation():
                                  layout=L.QW_LAYOUT_CSR)) == L.QW_EUNSUPPORTED
     assert _code(lambda: _create(I.cycle(40), kind=0, coin=7, dtype=1)) == L.QW_EINVAL
     assert _code(lambda: _create(I.cycle(40), kind=0, coin=0, dtype=1, shift=5)) == L.QW_EINVAL
+
+
+def test_szegedy_validation_and_path():
+    g = I.cycle(500)
+    p_arc = np.full(g.n_arcs, 0.5)
+    keep = np.ascontiguousarray(p_arc)
+    tp = keep.ctypes.data_as(C.POINTER(C.c_double))
+    p = _create(g, kind=0, coin=L.QW_SZEGEDY, dtype=1, transition=tp)
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] in ("small", "general")   # never the index-free kernels
+    L.qw_plan_destroy(p)
+    p = _create(g, kind=0, coin=L.QW_SZEGEDY, dtype=1, transition=tp, layout=L.QW_LAYOUT_STRUCTURED)
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "general"
+    L.qw_plan_destroy(p)
+    bad = np.ascontiguousarray(np.full(g.n_arcs, 0.4))
+    assert _code(lambda: _create(g, kind=0, coin=L.QW_SZEGEDY, dtype=1,
+                                 transition=bad.ctypes.data_as(C.POINTER(C.c_double)))) == L.QW_EINVAL
+    neg = np.ascontiguousarray(np.tile([1.5, -0.5], g.n))
+    assert _code(lambda: _create(g, kind=0, coin=L.QW_SZEGEDY, dtype=1,
+                                 transition=neg.ctypes.data_as(C.POINTER(C.c_double)))) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=0, coin=L.QW_SZEGEDY, dtype=1)) == L.QW_EINVAL
+    assert _code(lambda: _create(g, kind=0, coin=L.QW_SZEGEDY, dtype=1, transition=tp,
+                                 shift=L.QW_PERSISTENT)) == L.QW_EUNSUPPORTED
