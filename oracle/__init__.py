@@ -7,8 +7,10 @@ the seeded input generators, which hold none of the walk arithmetic.
 
 Contents
 --------
-* ``qw_oracle.c`` (loaded here through ctypes): the coined step and the
-  CTQW Taylor step written out from their definitions, plus probabilities.
+* ``qw_oracle.c`` (loaded here through ctypes): the coined step (Grover,
+  Hadamard, Fourier and matrix coins, flip-flop and persistent shifts), the
+  Szegedy and staggered walks and the CTQW Taylor step, written out from
+  their definitions, plus probabilities.
 * :mod:`oracle.taylor`: the truncation-order / step-size rule for the
   Taylor propagator.
 * :mod:`oracle.closed_forms`: exact results the physics fixes (Bessel
@@ -41,6 +43,10 @@ FAULTS = {
     "hadamard_swap": 7,
     "mark_plus": 8,
     "gamma_on_mark": 9,
+    "stag_one_proj": 10,
+    "stag_reversed": 11,
+    "stag_mark_after": 12,
+    "stag_theta_sign": 13,
 }
 
 
@@ -75,6 +81,9 @@ def _load():
         lib.orc_coined_evolve_general.restype = C.c_int
         lib.orc_szegedy_evolve.argtypes = [C.c_int64, i64p, i64p, dp, u8p, dp, C.c_int64]
         lib.orc_szegedy_evolve.restype = C.c_int
+        lib.orc_staggered_evolve.argtypes = [C.c_int64, C.c_int32, i64p, i64p, i32p, dp, u8p, i32p, dp, u8p,
+                                             dp, C.c_int64]
+        lib.orc_staggered_evolve.restype = C.c_int
         lib.orc_coined_prob.argtypes = [C.c_int64, i64p, i32p, dp, dp]
         lib.orc_coined_prob.restype = None
         lib.orc_ctqw_evolve.argtypes = [C.c_int64, i64p, i32p, C.c_double, u8p, C.c_double,
@@ -268,6 +277,58 @@ def szegedy_evolve(row_ptr, col, psi0, steps: int, p_arc, marked=None) -> np.nda
                                     _ptr(m, C.c_uint8), _ptr(buf, C.c_double), int(steps))
     if st != 0:
         raise RuntimeError(f"oracle Szegedy evolve failed ({st})")
+    return psi
+
+
+def staggered_evolve(n: int, tessellations, psi0, steps: int, marked=None) -> np.ndarray:
+    """Staggered walk (U_T ... U_1 R_M)^steps psi0 on the vertex basis.
+
+    ``tessellations``: a sequence of objects with ``poly_ptr`` (int64,
+    polygons + 1 entries), ``poly_vert`` (int32, n entries: polygon p is
+    poly_vert[poly_ptr[p]:poly_ptr[p+1]], every vertex exactly once),
+    ``amp`` (None for uniform 1/sqrt|alpha|, else n reals aligned with
+    poly_vert, each polygon's squares summing to 1) and ``theta`` (None for
+    the reflection 2P - I, else exp(i theta (2P - I))).  Applied in sequence
+    order after the phase flip of the marked vertices."""
+    n = int(n)
+    T = len(tessellations)
+    n_poly = np.zeros(max(T, 1), np.int64)
+    ptrs, verts, amps = [], [], []
+    has_amp = np.zeros(max(T, 1), np.uint8)
+    form = np.zeros(max(T, 1), np.int32)
+    theta = np.zeros(max(T, 1), np.float64)
+    for t, tess in enumerate(tessellations):
+        pp = np.ascontiguousarray(tess.poly_ptr, dtype=np.int64)
+        vv = np.ascontiguousarray(tess.poly_vert, dtype=np.int32)
+        if vv.size != n or pp[0] != 0 or pp[-1] != n or np.any(np.diff(pp) <= 0):
+            raise ValueError("a tessellation must split the n vertices into non-empty polygons")
+        if not np.array_equal(np.sort(vv), np.arange(n)):
+            raise ValueError("a tessellation must hold every vertex exactly once")
+        n_poly[t] = pp.size - 1
+        ptrs.append(pp)
+        verts.append(vv)
+        if tess.amp is not None:
+            has_amp[t] = 1
+            amps.append(np.ascontiguousarray(tess.amp, dtype=np.float64))
+        else:
+            amps.append(np.zeros(n, np.float64))
+        if tess.theta is not None:
+            form[t] = 1
+            theta[t] = float(tess.theta)
+    pp_all = np.concatenate(ptrs) if ptrs else np.zeros(1, np.int64)
+    vv_all = np.concatenate(verts) if verts and n else np.zeros(1, np.int32)
+    aa_all = np.concatenate(amps) if amps and n else np.zeros(1, np.float64)
+    psi = np.ascontiguousarray(np.array(psi0, dtype=np.complex128, copy=True))
+    if psi.size != n:
+        raise ValueError("state length must equal the vertex count")
+    m = _marked_bytes(n, marked)
+    buf = psi.view(np.float64) if psi.size else np.zeros(2, np.float64)
+    st = _load().orc_staggered_evolve(n, T, _ptr(n_poly, C.c_int64), _ptr(pp_all, C.c_int64),
+                                      _ptr(vv_all, C.c_int32), _ptr(aa_all, C.c_double), _ptr(has_amp, C.c_uint8),
+                                      _ptr(form, C.c_int32), _ptr(theta, C.c_double), _ptr(m, C.c_uint8),
+                                      _ptr(buf, C.c_double), int(steps))
+    if st != 0:
+        raise RuntimeError(f"oracle staggered evolve failed ({st})")
     return psi
 
 

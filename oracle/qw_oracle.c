@@ -22,6 +22,8 @@
  *     after the term k = K, evaluated in POWER form
  *       term_0 = psi,  term_k = (-i dt / k) H term_{k-1},  psi' = sum_k term_k.
  *   CTQW probability (Sec. 3.1):  p_v = |psi_v|^2.
+ *   Szegedy and staggered walks (named as future work in Sec. 5): see their
+ *     routines below.
  *
  * Arrays of complex numbers are interleaved (re, im) doubles.
  *
@@ -52,7 +54,11 @@ enum {
   ORC_FAULT_TAYLOR_SHORT = 6,      /* last Taylor term dropped                    */
   ORC_FAULT_HADAMARD_SWAP = 7,     /* Hadamard rows swapped                       */
   ORC_FAULT_MARK_PLUS = 8,         /* marked coin +I instead of -I                */
-  ORC_FAULT_GAMMA_ON_MARK = 9      /* marked term scaled by gamma                 */
+  ORC_FAULT_GAMMA_ON_MARK = 9,     /* marked term scaled by gamma                 */
+  ORC_FAULT_STAG_ONE_PROJ = 10,    /* staggered: P - I instead of 2P - I          */
+  ORC_FAULT_STAG_REVERSED = 11,    /* staggered: tessellations in reverse order   */
+  ORC_FAULT_STAG_MARK_AFTER = 12,  /* staggered: marked phase after the product   */
+  ORC_FAULT_STAG_THETA_SIGN = 13   /* staggered: exp(-i theta H) for exp(i theta H)*/
 };
 
 static int g_fault = ORC_FAULT_NONE;
@@ -252,6 +258,80 @@ int orc_szegedy_evolve(int64_t n, const int64_t *row_ptr, const int64_t *rev, co
     for (int64_t a = 0; a < n_arcs; ++a) psi[a] = phi[rev[a]];
   }
   free(phi);
+  return 0;
+}
+
+/*
+ * Staggered walk (the paper's frontend future work, Sec. 5; the model of
+ * Portugal, Santos, Fernandes and Goncalves, 2016), on the vertex basis.  A
+ * tessellation k is a partition of the vertices into polygons alpha, each
+ * with a real unit vector |alpha> = sum_{v in alpha} a_v |v> (uniform:
+ * a_v = 1/sqrt|alpha|), and P_k = sum_alpha |alpha><alpha| is the projector
+ * onto their span.  With H_k = 2 P_k - I (a reflection, H_k^2 = I) one step is
+ *   psi <- U_T ... U_2 U_1 R_M psi,
+ * R_M = I - 2 sum_{m in M} |m><m| (the marked vertices' phase flip, applied
+ * first), and U_k = H_k (form 0, the reflection) or U_k = exp(i theta_k H_k)
+ * = cos(theta_k) I + i sin(theta_k) H_k (form 1, the staggered model with
+ * Hamiltonians).  The projection is formed in a vector of its own, then
+ * psi <- c0 psi + c1 (2 P psi - psi) with (c0, c1) = (0, 1) or
+ * (cos theta, i sin theta).
+ *
+ * Tessellation t's polygons are n_poly[t] ranges of its vertex list: its
+ * pointer array (n_poly[t] + 1 entries) is the t-th block of poly_ptr (blocks
+ * back to back), its vertex list (n entries) the t-th block of n entries of
+ * vert, its amplitudes the t-th block of amp when has_amp[t] (else uniform).
+ * Returns 0, or -4 on allocation failure.
+ */
+int orc_staggered_evolve(int64_t n, int32_t n_tess, const int64_t *n_poly, const int64_t *poly_ptr,
+                         const int32_t *vert, const double *amp, const uint8_t *has_amp, const int32_t *form,
+                         const double *theta, const uint8_t *marked, double *psi_io, int64_t steps) {
+  cplx *psi = (cplx *)psi_io;
+  cplx *proj = (cplx *)malloc(sizeof(cplx) * (size_t)(n > 0 ? n : 1));
+  int64_t *ptr_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_tess > 0 ? n_tess : 1));
+  if (!proj || !ptr_off) {
+    free(proj);
+    free(ptr_off);
+    return -4;
+  }
+  int64_t off = 0;
+  for (int32_t t = 0; t < n_tess; ++t) {
+    ptr_off[t] = off;
+    off += n_poly[t] + 1;
+  }
+  for (int64_t s = 0; s < steps; ++s) {
+    if (marked && g_fault != ORC_FAULT_STAG_MARK_AFTER)
+      for (int64_t v = 0; v < n; ++v)
+        if (marked[v]) psi[v] = -psi[v];
+    for (int32_t k = 0; k < n_tess; ++k) {
+      int32_t t = (g_fault == ORC_FAULT_STAG_REVERSED) ? n_tess - 1 - k : k;
+      const int64_t *pp = poly_ptr + ptr_off[t];
+      const int32_t *vv = vert + (size_t)t * (size_t)n;
+      const double *aa = has_amp[t] ? amp + (size_t)t * (size_t)n : NULL;
+      /* proj = P_t psi, polygon by polygon: <alpha|psi> |alpha> */
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(orc_max_threads())
+      for (int64_t p = 0; p < n_poly[t]; ++p) {
+        int64_t lo = pp[p], hi = pp[p + 1];
+        double uni = 1.0 / sqrt((double)(hi - lo));
+        cplx inner = 0.0;
+        for (int64_t i = lo; i < hi; ++i) inner += (aa ? aa[i] : uni) * psi[vv[i]];
+        for (int64_t i = lo; i < hi; ++i) proj[vv[i]] = (aa ? aa[i] : uni) * inner;
+      }
+      cplx c0 = 0.0, c1 = 1.0;
+      if (form[t] == 1) {
+        double th = (g_fault == ORC_FAULT_STAG_THETA_SIGN) ? -theta[t] : theta[t];
+        c0 = cos(th);
+        c1 = I * sin(th);
+      }
+      double two = (g_fault == ORC_FAULT_STAG_ONE_PROJ) ? 1.0 : 2.0;
+#pragma omp parallel for schedule(static) num_threads(orc_max_threads())
+      for (int64_t v = 0; v < n; ++v) psi[v] = c0 * psi[v] + c1 * (two * proj[v] - psi[v]);
+    }
+    if (marked && g_fault == ORC_FAULT_STAG_MARK_AFTER)
+      for (int64_t v = 0; v < n; ++v)
+        if (marked[v]) psi[v] = -psi[v];
+  }
+  free(proj);
+  free(ptr_off);
   return 0;
 }
 

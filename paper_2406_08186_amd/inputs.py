@@ -1,8 +1,9 @@
 """Seeded synthetic inputs: graph families and initial states.
 
 This module is shared by the HIP path's tests and bench and by the CPU
-oracle's tests.  It draws graphs and states and does nothing else: no coin,
-no shift, no Hamiltonian, no probability -- none of the walk arithmetic.
+oracle's tests.  It draws graphs, states and staggered-walk tessellations
+(vertex partitions) and does nothing else: no coin, no shift, no
+Hamiltonian, no reflection, no probability -- none of the walk arithmetic.
 
 Graphs are returned as a symmetric 0/1 adjacency pattern in CSR form
 (``row_ptr`` int64[n+1], ``col`` int32[nnz]).  Row ``v`` lists the heads of
@@ -280,6 +281,146 @@ def random_mixed(n: int, seed: int, p: float = 0.15, n_isolated: int = 1,
         leaf = core + i
         edges.add((int(rng.integers(core)), leaf))
     return from_edges(n, sorted(edges), name=f"mixed{n}s{seed}")
+
+
+# ---------------------------------------------------------------------------
+# Staggered-walk tessellations
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Tessellation:
+    """A partition of the vertices into polygons (cliques of the walk's
+    graph): polygon p is ``poly_vert[poly_ptr[p]:poly_ptr[p+1]]``.  ``amp``
+    holds one real amplitude per position of ``poly_vert`` (None = uniform);
+    ``theta`` None asks for the reflection form, a number for the
+    Hamiltonian form with that angle."""
+
+    poly_ptr: np.ndarray  # int64[polygons + 1]
+    poly_vert: np.ndarray  # int32[n]
+    amp: np.ndarray | None = None
+    theta: float | None = None
+
+    @property
+    def n_polygons(self) -> int:
+        return int(self.poly_ptr.size - 1)
+
+    def sizes(self) -> np.ndarray:
+        return np.diff(self.poly_ptr)
+
+
+def tessellation(polygons, amp=None, theta=None) -> Tessellation:
+    """Tessellation from a list of vertex lists (one per polygon)."""
+    sizes = np.array([len(p) for p in polygons], dtype=np.int64)
+    ptr = np.zeros(sizes.size + 1, np.int64)
+    np.cumsum(sizes, out=ptr[1:])
+    vert = np.concatenate([np.asarray(p, dtype=np.int64) for p in polygons]) if polygons else np.zeros(0)
+    return Tessellation(ptr, vert.astype(np.int32), amp, theta)
+
+
+def _uniform_tessellation(vert_by_poly: np.ndarray) -> Tessellation:
+    """Polygons of one size: row p of ``vert_by_poly`` lists polygon p."""
+    npoly, size = vert_by_poly.shape
+    ptr = np.arange(0, npoly * size + 1, size, dtype=np.int64)
+    return Tessellation(ptr, vert_by_poly.reshape(-1).astype(np.int32))
+
+
+def union_graph(n: int, tessellations, name: str = "staggered") -> Graph:
+    """The graph whose edges are the pairs of vertices sharing a polygon of
+    some tessellation (every polygon a clique of it)."""
+    edges = []
+    for t in tessellations:
+        sizes = t.sizes()
+        for size in np.unique(sizes):
+            if size < 2:
+                continue
+            idx = np.flatnonzero(sizes == size)
+            members = t.poly_vert[t.poly_ptr[idx][:, None] + np.arange(size)[None, :]].astype(np.int64)
+            iu, ju = np.triu_indices(int(size), 1)
+            edges.append(np.stack([members[:, iu].reshape(-1), members[:, ju].reshape(-1)], 1))
+    if not edges:
+        return from_edges(n, [], name)
+    e = np.concatenate(edges)
+    e = np.sort(e, axis=1)
+    e = np.unique(e, axis=0)
+    return from_edges(n, e, name)
+
+
+def stag_cycle(n: int) -> tuple[Graph, list[Tessellation]]:
+    """Even cycle C_n, two tessellations by its edges: {2i, 2i+1} and
+    {2i+1, 2i+2 mod n}."""
+    if n < 4 or n % 2:
+        raise ValueError("an even cycle of at least 4 vertices")
+    v = np.arange(0, n, 2, dtype=np.int64)
+    a = _uniform_tessellation(np.stack([v, v + 1], 1))
+    b = _uniform_tessellation(np.stack([v + 1, (v + 2) % n], 1))
+    return cycle_sorted(n), [a, b]
+
+
+def stag_lattice(l1: int, l2: int | None = None) -> tuple[Graph, list[Tessellation]]:
+    """Periodic l1 x l2 lattice (vertex r*l2 + c) covered by 2 x 2 squares:
+    tessellation alpha holds the squares with top-left corner (2i, 2j), beta
+    those with corner (2i+1, 2j+1); each square lists its corners in the
+    order (r, c), (r, c+1), (r+1, c), (r+1, c+1).  The graph is the union of
+    the squares as cliques (degree 6)."""
+    l2 = l1 if l2 is None else l2
+    if l1 < 4 or l2 < 4 or l1 % 2 or l2 % 2:
+        raise ValueError("even sides of at least 4")
+    tess = []
+    for off in (0, 1):
+        r = (np.arange(0, l1, 2, dtype=np.int64) + off)[:, None]
+        c = (np.arange(0, l2, 2, dtype=np.int64) + off)[None, :]
+        r1, c1 = (r + 1) % l1, (c + 1) % l2
+        corners = np.stack([np.broadcast_to(x, (l1 // 2, l2 // 2)) for x in
+                            (r * l2 + c, r * l2 + c1, r1 * l2 + c, r1 * l2 + c1)], axis=-1)
+        tess.append(_uniform_tessellation(corners.reshape(-1, 4)))
+    return union_graph(l1 * l2, tess, name=f"stag_lattice{l1}x{l2}"), tess
+
+
+def stag_arcs(g: Graph) -> tuple[Graph, list[Tessellation]]:
+    """Staggered walk on the arcs of ``g`` (staggered vertex = arc position in
+    CSR order): tessellation 1 puts the arcs of each tail in one polygon (in
+    row order), tessellation 2 pairs every arc with its reverse."""
+    stars = [list(range(int(g.row_ptr[v]), int(g.row_ptr[v + 1]))) for v in range(g.n)
+             if g.row_ptr[v + 1] > g.row_ptr[v]]
+    tails = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    heads = g.col.astype(np.int64)
+    key = tails * g.n + heads
+    order = np.argsort(key)
+    rkey = heads * g.n + tails
+    rev = order[np.searchsorted(key[order], rkey)]
+    a = np.arange(g.n_arcs, dtype=np.int64)
+    first = a < rev
+    pairs = np.stack([a[first], rev[first]], 1)
+    tess = [tessellation(stars), _uniform_tessellation(pairs)]
+    return union_graph(g.n_arcs, tess, name=f"{g.name}_arcs"), tess
+
+
+def stag_random(n: int, n_tess: int, max_size: int, seed: int,
+                weighted: bool = False) -> tuple[Graph, list[Tessellation]]:
+    """``n_tess`` random tessellations of n vertices, polygon sizes uniform in
+    1..max_size (the last polygon takes what is left), vertices shuffled;
+    weighted: random real amplitudes scaled to unit length per polygon."""
+    rng = np.random.default_rng(seed)
+    tess = []
+    for _ in range(n_tess):
+        perm = rng.permutation(n)
+        sizes = []
+        left = n
+        while left > 0:
+            s = int(min(left, rng.integers(1, max_size + 1)))
+            sizes.append(s)
+            left -= s
+        ptr = np.zeros(len(sizes) + 1, np.int64)
+        np.cumsum(sizes, out=ptr[1:])
+        t = Tessellation(ptr, perm.astype(np.int32))
+        if weighted:
+            amp = rng.uniform(-1.0, 1.0, n)
+            for p in range(len(sizes)):
+                seg = slice(ptr[p], ptr[p + 1])
+                amp[seg] /= np.linalg.norm(amp[seg])
+            t.amp = amp
+        tess.append(t)
+    return union_graph(n, tess, name=f"stag_random{n}"), tess
 
 
 # ---------------------------------------------------------------------------

@@ -86,7 +86,27 @@ def _complete_search_ok():
     return abs(abs(psi[3]) ** 2 - 1) < 1e-12
 
 
-CHECKS = [_coined_dense_ok, _coined_norm_ok, _hadamard_ok, _hadamard_dense_ok, _hypercube_ok, _prob_tail_ok,
+def _stag_arcs_ok():
+    g = I.random_mixed(12, seed=3)
+    sg, tess = I.stag_arcs(g)
+    psi0 = I.random_state(g.n_arcs, 9)
+    a = oracle.staggered_evolve(sg.n, tess, psi0, 5)
+    return np.abs(a - oracle.coined_evolve(g.row_ptr, g.col, psi0, 5)).max() < 1e-13
+
+
+def _stag_mark_order_ok():
+    _, tess = I.stag_cycle(12)
+    got = oracle.staggered_evolve(12, tess, I.ket_vertex(12, 4), 1, marked=[4])
+    return np.abs(got + I.ket_vertex(12, 6)).max() < 1e-15
+
+
+def _stag_theta_ok():
+    edge = I.tessellation([[0, 1]], theta=0.3)
+    got = oracle.staggered_evolve(2, [edge], I.ket_vertex(2, 0), 3)
+    return np.abs(got - np.array([math.cos(0.9), 1j * math.sin(0.9)])).max() < 1e-14
+
+
+CHECKS = [_stag_arcs_ok, _stag_mark_order_ok, _stag_theta_ok, _coined_dense_ok, _coined_norm_ok, _hadamard_ok, _hadamard_dense_ok, _hypercube_ok, _prob_tail_ok,
           _ctqw_eigh_ok, _ctqw_poly_ok, _complete_search_ok]
 
 
