@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--workload", default="grid",
-                    choices=["grid", "batch", "serve", "dense", "hypercube", "cycle", "snapshots"],
+                    choices=["grid", "batch", "serve", "dense", "hypercube", "cycle", "snapshots", "staggered"],
                     help="grid: the 1024^2 CTQW (default); batch: many CTQW searches on random "
                          "regular graphs in one batch; serve: the Poisson job stream")
     ap.add_argument("--batch-walks", type=int, default=4096)
@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--hypercube-steps", type=int, default=0,
                     help="override the step count (profiling runs); 0 = ceil((pi/2) sqrt(N ln N))")
     ap.add_argument("--hypercube-dtypes", default="c64,c128")
+    ap.add_argument("--stag-side", type=int, default=4096, help="staggered workload: side of the square lattice")
+    ap.add_argument("--stag-steps", type=int, default=200, help="staggered workload: steps per timed pass")
+    ap.add_argument("--stag-dtypes", default="c64,c128")
     return ap.parse_args()
 
 
@@ -180,6 +183,9 @@ def main():
         return
     if args.workload == "snapshots":
         run_snapshots(args)
+        return
+    if args.workload == "staggered":
+        run_staggered(args)
         return
     spp = args.steps_per_pass
     dtypes = args.dtypes.split(",")
@@ -695,6 +701,72 @@ def run_snapshots(args):
         "streamed_states_GBps": mb_state / 1e3 / t_state, "d2h_alone_GBps": mb_state / 1e3 / t_d2h,
         "streamed_equals_naive": same, "final_equals_unsnapshotted": final_ok,
         "arc_steps_per_s_streamed": g.n_arcs * STEPS_PER_PASS / t_state}), flush=True)
+
+
+# ---------------------------------------------------------------- staggered lattice search
+
+def run_staggered(args):
+    """Staggered-walk search on the periodic L x L square lattice (default
+    L = 4096, 2^24 vertices): two tessellations of 2 x 2 squares (corners at
+    even and at odd coordinates), uniform amplitudes, reflection form, the
+    centre vertex marked, uniform start.  One timed pass is --stag-steps steps
+    (two tessellation launches each, the marked flip fused into the first),
+    timed with HIP events on the launch stream; the readout follows outside
+    the timed region.  3 steps from a random state are checked against the
+    oracle at full size."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Plan
+    side = args.stag_side
+    g, tess = I.stag_lattice(side)
+    marked = [(side // 2) * side + side // 2]
+    steps = args.stag_steps
+    psi0 = I.uniform(g.n)
+    # the check starts from a random state: from the uniform one every
+    # amplitude stays a short dyadic fraction and any path would be exact
+    chk0 = I.random_state(g.n, 1)
+    ref3 = oracle.staggered_evolve(g.n, tess, chk0, 3, marked=marked)
+    res = {}
+    for dtype in args.stag_dtypes.split(","):
+        pl = Plan(g, "staggered", dtype=dtype, marked=marked, tessellations=tess)
+        psi = pl.state(chk0)
+        pl.evolve(psi, 3)
+        torch.cuda.synchronize()
+        got3 = psi.cpu().numpy().astype(np.complex128)
+        err3 = float(np.abs(got3 - ref3).max()) if dtype == "c128" else float(np.linalg.norm(got3 - ref3))
+        psi = pl.state(psi0)
+        pl.evolve(psi, 5)
+        psi = pl.state(psi0)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        pl.evolve(psi, steps)
+        b.record()
+        p, norm, pm = pl.probabilities(psi)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        es = 8 if dtype == "c64" else 16
+        # algorithmic bytes of one tessellation launch: read and write every
+        # amplitude (2 S) and read its vertex index (4 B; the squares are one
+        # size, so no polygon pointers and no amplitudes are stored)
+        per_vertex = 2 * es + 4
+        launch_ms = ms / (steps * len(tess))
+        gbs = per_vertex * g.n / (launch_ms * 1e-3) / 1e9
+        res[dtype] = {"vertex_steps_per_s": g.n * steps / (ms * 1e-3), "ms": ms, "launch_ms": launch_ms,
+                      "bytes_per_vertex_launch": per_vertex, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                      "p_marked": float(pm), "norm": float(norm), "path": pl.structure,
+                      ("max_abs_err_3_steps" if dtype == "c128" else "l2_err_3_steps"): err3}
+        res[dtype]["state"] = psi
+        pl.close()
+    out = {k: {kk: vv for kk, vv in v.items() if kk != "state"} for k, v in res.items()}
+    if "c64" in res and "c128" in res:
+        out["l2_c64_vs_c128"] = float(torch.linalg.norm(res["c64"]["state"].to(torch.complex128)
+                                                        - res["c128"]["state"]).item())
+    print(json.dumps({"workload": f"staggered_lattice_{side}x{side}_squares_{steps}steps", "n": g.n,
+                      "tessellations": len(tess), "unit": "vertex-steps/s", **out}), flush=True)
 
 
 # ---------------------------------------------------------------- 64-cycle latency

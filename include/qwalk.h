@@ -58,6 +58,20 @@ extern "C" {
 /* ---- enums ------------------------------------------------------------- */
 #define QW_COINED 0
 #define QW_CTQW 1
+/* Staggered walk (named as future work in Sec. 5; the paper gives no
+ * definition, the engine follows the published staggered model of Portugal
+ * et al.).  The state lives on the vertices.  Each tessellation k partitions
+ * the vertices into polygons alpha (cliques of the graph) with real unit
+ * vectors |alpha> = sum_{v in alpha} a_v |v> (uniform a_v = 1/sqrt|alpha|
+ * unless given); P_k = sum_alpha |alpha><alpha| and H_k = 2 P_k - I.  One step
+ * is psi <- U_T ... U_1 R_M psi: first the phase flip R_M = I - 2 sum_{m in M}
+ * |m><m| of the marked vertices, then U_1, ..., U_T in order, with
+ * U_k = H_k (QW_REFLECTION) or U_k = exp(i theta_k H_k) = cos(theta_k) I +
+ * i sin(theta_k) H_k (QW_HAMILTONIAN).  Probability: p_v = |psi_v|^2. */
+#define QW_STAGGERED 2
+
+#define QW_REFLECTION 0
+#define QW_HAMILTONIAN 1
 
 /* Coins (Sec. 3.2).  GROVER: (2/d) J - I on each vertex's arcs.  HADAMARD:
  * (1/sqrt 2)[[1, 1], [1, -1]] (degree 2 only).  FOURIER: F[j][k] =
@@ -126,9 +140,32 @@ typedef struct qw_csr {
   const int32_t *col;
 } qw_csr;
 
+/* ---- staggered-walk tessellation ----------------------------------------- */
+/* One tessellation of a staggered walk (QW_STAGGERED above).  Host memory,
+ * read and copied at plan creation.
+ *   n_polygons  >= 1 (0 only when the graph has no vertices)
+ *   poly_ptr    int64[n_polygons + 1], poly_ptr[0] = 0, strictly increasing,
+ *               poly_ptr[n_polygons] = n: polygon p is the vertex list
+ *               poly_vert[poly_ptr[p] .. poly_ptr[p+1] - 1]
+ *   poly_vert   int32[n], every vertex exactly once (a partition); every
+ *               polygon must be a clique of the plan's graph (else QW_EGRAPH)
+ *   amp         double[n] aligned with poly_vert (the real amplitude of the
+ *               vertex in its polygon's vector; each polygon's squares sum to
+ *               1 within 1e-12), or NULL for uniform amplitudes
+ *   form        QW_REFLECTION or QW_HAMILTONIAN; theta: the angle of the
+ *               Hamiltonian form (finite), ignored by the reflection form */
+typedef struct qw_tessellation {
+  int64_t n_polygons;
+  const int64_t *poly_ptr;
+  const int32_t *poly_vert;
+  const double *amp;
+  int32_t form;
+  double theta;
+} qw_tessellation;
+
 /* ---- walk description --------------------------------------------------- */
 typedef struct qw_walk_desc {
-  int32_t kind;         /* QW_COINED or QW_CTQW                                */
+  int32_t kind;         /* QW_COINED, QW_CTQW or QW_STAGGERED                   */
   int32_t coin;         /* coined: QW_GROVER, QW_HADAMARD (degree 2 only),
                            QW_FOURIER, QW_MATRIX or QW_SZEGEDY                 */
   int32_t dtype;        /* QW_C64 or QW_C128                                   */
@@ -155,6 +192,9 @@ typedef struct qw_walk_desc {
                            arc (tail -> head) in CSR order, >= 0, every row
                            of a vertex with arcs summing to 1 within 1e-12;
                            copied at creation                                 */
+  int32_t n_tessellations; /* staggered: T in [1, 64]                         */
+  const qw_tessellation *tessellations; /* staggered: host array of T, applied
+                           in array order                                     */
 } qw_walk_desc;
 /* FOURIER and MATRIX coins and the PERSISTENT shift run on the index-free
  * lattice kernels only: the graph must be a cycle (rows ordered v+1, v-1) or
@@ -163,7 +203,12 @@ typedef struct qw_walk_desc {
  * PERSISTENT shift with the GROVER coin accepts the rows in any order.
  * Otherwise QW_EUNSUPPORTED.  Such walks cannot join a batch.  The SZEGEDY
  * coin runs on the one-workgroup and general CSR paths (any graph, flip-flop
- * shift) and cannot join a batch either. */
+ * shift) and cannot join a batch either.  A STAGGERED walk (state length n,
+ * marked vertices phase-flipped) runs on the one-workgroup path (AUTO, when
+ * the state fits one workgroup's LDS) or on per-tessellation polygon kernels
+ * (any layout but DENSE, which it rejects); it cannot join a batch but can
+ * join qw_small_many.  The graph only serves to check that every polygon is
+ * a clique: edges that lie in no polygon play no part in the walk. */
 
 typedef struct qw_plan qw_plan;
 
@@ -171,7 +216,7 @@ typedef struct qw_plan_info {
   int64_t n;               /* vertices                                        */
   int64_t n_arcs;          /* arcs (= 2|E|)                                   */
   int64_t state_len;       /* complex elements of the state: n_arcs (coined),
-                              n (CTQW) or n * columns (dense)                 */
+                              n (CTQW, staggered) or n * columns (dense)      */
   int32_t kind, coin, dtype, structure;
   int32_t dims[2];         /* CYCLE: {n,0}; TORUS: {l1,l2}; HYPERCUBE: {dim,0}*/
   int32_t max_degree;
@@ -212,10 +257,10 @@ int qw_plan_get_info(const qw_plan *plan, qw_plan_info *info);
  * QW_EDEVICE. */
 int qw_plan_upload(qw_plan *plan, void *d_graph, size_t graph_bytes, void *stream);
 
-/* Advance the state by `steps` steps in place: psi <- U^steps psi (coined)
- * or psi <- T_K(-iH dt)^steps psi (CTQW).  d_psi: device state of
+/* Advance the state by `steps` steps in place: psi <- U^steps psi (coined,
+ * staggered) or psi <- T_K(-iH dt)^steps psi (CTQW).  d_psi: device state of
  * info.state_len complex elements in the boundary layout (coined: CSR arc
- * order; CTQW: vertex order), read and written.  d_work: device workspace of
+ * order; CTQW and staggered: vertex order), read and written.  d_work: device workspace of
  * at least info.work_bytes bytes, contents undefined on return.  If any of
  * d_p (double[n]), d_norm (double[1]), d_pmarked (double[1]) is non-NULL the
  * readout of qw_probabilities is produced from the final state as part of
@@ -226,7 +271,8 @@ int qw_evolve(const qw_plan *plan, void *d_psi, void *d_work, size_t work_bytes,
               double *d_p, double *d_norm, double *d_pmarked, void *stream);
 
 /* FP64 readout of a state (Sec. 3.1, Sec. 3.2): d_p[v] = probability of
- * vertex v (coined: summed over arcs with tail v; CTQW: |psi_v|^2; dense
+ * vertex v (coined: summed over arcs with tail v; CTQW and
+ * staggered: |psi_v|^2; dense
  * layout: d_p has n * columns entries, p of walk b at v*columns + b, and the
  * norm and marked sums run over all walks),
  * *d_norm = sum_v p_v, *d_pmarked = sum over the marked set of p_v.  Each

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_PKG, "libqwalk.so")
 QW_OK, QW_EINVAL, QW_EGRAPH, QW_EUNSUPPORTED, QW_ENOMEM, QW_EDEVICE, QW_ESTATE = range(7)
 ERRORS = {1: "QW_EINVAL", 2: "QW_EGRAPH", 3: "QW_EUNSUPPORTED", 4: "QW_ENOMEM", 5: "QW_EDEVICE",
           6: "QW_ESTATE"}
-QW_COINED, QW_CTQW = 0, 1
+QW_COINED, QW_CTQW, QW_STAGGERED = 0, 1, 2
+QW_REFLECTION, QW_HAMILTONIAN = 0, 1
 QW_GROVER, QW_HADAMARD, QW_FOURIER, QW_MATRIX, QW_SZEGEDY = 0, 1, 2, 3, 4
 QW_FLIPFLOP, QW_PERSISTENT = 0, 1
 QW_C64, QW_C128 = 0, 1
@@ -39,13 +40,19 @@ class QwCsr(C.Structure):
     _fields_ = [("n", C.c_int64), ("row_ptr", C.POINTER(C.c_int64)), ("col", C.POINTER(C.c_int32))]
 
 
+class QwTessellation(C.Structure):
+    _fields_ = [("n_polygons", C.c_int64), ("poly_ptr", C.POINTER(C.c_int64)), ("poly_vert", C.POINTER(C.c_int32)),
+                ("amp", C.POINTER(C.c_double)), ("form", C.c_int32), ("theta", C.c_double)]
+
+
 class QwWalkDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("coin", C.c_int32), ("dtype", C.c_int32), ("layout", C.c_int32),
                 ("gamma", C.c_double), ("dt", C.c_double), ("taylor_order", C.c_int32),
                 ("trunc_tol", C.c_double), ("horizon_steps", C.c_int64),
                 ("marked", C.POINTER(C.c_int32)), ("n_marked", C.c_int64), ("columns", C.c_int32),
                 ("shift", C.c_int32), ("coin_dim", C.c_int32), ("coin_matrix", C.POINTER(C.c_double)),
-                ("transition", C.POINTER(C.c_double))]
+                ("transition", C.POINTER(C.c_double)), ("n_tessellations", C.c_int32),
+                ("tessellations", C.POINTER(QwTessellation))]
 
 
 class QwPlanInfo(C.Structure):

@@ -341,6 +341,7 @@ int qw_batch_set_slot(qw_batch *b, int32_t slot, const qw_plan *p, void *d_psi, 
   if (!p || !d_psi || !d_work) return set_error(QW_EINVAL, "null plan, state or workspace");
   if (!p->d_graph) return set_error(QW_ESTATE, "plan not uploaded");
   if (p->dtype != b->dtype) return set_error(QW_EINVAL, "plan dtype differs from the batch's");
+  if (p->kind == QW_STAGGERED) return set_error(QW_EUNSUPPORTED, "staggered walks cannot join a batch");
   const bool coined_struct = p->kind == QW_COINED &&
                              (p->structure == kCycle || p->structure == kTorus || p->structure == kHypercube);
   if (!(p->structure == kGeneral || (p->kind == QW_CTQW && p->structure == kEll) || coined_struct))

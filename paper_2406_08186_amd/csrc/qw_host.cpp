@@ -136,11 +136,142 @@ void put(std::vector<unsigned char> &img, size_t off, const X *src, size_t count
   if (count) std::memcpy(img.data() + off, src, count * sizeof(X));
 }
 
+// Host tables of one staggered tessellation before they go into the image.
+struct StagHost {
+  std::vector<int32_t> vert, ptr, bptr, bvert;
+  std::vector<double> amp, bamp;
+  std::vector<StagChunk> chunks;
+};
+
+// Validate the tessellations (partitions of the vertices into cliques of the
+// graph with unit polygon vectors) and split each into thread-path polygons
+// (at most kStagThreadMax vertices; one size -> column-major table) and big
+// polygons cut into chunks of kStagChunk positions.
+int build_tessellations(const qw_walk_desc *w, int64_t n, const std::vector<int64_t> &rp, const int32_t *col,
+                        std::vector<StagHost> &out, qw_plan *p) {
+  const int32_t T = w->n_tessellations;
+  if (T < 1 || T > kStagMaxTess) return fail(QW_EINVAL, "a staggered walk needs 1..%d tessellations, got %d", kStagMaxTess, T);
+  if (!w->tessellations) return fail(QW_EINVAL, "null tessellation array");
+  out.assign(static_cast<size_t>(T), StagHost());
+  p->stag.assign(static_cast<size_t>(T), StagTess());
+  std::vector<int32_t> seen(static_cast<size_t>(n), -1);
+  std::vector<int64_t> owner(static_cast<size_t>(n), -1);
+  int64_t poly_id = 0;
+  for (int32_t k = 0; k < T; ++k) {
+    const qw_tessellation &q = w->tessellations[k];
+    const int64_t np = q.n_polygons;
+    if (np < (n > 0 ? 1 : 0) || np > n) return fail(QW_EINVAL, "tessellation %d: %lld polygons for %lld vertices", k, (long long)np, (long long)n);
+    if (n > 0 && (!q.poly_ptr || !q.poly_vert)) return fail(QW_EINVAL, "tessellation %d: null polygon arrays", k);
+    if (q.form != QW_REFLECTION && q.form != QW_HAMILTONIAN) return fail(QW_EINVAL, "tessellation %d: bad form %d", k, q.form);
+    if (q.form == QW_HAMILTONIAN && !std::isfinite(q.theta)) return fail(QW_EINVAL, "tessellation %d: theta not finite", k);
+    if (n == 0) continue;
+    const int64_t *pp = q.poly_ptr;
+    if (pp[0] != 0 || pp[np] != n) return fail(QW_EINVAL, "tessellation %d: poly_ptr must run from 0 to n", k);
+    for (int64_t i = 0; i < np; ++i)
+      if (pp[i + 1] <= pp[i]) return fail(QW_EINVAL, "tessellation %d: polygon %lld is empty", k, (long long)i);
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t v = q.poly_vert[i];
+      if (v < 0 || v >= n) return fail(QW_EINVAL, "tessellation %d: vertex %d out of range", k, v);
+      if (seen[v] == k) return fail(QW_EINVAL, "tessellation %d: vertex %d in two polygons", k, v);
+      seen[v] = k;
+    }
+    for (int64_t i = 0; i < np; ++i) {
+      const int64_t lo = pp[i], hi = pp[i + 1], sz = hi - lo;
+      // clique: every member has the other sz - 1 members among its neighbours
+      for (int64_t j = lo; j < hi; ++j) owner[q.poly_vert[j]] = poly_id;
+      for (int64_t j = lo; j < hi; ++j) {
+        const int32_t u = q.poly_vert[j];
+        int64_t cnt = 0;
+        for (int64_t a = rp[u]; a < rp[u + 1]; ++a) cnt += owner[col[a]] == poly_id;
+        if (cnt != sz - 1)
+          return fail(QW_EGRAPH, "tessellation %d: polygon %lld is not a clique of the graph (vertex %d)", k, (long long)i, u);
+      }
+      ++poly_id;
+      if (q.amp) {
+        double ss = 0.0;
+        for (int64_t j = lo; j < hi; ++j) {
+          if (!std::isfinite(q.amp[j])) return fail(QW_EINVAL, "tessellation %d: amplitude %lld not finite", k, (long long)j);
+          ss += q.amp[j] * q.amp[j];
+        }
+        if (std::fabs(ss - 1.0) > 1e-12)
+          return fail(QW_EINVAL, "tessellation %d: polygon %lld has squared amplitudes summing to %.17g", k, (long long)i, ss);
+      }
+    }
+    // split into thread-path and big polygons
+    StagHost &h = out[static_cast<size_t>(k)];
+    StagTess &t = p->stag[static_cast<size_t>(k)];
+    int64_t n_small = 0, small_size = -1, max_small = 0, small_pos = 0;
+    for (int64_t i = 0; i < np; ++i) {
+      const int64_t sz = pp[i + 1] - pp[i];
+      if (sz > kStagThreadMax) continue;
+      ++n_small;
+      small_pos += sz;
+      max_small = std::max(max_small, sz);
+      small_size = (small_size < 0 || small_size == sz) ? sz : 0;
+    }
+    t.n_small = static_cast<int32_t>(n_small);
+    t.max_small = static_cast<int32_t>(max_small);
+    t.small_size = static_cast<int32_t>(std::max<int64_t>(small_size, 0));
+    if (n_small > 0) {
+      h.vert.resize(static_cast<size_t>(small_pos));
+      if (q.amp) h.amp.resize(static_cast<size_t>(small_pos));
+      if (t.small_size == 0) h.ptr.reserve(static_cast<size_t>(n_small) + 1);
+      int64_t ps = 0, at = 0;
+      for (int64_t i = 0; i < np; ++i) {
+        const int64_t lo = pp[i], sz = pp[i + 1] - lo;
+        if (sz > kStagThreadMax) continue;
+        if (t.small_size == 0) h.ptr.push_back(static_cast<int32_t>(at));
+        for (int64_t j = 0; j < sz; ++j) {
+          const size_t dst = t.small_size > 0 ? static_cast<size_t>(j * n_small + ps) : static_cast<size_t>(at + j);
+          h.vert[dst] = q.poly_vert[lo + j];
+          if (q.amp) h.amp[dst] = q.amp[lo + j];
+        }
+        at += sz;
+        ++ps;
+      }
+      if (t.small_size == 0) h.ptr.push_back(static_cast<int32_t>(at));
+    }
+    h.bptr.push_back(0);
+    for (int64_t i = 0; i < np; ++i) {
+      const int64_t lo = pp[i], sz = pp[i + 1] - lo;
+      if (sz <= kStagThreadMax) continue;
+      const int32_t begin = static_cast<int32_t>(h.bvert.size());
+      const int32_t first = static_cast<int32_t>(h.chunks.size());
+      const int32_t count = static_cast<int32_t>((sz + kStagChunk - 1) / kStagChunk);
+      for (int64_t j = 0; j < sz; ++j) {
+        h.bvert.push_back(q.poly_vert[lo + j]);
+        if (q.amp) h.bamp.push_back(q.amp[lo + j]);
+      }
+      for (int32_t c = 0; c < count; ++c) {
+        StagChunk ch{};
+        ch.begin = begin + c * kStagChunk;
+        ch.end = static_cast<int32_t>(std::min<int64_t>(begin + sz, int64_t{begin} + int64_t{c + 1} * kStagChunk));
+        ch.first = first;
+        ch.count = count;
+        ch.size = static_cast<int32_t>(sz);
+        h.chunks.push_back(ch);
+      }
+      h.bptr.push_back(static_cast<int32_t>(h.bvert.size()));
+    }
+    t.n_big = static_cast<int32_t>(h.bptr.size()) - 1;
+    t.n_chunks = static_cast<int32_t>(h.chunks.size());
+    if (t.n_big == 0) h.bptr.clear();
+    if (q.form == QW_HAMILTONIAN) {
+      t.c0[0] = std::cos(q.theta);
+      t.c0[1] = 0.0;
+      t.c1[0] = 0.0;
+      t.c1[1] = std::sin(q.theta);
+    }
+  }
+  return QW_OK;
+}
+
 int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (!g || !w) return fail(QW_EINVAL, "null graph or walk descriptor");
   const int64_t n = g->n;
   if (n < 0 || n >= (int64_t{1} << 31)) return fail(QW_EINVAL, "vertex count %lld out of range", (long long)n);
-  if (w->kind != QW_COINED && w->kind != QW_CTQW) return fail(QW_EINVAL, "bad walk kind %d", w->kind);
+  if (w->kind != QW_COINED && w->kind != QW_CTQW && w->kind != QW_STAGGERED)
+    return fail(QW_EINVAL, "bad walk kind %d", w->kind);
   if (w->dtype != QW_C64 && w->dtype != QW_C128) return fail(QW_EINVAL, "bad dtype %d", w->dtype);
   if (w->layout < QW_LAYOUT_AUTO || w->layout > QW_LAYOUT_DENSE)
     return fail(QW_EINVAL, "bad layout %d", w->layout);
@@ -240,6 +371,13 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     }
   }
 
+  // ---- staggered tessellations
+  std::vector<StagHost> tess;
+  if (p->kind == QW_STAGGERED) {
+    const int st = build_tessellations(w, n, rp, col, tess, p);
+    if (st != QW_OK) return st;
+  }
+
   // ---- walk parameters
   if (p->kind == QW_COINED && p->coin == QW_HADAMARD) {
     for (int64_t v = 0; v < n; ++v) {
@@ -279,7 +417,10 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   const bool small_fits = p->kind == QW_COINED
                               ? coined_small_lds(c128, static_cast<int>(n), static_cast<int>(na)) <= kSmallLdsBytes
                               : ctqw_small_lds(c128, static_cast<int>(n), static_cast<int>(na)) <= kSmallLdsBytes;
-  if (p->layout == QW_LAYOUT_DENSE) {
+  if (p->kind == QW_STAGGERED) {
+    const bool fits = stag_small_lds(c128, static_cast<int>(n)) <= kSmallLdsBytes;
+    structure = (p->layout == QW_LAYOUT_AUTO && fits && n > 0) ? kSmall : kGeneral;
+  } else if (p->layout == QW_LAYOUT_DENSE) {
     structure = kDense;
     p->columns = std::max(1, w->columns);
     p->ld = static_cast<int32_t>((n + kDenseK - 1) / kDenseK * kDenseK);
@@ -345,7 +486,8 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   p->has_rev = coined && (structure == kGeneral || structure == kSmall);
   p->has_tiles = coined && structure == kGeneral;
   p->has_perm = coined && (structure == kCycle || structure == kTorus || structure == kHypercube);
-  p->has_col = !coined && (structure == kGeneral || structure == kSmall || structure == kEll || structure == kDense);
+  const bool ctqw = p->kind == QW_CTQW;
+  p->has_col = ctqw && (structure == kGeneral || structure == kSmall || structure == kEll || structure == kDense);
 
   std::vector<int32_t> tiles;
   if (p->has_tiles) {
@@ -381,7 +523,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     for (int32_t x : perm)
       if (x < 0) return fail(QW_EINVAL, "internal: structured slot map has a hole");
   }
-  if (!coined && structure == kGeneral) {
+  if (ctqw && structure == kGeneral) {
     const double avg = n > 0 ? static_cast<double>(na) / n : 0.0;
     p->group = avg <= 6 ? 1 : avg <= 12 ? 2 : avg <= 24 ? 4 : avg <= 48 ? 8 : avg <= 96 ? 16 : avg <= 192 ? 32 : 64;
   }
@@ -389,7 +531,7 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   // grid CTQW: stages per launch and, per strip of the blocked kernel, whether
   // a marked vertex lies in its window (halo included)
   std::vector<uint8_t> tmark;
-  if (!coined && structure == kTorus) {
+  if (ctqw && structure == kTorus) {
     GraphView tv;
     tv.structure = structure;
     tv.dims[0] = p->dims[0];
@@ -443,6 +585,20 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (p->has_coin) p->off_coin = section(sizeof(double) * p->coin_mat.size());
   p->has_sqrtp = p->kind == QW_COINED && p->coin == QW_SZEGEDY;
   if (p->has_sqrtp) p->off_sqrtp = section(sizeof(double) * p->sqrt_p.size());
+  for (size_t k = 0; k < tess.size(); ++k) {
+    StagHost &h = tess[k];
+    StagTess &t = p->stag[k];
+    if (!h.vert.empty()) t.off_vert = static_cast<int64_t>(section(sizeof(int32_t) * h.vert.size()));
+    if (!h.amp.empty()) t.off_amp = static_cast<int64_t>(section(sizeof(double) * h.amp.size()));
+    if (!h.ptr.empty()) t.off_ptr = static_cast<int64_t>(section(sizeof(int32_t) * h.ptr.size()));
+    if (!h.bvert.empty()) {
+      t.off_bptr = static_cast<int64_t>(section(sizeof(int32_t) * h.bptr.size()));
+      t.off_bvert = static_cast<int64_t>(section(sizeof(int32_t) * h.bvert.size()));
+      if (!h.bamp.empty()) t.off_bamp = static_cast<int64_t>(section(sizeof(double) * h.bamp.size()));
+      t.off_chunk = static_cast<int64_t>(section(sizeof(StagChunk) * h.chunks.size()));
+    }
+  }
+  if (!tess.empty()) p->off_stag = section(sizeof(StagTess) * p->stag.size());
   p->image.assign(off, 0);
   if (structure == kDense) p->off_dense = align256(off);
   std::vector<int32_t> rp32(static_cast<size_t>(n) + 1);
@@ -466,6 +622,21 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (p->has_tmark) put(p->image, p->off_tmark, tmark.data(), tmark.size());
   if (p->has_coin) put(p->image, p->off_coin, p->coin_mat.data(), p->coin_mat.size());
   if (p->has_sqrtp) put(p->image, p->off_sqrtp, p->sqrt_p.data(), p->sqrt_p.size());
+  int64_t max_chunks = 0;
+  for (size_t k = 0; k < tess.size(); ++k) {
+    const StagHost &h = tess[k];
+    const StagTess &t = p->stag[k];
+    if (t.off_vert >= 0) put(p->image, static_cast<size_t>(t.off_vert), h.vert.data(), h.vert.size());
+    if (t.off_amp >= 0) put(p->image, static_cast<size_t>(t.off_amp), h.amp.data(), h.amp.size());
+    if (t.off_ptr >= 0) put(p->image, static_cast<size_t>(t.off_ptr), h.ptr.data(), h.ptr.size());
+    if (t.off_bptr >= 0) put(p->image, static_cast<size_t>(t.off_bptr), h.bptr.data(), h.bptr.size());
+    if (t.off_bvert >= 0) put(p->image, static_cast<size_t>(t.off_bvert), h.bvert.data(), h.bvert.size());
+    if (t.off_bamp >= 0) put(p->image, static_cast<size_t>(t.off_bamp), h.bamp.data(), h.bamp.size());
+    if (t.off_chunk >= 0) put(p->image, static_cast<size_t>(t.off_chunk), h.chunks.data(), h.chunks.size());
+    max_chunks = std::max<int64_t>(max_chunks, t.n_chunks);
+  }
+  if (!tess.empty()) put(p->image, p->off_stag, p->stag.data(), p->stag.size());
+  std::vector<StagHost>().swap(tess);
 
   // ---- workspace
   const size_t es = c128 ? 16 : 8;
@@ -483,8 +654,13 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     w_off = align256(w_off + std::max<size_t>(bytes, 8));
     return o;
   };
-  wsec(p->state_bytes);                    // buffer 0 at offset 0
-  p->off_w1 = wsec(p->state_bytes);        // buffer 1
+  if (p->kind == QW_STAGGERED) {
+    // in place on the caller's state: only the big-polygon partial sums
+    if (max_chunks > 0) p->off_stagpart = wsec(2 * sizeof(double) * static_cast<size_t>(max_chunks));
+  } else {
+    wsec(p->state_bytes);                  // buffer 0 at offset 0
+    p->off_w1 = wsec(p->state_bytes);      // buffer 1
+  }
   if (p->block_depth > 1) p->off_w2 = wsec(p->state_bytes);  // buffer 2: the other psi
   p->off_pscratch = wsec(sizeof(double) * static_cast<size_t>(n) * p->columns);
   p->off_partials = wsec(sizeof(double) * partials);
@@ -563,6 +739,22 @@ int evolve_coined(const qw_plan *p, void *psi, unsigned char *work, int64_t step
   QW_TRY(coined_perm_out(c128, g, cur, psi, ro, s), "layout permutation kernel");
   if (ro.any()) QW_TRY(finish_readout(g, readout_partials(g), ro, s), "readout reduction kernel");
   return QW_OK;
+}
+
+int evolve_staggered(const qw_plan *p, void *psi, unsigned char *work, int64_t steps, const Readout &ro,
+                     hipStream_t s) {
+  const bool c128 = p->dtype == QW_C128;
+  const GraphView &g = p->view;
+  if (p->structure == kSmall) {
+    QW_TRY(stag_small(c128, g, psi, steps, ro, s), "staggered small-graph kernel");
+    return QW_OK;
+  }
+  auto *partials = reinterpret_cast<double *>(work + p->off_stagpart);
+  for (int64_t i = 0; i < steps && p->n > 0; ++i)
+    for (size_t k = 0; k < p->stag.size(); ++k)
+      QW_TRY(stag_tess(c128, g, p->stag[k], psi, k == 0 && p->n_marked > 0, partials, s),
+             "staggered tessellation kernels");
+  return readout_only(p, psi, ro, s);
 }
 
 int evolve_ctqw(const qw_plan *p, void *psi, unsigned char *work, int64_t steps, const Readout &ro,
@@ -761,6 +953,11 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
   if (p->has_coin) g.coin = reinterpret_cast<const double *>(base + p->off_coin);
   if (p->has_sqrtp) g.sqrtp = reinterpret_cast<const double *>(base + p->off_sqrtp);
   g.columns = p->columns;
+  g.base = base;
+  if (!p->stag.empty()) {
+    g.stag = reinterpret_cast<const StagTess *>(base + p->off_stag);
+    g.n_tess = static_cast<int32_t>(p->stag.size());
+  }
   if (p->structure == kDense) {
     g.ld = p->ld;
     g.dense = base + p->off_dense;
@@ -780,7 +977,9 @@ int qw_evolve(const qw_plan *p, void *d_psi, void *d_work, size_t work_bytes, in
   auto *work = static_cast<unsigned char *>(d_work);
   const Readout ro = make_readout(p, work, d_p, d_norm, d_pmarked);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  st = p->kind == QW_COINED ? evolve_coined(p, d_psi, work, steps, ro, s) : evolve_ctqw(p, d_psi, work, steps, ro, s);
+  st = p->kind == QW_COINED     ? evolve_coined(p, d_psi, work, steps, ro, s)
+       : p->kind == QW_STAGGERED ? evolve_staggered(p, d_psi, work, steps, ro, s)
+                                 : evolve_ctqw(p, d_psi, work, steps, ro, s);
   return st == QW_OK ? ok() : st;
 }
 
@@ -829,17 +1028,20 @@ int qw_small_many(const qw_plan *const *plans, void *const *d_psi, const int64_t
     if (!d_psi[i] && p->state_bytes) return fail(QW_EINVAL, "walk %d: null state", i);
     const bool c128 = p->dtype == QW_C128, coined = p->kind == QW_COINED;
     const int n = static_cast<int>(p->n), na = static_cast<int>(p->n_arcs);
-    lds = std::max(lds, coined ? coined_small_lds(c128, n, na) : ctqw_small_lds(c128, n, na));
+    lds = std::max(lds, coined                      ? coined_small_lds(c128, n, na)
+                        : p->kind == QW_STAGGERED ? stag_small_lds(c128, n)
+                                                  : ctqw_small_lds(c128, n, na));
     const int want = coined ? na : n;
     while (threads < 1024 && threads < want) threads *= 2;
     SmallWalk &w = walks[static_cast<size_t>(i)];
     w.g = p->view;
     w.psi = d_psi[i];
     w.coined = coined;
+    w.staggered = p->kind == QW_STAGGERED;
     w.hadamard = p->coin == QW_HADAMARD;
     w.K = p->K;
     w.steps = steps[i];
-    for (int k = 1; k <= p->K && !coined; ++k) {
+    for (int k = 1; k <= p->K && p->kind == QW_CTQW; ++k) {
       w.beta[k - 1] = p->dt / k;
       w.alpha[k - 1] = p->gamma * p->dt / k;
     }

@@ -48,6 +48,44 @@ struct StripGrid {
   int64_t count() const { return static_cast<int64_t>(tiles_r) * tiles_c; }
 };
 
+// Staggered walk: polygons of at most kStagThreadMax vertices are handled one
+// per thread; larger ones are cut into chunks of at most kStagChunk positions,
+// one workgroup per chunk (partial inner products, then the update).
+constexpr int kStagThreadMax = 16;
+constexpr int kStagChunk = 2048;
+constexpr int kStagMaxTess = 64;
+
+// One tessellation of a staggered walk as the kernels see it.  Offsets are
+// bytes from the start of the plan's device buffer (-1: absent).
+struct StagTess {
+  int32_t n_small = 0;     // polygons on the thread path
+  int32_t small_size = 0;  // > 0: all of size small_size, column-major table vert[j*n_small + p]; 0: CSR
+  int32_t max_small = 0;   // largest thread-path polygon
+  int32_t n_big = 0;       // polygons above kStagThreadMax vertices
+  int32_t n_chunks = 0;    // chunks of the big polygons
+  int32_t pad = 0;
+  int64_t off_ptr = -1;    // thread path, CSR: int32[n_small + 1]
+  int64_t off_vert = -1;   // thread path: int32 vertices
+  int64_t off_amp = -1;    // thread path: double amplitudes (same layout as vert), -1 = uniform
+  int64_t off_bptr = -1;   // big polygons: int32[n_big + 1] into bvert
+  int64_t off_bvert = -1;
+  int64_t off_bamp = -1;   // -1 = uniform
+  int64_t off_chunk = -1;  // StagChunk[n_chunks]
+  double c0[2] = {0.0, 0.0};  // U = c0 I + c1 (2P - I): reflection (0, 1), Hamiltonian (cos t, i sin t)
+  double c1[2] = {1.0, 0.0};
+};
+
+// A chunk of a big polygon: positions [begin, end) of bvert; the polygon's
+// chunks are first .. first + count - 1.
+struct StagChunk {
+  int32_t begin;
+  int32_t end;
+  int32_t first;
+  int32_t count;
+  int32_t size;  // vertices of the polygon
+  int32_t pad[3];
+};
+
 // Device view of a plan's graph tables (pointers into the caller's buffer).
 struct GraphView {
   int32_t n = 0;
@@ -74,6 +112,9 @@ struct GraphView {
   int32_t persistent = 0;              // coined on a lattice: persistent shift
   const double *coin = nullptr;        // coined on a lattice: d x d complex coin (row-major), else null
   const double *sqrtp = nullptr;       // Szegedy coin: sqrt(P) per arc, else null
+  const unsigned char *base = nullptr; // start of the plan's device buffer
+  const StagTess *stag = nullptr;      // staggered: device array of n_tess descriptors
+  int32_t n_tess = 0;
 };
 
 // One walk of a many-small-walks launch (the whole walk in one workgroup's LDS).
@@ -83,7 +124,7 @@ struct SmallWalk {
   int32_t coined = 0;
   int32_t hadamard = 0;
   int32_t K = 0;
-  int32_t pad = 0;
+  int32_t staggered = 0;
   int64_t steps = 0;
   double alpha[64] = {};  // CTQW stage coefficients gamma dt / k, dt / k
   double beta[64] = {};
@@ -151,6 +192,15 @@ int torus_block_depth(bool c128, const GraphView &g, int K);
 StripGrid torus_strips(bool c128, int l1, int l2, int S);
 hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *P, const void *Yin, void *Out,
                               int kfirst, const double *alpha, const double *beta, hipStream_t s);
+
+// Staggered walk.  stag_small: every step in one workgroup's LDS (descriptors
+// read from g.stag).  stag_tess: one tessellation in place on psi; `mark`
+// applies the marked phase flip to what it reads (first tessellation of a
+// step); `partials` holds t.n_chunks complex partial sums (workspace).
+size_t stag_small_lds(bool c128, int n);
+hipError_t stag_small(bool c128, const GraphView &g, void *psi, int64_t steps, const Readout &ro, hipStream_t s);
+hipError_t stag_tess(bool c128, const GraphView &g, const StagTess &t, void *psi, bool mark, double *partials,
+                     hipStream_t s);
 
 // Sum of `count` partials -> *norm; sum over the marked list of p -> *pmarked.
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s);

@@ -831,6 +831,204 @@ __global__ __launch_bounds__(1024) void k_ctqw_small(GraphView g, T *psi, Coefs 
   ctqw_small_walk<T>(g, psi, c.alpha, c.beta, K, steps, ro, smem, red);
 }
 
+// ---- staggered walk -----------------------------------------------------------
+// One tessellation U = c0 I + c1 (2P - I), P = sum_alpha |alpha><alpha| over
+// the tessellation's polygons: for each polygon, inner = sum_v a_v psi_v in
+// position order, then psi_v <- c0 psi_v + c1 (2 a_v inner - psi_v).  The
+// polygons partition the vertices, so every update is in place and touches
+// only its own polygon.  On the first tessellation of a step the marked
+// vertices' phase flip is applied to the values as they are read.
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ double2 stag_update(const StagTess &t, double2 x, double a, double2 inner) {
+  const double2 r = sub(scale(inner, 2.0 * a), x);
+  return add(cmul(make_double2(t.c0[0], t.c0[1]), x), cmul(make_double2(t.c1[0], t.c1[1]), r));
+}
+
+template <typename X> __device__ __forceinline__ const X *at_off(const unsigned char *base, int64_t off) {
+  return off >= 0 ? reinterpret_cast<const X *>(base + off) : nullptr;
+}
+
+// Thread path: thread p owns polygon p (at most MAXS vertices).  ELL: the
+// polygons share one size and the vertex table is column-major, so lane p's
+// j-th load sits next to lane p+1's.
+template <typename T, int MAXS, bool ELL>
+__global__ __launch_bounds__(kBlock) void k_stag_poly(const unsigned char *__restrict__ base, StagTess t,
+                                                     T *psi, const uint32_t *__restrict__ markbits, int mark) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= t.n_small) return;
+  const int32_t *vert = at_off<int32_t>(base, t.off_vert);
+  const double *amp = at_off<double>(base, t.off_amp);
+  int lo, sz, stride;
+  if (ELL) {
+    lo = p;
+    sz = t.small_size;
+    stride = t.n_small;
+  } else {
+    const int32_t *ptr = at_off<int32_t>(base, t.off_ptr);
+    lo = ptr[p];
+    sz = ptr[p + 1] - lo;
+    stride = 1;
+  }
+  const double uni = 1.0 / sqrt(static_cast<double>(sz));
+  int v[MAXS];
+  double2 x[MAXS];
+  double a[MAXS];
+  double2 inner = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < MAXS; ++j) {
+    if (j < sz) {
+      const int pos = lo + j * stride;
+      v[j] = vert[pos];
+      double2 xv = ld(psi, v[j]);
+      if (mark && marked(markbits, v[j])) xv = scale(xv, -1.0);
+      x[j] = xv;
+      a[j] = amp ? amp[pos] : uni;
+      inner = add(inner, scale(xv, a[j]));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < MAXS; ++j)
+    if (j < sz) st(psi, v[j], stag_update(t, x[j], a[j], inner));
+}
+
+// Big polygons, pass 1: workgroup c sums a_v psi_v over chunk c.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_stag_big_partial(const unsigned char *__restrict__ base, StagTess t,
+                                                            const T *__restrict__ psi,
+                                                            const uint32_t *__restrict__ markbits, int mark,
+                                                            double2 *__restrict__ partials) {
+  __shared__ double red[16];
+  const StagChunk ch = at_off<StagChunk>(base, t.off_chunk)[blockIdx.x];
+  const int32_t *vert = at_off<int32_t>(base, t.off_bvert);
+  const double *amp = at_off<double>(base, t.off_bamp);
+  const double uni = 1.0 / sqrt(static_cast<double>(ch.size));
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
+    const int v = vert[i];
+    double2 xv = ld(psi, v);
+    if (mark && marked(markbits, v)) xv = scale(xv, -1.0);
+    acc = add(acc, scale(xv, amp ? amp[i] : uni));
+  }
+  const double re = block_sum(acc.x, red);
+  const double im = block_sum(acc.y, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(re, im);
+}
+
+// Big polygons, pass 2: workgroup c sums its polygon's partials (the same
+// order in every chunk of the polygon) and updates chunk c.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_stag_big_apply(const unsigned char *__restrict__ base, StagTess t,
+                                                          T *psi, const uint32_t *__restrict__ markbits, int mark,
+                                                          const double2 *__restrict__ partials) {
+  __shared__ double red[16];
+  const StagChunk ch = at_off<StagChunk>(base, t.off_chunk)[blockIdx.x];
+  const int32_t *vert = at_off<int32_t>(base, t.off_bvert);
+  const double *amp = at_off<double>(base, t.off_bamp);
+  const double uni = 1.0 / sqrt(static_cast<double>(ch.size));
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < ch.count; i += kBlock) acc = add(acc, partials[ch.first + i]);
+  const double2 inner = make_double2(block_sum(acc.x, red), block_sum(acc.y, red));
+  for (int i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
+    const int v = vert[i];
+    double2 xv = ld(psi, v);
+    if (mark && marked(markbits, v)) xv = scale(xv, -1.0);
+    st(psi, v, stag_update(t, xv, amp ? amp[i] : uni, inner));
+  }
+}
+
+// One-workgroup path: every step in LDS.  Thread-path polygons one per
+// thread, big polygons one per wavefront.
+template <typename T>
+__device__ void stag_small_walk(const GraphView &g, T *psi, int64_t steps, const Readout &ro, unsigned char *smem,
+                                double *red) {
+  const int n = g.n;
+  T *a = reinterpret_cast<T *>(smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = psi[i];
+  __syncthreads();
+  for (int64_t s = 0; s < steps; ++s) {
+    for (int i = threadIdx.x; i < g.n_marked; i += blockDim.x) {
+      const int m = g.marklist[i];
+      a[m] = pack<T>(scale(cvt(a[m]), -1.0));
+    }
+    __syncthreads();
+    for (int k = 0; k < g.n_tess; ++k) {
+      const StagTess &t = g.stag[k];
+      const int32_t *vert = at_off<int32_t>(g.base, t.off_vert);
+      const double *amp = at_off<double>(g.base, t.off_amp);
+      const int32_t *ptr = at_off<int32_t>(g.base, t.off_ptr);
+      for (int p = threadIdx.x; p < t.n_small; p += blockDim.x) {
+        int lo, sz, stride;
+        if (t.small_size > 0) {
+          lo = p;
+          sz = t.small_size;
+          stride = t.n_small;
+        } else {
+          lo = ptr[p];
+          sz = ptr[p + 1] - lo;
+          stride = 1;
+        }
+        const double uni = 1.0 / sqrt(static_cast<double>(sz));
+        double2 inner = make_double2(0.0, 0.0);
+        for (int j = 0; j < sz; ++j) {
+          const int pos = lo + j * stride;
+          inner = add(inner, scale(cvt(a[vert[pos]]), amp ? amp[pos] : uni));
+        }
+        for (int j = 0; j < sz; ++j) {
+          const int pos = lo + j * stride;
+          const int v = vert[pos];
+          a[v] = pack<T>(stag_update(t, cvt(a[v]), amp ? amp[pos] : uni, inner));
+        }
+      }
+      const int32_t *bptr = at_off<int32_t>(g.base, t.off_bptr);
+      const int32_t *bvert = at_off<int32_t>(g.base, t.off_bvert);
+      const double *bamp = at_off<double>(g.base, t.off_bamp);
+      for (int q = wave; q < t.n_big; q += nwaves) {
+        const int lo = bptr[q], hi = bptr[q + 1];
+        const double uni = 1.0 / sqrt(static_cast<double>(hi - lo));
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = lo + lane; i < hi; i += 64) acc = add(acc, scale(cvt(a[bvert[i]]), bamp ? bamp[i] : uni));
+        const double2 inner = make_double2(wave_sum(acc.x), wave_sum(acc.y));
+        for (int i = lo + lane; i < hi; i += 64) {
+          const int v = bvert[i];
+          a[v] = pack<T>(stag_update(t, cvt(a[v]), bamp ? bamp[i] : uni, inner));
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int v = threadIdx.x; v < n; v += blockDim.x) psi[v] = a[v];
+  if (ro.p || ro.norm || ro.pmarked) {
+    double *pout = ro.p ? ro.p : ro.pscratch;
+    double acc = 0.0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      const double pv = abs2(cvt(a[v]));
+      pout[v] = pv;
+      acc += pv;
+    }
+    const double tot = block_sum(acc, red);
+    __syncthreads();
+    double pm = 0.0;
+    for (int i = threadIdx.x; i < g.n_marked; i += blockDim.x) pm += abs2(cvt(a[g.marklist[i]]));
+    const double ptot = block_sum(pm, red);
+    if (threadIdx.x == 0) {
+      if (ro.norm) *ro.norm = tot;
+      if (ro.pmarked) *ro.pmarked = ptot;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_stag_small(GraphView g, T *psi, int64_t steps, Readout ro) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[16];
+  stag_small_walk<T>(g, psi, steps, ro, smem, red);
+}
+
 // Many independent small walks in one launch: workgroup b runs walk b whole,
 // its vectors in LDS, exactly as the one-walk kernels above do.
 template <typename T>
@@ -839,7 +1037,9 @@ __global__ __launch_bounds__(1024) void k_small_many(const SmallWalk *__restrict
   __shared__ double red[16];
   const SmallWalk &w = walks[blockIdx.x];
   const Readout none;
-  if (w.coined)
+  if (w.staggered)
+    stag_small_walk<T>(w.g, static_cast<T *>(w.psi), w.steps, none, smem, red);
+  else if (w.coined)
     coined_small_walk<T>(w.g, static_cast<T *>(w.psi), w.hadamard, w.steps, none, smem, red);
   else
     ctqw_small_walk<T>(w.g, static_cast<T *>(w.psi), w.alpha, w.beta, w.K, w.steps, none, smem, red);
@@ -1438,6 +1638,48 @@ hipError_t launch_ctqw_stage(const GraphView &g, const T *y, const T *psi, T *ou
   return hipGetLastError();
 }
 
+template <typename T> hipError_t launch_stag_small(const GraphView &g, void *psi, int64_t steps, const Readout &ro,
+                                                   hipStream_t s) {
+  const size_t lds = stag_small_lds(sizeof(T) == 16, g.n);
+  if (hipError_t e = allow_lds(&k_stag_small<T>, lds); e != hipSuccess) return e;
+  int threads = 64;
+  while (threads < 1024 && threads < g.n) threads *= 2;
+  hipLaunchKernelGGL(k_stag_small<T>, dim3(1), dim3(threads), lds, s, g, static_cast<T *>(psi), steps, ro);
+  return hipGetLastError();
+}
+
+template <typename T, int MAXS>
+void launch_stag_poly(const GraphView &g, const StagTess &t, T *psi, int mark, hipStream_t s) {
+  const dim3 grid(blocks_for(t.n_small, kBlock));
+  if (t.small_size > 0)
+    hipLaunchKernelGGL((k_stag_poly<T, MAXS, true>), grid, dim3(kBlock), 0, s, g.base, t, psi, g.markbits, mark);
+  else
+    hipLaunchKernelGGL((k_stag_poly<T, MAXS, false>), grid, dim3(kBlock), 0, s, g.base, t, psi, g.markbits, mark);
+}
+
+template <typename T>
+hipError_t launch_stag_tess(const GraphView &g, const StagTess &t, void *psi_v, bool mark, double *partials,
+                            hipStream_t s) {
+  T *psi = static_cast<T *>(psi_v);
+  const int mk = mark ? 1 : 0;
+  if (t.n_small > 0) {
+    if (t.max_small <= 2) launch_stag_poly<T, 2>(g, t, psi, mk, s);
+    else if (t.max_small <= 4) launch_stag_poly<T, 4>(g, t, psi, mk, s);
+    else if (t.max_small <= 8) launch_stag_poly<T, 8>(g, t, psi, mk, s);
+    else launch_stag_poly<T, kStagThreadMax>(g, t, psi, mk, s);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  }
+  if (t.n_chunks > 0) {
+    auto *part = reinterpret_cast<double2 *>(partials);
+    hipLaunchKernelGGL(k_stag_big_partial<T>, dim3(t.n_chunks), dim3(kBlock), 0, s, g.base, t,
+                       static_cast<const T *>(psi), g.markbits, mk, part);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stag_big_apply<T>, dim3(t.n_chunks), dim3(kBlock), 0, s, g.base, t, psi, g.markbits, mk,
+                       static_cast<const double2 *>(part));
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // ============================ launchers ======================================
@@ -1450,6 +1692,18 @@ size_t coined_small_lds(bool c128, int n, int n_arcs) {
 size_t ctqw_small_lds(bool c128, int n, int n_arcs) {
   const size_t es = c128 ? 16 : 8;
   return 3 * es * static_cast<size_t>(n) + 4 * (static_cast<size_t>(n) + 1 + n_arcs);
+}
+
+size_t stag_small_lds(bool c128, int n) { return (c128 ? 16 : 8) * static_cast<size_t>(n); }
+
+hipError_t stag_small(bool c128, const GraphView &g, void *psi, int64_t steps, const Readout &ro, hipStream_t s) {
+  return c128 ? launch_stag_small<double2>(g, psi, steps, ro, s) : launch_stag_small<float2>(g, psi, steps, ro, s);
+}
+
+hipError_t stag_tess(bool c128, const GraphView &g, const StagTess &t, void *psi, bool mark, double *partials,
+                     hipStream_t s) {
+  return c128 ? launch_stag_tess<double2>(g, t, psi, mark, partials, s)
+              : launch_stag_tess<float2>(g, t, psi, mark, partials, s);
 }
 
 hipError_t small_many(bool c128, const SmallWalk *d_walks, int count, size_t lds, int threads, hipStream_t s) {

@@ -44,6 +44,10 @@ struct qw_plan {
   qwk::GraphView view;
   // workspace layout
   size_t state_bytes = 0, off_w1 = 0, off_w2 = 0, off_pscratch = 0, off_partials = 0, work_bytes = 0;
+  // staggered walk: tessellation descriptors (offsets into the device buffer),
+  // where their array sits, and the workspace of big-polygon partial sums
+  std::vector<qwk::StagTess> stag;
+  size_t off_stag = 0, off_stagpart = 0;
   int32_t strip_rows = 0;   // grid CTQW blocked kernel: core rows per strip
   int32_t block_depth = 1;  // grid CTQW: Horner stages per launch (temporal blocking)
 };

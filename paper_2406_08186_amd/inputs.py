@@ -340,9 +340,9 @@ def union_graph(n: int, tessellations, name: str = "staggered") -> Graph:
     if not edges:
         return from_edges(n, [], name)
     e = np.concatenate(edges)
-    e = np.sort(e, axis=1)
-    e = np.unique(e, axis=0)
-    return from_edges(n, e, name)
+    keys = np.unique(np.minimum(e[:, 0], e[:, 1]) * np.int64(n) + np.maximum(e[:, 0], e[:, 1]))
+    lo, hi = np.divmod(keys, np.int64(n))
+    return from_edges(n, np.stack([lo, hi], 1), name)
 
 
 def stag_cycle(n: int) -> tuple[Graph, list[Tessellation]]:
@@ -373,7 +373,18 @@ def stag_lattice(l1: int, l2: int | None = None) -> tuple[Graph, list[Tessellati
         corners = np.stack([np.broadcast_to(x, (l1 // 2, l2 // 2)) for x in
                             (r * l2 + c, r * l2 + c1, r1 * l2 + c, r1 * l2 + c1)], axis=-1)
         tess.append(_uniform_tessellation(corners.reshape(-1, 4)))
-    return union_graph(l1 * l2, tess, name=f"stag_lattice{l1}x{l2}"), tess
+    # every vertex is a corner of one square per tessellation: its six
+    # neighbours are the other corners of its two squares
+    n = l1 * l2
+    nb = np.empty((n, 6), dtype=np.int64)
+    for k, t in enumerate(tess):
+        sq = t.poly_vert.reshape(-1, 4).astype(np.int64)
+        for i in range(4):
+            nb[sq[:, i], 3 * k:3 * k + 3] = sq[:, [j for j in range(4) if j != i]]
+    nb.sort(axis=1)
+    row_ptr = np.arange(0, 6 * n + 1, 6, dtype=np.int64)
+    g = Graph(n=n, row_ptr=row_ptr, col=nb.reshape(-1).astype(np.int32), name=f"stag_lattice{l1}x{l2}")
+    return g, tess
 
 
 def stag_arcs(g: Graph) -> tuple[Graph, list[Tessellation]]:

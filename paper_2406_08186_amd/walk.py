@@ -36,7 +36,9 @@ def _stream_ptr(stream, device) -> int:
 class Plan:
     """A validated walk on one graph with its device tables uploaded.
 
-    kind: "coined" or "ctqw"; coin: "grover", "hadamard", "fourier", "szegedy"
+    kind: "coined", "ctqw" or "staggered" (with `tessellations`, a sequence of
+    objects with poly_ptr, poly_vert, amp (None = uniform) and theta (None =
+    reflection form)); coin: "grover", "hadamard", "fourier", "szegedy"
     (with `transition`, P per arc in CSR order) or a d x d complex matrix;
     shift: "flipflop" or "persistent"; dtype: "c64" or "c128";
     layout: "auto", "csr", "structured" or "dense".  CTQW takes gamma, dt and
@@ -48,7 +50,7 @@ class Plan:
                  dtype: str = "c128", layout: str = "auto", gamma: float = 0.0, dt: float = 0.0,
                  taylor_order: int = 0, trunc_tol: float = 0.0, horizon_steps: int = 0,
                  marked: Sequence[int] = (), columns: int = 0, device=None, stream=None,
-                 upload: bool = True, transition=None):
+                 upload: bool = True, transition=None, tessellations=None):
         self.graph = graph
         self.kind = kind
         self.dtype = dtype
@@ -72,10 +74,30 @@ class Plan:
             self._coin = np.ascontiguousarray(np.asarray(coin, dtype=np.complex128))
             if self._coin.ndim != 2 or self._coin.shape[0] != self._coin.shape[1]:
                 raise ValueError("a coin matrix must be square")
+        n_tess, tess_arr = 0, None
+        if kind == "staggered":
+            if not tessellations:
+                raise ValueError("a staggered walk needs tessellations")
+            self._tess_keep = []
+            tess_arr = (L.QwTessellation * len(tessellations))()
+            for i, t in enumerate(tessellations):
+                pp = np.ascontiguousarray(t.poly_ptr, dtype=np.int64)
+                vv = np.ascontiguousarray(t.poly_vert, dtype=np.int32)
+                aa = None if t.amp is None else np.ascontiguousarray(t.amp, dtype=np.float64)
+                self._tess_keep += [pp, vv, aa]
+                tess_arr[i] = L.QwTessellation(
+                    n_polygons=int(pp.size - 1), poly_ptr=pp.ctypes.data_as(C.POINTER(C.c_int64)),
+                    poly_vert=vv.ctypes.data_as(C.POINTER(C.c_int32)),
+                    amp=None if aa is None else aa.ctypes.data_as(C.POINTER(C.c_double)),
+                    form=L.QW_REFLECTION if t.theta is None else L.QW_HAMILTONIAN,
+                    theta=0.0 if t.theta is None else float(t.theta))
+            n_tess = len(tessellations)
+        elif kind not in ("coined", "ctqw"):
+            raise ValueError(f"unknown walk kind {kind!r}")
         csr = L.QwCsr(graph.n, self._rp.ctypes.data_as(C.POINTER(C.c_int64)),
                       self._col.ctypes.data_as(C.POINTER(C.c_int32)))
         desc = L.QwWalkDesc(
-            kind=L.QW_COINED if kind == "coined" else L.QW_CTQW,
+            kind={"coined": L.QW_COINED, "ctqw": L.QW_CTQW, "staggered": L.QW_STAGGERED}[kind],
             coin=coin_id,
             dtype=_DT[dtype], layout=_LAYOUT[layout], gamma=float(gamma), dt=float(dt),
             taylor_order=int(taylor_order), trunc_tol=float(trunc_tol),
@@ -86,7 +108,8 @@ class Plan:
             coin_dim=0 if self._coin is None else int(self._coin.shape[0]),
             coin_matrix=None if self._coin is None else self._coin.view(np.float64).ctypes.data_as(
                 C.POINTER(C.c_double)),
-            transition=None if self._trans is None else self._trans.ctypes.data_as(C.POINTER(C.c_double)))
+            transition=None if self._trans is None else self._trans.ctypes.data_as(C.POINTER(C.c_double)),
+            n_tessellations=n_tess, tessellations=tess_arr)
         self._plan = L.qw_plan_create(csr, desc)
         self.info = L.qw_plan_get_info(self._plan)
         self.structure = L.STRUCTURES[self.info.structure]
@@ -398,6 +421,25 @@ class ContinuousTime(_Walk):
     def get_hamiltonian(self):
         """H as (row_ptr, col, value of the off-diagonal -gamma, diagonal marked list)."""
         return self.graph.row_ptr, self.graph.col, -self.gamma, list(self.marked)
+
+
+class Staggered(_Walk):
+    """Staggered walk (named as future work in Sec. 5): one step is the
+    marked vertices' phase flip followed by U_k = 2 P_k - I (or
+    exp(i theta_k (2 P_k - I))) for each tessellation in order, on the
+    vertex basis.  Every polygon must be a clique of `graph`."""
+
+    def __init__(self, graph: Graph, tessellations, marked: Sequence[int] = (), dtype: str = "c128",
+                 layout: str = "auto", device=None):
+        self.graph = graph
+        self.tessellations = list(tessellations)
+        self.plan = Plan(graph, "staggered", dtype=dtype, layout=layout, marked=marked, device=device,
+                         tessellations=self.tessellations)
+
+    def ket(self, v: int) -> np.ndarray:
+        psi = np.zeros(self.graph.n, dtype=np.complex128)
+        psi[v] = 1.0
+        return psi
 
 
 def uniform_state(n: int) -> np.ndarray:

@@ -303,3 +303,61 @@ def test_szegedy_validation_and_path():
     assert _code(lambda: _create(g, kind=0, coin=L.QW_SZEGEDY, dtype=1)) == L.QW_EINVAL
     assert _code(lambda: _create(g, kind=0, coin=L.QW_SZEGEDY, dtype=1, transition=tp,
                                  shift=L.QW_PERSISTENT)) == L.QW_EUNSUPPORTED
+
+
+def _tess_desc(tess):
+    arr = (L.QwTessellation * max(len(tess), 1))()
+    keep = []
+    for i, t in enumerate(tess):
+        pp = np.ascontiguousarray(t.poly_ptr, dtype=np.int64)
+        vv = np.ascontiguousarray(t.poly_vert, dtype=np.int32)
+        aa = None if t.amp is None else np.ascontiguousarray(t.amp, dtype=np.float64)
+        keep += [pp, vv, aa]
+        arr[i] = L.QwTessellation(pp.size - 1, pp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                  vv.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  None if aa is None else aa.ctypes.data_as(C.POINTER(C.c_double)),
+                                  L.QW_REFLECTION if t.theta is None else L.QW_HAMILTONIAN,
+                                  0.0 if t.theta is None else t.theta)
+    return arr, keep
+
+
+def _stag(g, tess, **kw):
+    arr, keep = _tess_desc(tess)
+    return _create(g, kind=L.QW_STAGGERED, dtype=kw.pop("dtype", 1), n_tessellations=len(tess),
+                   tessellations=C.cast(arr, C.POINTER(L.QwTessellation)), **kw), (arr, keep)
+
+
+def test_staggered_validation_and_path():
+    g, tess = I.stag_lattice(8, 6)
+    p, _ = _stag(g, tess)
+    info = L.qw_plan_get_info(p)
+    assert L.STRUCTURES[info.structure] == "small" and info.state_len == g.n and info.kind == L.QW_STAGGERED
+    L.qw_plan_destroy(p)
+    p, _ = _stag(g, tess, layout=L.QW_LAYOUT_CSR)
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "general"
+    L.qw_plan_destroy(p)
+    big, btess = I.stag_lattice(128, 128)
+    p, _ = _stag(big, btess, dtype=0)   # 16384 vertices x 8 B fits one workgroup
+    assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "small"
+    L.qw_plan_destroy(p)
+    p, _ = _stag(big, btess, dtype=1)   # x 16 B does not
+    info = L.qw_plan_get_info(p)
+    assert L.STRUCTURES[info.structure] == "general"
+    assert info.work_bytes < info.state_bytes  # in place: no state-sized workspace
+    L.qw_plan_destroy(p)
+    # not a partition, not a clique, bad amplitudes, bad form, no tessellation, dense layout
+    assert _code(lambda: _stag(g, [I.tessellation([[0, 1]] + [[v] for v in range(1, g.n)])])) == L.QW_EINVAL
+    assert _code(lambda: _stag(I.cycle(8), [I.tessellation([[0, 2], [1, 3], [4, 5], [6, 7]])])) == L.QW_EGRAPH
+    cyc, ct = I.stag_cycle(8)
+    bad_amp = I.Tessellation(ct[0].poly_ptr, ct[0].poly_vert, np.full(8, 0.6))
+    assert _code(lambda: _stag(cyc, [bad_amp])) == L.QW_EINVAL
+    nan_theta = I.Tessellation(ct[0].poly_ptr, ct[0].poly_vert, None, float("nan"))
+    assert _code(lambda: _stag(cyc, [nan_theta])) == L.QW_EINVAL
+    assert _code(lambda: _stag(cyc, [])) == L.QW_EINVAL
+    assert _code(lambda: _stag(cyc, ct, layout=L.QW_LAYOUT_DENSE)) == L.QW_EUNSUPPORTED
+    empty = I.Tessellation(np.array([0, 4, 4, 8]), ct[0].poly_vert)
+    assert _code(lambda: _stag(cyc, [empty])) == L.QW_EINVAL
+    # a weighted tessellation with unit polygons is accepted
+    ok_amp = I.Tessellation(ct[0].poly_ptr, ct[0].poly_vert, np.tile([0.6, 0.8], 4))
+    p, _ = _stag(cyc, [ok_amp, ct[1]])
+    L.qw_plan_destroy(p)
