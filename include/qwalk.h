@@ -283,7 +283,8 @@ int qw_probabilities(const qw_plan *plan, const void *d_psi, double *d_p, double
 
 /* ---- many small walks in one launch ------------------------------------- */
 /* Advance `count` independent walks by steps[i] steps each (Sec. 3.1 for
- * CTQW, Sec. 3.2 for coined walks) in a single launch, one workgroup per
+ * CTQW, Sec. 3.2 for coined walks, QW_STAGGERED above for staggered walks)
+ * in a single launch, one workgroup per
  * walk: each walk runs whole in its workgroup's LDS, with the arithmetic and
  * order of qw_evolve on the same plan, so results are bitwise those of
  * qw_evolve(plans[i], d_psi[i], ..., steps[i]).  Every plan must be uploaded,
