@@ -13,8 +13,11 @@ HBM budget.  Three lanes share the GPU on their own streams:
   jobs join between chunks of launches, their states stay resident until they
   finish, and every chunk advances every job in the batch; a cap on the arcs
   in the batch bounds the time of a launch;
-* the solo lane runs jobs large enough to fill the GPU on their own, one at
-  a time in arrival order, in chunks of steps on the single-walk path.
+* the solo lanes run, each on its own stream and in arrival order, jobs
+  large enough to fill the GPU on their own and jobs that need many launches
+  (steps x Taylor order for a CTQW): in the batch such a job would pay the
+  whole batch's launch time for every one of its launches.  A solo job runs
+  in chunks of steps on the single-walk path.
 
 The lanes are polled independently, so a small job never waits for a large
 job's launches, and a large job does not slow every launch of the batch.
@@ -175,15 +178,16 @@ class WalkServer:
     """Serve walk jobs on one GPU (complex64 by default): groups of whole-walk
     launches for jobs that fit one workgroup (up to `small_group` per launch, on
     `small_streams` streams), a continuous batch for mid-size jobs, and
-    `solo_slots` solo lanes for jobs of at least `solo_arcs` arcs.
+    `solo_slots` solo lanes for jobs of at least `solo_arcs` arcs or at least
+    `solo_units` launches (steps, times the Taylor order for a CTQW).
     The batch admits jobs while their arcs total at most `batch_arcs`, which
     bounds the time of one batch launch and so the latency of every job in it."""
 
     def __init__(self, capacity: int = 64, budget_bytes: int | None = None, chunk: int = 64,
                  dtype: str = "c64", max_tiles: int = 1 << 18, workers: int = 4, device=None,
                  keep_states: bool = False, solo_arcs: int = 1 << 19, solo_chunk: int = 64,
-                 batch_arcs: int | None = 1 << 21, solo_slots: int = 1, small_group: int = 16,
-                 small_streams: int = 3):
+                 batch_arcs: int | None = 1 << 21, solo_slots: int = 3, small_group: int = 16,
+                 small_streams: int = 3, solo_units: int | None = 16384):
         import torch
 
         from .walk import Batch
@@ -195,6 +199,7 @@ class WalkServer:
         self.dtype = dtype
         self.chunk = chunk
         self.solo_arcs = solo_arcs
+        self.solo_units = solo_units
         self.solo_chunk = solo_chunk
         self.keep_states = keep_states
         self.s_batch = torch.cuda.Stream(self.device)
@@ -232,10 +237,11 @@ class WalkServer:
             # index-free slot-major layout, everything else on CSR)
             plan = Plan(job.graph, job.kind, dtype=self.dtype, layout="auto", device=self.device,
                         upload=False, **job.params)
-            if solo:
-                return plan, "solo"
-            if plan.structure == "small":
+            if plan.structure == "small" and not solo:
                 return plan, "small"
+            units = job.steps * (int(plan.info.taylor_order) if job.kind == "ctqw" else 1)
+            if solo or (self.solo_units is not None and units >= self.solo_units):
+                return plan, "solo"
             plan.close()
             layout = "structured" if job.kind == "coined" else "csr"
             return Plan(job.graph, job.kind, dtype=self.dtype, layout=layout, device=self.device,
