@@ -118,36 +118,39 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
   T *b = a + na;
   int32_t *srp = reinterpret_cast<int32_t *>(b + na);
   int32_t *srev = srp + n + 1;
+  uint32_t *smark = reinterpret_cast<uint32_t *>(srev + na);  // the marked bitmap, read every step
   for (int i = threadIdx.x; i < na; i += blockDim.x) {
     a[i] = psi[i];
     srev[i] = g.rev[i];
   }
   for (int i = threadIdx.x; i <= n; i += blockDim.x) srp[i] = g.rp[i];
+  for (int i = threadIdx.x; i < (n + 31) / 32; i += blockDim.x) smark[i] = g.markbits[i];
   __syncthreads();
+  // One step per pass: each vertex's coin output goes straight to the
+  // reverse arcs' slots of the other buffer (the flip-flop shift), so a step
+  // is one LDS pass and one barrier.
   for (int64_t s = 0; s < steps; ++s) {
     for (int v = threadIdx.x; v < n; v += blockDim.x) {
       const int lo = srp[v], hi = srp[v + 1], d = hi - lo;
       if (d == 0) continue;
-      if (marked(g.markbits, v)) {
-        for (int i = lo; i < hi; ++i) a[i] = pack<T>(scale(cvt(a[i]), -1.0));
+      if (marked(smark, v)) {
+        for (int i = lo; i < hi; ++i) b[srev[i]] = pack<T>(scale(cvt(a[i]), -1.0));
       } else if (hadamard) {
         double2 x0 = cvt(a[lo]), x1 = cvt(a[lo + 1]);
-        a[lo] = pack<T>(scale(add(x0, x1), kInvSqrt2));
-        a[lo + 1] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
+        b[srev[lo]] = pack<T>(scale(add(x0, x1), kInvSqrt2));
+        b[srev[lo + 1]] = pack<T>(scale(sub(x0, x1), kInvSqrt2));
       } else if (g.sqrtp) {
         const double *wt = g.sqrtp + g.rp[v];  // Szegedy: 2 w_a <w, x> - x_a
         double2 sum = make_double2(0.0, 0.0);
         for (int i = lo; i < hi; ++i) sum = add(sum, scale(cvt(a[i]), wt[i - lo]));
-        for (int i = lo; i < hi; ++i) a[i] = pack<T>(sub(scale(sum, 2.0 * wt[i - lo]), cvt(a[i])));
+        for (int i = lo; i < hi; ++i) b[srev[i]] = pack<T>(sub(scale(sum, 2.0 * wt[i - lo]), cvt(a[i])));
       } else {
         double2 sum = make_double2(0.0, 0.0);
         for (int i = lo; i < hi; ++i) sum = add(sum, cvt(a[i]));
         double2 m = grover_mean(sum, d);
-        for (int i = lo; i < hi; ++i) a[i] = pack<T>(sub(add(m, m), cvt(a[i])));
+        for (int i = lo; i < hi; ++i) b[srev[i]] = pack<T>(sub(add(m, m), cvt(a[i])));
       }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < na; i += blockDim.x) b[srev[i]] = a[i];
     __syncthreads();
     T *t = a;
     a = b;
@@ -776,9 +779,11 @@ __device__ void ctqw_small_walk(const GraphView &g, T *psi, const double *alpha,
   T *yb = ya + n;
   int32_t *srp = reinterpret_cast<int32_t *>(yb + n);
   int32_t *scol = srp + n + 1;
+  uint32_t *smark = reinterpret_cast<uint32_t *>(scol + na);  // the marked bitmap, read every stage
   for (int i = threadIdx.x; i < n; i += blockDim.x) ps[i] = psi[i];
   for (int i = threadIdx.x; i <= n; i += blockDim.x) srp[i] = g.rp[i];
   for (int i = threadIdx.x; i < na; i += blockDim.x) scol[i] = g.col[i];
+  for (int i = threadIdx.x; i < (n + 31) / 32; i += blockDim.x) smark[i] = g.markbits[i];
   __syncthreads();
   for (int64_t s = 0; s < steps; ++s) {
     const T *yin = ps;
@@ -789,7 +794,7 @@ __device__ void ctqw_small_walk(const GraphView &g, T *psi, const double *alpha,
       for (int v = threadIdx.x; v < n; v += blockDim.x) {
         double2 sum = make_double2(0.0, 0.0);
         for (int a = srp[v]; a < srp[v + 1]; ++a) sum = add(sum, cvt(yin[scol[a]]));
-        const bool mk = marked(g.markbits, v);
+        const bool mk = marked(smark, v);
         double2 yv = mk ? cvt(yin[v]) : make_double2(0.0, 0.0);
         double2 r = horner_out(cvt(ps[v]), sum, yv, mk, alpha[k - 1], beta[k - 1]);
         yout[v] = pack<T>(r);
@@ -1684,14 +1689,18 @@ hipError_t launch_stag_tess(const GraphView &g, const StagTess &t, void *psi_v, 
 
 // ============================ launchers ======================================
 
+// LDS of the one-workgroup kernels: vectors, row pointers, reverse arcs or
+// columns, and the marked bitmap.
 size_t coined_small_lds(bool c128, int n, int n_arcs) {
   const size_t es = c128 ? 16 : 8;
-  return 2 * es * static_cast<size_t>(n_arcs) + 4 * (static_cast<size_t>(n) + 1 + n_arcs);
+  return 2 * es * static_cast<size_t>(n_arcs) + 4 * (static_cast<size_t>(n) + 1 + n_arcs) +
+         4 * ((static_cast<size_t>(n) + 31) / 32);
 }
 
 size_t ctqw_small_lds(bool c128, int n, int n_arcs) {
   const size_t es = c128 ? 16 : 8;
-  return 3 * es * static_cast<size_t>(n) + 4 * (static_cast<size_t>(n) + 1 + n_arcs);
+  return 3 * es * static_cast<size_t>(n) + 4 * (static_cast<size_t>(n) + 1 + n_arcs) +
+         4 * ((static_cast<size_t>(n) + 31) / 32);
 }
 
 size_t stag_small_lds(bool c128, int n) { return (c128 ? 16 : 8) * static_cast<size_t>(n); }
