@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--workload", default="grid",
-                    choices=["grid", "batch", "serve", "dense", "hypercube", "cycle", "snapshots", "staggered"],
+                    choices=["grid", "batch", "serve", "dense", "hypercube", "cycle", "snapshots", "staggered",
+                             "lattice"],
                     help="grid: the 1024^2 CTQW (default); batch: many CTQW searches on random "
                          "regular graphs in one batch; serve: the Poisson job stream")
     ap.add_argument("--batch-walks", type=int, default=4096)
@@ -86,6 +87,8 @@ def parse():
     ap.add_argument("--stag-side", type=int, default=4096, help="staggered workload: side of the square lattice")
     ap.add_argument("--stag-steps", type=int, default=200, help="staggered workload: steps per timed pass")
     ap.add_argument("--stag-dtypes", default="c64,c128")
+    ap.add_argument("--lattice-side", type=int, default=2048, help="lattice workload: side of the periodic grid")
+    ap.add_argument("--lattice-steps", type=int, default=200, help="lattice workload: steps per timed pass")
     return ap.parse_args()
 
 
@@ -188,6 +191,9 @@ def main():
         return
     if args.workload == "staggered":
         run_staggered(args)
+        return
+    if args.workload == "lattice":
+        run_lattice(args)
         return
     spp = args.steps_per_pass
     dtypes = args.dtypes.split(",")
@@ -771,6 +777,68 @@ def run_staggered(args):
                                                         - res["c128"]["state"]).item())
     print(json.dumps({"workload": f"staggered_lattice_{side}x{side}_squares_{steps}steps", "n": g.n,
                       "tessellations": len(tess), "unit": "vertex-steps/s", **out}), flush=True)
+
+
+# ---------------------------------------------------------------- lattice walk (position-coin notation)
+
+def run_lattice(args):
+    """Coined walk on the periodic L x L grid (default L = 2048, 2^22
+    vertices, 2^24 arcs) in position-coin notation: rows in direction order
+    (c+1, c-1, r+1, r-1), the 4 x 4 Fourier coin and the persistent shift,
+    started with amplitude 1/2 on the four arcs of the centre vertex.  One
+    timed pass is --lattice-steps steps (one launch each, plus the layout
+    permutation in and out of the call), timed with HIP events on the launch
+    stream.  3 steps from a random state are checked against the oracle at
+    full size."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Coined
+    side = args.lattice_side
+    g = I.torus_directed(side, side)
+    steps = args.lattice_steps
+    v0 = (side // 2) * side + side // 2
+    psi0 = np.zeros(g.n_arcs, dtype=np.complex128)
+    psi0[g.row_ptr[v0]:g.row_ptr[v0 + 1]] = 0.5
+    chk0 = I.random_state(g.n_arcs, 2)
+    ref3 = oracle.coined_evolve_general(g.row_ptr, g.col, chk0, 3, coin="fourier", shift="persistent",
+                                        dims=(side, side))
+    res = {}
+    for dtype in ("c64", "c128"):
+        w = Coined(g, shift="persistent", coin="fourier", dtype=dtype)
+        pl = w.plan
+        x = pl.state(chk0)
+        pl.evolve(x, 3)
+        torch.cuda.synchronize()
+        got3 = x.cpu().numpy().astype(np.complex128)
+        err3 = float(np.abs(got3 - ref3).max()) if dtype == "c128" else float(np.linalg.norm(got3 - ref3))
+        del x
+        psi = pl.state(psi0)
+        pl.evolve(psi, 4)
+        psi = pl.state(psi0)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        pl.evolve(psi, steps)
+        b.record()
+        p, norm, _ = pl.probabilities(psi)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        es = 8 if dtype == "c64" else 16
+        # algorithmic bytes per arc-step of the slot-major kernel: read and write
+        # the state (2S); the coin is 16 complex numbers read by every workgroup
+        step_ms = ms / steps
+        gbs = 2 * es * g.n_arcs / (step_ms * 1e-3) / 1e9
+        res[dtype] = {"arc_steps_per_s": g.n_arcs * steps / (ms * 1e-3), "ms": ms, "step_us": step_ms * 1e3,
+                      "bytes_per_arc_step": 2 * es, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                      "norm": float(norm), "path": pl.structure,
+                      ("max_abs_err_3_steps" if dtype == "c128" else "l2_err_3_steps"): err3}
+        del psi
+        pl.close()
+    print(json.dumps({"workload": f"coined_fourier_persistent_grid_{side}x{side}_{steps}steps", "n": g.n,
+                      "arcs": g.n_arcs, "unit": "arc-steps/s", **res}), flush=True)
 
 
 # ---------------------------------------------------------------- 64-cycle latency

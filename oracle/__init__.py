@@ -199,14 +199,19 @@ def persistent_successor(row_ptr, col, dims) -> np.ndarray:
     step = (coords[cl] - coords[tails]) % side        # displacement w - v, modulo the sides
     ahead = (coords[cl] + step) % side                # u = w + (w - v)
     u = ahead[:, 0] if len(dims) == 1 else ahead[:, 0] * dims[1] + ahead[:, 1]
-    succ = np.empty(cl.size, dtype=np.int64)
-    for a in range(cl.size):                          # the arc w -> u in row w
-        w = int(cl[a])
-        row = cl[rp[w]:rp[w + 1]]
-        hit = np.nonzero(row == u[a])[0]
-        if hit.size != 1:
-            raise ValueError(f"arc {a}: no unique arc {w} -> {int(u[a])}")
-        succ[a] = rp[w] + int(hit[0])
+    # the arc w -> u: look the key (w, u) up among the keys (tail, head) of all arcs
+    key = tails * np.int64(n) + cl
+    order = np.argsort(key, kind="stable")
+    want = cl.astype(np.int64) * np.int64(n) + u
+    pos = np.searchsorted(key[order], want)
+    pos = np.minimum(pos, max(cl.size - 1, 0))
+    succ = order[pos].astype(np.int64) if cl.size else np.zeros(0, np.int64)
+    bad = np.flatnonzero(key[succ] != want) if cl.size else np.zeros(0, np.int64)
+    if bad.size:
+        a = int(bad[0])
+        raise ValueError(f"arc {a}: no arc {int(cl[a])} -> {int(u[a])}")
+    if np.unique(succ).size != succ.size:
+        raise ValueError("the persistent successor is not a permutation of the arcs")
     return succ
 
 
