@@ -1457,6 +1457,83 @@ __global__ __launch_bounds__(256) void k_dense_stage_sk(const R *__restrict__ H,
   }
 }
 
+// One walk (B = 1): H y is a matrix-vector product, bound by streaming H, so
+// it runs on the vector units with FP64 accumulation and no matrix cores.  A
+// wavefront owns kGemvRows rows; lane l reads 16 contiguous bytes of each row
+// per chunk (VEC = 16 / sizeof(R) columns, a wavefront's loads of one row are
+// one contiguous 1 KiB) and the matching real and imaginary parts of y, and
+// accumulates z = a + ib per row in a fixed order (chunks in sequence, then a
+// butterfly over the lanes).  Then y_out = psi + c (b - i a).
+constexpr int kGemvRows = 4;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_dense_gemv(const R *__restrict__ H, int ld, int n, const R *__restrict__ yin,
+                                                    const R *psi, R *out, double c) {
+  constexpr int VEC = 16 / static_cast<int>(sizeof(R));
+  constexpr int CH = 64 * VEC;  // columns per wavefront chunk
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + wave) * kGemvRows;
+  if (row0 >= n) return;  // whole wavefront
+  double za[kGemvRows], zb[kGemvRows];
+  const R *hr[kGemvRows];
+#pragma unroll
+  for (int r = 0; r < kGemvRows; ++r) {
+    za[r] = zb[r] = 0.0;
+    hr[r] = H + static_cast<int64_t>(min(row0 + r, n - 1)) * ld;  // rows past n re-read row n-1, unused
+  }
+  // one chunk: y rows k .. k+VEC-1 as (re, im) pairs (2 VEC values, 32
+  // contiguous bytes) and VEC columns of each row of H
+  auto chunk = [&](int k, auto guarded_tag) {
+    constexpr bool GUARDED = decltype(guarded_tag)::value;
+    R yv[2 * VEC];
+    if (!GUARDED || k + VEC <= n) {
+      *reinterpret_cast<uint4 *>(yv) = *reinterpret_cast<const uint4 *>(yin + 2 * static_cast<int64_t>(k));
+      *reinterpret_cast<uint4 *>(yv + VEC) = *reinterpret_cast<const uint4 *>(yin + 2 * static_cast<int64_t>(k) + VEC);
+    } else {  // the lane straddles n: H is zero past n, y has n rows
+#pragma unroll
+      for (int j = 0; j < 2 * VEC; ++j) yv[j] = k + j / 2 < n ? yin[2 * static_cast<int64_t>(k) + j] : R(0);
+    }
+    R h[kGemvRows][VEC];
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r) *reinterpret_cast<uint4 *>(h[r]) = *reinterpret_cast<const uint4 *>(hr[r] + k);
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r) {
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) {
+        const double hv = static_cast<double>(h[r][j]);
+        za[r] = __fma_rn(hv, static_cast<double>(yv[2 * j]), za[r]);
+        zb[r] = __fma_rn(hv, static_cast<double>(yv[2 * j + 1]), zb[r]);
+      }
+    }
+  };
+  // chunks whose columns all lie below n need no guard; the rest (at most
+  // one or two) check each lane against ld and n
+  const int kmain = n / CH * CH;
+  int k0 = 0;
+#pragma unroll 2
+  for (; k0 < kmain; k0 += CH) chunk(k0 + l * VEC, std::false_type{});
+  for (; k0 < ld; k0 += CH)
+    if (k0 + l * VEC < ld) chunk(k0 + l * VEC, std::true_type{});
+#pragma unroll
+  for (int r = 0; r < kGemvRows; ++r) {
+    za[r] = wave_sum(za[r]);
+    zb[r] = wave_sum(zb[r]);
+  }
+  if (l < kGemvRows && row0 + l < n) {
+    double a = za[0], b = zb[0];
+#pragma unroll
+    for (int r = 1; r < kGemvRows; ++r)
+      if (l == r) {
+        a = za[r];
+        b = zb[r];
+      }
+    const int64_t e = static_cast<int64_t>(row0 + l);
+    const double pr = static_cast<double>(psi[2 * e]), pi = static_cast<double>(psi[2 * e + 1]);
+    out[2 * e] = static_cast<R>(pr + c * b);
+    out[2 * e + 1] = static_cast<R>(pi - c * a);
+  }
+}
+
 // Split-k epilogue: z = sum of the partial products in split order (fixed),
 // then y_out = psi + c (b - i a) for z = a + i b.  One thread per complex entry.
 template <typename R>
@@ -1522,6 +1599,12 @@ void launch_dense_sk(const GraphView &g, const void *y, const void *psi, void *o
 template <typename R>
 void launch_dense_nt(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
   const int c2 = 2 * g.columns;
+  if (c2 == 2) {
+    const dim3 grid((g.n + 4 * kGemvRows - 1) / (4 * kGemvRows));
+    hipLaunchKernelGGL((k_dense_gemv<R>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld, g.n,
+                       static_cast<const R *>(y), static_cast<const R *>(psi), static_cast<R *>(out), c);
+    return;
+  }
   if (c2 <= 16) launch_dense_sk<R, 1>(g, y, psi, out, c, s);
   else if (c2 <= 32) launch_dense_sk<R, 2>(g, y, psi, out, c, s);
   else if (c2 <= 64) launch_dense<R, 4>(g, y, psi, out, c, s);
