@@ -1378,7 +1378,8 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
   }
 }
 
-// Few walks (NT = 1, 2: HBM-bound on H): 16 rows per workgroup, so the grid
+// Few walks (NT = 1, 2: HBM-bound on H; the fewest take k_dense_gemv below):
+// 16 rows per workgroup, so the grid
 // has n/16 workgroups, and the 4 wavefronts take interleaved k-chunks of the
 // same 16 rows; their accumulators are summed in LDS in wave order (fixed).
 // Every operand comes straight from global memory: the A fragment of an MFMA
@@ -1457,52 +1458,56 @@ __global__ __launch_bounds__(256) void k_dense_stage_sk(const R *__restrict__ H,
   }
 }
 
-// One walk (B = 1): H y is a matrix-vector product, bound by streaming H, so
-// it runs on the vector units with FP64 accumulation and no matrix cores.  A
-// wavefront owns kGemvRows rows; lane l reads 16 contiguous bytes of each row
-// per chunk (VEC = 16 / sizeof(R) columns, a wavefront's loads of one row are
-// one contiguous 1 KiB) and the matching real and imaginary parts of y, and
-// accumulates z = a + ib per row in a fixed order (chunks in sequence, then a
-// butterfly over the lanes).  Then y_out = psi + c (b - i a).
-constexpr int kGemvRows = 4;
-
-template <typename R>
+// Fewest walks (B <= 2 for FP64 H, B <= 4 for FP32 H): H Y is bound by
+// streaming H once, so it runs on the vector units with FP64 accumulation
+// and no matrix cores.  A wavefront owns
+// RW rows; lane l reads 16 contiguous bytes of each row per chunk (VEC =
+// 16 / sizeof(R) columns; a wavefront's loads of one row are one contiguous
+// 1 KiB) and the matching VEC rows of the states (2 B VEC contiguous reals),
+// and accumulates z = a + ib per row and walk in a fixed order (chunks in
+// sequence, then a butterfly over the lanes).  Then y_out = psi + c (b - i a).
+template <typename R, int NB, int RW>
 __global__ __launch_bounds__(256) void k_dense_gemv(const R *__restrict__ H, int ld, int n, const R *__restrict__ yin,
                                                     const R *psi, R *out, double c) {
   constexpr int VEC = 16 / static_cast<int>(sizeof(R));
-  constexpr int CH = 64 * VEC;  // columns per wavefront chunk
+  constexpr int CH = 64 * VEC;      // columns per wavefront chunk
+  constexpr int YV = 2 * NB * VEC;  // state reals per lane per chunk
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + wave) * kGemvRows;
+  const int row0 = (blockIdx.x * 4 + wave) * RW;
   if (row0 >= n) return;  // whole wavefront
-  double za[kGemvRows], zb[kGemvRows];
-  const R *hr[kGemvRows];
+  double za[RW][NB], zb[RW][NB];
+  const R *hr[RW];
 #pragma unroll
-  for (int r = 0; r < kGemvRows; ++r) {
-    za[r] = zb[r] = 0.0;
+  for (int r = 0; r < RW; ++r) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) za[r][b] = zb[r][b] = 0.0;
     hr[r] = H + static_cast<int64_t>(min(row0 + r, n - 1)) * ld;  // rows past n re-read row n-1, unused
   }
-  // one chunk: y rows k .. k+VEC-1 as (re, im) pairs (2 VEC values, 32
-  // contiguous bytes) and VEC columns of each row of H
   auto chunk = [&](int k, auto guarded_tag) {
     constexpr bool GUARDED = decltype(guarded_tag)::value;
-    R yv[2 * VEC];
+    R yv[YV];  // state rows k .. k+VEC-1: (re, im) of walk b of row k+j at 2 (j NB + b)
+    const R *ys = yin + 2 * static_cast<int64_t>(k) * NB;
     if (!GUARDED || k + VEC <= n) {
-      *reinterpret_cast<uint4 *>(yv) = *reinterpret_cast<const uint4 *>(yin + 2 * static_cast<int64_t>(k));
-      *reinterpret_cast<uint4 *>(yv + VEC) = *reinterpret_cast<const uint4 *>(yin + 2 * static_cast<int64_t>(k) + VEC);
-    } else {  // the lane straddles n: H is zero past n, y has n rows
 #pragma unroll
-      for (int j = 0; j < 2 * VEC; ++j) yv[j] = k + j / 2 < n ? yin[2 * static_cast<int64_t>(k) + j] : R(0);
+      for (int q = 0; q < YV / VEC; ++q)
+        *reinterpret_cast<uint4 *>(yv + q * VEC) = *reinterpret_cast<const uint4 *>(ys + q * VEC);
+    } else {  // the lane straddles n: H is zero past n, the states have n rows
+#pragma unroll
+      for (int j = 0; j < YV; ++j) yv[j] = k + j / (2 * NB) < n ? ys[j] : R(0);
     }
-    R h[kGemvRows][VEC];
+    R h[RW][VEC];
 #pragma unroll
-    for (int r = 0; r < kGemvRows; ++r) *reinterpret_cast<uint4 *>(h[r]) = *reinterpret_cast<const uint4 *>(hr[r] + k);
+    for (int r = 0; r < RW; ++r) *reinterpret_cast<uint4 *>(h[r]) = *reinterpret_cast<const uint4 *>(hr[r] + k);
 #pragma unroll
-    for (int r = 0; r < kGemvRows; ++r) {
+    for (int r = 0; r < RW; ++r) {
 #pragma unroll
       for (int j = 0; j < VEC; ++j) {
         const double hv = static_cast<double>(h[r][j]);
-        za[r] = __fma_rn(hv, static_cast<double>(yv[2 * j]), za[r]);
-        zb[r] = __fma_rn(hv, static_cast<double>(yv[2 * j + 1]), zb[r]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          za[r][b] = __fma_rn(hv, static_cast<double>(yv[2 * (j * NB + b)]), za[r][b]);
+          zb[r][b] = __fma_rn(hv, static_cast<double>(yv[2 * (j * NB + b) + 1]), zb[r][b]);
+        }
       }
     }
   };
@@ -1515,21 +1520,26 @@ __global__ __launch_bounds__(256) void k_dense_gemv(const R *__restrict__ H, int
   for (; k0 < ld; k0 += CH)
     if (k0 + l * VEC < ld) chunk(k0 + l * VEC, std::true_type{});
 #pragma unroll
-  for (int r = 0; r < kGemvRows; ++r) {
-    za[r] = wave_sum(za[r]);
-    zb[r] = wave_sum(zb[r]);
-  }
-  if (l < kGemvRows && row0 + l < n) {
-    double a = za[0], b = zb[0];
+  for (int r = 0; r < RW; ++r)
 #pragma unroll
-    for (int r = 1; r < kGemvRows; ++r)
-      if (l == r) {
-        a = za[r];
-        b = zb[r];
-      }
-    const int64_t e = static_cast<int64_t>(row0 + l);
+    for (int b = 0; b < NB; ++b) {
+      za[r][b] = wave_sum(za[r][b]);
+      zb[r][b] = wave_sum(zb[r][b]);
+    }
+  // lane r NB + b writes walk b of row row0 + r
+  if (l < RW * NB && row0 + l / NB < n) {
+    double a = 0.0, bb = 0.0;
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (l == r * NB + b) {
+          a = za[r][b];
+          bb = zb[r][b];
+        }
+    const int64_t e = static_cast<int64_t>(row0) * NB + l;  // complex index (row, walk)
     const double pr = static_cast<double>(psi[2 * e]), pi = static_cast<double>(psi[2 * e + 1]);
-    out[2 * e] = static_cast<R>(pr + c * b);
+    out[2 * e] = static_cast<R>(pr + c * bb);
     out[2 * e + 1] = static_cast<R>(pi - c * a);
   }
 }
@@ -1596,14 +1606,27 @@ void launch_dense_sk(const GraphView &g, const void *y, const void *psi, void *o
                      static_cast<R *>(out), c);
 }
 
+template <typename R, int NB, int RW>
+void launch_gemv(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
+  const dim3 grid((g.n + 4 * RW - 1) / (4 * RW));
+  hipLaunchKernelGGL((k_dense_gemv<R, NB, RW>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld, g.n,
+                     static_cast<const R *>(y), static_cast<const R *>(psi), static_cast<R *>(out), c);
+}
+
 template <typename R>
 void launch_dense_nt(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
   const int c2 = 2 * g.columns;
-  if (c2 == 2) {
-    const dim3 grid((g.n + 4 * kGemvRows - 1) / (4 * kGemvRows));
-    hipLaunchKernelGGL((k_dense_gemv<R>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld, g.n,
-                       static_cast<const R *>(y), static_cast<const R *>(psi), static_cast<R *>(out), c);
-    return;
+  // the vector kernel reads 2 B state reals per H element from cache, which
+  // outgrows the matrix-core kernel (about 3.4 TB/s of FP64 H and 1.9 TB/s of
+  // FP32 H whatever B) above 2 walks for FP64 H and 4 for FP32 H
+  constexpr int kGemvMax = sizeof(R) == 8 ? 2 : 4;
+  if (g.columns <= kGemvMax) {
+    switch (g.columns) {
+      case 1: return launch_gemv<R, 1, 4>(g, y, psi, out, c, s);
+      case 2: return launch_gemv<R, 2, 4>(g, y, psi, out, c, s);
+      case 3: return launch_gemv<R, 3, 4>(g, y, psi, out, c, s);
+      default: return launch_gemv<R, 4, 4>(g, y, psi, out, c, s);
+    }
   }
   if (c2 <= 16) launch_dense_sk<R, 1>(g, y, psi, out, c, s);
   else if (c2 <= 32) launch_dense_sk<R, 2>(g, y, psi, out, c, s);
