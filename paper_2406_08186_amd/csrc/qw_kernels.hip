@@ -1311,12 +1311,17 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
 #pragma unroll
     for (int r = 0; r < 4; ++r) wide[t][r] = 0.0;
   }
+  // H is fetched in 16-byte pieces: V consecutive k of one row per load
+  constexpr int V = 16 / static_cast<int>(sizeof(R)), PR = kDenseK / V;  // pieces per row of a chunk
+  static_assert(HPT % V == 0 && kDenseK % V == 0, "whole 16-byte pieces");
   R hreg[HPT], xreg[XPT];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < HPT; ++q) {
-      const int e = threadIdx.x + q * 256, i = e / kDenseK, j = e % kDenseK;
-      hreg[q] = H[static_cast<int64_t>(row0 + i) * ld + k0 + j];  // rows padded, k0 + j < ld
+    for (int q = 0; q < HPT / V; ++q) {
+      const int e = threadIdx.x + q * 256, i = e / PR, j = (e % PR) * V;
+      // rows padded, k0 + j + V <= ld, and ld and k0 multiples of kDenseK keep the piece aligned
+      *reinterpret_cast<uint4 *>(hreg + q * V) =
+          *reinterpret_cast<const uint4 *>(H + static_cast<int64_t>(row0 + i) * ld + k0 + j);
     }
 #pragma unroll
     for (int q = 0; q < XPT; ++q) {
@@ -1329,9 +1334,10 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
   for (int k0 = kbeg; k0 < kend; k0 += kDenseK, ++chunk) {
     const int buf = chunk & 1;
 #pragma unroll
-    for (int q = 0; q < HPT; ++q) {
-      const int e = threadIdx.x + q * 256;
-      hs[buf][e / kDenseK][e % kDenseK] = hreg[q];
+    for (int q = 0; q < HPT / V; ++q) {
+      const int e = threadIdx.x + q * 256, i = e / PR, j = (e % PR) * V;
+#pragma unroll
+      for (int t = 0; t < V; ++t) hs[buf][i][j + t] = hreg[q * V + t];
     }
 #pragma unroll
     for (int q = 0; q < XPT; ++q) {
@@ -1378,87 +1384,7 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
   }
 }
 
-// Few walks (NT = 1, 2: HBM-bound on H; the fewest take k_dense_gemv below):
-// 16 rows per workgroup, so the grid
-// has n/16 workgroups, and the 4 wavefronts take interleaved k-chunks of the
-// same 16 rows; their accumulators are summed in LDS in wave order (fixed).
-// Every operand comes straight from global memory: the A fragment of an MFMA
-// is 16 rows x 4 consecutive k of H (rows padded with zeros up to ld), the B
-// fragment 4 rows x 16 real columns of Y (small and cache-resident; guarded
-// past n and past 2C).  No LDS is shared between waves inside the k loop, so
-// waves with different trip counts never wait for each other.
-template <typename R, int NT, int KC>
-__global__ __launch_bounds__(256) void k_dense_stage_sk(const R *__restrict__ H, int ld, int n, int c2,
-                                                        const R *__restrict__ yin, const R *psi, R *out,
-                                                        double c) {
-  using M = Mfma<R>;
-  static_assert(KC % 16 == 0 && 256 % KC == 0, "k per wave per chunk: a multiple of 16 dividing 256");
-  constexpr int FOLD = 256 / KC;  // FP32 products fold into FP64 every 256 k of a wave
-  __shared__ double red[4][NT][4][64];
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int row0 = blockIdx.x * 16;
-  typename M::acc acc[NT];
-  double wide[NT][4];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    acc[t] = M::zero();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) wide[t][r] = 0.0;
-  }
-  const R *hrow = H + static_cast<int64_t>(row0 + (l & 15)) * ld;
-  int chunk = 0;
-  for (int kb = wave * KC; kb < n; kb += 4 * KC, ++chunk) {
-    R a[KC / 4];
-    R b[KC / 4][NT];
-#pragma unroll
-    for (int q = 0; q < KC / 4; ++q) {
-      const int k = kb + 4 * q + (l >> 4);
-      a[q] = (k < ld) ? hrow[k] : R(0);  // H columns past ld do not exist (KC may exceed 16)
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int j = t * 16 + (l & 15);
-        b[q][t] = (k < n && j < c2) ? yin[static_cast<int64_t>(k) * c2 + j] : R(0);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < KC / 4; ++q) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = M::mma(a[q], b[q][t], acc[t]);
-    }
-    if (sizeof(R) == 4 && (chunk % FOLD) == FOLD - 1) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) wide[t][r] += static_cast<double>(acc[t][r]);
-        acc[t] = M::zero();
-      }
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) red[wave][t][r][l] = wide[t][r] + static_cast<double>(acc[t][r]);
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double z = ((red[0][t][r][l] + red[1][t][r][l]) + red[2][t][r][l]) + red[3][t][r][l];
-        const double zp = __shfl_xor(z, 1, 64);
-        const int row = row0 + M::row(l, r);
-        const int col = t * 16 + (l & 15);
-        if (row < n && col < c2) {
-          const int64_t idx = static_cast<int64_t>(row) * c2 + col;
-          const double ps = static_cast<double>(psi[idx]);
-          out[idx] = static_cast<R>((col & 1) ? ps - c * zp : ps + c * zp);
-        }
-      }
-    }
-  }
-}
-
-// Fewest walks (B <= 2 for FP64 H, B <= 4 for FP32 H): H Y is bound by
+// Fewest walks (B = 1 for FP64 H, B <= 2 for FP32 H): H Y is bound by
 // streaming H once, so it runs on the vector units with FP64 accumulation
 // and no matrix cores.  A wavefront owns
 // RW rows; lane l reads 16 contiguous bytes of each row per chunk (VEC =
@@ -1597,15 +1523,6 @@ void launch_dense(const GraphView &g, const void *y, const void *psi, void *out,
   }
 }
 
-template <typename R, int NT>
-void launch_dense_sk(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
-  constexpr int KC = NT == 1 ? 64 : 32;
-  const dim3 grid((g.n + 15) / 16);
-  hipLaunchKernelGGL((k_dense_stage_sk<R, NT, KC>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld,
-                     g.n, 2 * g.columns, static_cast<const R *>(y), static_cast<const R *>(psi),
-                     static_cast<R *>(out), c);
-}
-
 template <typename R, int NB, int RW>
 void launch_gemv(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
   const dim3 grid((g.n + 4 * RW - 1) / (4 * RW));
@@ -1616,20 +1533,16 @@ void launch_gemv(const GraphView &g, const void *y, const void *psi, void *out, 
 template <typename R>
 void launch_dense_nt(const GraphView &g, const void *y, const void *psi, void *out, double c, hipStream_t s) {
   const int c2 = 2 * g.columns;
-  // the vector kernel reads 2 B state reals per H element from cache, which
-  // outgrows the matrix-core kernel (about 3.4 TB/s of FP64 H and 1.9 TB/s of
-  // FP32 H whatever B) above 2 walks for FP64 H and 4 for FP32 H
-  constexpr int kGemvMax = sizeof(R) == 8 ? 2 : 4;
+  // the vector kernel reads 2 B state reals per H element from cache; the
+  // LDS-staged matrix-core kernel streams H at a rate that does not depend on
+  // B up to 8 walks, and overtakes it above 1 walk for FP64 H and 2 for FP32 H
+  constexpr int kGemvMax = sizeof(R) == 8 ? 1 : 2;
   if (g.columns <= kGemvMax) {
-    switch (g.columns) {
-      case 1: return launch_gemv<R, 1, 4>(g, y, psi, out, c, s);
-      case 2: return launch_gemv<R, 2, 4>(g, y, psi, out, c, s);
-      case 3: return launch_gemv<R, 3, 4>(g, y, psi, out, c, s);
-      default: return launch_gemv<R, 4, 4>(g, y, psi, out, c, s);
-    }
+    if (g.columns == 1) return launch_gemv<R, 1, 4>(g, y, psi, out, c, s);
+    return launch_gemv<R, 2, 4>(g, y, psi, out, c, s);
   }
-  if (c2 <= 16) launch_dense_sk<R, 1>(g, y, psi, out, c, s);
-  else if (c2 <= 32) launch_dense_sk<R, 2>(g, y, psi, out, c, s);
+  if (c2 <= 16) launch_dense<R, 1>(g, y, psi, out, c, s);
+  else if (c2 <= 32) launch_dense<R, 2>(g, y, psi, out, c, s);
   else if (c2 <= 64) launch_dense<R, 4>(g, y, psi, out, c, s);
   else if (c2 <= 128) launch_dense<R, 8>(g, y, psi, out, c, s);
   else launch_dense<R, 16>(g, y, psi, out, c, s);
@@ -1962,7 +1875,6 @@ hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const Ti
 }
 
 int dense_splits(const GraphView &g) {
-  if (2 * g.columns <= 32) return 1;  // the 16-row kernel fills the device itself
   const int rblocks = (g.n + kDenseRows - 1) / kDenseRows;
   int sp = (512 + rblocks - 1) / rblocks;
   sp = std::min(sp, kMaxDenseSplits);
