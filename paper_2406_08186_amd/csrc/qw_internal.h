@@ -24,7 +24,7 @@ constexpr int kMaxHypercubeDim = 30;
 enum Structure : int32_t { kGeneral = 0, kCycle = 1, kTorus = 2, kHypercube = 3, kSmall = 4, kEll = 5, kDense = 6 };
 // Dense-H GEMM tiles: rows of H per workgroup, k per LDS chunk.
 constexpr int kDenseRows = 64;
-constexpr int kDenseK = 16;
+constexpr int kDenseK = 32;  // H's leading dimension and split-k ranges are multiples of it
 constexpr int kMaxDenseColumns = 128;
 constexpr int kMaxDenseSplits = 8;
 // Largest degree of the ELL (regular-graph) CTQW layout.

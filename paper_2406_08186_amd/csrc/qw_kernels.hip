@@ -1259,7 +1259,8 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
 // real view of the state block Y (n x 2C: each complex column b is the real
 // columns 2b, 2b+1).  Workgroup = 4 wavefronts, 64 rows of H; each wave owns
 // 16 rows and all NT*16 real columns as NT accumulator tiles of the
-// 16x16x4 MFMA.  H and Y chunks of kDenseK values of k are staged in LDS.
+// 16x16x4 MFMA.  H and Y chunks of KC values of k (16 or 32) are staged in
+// LDS.
 // Epilogue: with z = (H y)_v = a + i b, y_out = psi + c (b - i a): real
 // column 2b takes +c * (its odd partner), column 2b+1 takes -c * (its even
 // partner); partners sit in neighbouring lanes.
@@ -1286,18 +1287,20 @@ template <> struct Mfma<float> {
   }
 };
 
-template <typename R, int NT>
+template <typename R, int NT, int KC>
 __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, int ld, int n, int c2,
                                                      const R *__restrict__ yin, const R *psi, R *out,
                                                      double c, int ksplit, double *partial) {
   using M = Mfma<R>;
   constexpr int NC = NT * 16;
-  constexpr int HPT = kDenseRows * kDenseK / 256;  // H values each thread stages per chunk
-  constexpr int XPT = kDenseK * NC / 256;          // Y values each thread stages per chunk
+  static_assert(kDenseK % KC == 0 && 256 % KC == 0, "chunks tile the split ranges and the FP32 fold");
+  constexpr int HPT = kDenseRows * KC / 256;  // H values each thread stages per chunk
+  constexpr int XPT = KC * NC / 256;          // Y values each thread stages per chunk
+  constexpr int FOLD = 256 / KC;              // FP32 products fold into FP64 every 256 k
   // double-buffered LDS: chunk c is read from buffer c & 1 while the global
   // loads of chunk c+1 are in flight in registers
-  __shared__ R hs[2][kDenseRows][kDenseK + 1];
-  __shared__ R xs[2][kDenseK][NC];
+  __shared__ R hs[2][kDenseRows][KC + 1];
+  __shared__ R xs[2][KC][NC];
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int rblocks = (n + kDenseRows - 1) / kDenseRows;
   const int split = blockIdx.x / rblocks;            // k range of this workgroup
@@ -1312,14 +1315,14 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
     for (int r = 0; r < 4; ++r) wide[t][r] = 0.0;
   }
   // H is fetched in 16-byte pieces: V consecutive k of one row per load
-  constexpr int V = 16 / static_cast<int>(sizeof(R)), PR = kDenseK / V;  // pieces per row of a chunk
-  static_assert(HPT % V == 0 && kDenseK % V == 0, "whole 16-byte pieces");
+  constexpr int V = 16 / static_cast<int>(sizeof(R)), PR = KC / V;  // pieces per row of a chunk
+  static_assert(HPT % V == 0 && KC % V == 0, "whole 16-byte pieces");
   R hreg[HPT], xreg[XPT];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < HPT / V; ++q) {
       const int e = threadIdx.x + q * 256, i = e / PR, j = (e % PR) * V;
-      // rows padded, k0 + j + V <= ld, and ld and k0 multiples of kDenseK keep the piece aligned
+      // rows padded, k0 + j + V <= ld, and ld and k0 multiples of KC keep the piece aligned
       *reinterpret_cast<uint4 *>(hreg + q * V) =
           *reinterpret_cast<const uint4 *>(H + static_cast<int64_t>(row0 + i) * ld + k0 + j);
     }
@@ -1331,7 +1334,7 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
   };
   if (kbeg < kend) fetch(kbeg);
   int chunk = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += kDenseK, ++chunk) {
+  for (int k0 = kbeg; k0 < kend; k0 += KC, ++chunk) {
     const int buf = chunk & 1;
 #pragma unroll
     for (int q = 0; q < HPT / V; ++q) {
@@ -1347,14 +1350,14 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
     // one barrier per chunk: a wave passing it has finished its MMAs of chunk-1, so the
     // buffer written next iteration (chunk+1 & 1 = chunk-1 & 1) is free
     __syncthreads();
-    if (k0 + kDenseK < kend) fetch(k0 + kDenseK);
+    if (k0 + KC < kend) fetch(k0 + KC);
 #pragma unroll
-    for (int kk = 0; kk < kDenseK; kk += 4) {
+    for (int kk = 0; kk < KC; kk += 4) {
       const R a = hs[buf][wave * 16 + (l & 15)][kk + (l >> 4)];
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t] = M::mma(a, xs[buf][kk + (l >> 4)][t * 16 + (l & 15)], acc[t]);
     }
-    if (sizeof(R) == 4 && (chunk & 15) == 15) {  // FP32 products: fold into FP64 every 256 k
+    if (sizeof(R) == 4 && chunk % FOLD == FOLD - 1) {  // FP32 products: fold into FP64 every 256 k
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -1384,9 +1387,9 @@ __global__ __launch_bounds__(256) void k_dense_stage(const R *__restrict__ H, in
   }
 }
 
-// Fewest walks (B = 1 for FP64 H, B <= 2 for FP32 H): H Y is bound by
-// streaming H once, so it runs on the vector units with FP64 accumulation
-// and no matrix cores.  A wavefront owns
+// One walk with FP32 H: H y is bound by streaming H once, so it runs on the
+// vector units with FP64 accumulation and no matrix cores (for FP64 H the
+// LDS-staged matrix-core kernel streams H slightly faster).  A wavefront owns
 // RW rows; lane l reads 16 contiguous bytes of each row per chunk (VEC =
 // 16 / sizeof(R) columns; a wavefront's loads of one row are one contiguous
 // 1 KiB) and the matching VEC rows of the states (2 B VEC contiguous reals),
@@ -1513,7 +1516,12 @@ void launch_dense(const GraphView &g, const void *y, const void *psi, void *out,
   const int used = (g.n + ksplit - 1) / ksplit;  // splits that own at least one k
   const dim3 grid(rblocks * used);
   double *partial = used > 1 ? g.dense_partial : nullptr;
-  hipLaunchKernelGGL((k_dense_stage<R, NT>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld, g.n,
+  // 32-k chunks halve the barriers per byte of H where the stage streams H
+  // (one 16-column tile) and for FP32 from 64 columns; the FP64 tiles of 32
+  // and more columns measured faster with 16 (and with 256 columns 32 would
+  // not fit LDS twice)
+  constexpr int KC = (NT == 1 || (sizeof(R) == 4 && (NT == 4 || NT == 16))) ? 32 : 16;
+  hipLaunchKernelGGL((k_dense_stage<R, NT, KC>), grid, dim3(256), 0, s, static_cast<const R *>(g.dense), g.ld, g.n,
                      2 * g.columns, static_cast<const R *>(y), static_cast<const R *>(psi), static_cast<R *>(out),
                      c, ksplit, partial);
   if (partial) {
@@ -1535,12 +1543,8 @@ void launch_dense_nt(const GraphView &g, const void *y, const void *psi, void *o
   const int c2 = 2 * g.columns;
   // the vector kernel reads 2 B state reals per H element from cache; the
   // LDS-staged matrix-core kernel streams H at a rate that does not depend on
-  // B up to 8 walks, and overtakes it above 1 walk for FP64 H and 2 for FP32 H
-  constexpr int kGemvMax = sizeof(R) == 8 ? 1 : 2;
-  if (g.columns <= kGemvMax) {
-    if (g.columns == 1) return launch_gemv<R, 1, 4>(g, y, psi, out, c, s);
-    return launch_gemv<R, 2, 4>(g, y, psi, out, c, s);
-  }
+  // B up to 8 walks: for FP64 H it is ahead from B = 1, for FP32 H from B = 2
+  if (sizeof(R) == 4 && g.columns == 1) return launch_gemv<R, 1, 4>(g, y, psi, out, c, s);
   if (c2 <= 16) launch_dense<R, 1>(g, y, psi, out, c, s);
   else if (c2 <= 32) launch_dense<R, 2>(g, y, psi, out, c, s);
   else if (c2 <= 64) launch_dense<R, 4>(g, y, psi, out, c, s);

@@ -217,7 +217,7 @@ def test_dense_layout_plans():
     info = L.qw_plan_get_info(p)
     assert L.STRUCTURES[info.structure] == "dense" and info.columns == 8
     assert info.state_len == 50 * 8 and info.state_bytes == 16 * 400
-    assert info.graph_bytes >= 64 * 64 * 8  # H rows padded to 64, ld to 16
+    assert info.graph_bytes >= 64 * 64 * 8  # H rows padded to 64, ld to 32
     L.qw_plan_destroy(p)
     assert _code(lambda: _create(g, kind=0, dtype=1, layout=L.QW_LAYOUT_DENSE)) == L.QW_EUNSUPPORTED
     assert _code(lambda: _create(g, kind=1, dtype=1, gamma=0.1, dt=0.1, taylor_order=4,
