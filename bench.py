@@ -55,7 +55,7 @@ def parse():
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--workload", default="grid",
                     choices=["grid", "batch", "serve", "dense", "hypercube", "cycle", "snapshots", "staggered",
-                             "lattice"],
+                             "lattice", "sparse"],
                     help="grid: the 1024^2 CTQW (default); batch: many CTQW searches on random "
                          "regular graphs in one batch; serve: the Poisson job stream")
     ap.add_argument("--batch-walks", type=int, default=4096)
@@ -194,6 +194,9 @@ def main():
         return
     if args.workload == "lattice":
         run_lattice(args)
+        return
+    if args.workload == "sparse":
+        run_sparse(args)
         return
     spp = args.steps_per_pass
     dtypes = args.dtypes.split(",")
@@ -839,6 +842,69 @@ def run_lattice(args):
         pl.close()
     print(json.dumps({"workload": f"coined_fourier_persistent_grid_{side}x{side}_{steps}steps", "n": g.n,
                       "arcs": g.n_arcs, "unit": "arc-steps/s", **res}), flush=True)
+
+
+# ---------------------------------------------------------------- CTQW on random sparse graphs
+
+def run_sparse(args):
+    """CTQW search on two random sparse graphs of 2^20 vertices through the
+    general kernels: Erdos-Renyi G(N, 8/(N-1)) (irregular: CSR rows, lanes per
+    row by mean degree) and a random 6-regular graph (column-major neighbour
+    table, no row pointers).  gamma = 1/mean degree, dt = 1/||H||_inf, K from
+    the truncation rule (tolerance 1e-8 over the pass), vertex 0 marked,
+    uniform start, 50 steps per timed pass (HIP events on the launch stream).
+    2 steps from a random state are checked against the oracle at full size.
+    Algorithmic bytes per row-stage: 4 (row pointer, CSR only) + 4 d (column
+    indices) + 3 S (gathered y, psi, y out), with each gathered value counted
+    once; random neighbours make each gather move a whole cache line."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Plan
+    n = 1 << 20
+    steps = 50
+    graphs = [("er", I.erdos_renyi(n, 8 / (n - 1), seed=3), 8.0), ("rr6", I.random_regular(n, 6, seed=4), 6.0)]
+    out = {}
+    for name, g, dbar in graphs:
+        dmax = int(np.diff(g.row_ptr).max())
+        gamma = 1.0 / dbar
+        dt = 1.0 / (gamma * dmax + 1.0)
+        chk0 = I.random_state(g.n, 5)
+        res = {"arcs": g.n_arcs, "max_degree": dmax}
+        for dtype in ("c64", "c128"):
+            pl = Plan(g, "ctqw", dtype=dtype, gamma=gamma, dt=dt, taylor_order=0, trunc_tol=1e-8,
+                      horizon_steps=steps, marked=[0], layout="auto")
+            K = int(pl.info.taylor_order)
+            if dtype == "c128":
+                ref2 = oracle.ctqw_evolve(g.row_ptr, g.col, chk0, 2, gamma=gamma, dt=dt, K=K, marked=[0])
+                x = pl.state(chk0)
+                pl.evolve(x, 2)
+                torch.cuda.synchronize()
+                res["max_abs_err_2_steps"] = float(np.abs(x.cpu().numpy() - ref2).max())
+                del x
+            psi = pl.state(I.uniform(g.n))
+            pl.evolve(psi, 2)
+            psi = pl.state(I.uniform(g.n))
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            pl.evolve(psi, steps)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            es = 8 if dtype == "c64" else 16
+            per_launch = (4 * g.n if pl.structure == "general" else 0) + 4 * g.n_arcs + 3 * es * g.n
+            launch_ms = ms / (steps * K)
+            gbs = per_launch / (launch_ms * 1e-3) / 1e9
+            res[dtype] = {"path": pl.structure, "K": K, "arc_steps_per_s": g.n_arcs * steps / (ms * 1e-3),
+                          "arc_spmv_per_s": g.n_arcs * steps * K / (ms * 1e-3), "stage_us": launch_ms * 1e3,
+                          "bytes_per_stage": per_launch, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            del psi
+            pl.close()
+        out[name] = res
+    print(json.dumps({"workload": "ctqw_search_sparse_random_2^20", "steps": steps, **out}), flush=True)
 
 
 # ---------------------------------------------------------------- 64-cycle latency
