@@ -32,11 +32,12 @@ DT = 0.1
 K_ORDER = 20
 STEPS_PER_PASS = 1000
 METRIC = "arc-steps/s (c64 batched vs c128 plain, L2 err<=1e-4); p50/p99 latency"
-# HBM bytes per launch of the grid kernel (1024 x 1024, c64, averaged over the
-# four launches of a time step) measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# scaled by a 256 MiB copy (x2.00 / x1.00); profiles/ctqw_torus1024_sweep.md.
-# Valid only for the kernel version named here; None for any other.
-MEASURED_TRAFFIC = {"k_ctqw_torus_sweep<float2,5>": ((4576.5 + 3 * 8995.1) / 4 * 2 + 8194.5) * 1024}
+# HBM bytes per launch of the grid kernel (1024 x 1024, c64, 10-row strips, two
+# wavefronts per SIMD, averaged over the four launches of a time step) measured
+# with rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a 256 MiB copy (x2.00 /
+# x1.00); profiles/ctqw_torus1024_sweep.md.  Valid only for the kernel version
+# and strip geometry named here; None for any other.
+MEASURED_TRAFFIC = {"k_ctqw_torus_sweep<float2,5>": ((4571.5 + 3 * 8972.9) / 4 * 2 + 8193.3) * 1024}
 
 
 def parse():

@@ -31,8 +31,9 @@ constexpr int kMaxDenseSplits = 8;
 constexpr int kMaxEllDegree = 64;
 
 // Grid CTQW strips (streaming temporal blocking): one wavefront sweeps a strip
-// of 64 columns; strips are sized so each SIMD gets one or two of them, with
-// at least kSweepMinRowsPerStage * S core rows.
+// of 64 columns; strips are sized so each SIMD gets two of them (complex64,
+// strips of at least 2S core rows), else one (at least kSweepMinRowsPerStage
+// * S rows).
 constexpr int kStripWaves = 4;  // wavefronts (strips) per workgroup
 constexpr int kSimds = 256 * 4;  // MI355X: 256 compute units of 4 SIMDs
 constexpr int kSweepMinRowsPerStage = 4;

@@ -1915,16 +1915,19 @@ StripGrid torus_strips(bool c128, int l1, int l2, int S) {
   sg.core = 64 - 2 * S;
   sg.halo = S;
   sg.tiles_c = (l2 + sg.core - 1) / sg.core;
-  // strips as tall as possible while every SIMD still gets its wavefronts
-  // (complex64: two per SIMD where the strips stay at least 8S rows tall, so a
-  // second wavefront hides latency at little halo cost; else one; complex128,
-  // bound by memory, one), and never below 4S rows, so the halo rows stay a
-  // minor share of a strip's work
+  // strips as tall as possible while every SIMD still gets its wavefronts.
+  // complex64: two per SIMD as long as the strips stay at least 2S rows tall;
+  // the second wavefront hides the latency of the first's dependent stages
+  // and loads, which measured worth more than the extra halo rows (S = 5:
+  // 1024^2 4% and 2048^2 18% faster than one wavefront per SIMD, 4096^2 the
+  // same; three per SIMD no better).  complex128: one per SIMD (two measured
+  // 2% slower on 2048^2 and 4096^2).  Strips with one wavefront per SIMD keep
+  // at least 4S rows, so the halo rows stay a minor share of the work.
   auto rows_for = [&](int waves_per_simd) {
     const int want_r = std::max(1, kSimds * waves_per_simd / sg.tiles_c);
     return (l1 + want_r - 1) / want_r;
   };
-  int rows = !c128 && rows_for(2) >= 8 * S ? rows_for(2) : std::max(rows_for(1), kSweepMinRowsPerStage * S);
+  int rows = !c128 && rows_for(2) >= 2 * S ? rows_for(2) : std::max(rows_for(1), kSweepMinRowsPerStage * S);
   rows = std::min(rows, l1 - 2 * S);  // a strip's window rows must be distinct grid rows
   if (rows < 1) return StripGrid{};
   sg.rows = rows;
