@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--stag-side", type=int, default=4096, help="staggered workload: side of the square lattice")
     ap.add_argument("--stag-steps", type=int, default=200, help="staggered workload: steps per timed pass")
     ap.add_argument("--stag-dtypes", default="c64,c128")
+    ap.add_argument("--stag-layout", default="auto", choices=["auto", "csr"],
+                    help="auto: the fused square-lattice kernel; csr: the per-tessellation polygon kernels")
     ap.add_argument("--lattice-side", type=int, default=2048, help="lattice workload: side of the periodic grid")
     ap.add_argument("--lattice-steps", type=int, default=200, help="lattice workload: steps per timed pass")
     return ap.parse_args()
@@ -724,9 +726,9 @@ def run_staggered(args):
     L = 4096, 2^24 vertices): two tessellations of 2 x 2 squares (corners at
     even and at odd coordinates), uniform amplitudes, reflection form, the
     centre vertex marked, uniform start.  One timed pass is --stag-steps steps
-    (two tessellation launches each, the marked flip fused into the first),
-    timed with HIP events on the launch stream; the readout follows outside
-    the timed region.  3 steps from a random state are checked against the
+    (one fused launch per step on the square-lattice kernel, the marked flip
+    applied as it loads), timed with HIP events on the launch stream; the
+    readout follows outside the timed region.  3 steps from a random state are checked against the
     oracle at full size."""
     import numpy as np
     import torch
@@ -745,7 +747,7 @@ def run_staggered(args):
     ref3 = oracle.staggered_evolve(g.n, tess, chk0, 3, marked=marked)
     res = {}
     for dtype in args.stag_dtypes.split(","):
-        pl = Plan(g, "staggered", dtype=dtype, marked=marked, tessellations=tess)
+        pl = Plan(g, "staggered", dtype=dtype, marked=marked, tessellations=tess, layout=args.stag_layout)
         psi = pl.state(chk0)
         pl.evolve(psi, 3)
         torch.cuda.synchronize()
@@ -763,11 +765,16 @@ def run_staggered(args):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b)
         es = 8 if dtype == "c64" else 16
-        # algorithmic bytes of one tessellation launch: read and write every
-        # amplitude (2 S) and read its vertex index (4 B; the squares are one
-        # size, so no polygon pointers and no amplitudes are stored)
-        per_vertex = 2 * es + 4
-        launch_ms = ms / (steps * len(tess))
+        if pl.structure == "stag_lattice":
+            # the fused square-lattice kernel: one launch per step, reading and
+            # writing every amplitude once (2 S), no index
+            per_vertex, launches = 2 * es, steps
+        else:
+            # one launch per tessellation: read and write every amplitude (2 S)
+            # and read its vertex index (4 B; the squares are one size, so no
+            # polygon pointers and no amplitudes are stored)
+            per_vertex, launches = 2 * es + 4, steps * len(tess)
+        launch_ms = ms / launches
         gbs = per_vertex * g.n / (launch_ms * 1e-3) / 1e9
         res[dtype] = {"vertex_steps_per_s": g.n * steps / (ms * 1e-3), "ms": ms, "launch_ms": launch_ms,
                       "bytes_per_vertex_launch": per_vertex, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,

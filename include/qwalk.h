@@ -123,6 +123,11 @@ extern "C" {
 #define QW_STRUCT_SMALL 4 /* whole walk resident in one workgroup's LDS */
 #define QW_STRUCT_ELL 5   /* CTQW on a regular graph: column-major neighbour table */
 #define QW_STRUCT_DENSE 6 /* CTQW with a dense H on MFMA (QW_LAYOUT_DENSE)        */
+#define QW_STRUCT_STAG_LATTICE 7 /* staggered walk on an even periodic l1 x l2
+                                    lattice tessellated by its 2 x 2 squares
+                                    (corners at even, then at odd coordinates,
+                                    uniform amplitudes): both tessellations of
+                                    a step in one index-free launch          */
 
 /* ---- graph ------------------------------------------------------------- */
 /* Adjacency pattern of a simple undirected graph (Sec. 3.1 and 3.2 take the
@@ -206,7 +211,11 @@ typedef struct qw_walk_desc {
  * shift) and cannot join a batch either.  A STAGGERED walk (state length n,
  * marked vertices phase-flipped) runs on the one-workgroup path (AUTO, when
  * the state fits one workgroup's LDS) or on per-tessellation polygon kernels
- * (any layout but DENSE, which it rejects); it cannot join a batch but can
+ * (any layout but DENSE, which it rejects); with layout AUTO or STRUCTURED,
+ * two tessellations that are the 2 x 2 squares of a periodic l1 x l2 lattice
+ * (vertex r*l2 + c, l1 and l2 even and >= 4; the first with corners at even
+ * coordinates, the second at odd ones; uniform amplitudes; either form) run
+ * on a fused index-free kernel instead.  It cannot join a batch but can
  * join qw_small_many.  The graph only serves to check that every polygon is
  * a clique: edges that lie in no polygon play no part in the walk. */
 

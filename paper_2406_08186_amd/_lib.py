@@ -24,7 +24,8 @@ QW_GROVER, QW_HADAMARD, QW_FOURIER, QW_MATRIX, QW_SZEGEDY = 0, 1, 2, 3, 4
 QW_FLIPFLOP, QW_PERSISTENT = 0, 1
 QW_C64, QW_C128 = 0, 1
 QW_LAYOUT_AUTO, QW_LAYOUT_CSR, QW_LAYOUT_STRUCTURED, QW_LAYOUT_DENSE = 0, 1, 2, 3
-STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small", 5: "ell", 6: "dense"}
+STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small", 5: "ell", 6: "dense",
+              7: "stag_lattice"}
 
 EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upload", "qw_evolve",
            "qw_probabilities", "qw_small_many_desc_bytes", "qw_small_many",

@@ -266,6 +266,46 @@ int build_tessellations(const qw_walk_desc *w, int64_t n, const std::vector<int6
   return QW_OK;
 }
 
+// Two tessellations that are the 2 x 2 squares of a periodic l1 x l2 lattice
+// (vertex r*l2 + c, l1, l2 even >= 4): the first with top-left corners at even
+// coordinates, the second at odd ones, uniform amplitudes.  Polygon order and
+// the order of the corners inside a polygon are free.
+bool stag_square_lattice(const qw_walk_desc *w, int64_t n, int32_t *l1o, int32_t *l2o) {
+  if (w->n_tessellations != 2 || n < 16) return false;
+  const qw_tessellation *tess = w->tessellations;
+  if (tess[0].amp || tess[1].amp || tess[0].n_polygons * 4 != n || tess[1].n_polygons * 4 != n) return false;
+  if (tess[0].poly_ptr[1] - tess[0].poly_ptr[0] != 4) return false;
+  int64_t f[4];
+  for (int i = 0; i < 4; ++i) f[i] = tess[0].poly_vert[tess[0].poly_ptr[0] + i];
+  std::sort(f, f + 4);
+  if (f[1] != f[0] + 1 || f[3] != f[2] + 1) return false;
+  const int64_t l2 = f[2] - f[0];
+  if (l2 < 4 || l2 % 2 != 0 || n % l2 != 0) return false;
+  const int64_t l1 = n / l2;
+  if (l1 < 4 || l1 % 2 != 0 || l1 >= (int64_t{1} << 31)) return false;
+  for (int k = 0; k < 2; ++k) {
+    const qw_tessellation &t = tess[k];
+    for (int64_t q = 0; q < t.n_polygons; ++q) {
+      const int64_t lo = t.poly_ptr[q];
+      if (t.poly_ptr[q + 1] - lo != 4) return false;
+      int64_t got[4], corner = -1;
+      for (int i = 0; i < 4; ++i) {
+        got[i] = t.poly_vert[lo + i];
+        if ((got[i] / l2) % 2 == k && (got[i] % l2) % 2 == k) corner = got[i];
+      }
+      if (corner < 0) return false;
+      const int64_t r = corner / l2, c = corner % l2, r1 = (r + 1) % l1, c1 = (c + 1) % l2;
+      int64_t want[4] = {r * l2 + c, r * l2 + c1, r1 * l2 + c, r1 * l2 + c1};
+      std::sort(got, got + 4);
+      std::sort(want, want + 4);
+      if (!std::equal(got, got + 4, want)) return false;
+    }
+  }
+  *l1o = static_cast<int32_t>(l1);
+  *l2o = static_cast<int32_t>(l2);
+  return true;
+}
+
 int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (!g || !w) return fail(QW_EINVAL, "null graph or walk descriptor");
   const int64_t n = g->n;
@@ -419,7 +459,17 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
                               : ctqw_small_lds(c128, static_cast<int>(n), static_cast<int>(na)) <= kSmallLdsBytes;
   if (p->kind == QW_STAGGERED) {
     const bool fits = stag_small_lds(c128, static_cast<int>(n)) <= kSmallLdsBytes;
-    structure = (p->layout == QW_LAYOUT_AUTO && fits && n > 0) ? kSmall : kGeneral;
+    int32_t a = 0, b = 0;
+    if (p->layout == QW_LAYOUT_AUTO && fits && n > 0) {
+      structure = kSmall;
+    } else if ((p->layout == QW_LAYOUT_AUTO || p->layout == QW_LAYOUT_STRUCTURED) &&
+               stag_square_lattice(w, n, &a, &b)) {
+      structure = kStagLattice;
+      p->dims[0] = a;
+      p->dims[1] = b;
+    } else {
+      structure = kGeneral;
+    }
   } else if (p->layout == QW_LAYOUT_DENSE) {
     structure = kDense;
     p->columns = std::max(1, w->columns);
@@ -655,7 +705,9 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
     return o;
   };
   if (p->kind == QW_STAGGERED) {
-    // in place on the caller's state: only the big-polygon partial sums
+    // in place on the caller's state: only the big-polygon partial sums; the
+    // square-lattice kernel writes every step to the other of two buffers
+    if (structure == kStagLattice) p->off_w1 = wsec(p->state_bytes);
     if (max_chunks > 0) p->off_stagpart = wsec(2 * sizeof(double) * static_cast<size_t>(max_chunks));
   } else {
     wsec(p->state_bytes);                  // buffer 0 at offset 0
@@ -748,6 +800,15 @@ int evolve_staggered(const qw_plan *p, void *psi, unsigned char *work, int64_t s
   if (p->structure == kSmall) {
     QW_TRY(stag_small(c128, g, psi, steps, ro, s), "staggered small-graph kernel");
     return QW_OK;
+  }
+  if (p->structure == kStagLattice) {
+    void *cur = psi, *oth = work + p->off_w1;
+    for (int64_t i = 0; i < steps; ++i) {
+      QW_TRY(stag_lattice_step(c128, g, p->stag[0], p->stag[1], cur, oth, s), "staggered lattice kernel");
+      std::swap(cur, oth);
+    }
+    if (cur != psi) QW_TRY(copy_state(c128, p->n, cur, psi, s), "state copy kernel");
+    return readout_only(p, psi, ro, s);
   }
   auto *partials = reinterpret_cast<double *>(work + p->off_stagpart);
   for (int64_t i = 0; i < steps && p->n > 0; ++i)

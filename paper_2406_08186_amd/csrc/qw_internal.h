@@ -21,7 +21,9 @@ constexpr size_t kSmallLdsBytes = 156 * 1024;  // dynamic LDS of the one-workgro
 // Largest hypercube dimension the structured kernels handle.
 constexpr int kMaxHypercubeDim = 30;
 
-enum Structure : int32_t { kGeneral = 0, kCycle = 1, kTorus = 2, kHypercube = 3, kSmall = 4, kEll = 5, kDense = 6 };
+enum Structure : int32_t {
+  kGeneral = 0, kCycle = 1, kTorus = 2, kHypercube = 3, kSmall = 4, kEll = 5, kDense = 6, kStagLattice = 7
+};
 // Dense-H GEMM tiles: rows of H per workgroup, k per LDS chunk.
 constexpr int kDenseRows = 64;
 constexpr int kDenseK = 32;  // H's leading dimension and split-k ranges are multiples of it
@@ -202,6 +204,11 @@ size_t stag_small_lds(bool c128, int n);
 hipError_t stag_small(bool c128, const GraphView &g, void *psi, int64_t steps, const Readout &ro, hipStream_t s);
 hipError_t stag_tess(bool c128, const GraphView &g, const StagTess &t, void *psi, bool mark, double *partials,
                      hipStream_t s);
+// Staggered walk on the square lattice (structure kStagLattice, dims {l1, l2}):
+// one step, both tessellations, from `in` to `out` (distinct buffers); `ta`,
+// `tb` give the two tessellations' (c0, c1).
+hipError_t stag_lattice_step(bool c128, const GraphView &g, const StagTess &ta, const StagTess &tb, const void *in,
+                             void *out, hipStream_t s);
 
 // Sum of `count` partials -> *norm; sum over the marked list of p -> *pmarked.
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s);

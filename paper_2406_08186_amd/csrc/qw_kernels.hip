@@ -1034,6 +1034,94 @@ __global__ __launch_bounds__(1024) void k_stag_small(GraphView g, T *psi, int64_
   stag_small_walk<T>(g, psi, steps, ro, smem, red);
 }
 
+// Staggered walk on the periodic l1 x l2 square lattice (l1, l2 even):
+// tessellation a holds the 2 x 2 squares with top-left corner at even
+// coordinates, tessellation b those at odd coordinates, amplitudes 1/2.  A
+// workgroup owns a tile of kLatRows x kLatCols vertices (top-left corner at
+// even coordinates) and stages it with a halo of two cells on every side
+// (periodic) in LDS as FP64: the marked flip as it loads, tessellation a on
+// every whole a-square of the staged region, then tessellation b on the
+// b-squares that cover the tile (their corners lie at most one cell outside
+// it, where the halo's a-squares have been applied).  Each vertex of the tile
+// is a corner of exactly one b-square, whose update is stored once.
+constexpr int kLatRows = 16, kLatCols = 64;
+constexpr int kLatR = kLatRows + 4, kLatC = kLatCols + 4;  // staged region
+
+// One square: inner = <alpha|x> with alpha = (1, 1, 1, 1)/2, and
+// x_v <- c0 x_v + c1 (2 (1/2) inner - x_v), which for the reflection form
+// (c0, c1) = (0, 1) is inner - x_v.
+template <bool REFL>
+__device__ __forceinline__ void lat_square(double2 &x0, double2 &x1, double2 &x2, double2 &x3, double2 c0,
+                                           double2 c1) {
+  const double2 inner = scale(add(add(x0, x1), add(x2, x3)), 0.5);
+  if (REFL) {
+    x0 = sub(inner, x0);
+    x1 = sub(inner, x1);
+    x2 = sub(inner, x2);
+    x3 = sub(inner, x3);
+  } else {
+    x0 = add(cmul(c0, x0), cmul(c1, sub(inner, x0)));
+    x1 = add(cmul(c0, x1), cmul(c1, sub(inner, x1)));
+    x2 = add(cmul(c0, x2), cmul(c1, sub(inner, x2)));
+    x3 = add(cmul(c0, x3), cmul(c1, sub(inner, x3)));
+  }
+}
+
+template <typename T, bool REFL>
+__global__ __launch_bounds__(256) void k_stag_lattice(GraphView g, const T *__restrict__ in, T *__restrict__ out,
+                                                      double2 c0a, double2 c1a, double2 c0b, double2 c1b) {
+  __shared__ double2 sv[kLatR][kLatC];
+  const int l1 = g.dims[0], l2 = g.dims[1];
+  const int tiles_c = (l2 + kLatCols - 1) / kLatCols;
+  // consecutive tiles (a row of tiles, then the next) on one XCD, so the halo
+  // rows a tile shares with the tile row above come from that XCD's L2
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tr = tile / tiles_c, tc = tile - tr * tiles_c;
+  const int r0 = tr * kLatRows, c0 = tc * kLatCols;  // even: kLatRows, kLatCols are even
+  const bool mark = g.n_marked > 0;
+  for (int e = threadIdx.x; e < kLatR * kLatC; e += blockDim.x) {
+    const int i = e / kLatC, j = e - i * kLatC;
+    // periodic: on lattices smaller than the staged region a vertex is staged
+    // more than once, and every copy goes through the same updates
+    int gr = r0 - 2 + i, gc = c0 - 2 + j;
+    gr += gr < 0 ? l1 : 0;
+    gc += gc < 0 ? l2 : 0;
+    while (gr >= l1) gr -= l1;
+    while (gc >= l2) gc -= l2;
+    const int v = gr * l2 + gc;
+    double2 x = ld(in, v);
+    if (mark && marked(g.markbits, v)) x = scale(x, -1.0);
+    sv[i][j] = x;
+  }
+  __syncthreads();
+  // tessellation a: squares at region rows/cols (2p, 2q), p < kLatR/2, q < kLatC/2
+  for (int e = threadIdx.x; e < (kLatR / 2) * (kLatC / 2); e += blockDim.x) {
+    const int p = e / (kLatC / 2), q = e - p * (kLatC / 2);
+    const int i = 2 * p, j = 2 * q;
+    double2 x0 = sv[i][j], x1 = sv[i][j + 1], x2 = sv[i + 1][j], x3 = sv[i + 1][j + 1];
+    lat_square<REFL>(x0, x1, x2, x3, c0a, c1a);
+    sv[i][j] = x0;
+    sv[i][j + 1] = x1;
+    sv[i + 1][j] = x2;
+    sv[i + 1][j + 1] = x3;
+  }
+  __syncthreads();
+  // tessellation b: squares at region rows/cols (2p+1, 2q+1) covering the tile
+  for (int e = threadIdx.x; e < (kLatRows / 2 + 1) * (kLatCols / 2 + 1); e += blockDim.x) {
+    const int p = e / (kLatCols / 2 + 1), q = e - p * (kLatCols / 2 + 1);
+    const int i = 2 * p + 1, j = 2 * q + 1;
+    double2 x[4] = {sv[i][j], sv[i][j + 1], sv[i + 1][j], sv[i + 1][j + 1]};
+    lat_square<REFL>(x[0], x[1], x[2], x[3], c0b, c1b);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int li = i + (k >> 1), lj = j + (k & 1);  // region cell of corner k
+      const int gr = r0 - 2 + li, gc = c0 - 2 + lj;
+      if (li >= 2 && li < 2 + kLatRows && lj >= 2 && lj < 2 + kLatCols && gr < l1 && gc < l2)
+        st(out, gr * l2 + gc, x[k]);
+    }
+  }
+}
+
 // Many independent small walks in one launch: workgroup b runs walk b whole,
 // its vectors in LDS, exactly as the one-walk kernels above do.
 template <typename T>
@@ -1724,6 +1812,29 @@ size_t ctqw_small_lds(bool c128, int n, int n_arcs) {
   const size_t es = c128 ? 16 : 8;
   return 3 * es * static_cast<size_t>(n) + 4 * (static_cast<size_t>(n) + 1 + n_arcs) +
          4 * ((static_cast<size_t>(n) + 31) / 32);
+}
+
+hipError_t stag_lattice_step(bool c128, const GraphView &g, const StagTess &ta, const StagTess &tb, const void *in,
+                             void *out, hipStream_t s) {
+  const int l1 = g.dims[0], l2 = g.dims[1];
+  const dim3 grid(static_cast<unsigned>(((l1 + kLatRows - 1) / kLatRows) * ((l2 + kLatCols - 1) / kLatCols)));
+  const double2 c0a = make_double2(ta.c0[0], ta.c0[1]), c1a = make_double2(ta.c1[0], ta.c1[1]);
+  const double2 c0b = make_double2(tb.c0[0], tb.c0[1]), c1b = make_double2(tb.c1[0], tb.c1[1]);
+  const bool refl = ta.c0[0] == 0.0 && ta.c0[1] == 0.0 && ta.c1[0] == 1.0 && ta.c1[1] == 0.0 && tb.c0[0] == 0.0 &&
+                    tb.c0[1] == 0.0 && tb.c1[0] == 1.0 && tb.c1[1] == 0.0;
+  if (c128 && refl)
+    hipLaunchKernelGGL((k_stag_lattice<double2, true>), grid, dim3(256), 0, s, g, static_cast<const double2 *>(in),
+                       static_cast<double2 *>(out), c0a, c1a, c0b, c1b);
+  else if (c128)
+    hipLaunchKernelGGL((k_stag_lattice<double2, false>), grid, dim3(256), 0, s, g, static_cast<const double2 *>(in),
+                       static_cast<double2 *>(out), c0a, c1a, c0b, c1b);
+  else if (refl)
+    hipLaunchKernelGGL((k_stag_lattice<float2, true>), grid, dim3(256), 0, s, g, static_cast<const float2 *>(in),
+                       static_cast<float2 *>(out), c0a, c1a, c0b, c1b);
+  else
+    hipLaunchKernelGGL((k_stag_lattice<float2, false>), grid, dim3(256), 0, s, g, static_cast<const float2 *>(in),
+                       static_cast<float2 *>(out), c0a, c1a, c0b, c1b);
+  return hipGetLastError();
 }
 
 size_t stag_small_lds(bool c128, int n) { return (c128 ? 16 : 8) * static_cast<size_t>(n); }

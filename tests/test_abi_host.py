@@ -340,11 +340,29 @@ def test_staggered_validation_and_path():
     p, _ = _stag(big, btess, dtype=0)   # 16384 vertices x 8 B fits one workgroup
     assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == "small"
     L.qw_plan_destroy(p)
-    p, _ = _stag(big, btess, dtype=1)   # x 16 B does not
+    p, _ = _stag(big, btess, dtype=1)   # x 16 B does not: the fused square-lattice kernel
+    info = L.qw_plan_get_info(p)
+    assert L.STRUCTURES[info.structure] == "stag_lattice" and tuple(info.dims) == (128, 128)
+    assert info.work_bytes >= info.state_bytes  # it ping-pongs between two buffers
+    L.qw_plan_destroy(p)
+    p, _ = _stag(big, btess, dtype=1, layout=L.QW_LAYOUT_CSR)
     info = L.qw_plan_get_info(p)
     assert L.STRUCTURES[info.structure] == "general"
     assert info.work_bytes < info.state_bytes  # in place: no state-sized workspace
     L.qw_plan_destroy(p)
+    # the square pattern is recognised whatever the polygon and corner order,
+    # and not with the tessellations swapped or with amplitudes given
+    rng = np.random.default_rng(0)
+    shuffled = []
+    for t in btess:
+        sq = t.poly_vert.reshape(-1, 4)[rng.permutation(t.n_polygons)]
+        shuffled.append(I.tessellation([list(rng.permutation(q)) for q in sq]))
+    for tl, want in ((shuffled, "stag_lattice"), (btess[::-1], "general"),
+                     ([I.Tessellation(btess[0].poly_ptr, btess[0].poly_vert, np.full(big.n, 0.5)), btess[1]],
+                      "general")):
+        p, _ = _stag(big, tl, dtype=1, layout=L.QW_LAYOUT_STRUCTURED)
+        assert L.STRUCTURES[L.qw_plan_get_info(p).structure] == want
+        L.qw_plan_destroy(p)
     # not a partition, not a clique, bad amplitudes, bad form, no tessellation, dense layout
     assert _code(lambda: _stag(g, [I.tessellation([[0, 1]] + [[v] for v in range(1, g.n)])])) == L.QW_EINVAL
     assert _code(lambda: _stag(I.cycle(8), [I.tessellation([[0, 2], [1, 3], [4, 5], [6, 7]])])) == L.QW_EGRAPH

@@ -1,8 +1,9 @@
 """GPU parity of the staggered walk against the oracle, through the C ABI.
 
-Both engine paths are covered: the one-workgroup path (layout "auto" on
-graphs whose state fits LDS) and the per-tessellation polygon kernels
-(layout "csr"), with uniform and weighted polygons, the reflection and
+All engine paths are covered: the one-workgroup path (layout "auto" on
+graphs whose state fits LDS), the per-tessellation polygon kernels (layout
+"csr") and the fused square-lattice kernel (layout "structured", or "auto"
+on lattices too large for LDS), with uniform and weighted polygons, the reflection and
 Hamiltonian forms, marked vertices, thread-path polygons of one size
 (column-major table) and of mixed sizes (CSR), and big polygons cut into
 several chunks.  complex128 within 1e-12 (max abs), complex64 within L2 1e-5;
@@ -155,7 +156,7 @@ def test_staggered_lattice_full_size(dtype):
     marked = [1024 * 512 + 512]
     steps = 12
     pl, psi0, got, p, norm, pm = _run(g, tess, dtype, "auto", steps, marked, seed=1)
-    assert pl.structure == "general"
+    assert pl.structure == "stag_lattice"
     ref = oracle.staggered_evolve(g.n, tess, psi0, steps, marked=marked)
     if dtype == "c128":
         assert np.abs(got - ref).max() < 1e-12
@@ -164,7 +165,8 @@ def test_staggered_lattice_full_size(dtype):
     assert abs(norm - 1.0) < (1e-12 if dtype == "c128" else 1e-5)
 
 
-def test_staggered_lattice_search_long_run_c64():
+@pytest.mark.parametrize("layout", ["csr", "structured"])
+def test_staggered_lattice_search_long_run_c64(layout):
     """complex64 norm drift after 10^4 steps of the lattice search stays
     within 1e-5; the state matches complex128 within L2 1e-4."""
     from paper_2406_08186_amd.walk import Plan
@@ -173,7 +175,7 @@ def test_staggered_lattice_search_long_run_c64():
     psi0 = I.uniform(g.n)
     out = {}
     for dtype in ("c64", "c128"):
-        pl = Plan(g, "staggered", dtype=dtype, layout="csr", marked=marked, tessellations=tess)
+        pl = Plan(g, "staggered", dtype=dtype, layout=layout, marked=marked, tessellations=tess)
         x = pl.state(psi0)
         _, norm, _ = pl.evolve(x, 10000, readout=True)
         torch.cuda.synchronize()
@@ -238,3 +240,56 @@ def test_hamiltonian_quarter_turn_on_engine():
     b.evolve(y, 7)
     torch.cuda.synchronize()
     assert np.abs((1j) ** 14 * x.cpu().numpy() - y.cpu().numpy()).max() < 1e-12
+
+
+LATTICES = [(4, 4), (6, 8), (16, 64), (18, 66), (34, 130), (100, 62), (4, 200)]
+
+
+@pytest.mark.parametrize("l1,l2", LATTICES)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("form", ["reflection", "hamiltonian"])
+def test_square_lattice_kernel_matches_oracle(l1, l2, dtype, form):
+    """The fused index-free kernel (both tessellations of a step in one
+    launch, tiles of 16 x 64 with a two-cell periodic halo): lattices smaller
+    than one tile (staged vertices repeat), ragged tiles in both directions,
+    marked vertices on tile edges and corners, both forms."""
+    from paper_2406_08186_amd.walk import Plan
+    g, tess = I.stag_lattice(l1, l2)
+    if form == "hamiltonian":
+        tess = [I.Tessellation(tess[0].poly_ptr, tess[0].poly_vert, None, 0.83),
+                I.Tessellation(tess[1].poly_ptr, tess[1].poly_vert, None, -0.41)]
+    marked = sorted({0, l2 - 1, 15 * l2 % g.n, (16 * l2 + 63) % g.n, g.n - 1})
+    print(f"[case] stag lattice {l1}x{l2} {dtype} {form}", flush=True)
+    pl = Plan(g, "staggered", dtype=dtype, layout="structured", marked=marked, tessellations=tess)
+    assert pl.structure == "stag_lattice"
+    psi0 = I.random_state(g.n, l1 + l2)
+    for steps in (0, 1, 8):
+        x = pl.state(psi0)
+        p, norm, pm = pl.evolve(x, steps, readout=True)
+        torch.cuda.synchronize()
+        got = x.cpu().numpy().astype(np.complex128)
+        ref = oracle.staggered_evolve(g.n, tess, psi0, steps, marked=marked)
+        if dtype == "c128":
+            assert np.abs(got - ref).max() < 1e-12, steps
+            assert np.abs(p.cpu().numpy() - np.abs(ref) ** 2).max() < 1e-12
+        else:
+            assert np.linalg.norm(got - ref) < 1e-5, steps
+        assert abs(float(pm) - float(p.cpu().numpy()[marked].sum())) < 1e-12
+
+
+def test_square_lattice_kernel_agrees_with_polygon_kernels_and_repeats():
+    from paper_2406_08186_amd.walk import Plan
+    g, tess = I.stag_lattice(258, 130)
+    psi0 = I.random_state(g.n, 9)
+    out = {}
+    for layout in ("structured", "csr"):
+        pl = Plan(g, "staggered", dtype="c128", layout=layout, marked=[7, 1000], tessellations=tess)
+        runs = []
+        for _ in range(2):
+            x = pl.state(psi0)
+            pl.evolve(x, 33)
+            torch.cuda.synchronize()
+            runs.append(x.cpu().numpy())
+        assert np.array_equal(runs[0], runs[1])
+        out[pl.structure] = runs[0]
+    assert np.abs(out["stag_lattice"] - out["general"]).max() < 1e-12
