@@ -128,8 +128,49 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
   __syncthreads();
   // One step per pass: each vertex's coin output goes straight to the
   // reverse arcs' slots of the other buffer (the flip-flop shift), so a step
-  // is one LDS pass and one barrier.
-  for (int64_t s = 0; s < steps; ++s) {
+  // is one LDS pass and one barrier.  When every vertex has a thread of its
+  // own and degree <= 4 (cycles, grids), the thread keeps its vertex's arc
+  // range, reverse-arc slots and mark in registers across the steps.
+  constexpr int kRegDeg = 4;
+  int own_ok = n <= static_cast<int>(blockDim.x) ? 1 : 0;
+  int rlo = 0, rd = 0, rmk = 0, rrev[kRegDeg] = {0, 0, 0, 0};
+  if (own_ok && threadIdx.x < n) {
+    rlo = srp[threadIdx.x];
+    rd = srp[threadIdx.x + 1] - rlo;
+    rmk = marked(smark, threadIdx.x) ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < kRegDeg; ++k) rrev[k] = k < rd ? srev[rlo + k] : 0;
+  }
+  own_ok = __syncthreads_and(own_ok && (threadIdx.x >= n || rd <= kRegDeg) && !g.sqrtp);
+  for (int64_t s = 0; s < steps && own_ok; ++s) {
+    if (threadIdx.x < n && rd > 0) {
+      double2 x[kRegDeg];
+#pragma unroll
+      for (int k = 0; k < kRegDeg; ++k) x[k] = k < rd ? cvt(a[rlo + k]) : make_double2(0.0, 0.0);
+      if (rmk) {
+#pragma unroll
+        for (int k = 0; k < kRegDeg; ++k)
+          if (k < rd) b[rrev[k]] = pack<T>(scale(x[k], -1.0));
+      } else if (hadamard) {
+        b[rrev[0]] = pack<T>(scale(add(x[0], x[1]), kInvSqrt2));
+        b[rrev[1]] = pack<T>(scale(sub(x[0], x[1]), kInvSqrt2));
+      } else {
+        double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < kRegDeg; ++k)
+          if (k < rd) sum = add(sum, x[k]);
+        const double2 m = grover_mean(sum, rd);
+#pragma unroll
+        for (int k = 0; k < kRegDeg; ++k)
+          if (k < rd) b[rrev[k]] = pack<T>(sub(add(m, m), x[k]));
+      }
+    }
+    __syncthreads();
+    T *t = a;
+    a = b;
+    b = t;
+  }
+  for (int64_t s = 0; s < steps && !own_ok; ++s) {
     for (int v = threadIdx.x; v < n; v += blockDim.x) {
       const int lo = srp[v], hi = srp[v + 1], d = hi - lo;
       if (d == 0) continue;
