@@ -1080,7 +1080,9 @@ __global__ __launch_bounds__(1024) void k_stag_small(GraphView g, T *psi, int64_
 // coordinates, tessellation b those at odd coordinates, amplitudes 1/2.  A
 // workgroup owns a tile of kLatRows x kLatCols vertices (top-left corner at
 // even coordinates) and stages it with a halo of two cells on every side
-// (periodic) in LDS as FP64: the marked flip as it loads, tessellation a on
+// (periodic) in LDS in the storage type (each tessellation computes in FP64
+// and rounds once, as the per-tessellation kernels do): the marked flip as
+// it loads, tessellation a on
 // every whole a-square of the staged region, then tessellation b on the
 // b-squares that cover the tile (their corners lie at most one cell outside
 // it, where the halo's a-squares have been applied).  Each vertex of the tile
@@ -1111,7 +1113,7 @@ __device__ __forceinline__ void lat_square(double2 &x0, double2 &x1, double2 &x2
 template <typename T, bool REFL>
 __global__ __launch_bounds__(256) void k_stag_lattice(GraphView g, const T *__restrict__ in, T *__restrict__ out,
                                                       double2 c0a, double2 c1a, double2 c0b, double2 c1b) {
-  __shared__ double2 sv[kLatR][kLatC];
+  __shared__ T sv[kLatR][kLatC];
   const int l1 = g.dims[0], l2 = g.dims[1];
   const int tiles_c = (l2 + kLatCols - 1) / kLatCols;
   // consecutive tiles (a row of tiles, then the next) on one XCD, so the halo
@@ -1130,8 +1132,8 @@ __global__ __launch_bounds__(256) void k_stag_lattice(GraphView g, const T *__re
     while (gr >= l1) gr -= l1;
     while (gc >= l2) gc -= l2;
     const int v = gr * l2 + gc;
-    double2 x = ld(in, v);
-    if (mark && marked(g.markbits, v)) x = scale(x, -1.0);
+    T x = in[v];
+    if (mark && marked(g.markbits, v)) x = pack<T>(scale(cvt(x), -1.0));
     sv[i][j] = x;
   }
   __syncthreads();
@@ -1139,19 +1141,19 @@ __global__ __launch_bounds__(256) void k_stag_lattice(GraphView g, const T *__re
   for (int e = threadIdx.x; e < (kLatR / 2) * (kLatC / 2); e += blockDim.x) {
     const int p = e / (kLatC / 2), q = e - p * (kLatC / 2);
     const int i = 2 * p, j = 2 * q;
-    double2 x0 = sv[i][j], x1 = sv[i][j + 1], x2 = sv[i + 1][j], x3 = sv[i + 1][j + 1];
+    double2 x0 = cvt(sv[i][j]), x1 = cvt(sv[i][j + 1]), x2 = cvt(sv[i + 1][j]), x3 = cvt(sv[i + 1][j + 1]);
     lat_square<REFL>(x0, x1, x2, x3, c0a, c1a);
-    sv[i][j] = x0;
-    sv[i][j + 1] = x1;
-    sv[i + 1][j] = x2;
-    sv[i + 1][j + 1] = x3;
+    sv[i][j] = pack<T>(x0);
+    sv[i][j + 1] = pack<T>(x1);
+    sv[i + 1][j] = pack<T>(x2);
+    sv[i + 1][j + 1] = pack<T>(x3);
   }
   __syncthreads();
   // tessellation b: squares at region rows/cols (2p+1, 2q+1) covering the tile
   for (int e = threadIdx.x; e < (kLatRows / 2 + 1) * (kLatCols / 2 + 1); e += blockDim.x) {
     const int p = e / (kLatCols / 2 + 1), q = e - p * (kLatCols / 2 + 1);
     const int i = 2 * p + 1, j = 2 * q + 1;
-    double2 x[4] = {sv[i][j], sv[i][j + 1], sv[i + 1][j], sv[i + 1][j + 1]};
+    double2 x[4] = {cvt(sv[i][j]), cvt(sv[i][j + 1]), cvt(sv[i + 1][j]), cvt(sv[i + 1][j + 1])};
     lat_square<REFL>(x[0], x[1], x[2], x[3], c0b, c1b);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
