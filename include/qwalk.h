@@ -227,7 +227,8 @@ typedef struct qw_plan_info {
   int64_t state_len;       /* complex elements of the state: n_arcs (coined),
                               n (CTQW, staggered) or n * columns (dense)      */
   int32_t kind, coin, dtype, structure;
-  int32_t dims[2];         /* CYCLE: {n,0}; TORUS: {l1,l2}; HYPERCUBE: {dim,0}*/
+  int32_t dims[2];         /* CYCLE: {n,0}; TORUS, STAG_LATTICE: {l1,l2};
+                              HYPERCUBE: {dim,0}; ELL: {degree,0}             */
   int32_t max_degree;
   int32_t taylor_order;    /* CTQW: K in use                                  */
   double dt;               /* CTQW: step length                               */
