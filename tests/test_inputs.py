@@ -46,3 +46,55 @@ def test_batch_specs():
         assert 3 <= s["d"] <= 8 and (s["n"] * s["d"]) % 2 == 0
         assert 1000 <= s["n"] <= 200001
         assert 0 <= s["marked"] < s["n"]
+
+
+# ---- staggered-walk tessellations ------------------------------------------------
+
+def _is_partition(t, n):
+    return (t.poly_ptr[0] == 0 and t.poly_ptr[-1] == n and np.all(np.diff(t.poly_ptr) > 0)
+            and np.array_equal(np.sort(t.poly_vert), np.arange(n)))
+
+
+def _polygons_are_cliques(g, t):
+    adj = {v: set(int(u) for u in g.row(v)) for v in range(g.n)}
+    for p in range(t.n_polygons):
+        vs = [int(v) for v in t.poly_vert[t.poly_ptr[p]:t.poly_ptr[p + 1]]]
+        if any(b not in adj[a] for a in vs for b in vs if a != b):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("l1,l2", [(4, 4), (6, 8), (10, 4), (16, 12)])
+def test_stag_lattice_partitions_and_graph(l1, l2):
+    g, tess = I.stag_lattice(l1, l2)
+    assert g.n == l1 * l2 and set(np.diff(g.row_ptr)) == {6}
+    u = I.union_graph(g.n, tess)
+    assert np.array_equal(u.row_ptr, g.row_ptr) and np.array_equal(u.col, g.col)
+    for k, t in enumerate(tess):
+        assert _is_partition(t, g.n) and set(t.sizes()) == {4}
+        assert _polygons_are_cliques(g, t)
+        first = t.poly_vert[:4]  # corners (r, c), (r, c+1), (r+1, c), (r+1, c+1) of the first square
+        assert first[0] // l2 % 2 == k and first[0] % l2 % 2 == k
+
+
+def test_stag_cycle_and_arcs():
+    g, tess = I.stag_cycle(10)
+    assert all(_is_partition(t, 10) and set(t.sizes()) == {2} for t in tess)
+    assert all(_polygons_are_cliques(g, t) for t in tess)
+    h = I.random_mixed(15, seed=4)
+    sg, (stars, pairs) = I.stag_arcs(h)
+    assert sg.n == h.n_arcs and _is_partition(stars, sg.n) and _is_partition(pairs, sg.n)
+    # each pair is an arc and its reverse; each star is one tail's row, in row order
+    tails = np.repeat(np.arange(h.n), np.diff(h.row_ptr))
+    for a, b in pairs.poly_vert.reshape(-1, 2):
+        assert tails[a] == h.col[b] and tails[b] == h.col[a]
+    assert np.array_equal(stars.poly_vert, np.arange(h.n_arcs))
+
+
+def test_stag_random_weighted_is_normalised():
+    g, tess = I.stag_random(200, 3, 7, seed=2, weighted=True)
+    for t in tess:
+        assert _is_partition(t, 200) and t.sizes().max() <= 7
+        sq = np.add.reduceat(t.amp ** 2, t.poly_ptr[:-1])
+        assert np.abs(sq - 1).max() < 1e-12
+        assert _polygons_are_cliques(g, t)
