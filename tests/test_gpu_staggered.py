@@ -293,3 +293,23 @@ def test_square_lattice_kernel_agrees_with_polygon_kernels_and_repeats():
         assert np.array_equal(runs[0], runs[1])
         out[pl.structure] = runs[0]
     assert np.abs(out["stag_lattice"] - out["general"]).max() < 1e-12
+
+
+def test_staggered_class_simulate_and_distributions():
+    """The paper-style surface: simulate(range=...) snapshots, their FP64
+    distributions, and the host-streamed snapshots, on the lattice kernel."""
+    from paper_2406_08186_amd.walk import Staggered
+    g, tess = I.stag_lattice(40, 132)
+    w = Staggered(g, tess, marked=[5, 700], dtype="c128", layout="structured")
+    assert w.plan.structure == "stag_lattice"
+    psi0 = I.random_state(g.n, 1)
+    idx = list(range(0, 9, 3))
+    states = w.simulate(range=(0, 9, 3), state=psi0)
+    dists = w.probability_distribution(states)
+    host = w.simulate_host(range=(0, 9, 3), state=psi0)
+    for k, s, d, h in zip(idx, states, dists, host):
+        ref = oracle.staggered_evolve(g.n, tess, psi0, k, marked=[5, 700])
+        assert np.abs(s.cpu().numpy() - ref).max() < 1e-12
+        assert np.abs(d.cpu().numpy() - np.abs(ref) ** 2).max() < 1e-12
+        assert np.array_equal(h, s.cpu().numpy())
+    assert np.array_equal(w.ket(3), I.ket_vertex(g.n, 3))
