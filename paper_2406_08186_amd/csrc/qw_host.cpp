@@ -803,9 +803,11 @@ int evolve_staggered(const qw_plan *p, void *psi, unsigned char *work, int64_t s
   }
   if (p->structure == kStagLattice) {
     void *cur = psi, *oth = work + p->off_w1;
-    for (int64_t i = 0; i < steps; ++i) {
-      QW_TRY(stag_lattice_step(c128, g, p->stag[0], p->stag[1], cur, oth, s), "staggered lattice kernel");
+    for (int64_t i = 0; i < steps;) {
+      const int k = steps - i >= 2 ? 2 : 1;  // two steps per launch, an odd last one alone
+      QW_TRY(stag_lattice_step(c128, g, p->stag[0], p->stag[1], k, cur, oth, s), "staggered lattice kernel");
       std::swap(cur, oth);
+      i += k;
     }
     if (cur != psi) QW_TRY(copy_state(c128, p->n, cur, psi, s), "state copy kernel");
     return readout_only(p, psi, ro, s);

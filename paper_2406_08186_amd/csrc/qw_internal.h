@@ -205,10 +205,10 @@ hipError_t stag_small(bool c128, const GraphView &g, void *psi, int64_t steps, c
 hipError_t stag_tess(bool c128, const GraphView &g, const StagTess &t, void *psi, bool mark, double *partials,
                      hipStream_t s);
 // Staggered walk on the square lattice (structure kStagLattice, dims {l1, l2}):
-// one step, both tessellations, from `in` to `out` (distinct buffers); `ta`,
-// `tb` give the two tessellations' (c0, c1).
-hipError_t stag_lattice_step(bool c128, const GraphView &g, const StagTess &ta, const StagTess &tb, const void *in,
-                             void *out, hipStream_t s);
+// `steps` (1 or 2) steps, both tessellations each, in one launch, from `in`
+// to `out` (distinct buffers); `ta`, `tb` give the tessellations' (c0, c1).
+hipError_t stag_lattice_step(bool c128, const GraphView &g, const StagTess &ta, const StagTess &tb, int steps,
+                             const void *in, void *out, hipStream_t s);
 
 // Sum of `count` partials -> *norm; sum over the marked list of p -> *pmarked.
 hipError_t finish_readout(const GraphView &g, int count, const Readout &ro, hipStream_t s);

@@ -249,10 +249,11 @@ LATTICES = [(4, 4), (6, 8), (16, 64), (18, 66), (34, 130), (100, 62), (4, 200)]
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("form", ["reflection", "hamiltonian"])
 def test_square_lattice_kernel_matches_oracle(l1, l2, dtype, form):
-    """The fused index-free kernel (both tessellations of a step in one
-    launch, tiles of 16 x 64 with a two-cell periodic halo): lattices smaller
-    than one tile (staged vertices repeat), ragged tiles in both directions,
-    marked vertices on tile edges and corners, both forms."""
+    """The fused index-free kernels (both tessellations of a step in one
+    launch, tiles of 16 x 64 with a periodic halo; two steps per launch with
+    a four-cell halo, an odd last step alone): lattices smaller than one tile
+    (staged vertices repeat), ragged tiles in both directions, marked
+    vertices on tile edges and corners, both forms."""
     from paper_2406_08186_amd.walk import Plan
     g, tess = I.stag_lattice(l1, l2)
     if form == "hamiltonian":
@@ -263,7 +264,7 @@ def test_square_lattice_kernel_matches_oracle(l1, l2, dtype, form):
     pl = Plan(g, "staggered", dtype=dtype, layout="structured", marked=marked, tessellations=tess)
     assert pl.structure == "stag_lattice"
     psi0 = I.random_state(g.n, l1 + l2)
-    for steps in (0, 1, 8):
+    for steps in (0, 1, 3, 8):  # one-step and two-step launches
         x = pl.state(psi0)
         p, norm, pm = pl.evolve(x, steps, readout=True)
         torch.cuda.synchronize()
