@@ -55,6 +55,41 @@ __device__ __forceinline__ bool marked(const uint32_t *bits, int v) {
   return (bits[v >> 5] >> (v & 31)) & 1u;
 }
 
+// The value x holds in lane `src` of the wavefront (a cross-lane permute).
+__device__ __forceinline__ float2 lane_pull(float2 x, int src) {
+  return make_float2(__shfl(x.x, src, 64), __shfl(x.y, src, 64));
+}
+__device__ __forceinline__ double2 lane_pull(double2 x, int src) {
+  return make_double2(__shfl(x.x, src, 64), __shfl(x.y, src, 64));
+}
+
+constexpr int kFromLower = 0x138;  // DPP wave_shr:1, lane i receives lane i-1 (lane 0 receives 0)
+constexpr int kFromUpper = 0x130;  // DPP wave_shl:1, lane i receives lane i+1 (lane 63 receives 0)
+
+// Lane v of the first wavefront receives lane (v + 1) mod n of x (UP) or lane
+// (v - 1) mod n (down), for n <= 64: a one-lane DPP shift, and the lane that
+// wraps reads its source lane directly.
+template <bool UP> __device__ __forceinline__ int ring_pull(int x, int n) {
+  const int shifted = __builtin_amdgcn_update_dpp(0, x, UP ? kFromUpper : kFromLower, 0xf, 0xf, true);
+  const int wrapped = __builtin_amdgcn_readlane(x, UP ? 0 : n - 1);
+  return static_cast<int>(threadIdx.x) == (UP ? n - 1 : 0) ? wrapped : shifted;
+}
+template <bool UP> __device__ __forceinline__ float ring_pull(float x, int n) {
+  return __int_as_float(ring_pull<UP>(__float_as_int(x), n));
+}
+template <bool UP> __device__ __forceinline__ double ring_pull(double x, int n) {
+  const long long b = __double_as_longlong(x);
+  const int lo = ring_pull<UP>(static_cast<int>(b), n);
+  const int hi = ring_pull<UP>(static_cast<int>(b >> 32), n);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <bool UP> __device__ __forceinline__ float2 ring_pull(float2 v, int n) {
+  return make_float2(ring_pull<UP>(v.x, n), ring_pull<UP>(v.y, n));
+}
+template <bool UP> __device__ __forceinline__ double2 ring_pull(double2 v, int n) {
+  return make_double2(ring_pull<UP>(v.x, n), ring_pull<UP>(v.y, n));
+}
+
 // Workgroup b is dispatched to XCD b % 8 (round-robin over the 8 XCDs).  This
 // remap gives XCD x one contiguous range of logical blocks, so neighbouring
 // rows of a stencil are read through the same L2.  It is a bijection on
@@ -110,6 +145,43 @@ __global__ __launch_bounds__(256) void k_finish(const double *partials, int coun
 }
 
 // ---- coined: whole walk in one workgroup's LDS -------------------------------
+// Steps of a graph whose vertices all have degree 2, at most 64 of them, held
+// in the first wavefront's registers: lane v has the amplitudes x0, x1 of arcs
+// 2v, 2v + 1, whose reverse arcs are r0, r1; mk marks vertex v.  HAD picks the
+// Hadamard coin (else Grover), MARKS says some vertex is marked, RING that the
+// graph is a cycle in direction order (one-lane shifts instead of permutes).
+// The loop body has no branch; arithmetic and rounding are those of the LDS
+// loops of coined_small_walk.
+template <typename T, bool HAD, bool MARKS, bool RING>
+__device__ void two_reg_steps(T &x0, T &x1, int r0, int r1, bool mk, int n, int64_t steps) {
+  for (int64_t s = 0; s < steps; ++s) {
+    const double2 y0 = cvt(x0), y1 = cvt(x1);
+    double2 f0, f1;
+    if (HAD) {
+      f0 = scale(add(y0, y1), kInvSqrt2);
+      f1 = scale(sub(y0, y1), kInvSqrt2);
+    } else {
+      const double2 m = grover_mean(add(add(make_double2(0.0, 0.0), y0), y1), 2);
+      f0 = sub(add(m, m), y0);
+      f1 = sub(add(m, m), y1);
+    }
+    if (MARKS) {
+      f0 = mk ? scale(y0, -1.0) : f0;
+      f1 = mk ? scale(y1, -1.0) : f1;
+    }
+    const T q0 = pack<T>(f0), q1 = pack<T>(f1);
+    if (RING) {
+      x0 = ring_pull<true>(q1, n);
+      x1 = ring_pull<false>(q0, n);
+    } else {
+      const T u0 = lane_pull(q0, r0 >> 1), w0 = lane_pull(q1, r0 >> 1);
+      const T u1 = lane_pull(q0, r1 >> 1), w1 = lane_pull(q1, r1 >> 1);
+      x0 = (r0 & 1) ? w0 : u0;
+      x1 = (r1 & 1) ? w1 : u1;
+    }
+  }
+}
+
 template <typename T>
 __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int64_t steps, const Readout &ro,
                                   unsigned char *smem, double *red) {
@@ -126,6 +198,49 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
   for (int i = threadIdx.x; i <= n; i += blockDim.x) srp[i] = g.rp[i];
   for (int i = threadIdx.x; i < (n + 31) / 32; i += blockDim.x) smark[i] = g.markbits[i];
   __syncthreads();
+  // Every vertex of degree 2 and at most 64 of them (cycles, unions of
+  // cycles): lane v of the first wavefront keeps vertex v's two amplitudes
+  // (arcs 2v, 2v + 1) in registers and takes the shifted ones from the lane
+  // that owns the reverse arc, so a step needs no LDS array and no barrier.
+  // Arithmetic and rounding are those of the loops below.
+  int two_reg = n > 0 && n <= 64 && na == 2 * n && !g.sqrtp ? 1 : 0;  // the same in every thread
+  if (two_reg)
+    two_reg = __syncthreads_and(static_cast<int>(threadIdx.x) >= n ||
+                                srp[threadIdx.x + 1] - srp[threadIdx.x] == 2);
+  // A cycle in direction order (arc 2v = v -> v+1, arc 2v + 1 = v -> v-1)
+  // moves slot 1 of lane v+1 and slot 0 of lane v-1 into lane v: one-lane
+  // shifts instead of general permutes.
+  int ring = 0;
+  if (two_reg) {
+    const int v = static_cast<int>(threadIdx.x);
+    ring = __syncthreads_and(v >= n || (srev[2 * v] == 2 * ((v + 1) % n) + 1 &&
+                                        srev[2 * v + 1] == 2 * ((v + n - 1) % n)));
+  }
+  if (two_reg) {
+    if (threadIdx.x < 64) {
+      const int v = static_cast<int>(threadIdx.x) < n ? static_cast<int>(threadIdx.x) : 0;
+      T x0 = a[2 * v], x1 = a[2 * v + 1];
+      // new amplitude of arc 2v + k = coin output at arc rev[2v + k], held by
+      // lane rev >> 1 in its slot rev & 1
+      const int r0 = srev[2 * v], r1 = srev[2 * v + 1];
+      const bool mk = marked(smark, v);
+      switch ((hadamard ? 4 : 0) | (g.n_marked > 0 ? 2 : 0) | (ring ? 1 : 0)) {
+        case 0: two_reg_steps<T, false, false, false>(x0, x1, r0, r1, mk, n, steps); break;
+        case 1: two_reg_steps<T, false, false, true>(x0, x1, r0, r1, mk, n, steps); break;
+        case 2: two_reg_steps<T, false, true, false>(x0, x1, r0, r1, mk, n, steps); break;
+        case 3: two_reg_steps<T, false, true, true>(x0, x1, r0, r1, mk, n, steps); break;
+        case 4: two_reg_steps<T, true, false, false>(x0, x1, r0, r1, mk, n, steps); break;
+        case 5: two_reg_steps<T, true, false, true>(x0, x1, r0, r1, mk, n, steps); break;
+        case 6: two_reg_steps<T, true, true, false>(x0, x1, r0, r1, mk, n, steps); break;
+        default: two_reg_steps<T, true, true, true>(x0, x1, r0, r1, mk, n, steps); break;
+      }
+      if (static_cast<int>(threadIdx.x) < n) {
+        a[2 * v] = x0;
+        a[2 * v + 1] = x1;
+      }
+    }
+    __syncthreads();
+  }
   // One step per pass: each vertex's coin output goes straight to the
   // reverse arcs' slots of the other buffer (the flip-flop shift), so a step
   // is one LDS pass and one barrier.  When every vertex has a thread of its
@@ -142,7 +257,8 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
     for (int k = 0; k < kRegDeg; ++k) rrev[k] = k < rd ? srev[rlo + k] : 0;
   }
   own_ok = __syncthreads_and(own_ok && (threadIdx.x >= n || rd <= kRegDeg) && !g.sqrtp);
-  for (int64_t s = 0; s < steps && own_ok; ++s) {
+  const int64_t lds_steps = two_reg ? 0 : steps;
+  for (int64_t s = 0; s < lds_steps && own_ok; ++s) {
     if (threadIdx.x < n && rd > 0) {
       double2 x[kRegDeg];
 #pragma unroll
@@ -170,7 +286,7 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
     a = b;
     b = t;
   }
-  for (int64_t s = 0; s < steps && !own_ok; ++s) {
+  for (int64_t s = 0; s < lds_steps && !own_ok; ++s) {
     for (int v = threadIdx.x; v < n; v += blockDim.x) {
       const int lo = srp[v], hi = srp[v + 1], d = hi - lo;
       if (d == 0) continue;
@@ -657,8 +773,6 @@ __device__ __forceinline__ double lane_shift(double x) {
   const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
-constexpr int kFromLower = 0x138;  // wave_shr:1, lane i receives lane i-1 (lane 0 receives 0)
-constexpr int kFromUpper = 0x130;  // wave_shl:1, lane i receives lane i+1 (lane 63 receives 0)
 template <int CTRL>
 __device__ __forceinline__ float lane_shift(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));

@@ -130,6 +130,45 @@ def test_coined_hadamard_cycle_parity(layout, dtype, n):
     assert abs(norm - 1.0) < (1e-12 if dtype == "c128" else 1e-6)
 
 
+def _two_regular(name):
+    """Degree-2 graphs of at most 64 vertices (the one-workgroup kernel keeps
+    them in registers of one wavefront) and graphs just outside that case."""
+    if name == "union27_37":  # two cycles, labels shuffled so reverse arcs lie far apart
+        perm = np.random.default_rng(4).permutation(64)
+        edges = [(perm[i], perm[(i + 1) % 27]) for i in range(27)]
+        edges += [(perm[27 + i], perm[27 + (i + 1) % 37]) for i in range(37)]
+        return I.from_edges(64, sorted((min(a, b), max(a, b)) for a, b in edges), name=name)
+    if name == "deg123":  # as many arcs as 2n, but degrees 3, 2, 2, 2, 2, 1
+        return I.from_edges(6, [(0, 1), (1, 2), (2, 3), (0, 3), (0, 4), (4, 5)], name=name)
+    kind, n = name.split("_")
+    return I.cycle(int(n)) if kind == "dir" else I.cycle_sorted(int(n))
+
+
+@pytest.mark.parametrize("name", ["dir_3", "dir_17", "sorted_40", "dir_64", "union27_37", "deg123", "dir_65"])
+@pytest.mark.parametrize("coin", ["grover", "hadamard"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_coined_two_regular_small(name, coin, dtype):
+    g = _two_regular(name)
+    if coin == "hadamard" and name == "deg123":
+        pytest.skip("the Hadamard coin needs degree 2 everywhere")
+    marked = sorted({1, g.n // 2})
+    psi0 = I.random_state(g.n_arcs, seed=g.n)
+    for steps in (0, 1, 37, 100):
+        ref = oracle.coined_evolve(g.row_ptr, g.col, psi0, steps, marked=marked,
+                                   coin=oracle.HADAMARD if coin == "hadamard" else oracle.GROVER)
+        pref = oracle.coined_prob(g.row_ptr, g.col, ref)
+        got, p, norm, pm, path = run_coined(g, psi0, steps, dtype, "auto", coin=coin, marked=marked)
+        assert path == "small"
+        if dtype == "c128":
+            assert np.abs(got - ref).max() < C128_TOL
+            assert np.abs(p - pref).max() < C128_TOL
+        else:
+            assert np.linalg.norm(got - ref) < 1e-5
+            assert np.abs(p - pref).max() < 1e-6
+        assert abs(norm - pref.sum()) < (1e-12 if dtype == "c128" else 1e-6)
+        assert abs(pm - pref[marked].sum()) < (1e-12 if dtype == "c128" else 1e-6)
+
+
 def test_cycle64_hadamard_golden():
     """The 64-cycle workload: 100 steps, c128, one-workgroup path, vs the stored values."""
     import os
