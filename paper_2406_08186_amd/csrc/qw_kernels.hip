@@ -191,12 +191,32 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
   int32_t *srp = reinterpret_cast<int32_t *>(b + na);
   int32_t *srev = srp + n + 1;
   uint32_t *smark = reinterpret_cast<uint32_t *>(srev + na);  // the marked bitmap, read every step
-  for (int i = threadIdx.x; i < na; i += blockDim.x) {
+  const int n_words = (n + 31) / 32;
+  {
+    // each thread's first element of every table: the loads go out together
+    const int t = threadIdx.x;
+    T v0{};
+    int32_t r0 = 0, p0 = 0;
+    uint32_t m0 = 0;
+    if (t < na) {
+      v0 = psi[t];
+      r0 = g.rev[t];
+    }
+    if (t <= n) p0 = g.rp[t];
+    if (t < n_words) m0 = g.markbits[t];
+    if (t < na) {
+      a[t] = v0;
+      srev[t] = r0;
+    }
+    if (t <= n) srp[t] = p0;
+    if (t < n_words) smark[t] = m0;
+  }
+  for (int i = threadIdx.x + blockDim.x; i < na; i += blockDim.x) {
     a[i] = psi[i];
     srev[i] = g.rev[i];
   }
-  for (int i = threadIdx.x; i <= n; i += blockDim.x) srp[i] = g.rp[i];
-  for (int i = threadIdx.x; i < (n + 31) / 32; i += blockDim.x) smark[i] = g.markbits[i];
+  for (int i = threadIdx.x + blockDim.x; i <= n; i += blockDim.x) srp[i] = g.rp[i];
+  for (int i = threadIdx.x + blockDim.x; i < n_words; i += blockDim.x) smark[i] = g.markbits[i];
   __syncthreads();
   // Every vertex of degree 2 and at most 64 of them (cycles, unions of
   // cycles): lane v of the first wavefront keeps vertex v's two amplitudes
@@ -315,19 +335,16 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
   }
   for (int i = threadIdx.x; i < na; i += blockDim.x) psi[i] = a[i];
   if (ro.p || ro.norm || ro.pmarked) {
-    double *pout = ro.p ? ro.p : ro.pscratch;
-    double acc = 0.0;
+    // p_v from the LDS copy; p_M adds the marked vertices' p_v as they pass
+    double acc = 0.0, pm = 0.0;
     for (int v = threadIdx.x; v < n; v += blockDim.x) {
       double pv = 0.0;
       for (int i = srp[v]; i < srp[v + 1]; ++i) pv += abs2(cvt(a[i]));
-      pout[v] = pv;
+      if (ro.p) ro.p[v] = pv;
       acc += pv;
+      if (marked(smark, v)) pm += pv;
     }
     double tot = block_sum(acc, red);
-    __threadfence_block();
-    __syncthreads();
-    double pm = 0.0;
-    for (int i = threadIdx.x; i < g.n_marked; i += blockDim.x) pm += pout[g.marklist[i]];
     double ptot = block_sum(pm, red);
     if (threadIdx.x == 0) {
       if (ro.norm) *ro.norm = tot;
