@@ -123,19 +123,14 @@ def timed_passes(plan, psi, steps, warmup, spp):
     return wall, per, out
 
 
-def stage_launch_ms(plan, psi, reps=20):
-    """Average duration of one launch of the stage kernel: HIP events around
-    single-step evolves (K / block_depth launches each) on the launch stream."""
-    import torch
-    plan.evolve(psi, 1)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        plan.evolve(psi, 1)
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / (reps * (K_ORDER // max(1, plan.info.block_depth)))
+def stage_launch_ms(plan, per_pass_ms, steps_per_pass):
+    """Average duration of one launch of the stage kernel over the timed
+    region: the HIP-event time of the timed passes (recorded on the stream
+    the kernels run on) over the number of stage launches they made
+    (K / block_depth per time step).  The FP64 readout at the end of each
+    pass, one small launch per thousands, is counted in."""
+    launches = len(per_pass_ms) * steps_per_pass * (K_ORDER // max(1, plan.info.block_depth))
+    return sum(per_pass_ms) / launches
 
 
 def pct(sorted_vals, q):
@@ -221,7 +216,7 @@ def main():
         wall, per, (p, norm, _) = timed_passes(pl, psi, args.steps, args.warmup, spp)
         total_steps = (args.steps + args.warmup) * spp
         state = psi.cpu().numpy().astype(np.complex128)
-        launch_ms = stage_launch_ms(pl, pl.state(psi0))
+        launch_ms = stage_launch_ms(pl, per, spp)
         es = 8 if dtype == "c64" else 16
         # algorithmic bytes of one row-stage of the matrix-free grid stencil: read y,
         # read psi, write y' (3 S); one launch runs block_depth stages of every row
