@@ -66,28 +66,33 @@ __device__ __forceinline__ double2 lane_pull(double2 x, int src) {
 constexpr int kFromLower = 0x138;  // DPP wave_shr:1, lane i receives lane i-1 (lane 0 receives 0)
 constexpr int kFromUpper = 0x130;  // DPP wave_shl:1, lane i receives lane i+1 (lane 63 receives 0)
 
+constexpr int kRotFromUpper = 0x134;  // DPP wave_rol:1, lane i receives lane (i+1) mod 64
+constexpr int kRotFromLower = 0x13C;  // DPP wave_ror:1, lane i receives lane (i-1) mod 64
+
 // Lane v of the first wavefront receives lane (v + 1) mod n of x (UP) or lane
-// (v - 1) mod n (down), for n <= 64: a one-lane DPP shift, and the lane that
-// wraps reads its source lane directly.
-template <bool UP> __device__ __forceinline__ int ring_pull(int x, int n) {
+// (v - 1) mod n (down), for n <= 64.  FULL (n = 64): one DPP rotation of the
+// wavefront.  Otherwise a one-lane DPP shift, and the lane that wraps reads
+// its source lane directly.
+template <bool UP, bool FULL> __device__ __forceinline__ int ring_pull(int x, int n) {
+  if (FULL) return __builtin_amdgcn_update_dpp(0, x, UP ? kRotFromUpper : kRotFromLower, 0xf, 0xf, false);
   const int shifted = __builtin_amdgcn_update_dpp(0, x, UP ? kFromUpper : kFromLower, 0xf, 0xf, true);
   const int wrapped = __builtin_amdgcn_readlane(x, UP ? 0 : n - 1);
   return static_cast<int>(threadIdx.x) == (UP ? n - 1 : 0) ? wrapped : shifted;
 }
-template <bool UP> __device__ __forceinline__ float ring_pull(float x, int n) {
-  return __int_as_float(ring_pull<UP>(__float_as_int(x), n));
+template <bool UP, bool FULL> __device__ __forceinline__ float ring_pull(float x, int n) {
+  return __int_as_float(ring_pull<UP, FULL>(__float_as_int(x), n));
 }
-template <bool UP> __device__ __forceinline__ double ring_pull(double x, int n) {
+template <bool UP, bool FULL> __device__ __forceinline__ double ring_pull(double x, int n) {
   const long long b = __double_as_longlong(x);
-  const int lo = ring_pull<UP>(static_cast<int>(b), n);
-  const int hi = ring_pull<UP>(static_cast<int>(b >> 32), n);
+  const int lo = ring_pull<UP, FULL>(static_cast<int>(b), n);
+  const int hi = ring_pull<UP, FULL>(static_cast<int>(b >> 32), n);
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
-template <bool UP> __device__ __forceinline__ float2 ring_pull(float2 v, int n) {
-  return make_float2(ring_pull<UP>(v.x, n), ring_pull<UP>(v.y, n));
+template <bool UP, bool FULL> __device__ __forceinline__ float2 ring_pull(float2 v, int n) {
+  return make_float2(ring_pull<UP, FULL>(v.x, n), ring_pull<UP, FULL>(v.y, n));
 }
-template <bool UP> __device__ __forceinline__ double2 ring_pull(double2 v, int n) {
-  return make_double2(ring_pull<UP>(v.x, n), ring_pull<UP>(v.y, n));
+template <bool UP, bool FULL> __device__ __forceinline__ double2 ring_pull(double2 v, int n) {
+  return make_double2(ring_pull<UP, FULL>(v.x, n), ring_pull<UP, FULL>(v.y, n));
 }
 
 // Workgroup b is dispatched to XCD b % 8 (round-robin over the 8 XCDs).  This
@@ -149,10 +154,11 @@ __global__ __launch_bounds__(256) void k_finish(const double *partials, int coun
 // in the first wavefront's registers: lane v has the amplitudes x0, x1 of arcs
 // 2v, 2v + 1, whose reverse arcs are r0, r1; mk marks vertex v.  HAD picks the
 // Hadamard coin (else Grover), MARKS says some vertex is marked, RING that the
-// graph is a cycle in direction order (one-lane shifts instead of permutes).
-// The loop body has no branch; arithmetic and rounding are those of the LDS
-// loops of coined_small_walk.
-template <typename T, bool HAD, bool MARKS, bool RING>
+// graph is a cycle in direction order (1: one-lane shifts instead of
+// permutes; 2: 64 vertices, wavefront rotations).  The loop body has no
+// branch; arithmetic and rounding are those of the LDS loops of
+// coined_small_walk.
+template <typename T, bool HAD, bool MARKS, int RING>
 __device__ void two_reg_steps(T &x0, T &x1, int r0, int r1, bool mk, int n, int64_t steps) {
   for (int64_t s = 0; s < steps; ++s) {
     const double2 y0 = cvt(x0), y1 = cvt(x1);
@@ -171,8 +177,8 @@ __device__ void two_reg_steps(T &x0, T &x1, int r0, int r1, bool mk, int n, int6
     }
     const T q0 = pack<T>(f0), q1 = pack<T>(f1);
     if (RING) {
-      x0 = ring_pull<true>(q1, n);
-      x1 = ring_pull<false>(q0, n);
+      x0 = ring_pull<true, RING == 2>(q1, n);
+      x1 = ring_pull<false, RING == 2>(q0, n);
     } else {
       const T u0 = lane_pull(q0, r0 >> 1), w0 = lane_pull(q1, r0 >> 1);
       const T u1 = lane_pull(q0, r1 >> 1), w1 = lane_pull(q1, r1 >> 1);
@@ -244,15 +250,20 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
       // lane rev >> 1 in its slot rev & 1
       const int r0 = srev[2 * v], r1 = srev[2 * v + 1];
       const bool mk = marked(smark, v);
-      switch ((hadamard ? 4 : 0) | (g.n_marked > 0 ? 2 : 0) | (ring ? 1 : 0)) {
-        case 0: two_reg_steps<T, false, false, false>(x0, x1, r0, r1, mk, n, steps); break;
-        case 1: two_reg_steps<T, false, false, true>(x0, x1, r0, r1, mk, n, steps); break;
-        case 2: two_reg_steps<T, false, true, false>(x0, x1, r0, r1, mk, n, steps); break;
-        case 3: two_reg_steps<T, false, true, true>(x0, x1, r0, r1, mk, n, steps); break;
-        case 4: two_reg_steps<T, true, false, false>(x0, x1, r0, r1, mk, n, steps); break;
-        case 5: two_reg_steps<T, true, false, true>(x0, x1, r0, r1, mk, n, steps); break;
-        case 6: two_reg_steps<T, true, true, false>(x0, x1, r0, r1, mk, n, steps); break;
-        default: two_reg_steps<T, true, true, true>(x0, x1, r0, r1, mk, n, steps); break;
+      const int rk = ring ? (n == 64 ? 2 : 1) : 0;
+      switch ((hadamard ? 6 : 0) + (g.n_marked > 0 ? 3 : 0) + rk) {
+        case 0: two_reg_steps<T, false, false, 0>(x0, x1, r0, r1, mk, n, steps); break;
+        case 1: two_reg_steps<T, false, false, 1>(x0, x1, r0, r1, mk, n, steps); break;
+        case 2: two_reg_steps<T, false, false, 2>(x0, x1, r0, r1, mk, n, steps); break;
+        case 3: two_reg_steps<T, false, true, 0>(x0, x1, r0, r1, mk, n, steps); break;
+        case 4: two_reg_steps<T, false, true, 1>(x0, x1, r0, r1, mk, n, steps); break;
+        case 5: two_reg_steps<T, false, true, 2>(x0, x1, r0, r1, mk, n, steps); break;
+        case 6: two_reg_steps<T, true, false, 0>(x0, x1, r0, r1, mk, n, steps); break;
+        case 7: two_reg_steps<T, true, false, 1>(x0, x1, r0, r1, mk, n, steps); break;
+        case 8: two_reg_steps<T, true, false, 2>(x0, x1, r0, r1, mk, n, steps); break;
+        case 9: two_reg_steps<T, true, true, 0>(x0, x1, r0, r1, mk, n, steps); break;
+        case 10: two_reg_steps<T, true, true, 1>(x0, x1, r0, r1, mk, n, steps); break;
+        default: two_reg_steps<T, true, true, 2>(x0, x1, r0, r1, mk, n, steps); break;
       }
       if (static_cast<int>(threadIdx.x) < n) {
         a[2 * v] = x0;

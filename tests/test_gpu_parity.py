@@ -169,6 +169,22 @@ def test_coined_two_regular_small(name, coin, dtype):
         assert abs(pm - pref[marked].sum()) < (1e-12 if dtype == "c128" else 1e-6)
 
 
+@pytest.mark.parametrize("name,coin", [("dir_64", "hadamard"), ("dir_17", "hadamard"), ("union27_37", "grover")])
+def test_c64_drift_after_1e4_steps_two_regular(name, coin):
+    """complex64 on the one-wavefront register path: L2 <= 1e-4 and norm drift
+    <= 1e-5 against the FP64 oracle after 10^4 steps."""
+    g = _two_regular(name)
+    marked = [] if coin == "hadamard" else [5]
+    psi0 = I.random_state(g.n_arcs, seed=3)
+    steps = 10000
+    ref = oracle.coined_evolve(g.row_ptr, g.col, psi0, steps, marked=marked,
+                               coin=oracle.HADAMARD if coin == "hadamard" else oracle.GROVER)
+    got, _, norm, _, path = run_coined(g, psi0, steps, "c64", "auto", coin=coin, marked=marked)
+    assert path == "small"
+    assert np.linalg.norm(got - ref) < 1e-4
+    assert abs(norm - 1.0) < 1e-5
+
+
 def test_cycle64_hadamard_golden():
     """The 64-cycle workload: 100 steps, c128, one-workgroup path, vs the stored values."""
     import os
