@@ -265,12 +265,24 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
         case 10: two_reg_steps<T, true, true, 1>(x0, x1, r0, r1, mk, n, steps); break;
         default: two_reg_steps<T, true, true, 2>(x0, x1, r0, r1, mk, n, steps); break;
       }
-      if (static_cast<int>(threadIdx.x) < n) {
-        a[2 * v] = x0;
-        a[2 * v + 1] = x1;
+      // store and read out from the registers: p_v, the norm and p_M are
+      // summed in the order of the LDS readout below, so the results match
+      // it bit for bit
+      const bool live = static_cast<int>(threadIdx.x) < n;
+      if (live) {
+        psi[2 * v] = x0;
+        psi[2 * v + 1] = x1;
+      }
+      const double pv = live ? (0.0 + abs2(cvt(x0))) + abs2(cvt(x1)) : 0.0;
+      if (ro.p && live) ro.p[v] = pv;
+      const double tot = wave_sum(0.0 + pv);
+      const double ptot = wave_sum(live && mk ? 0.0 + pv : 0.0);
+      if (threadIdx.x == 0) {
+        if (ro.norm) *ro.norm = tot;
+        if (ro.pmarked) *ro.pmarked = ptot;
       }
     }
-    __syncthreads();
+    return;  // every thread: two_reg is the same in all of them
   }
   // One step per pass: each vertex's coin output goes straight to the
   // reverse arcs' slots of the other buffer (the flip-flop shift), so a step
