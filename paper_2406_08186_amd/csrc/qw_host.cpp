@@ -634,6 +634,18 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   p->has_coin = !p->coin_mat.empty();
   if (p->has_coin) p->off_coin = section(sizeof(double) * p->coin_mat.size());
   p->has_sqrtp = p->kind == QW_COINED && p->coin == QW_SZEGEDY;
+  // Degree-2 graphs of at most 64 vertices on the one-workgroup path keep
+  // their amplitudes in one wavefront's registers; cycles in direction order
+  // move them by lane shifts.
+  if (p->kind == QW_COINED && p->structure == kSmall && !p->has_sqrtp && !p->lattice() && n >= 3 && n <= 64 &&
+      na == 2 * n) {
+    bool deg2 = true, ring = true;
+    for (int64_t v = 0; v < n && deg2; ++v) {
+      deg2 = rp[v + 1] - rp[v] == 2;
+      ring = ring && deg2 && rev[2 * v] == 2 * ((v + 1) % n) + 1 && rev[2 * v + 1] == 2 * ((v + n - 1) % n);
+    }
+    p->two_reg = deg2 ? (ring ? 2 : 1) : 0;
+  }
   if (p->has_sqrtp) p->off_sqrtp = section(sizeof(double) * p->sqrt_p.size());
   for (size_t k = 0; k < tess.size(); ++k) {
     StagHost &h = tess[k];
@@ -1012,6 +1024,7 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
   g.marklist = reinterpret_cast<const int32_t *>(base + p->off_mlist);
   if (p->has_tmark) g.tmark = reinterpret_cast<const uint8_t *>(base + p->off_tmark);
   g.strip_rows = p->strip_rows;
+  g.two_reg = p->two_reg;
   g.persistent = p->shift == QW_PERSISTENT;
   if (p->has_coin) g.coin = reinterpret_cast<const double *>(base + p->off_coin);
   if (p->has_sqrtp) g.sqrtp = reinterpret_cast<const double *>(base + p->off_sqrtp);

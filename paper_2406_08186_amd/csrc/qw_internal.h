@@ -112,6 +112,9 @@ struct GraphView {
   const int32_t *marklist = nullptr;   // n_marked
   const uint8_t *tmark = nullptr;      // grid CTQW strips: 1 if a marked vertex lies in the strip's window
   int32_t strip_rows = 0;              // grid CTQW strips: core rows per strip
+  int32_t two_reg = 0;                 // coined, one workgroup: 1 if every vertex has degree 2 and n <= 64
+                                       // (amplitudes in one wavefront's registers), 2 if moreover a cycle in
+                                       // direction order (rev[2v] = 2(v+1)+1, rev[2v+1] = 2(v-1), mod n)
   int32_t persistent = 0;              // coined on a lattice: persistent shift
   const double *coin = nullptr;        // coined on a lattice: d x d complex coin (row-major), else null
   const double *sqrtp = nullptr;       // Szegedy coin: sqrt(P) per arc, else null

@@ -192,6 +192,53 @@ template <typename T>
 __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int64_t steps, const Readout &ro,
                                   unsigned char *smem, double *red) {
   const int n = g.n, na = g.n_arcs;
+  if (g.two_reg) {
+    // Every vertex has degree 2 and there are at most 64 (cycles, unions of
+    // cycles; the plan checked): lane v of the first wavefront keeps vertex
+    // v's two amplitudes (arcs 2v, 2v + 1) in registers from the first load
+    // to the last store and takes the shifted ones from the lanes that own
+    // the reverse arcs, so the walk needs no LDS and no barrier.  Arithmetic,
+    // rounding and the readout's summation order are those of the LDS path.
+    if (threadIdx.x < 64) {
+      const bool live = static_cast<int>(threadIdx.x) < n;
+      const int v = live ? static_cast<int>(threadIdx.x) : 0;
+      T x0 = psi[2 * v], x1 = psi[2 * v + 1];
+      // new amplitude of arc 2v + k = coin output at arc rev[2v + k], held by
+      // lane rev >> 1 in its slot rev & 1
+      const int r0 = g.rev[2 * v], r1 = g.rev[2 * v + 1];
+      const bool mk = marked(g.markbits, v);
+      const int rk = g.two_reg == 2 ? (n == 64 ? 2 : 1) : 0;
+      switch ((hadamard ? 6 : 0) + (g.n_marked > 0 ? 3 : 0) + rk) {
+        case 0: two_reg_steps<T, false, false, 0>(x0, x1, r0, r1, mk, n, steps); break;
+        case 1: two_reg_steps<T, false, false, 1>(x0, x1, r0, r1, mk, n, steps); break;
+        case 2: two_reg_steps<T, false, false, 2>(x0, x1, r0, r1, mk, n, steps); break;
+        case 3: two_reg_steps<T, false, true, 0>(x0, x1, r0, r1, mk, n, steps); break;
+        case 4: two_reg_steps<T, false, true, 1>(x0, x1, r0, r1, mk, n, steps); break;
+        case 5: two_reg_steps<T, false, true, 2>(x0, x1, r0, r1, mk, n, steps); break;
+        case 6: two_reg_steps<T, true, false, 0>(x0, x1, r0, r1, mk, n, steps); break;
+        case 7: two_reg_steps<T, true, false, 1>(x0, x1, r0, r1, mk, n, steps); break;
+        case 8: two_reg_steps<T, true, false, 2>(x0, x1, r0, r1, mk, n, steps); break;
+        case 9: two_reg_steps<T, true, true, 0>(x0, x1, r0, r1, mk, n, steps); break;
+        case 10: two_reg_steps<T, true, true, 1>(x0, x1, r0, r1, mk, n, steps); break;
+        default: two_reg_steps<T, true, true, 2>(x0, x1, r0, r1, mk, n, steps); break;
+      }
+      if (live) {
+        psi[2 * v] = x0;
+        psi[2 * v + 1] = x1;
+      }
+      // p_v, the norm and p_M in the summation order of the LDS readout below
+      // (one vertex per thread there; the other wavefronts add exact zeros)
+      const double pv = live ? (0.0 + abs2(cvt(x0))) + abs2(cvt(x1)) : 0.0;
+      if (ro.p && live) ro.p[v] = pv;
+      const double tot = wave_sum(0.0 + pv);
+      const double ptot = wave_sum(live && mk ? 0.0 + pv : 0.0);
+      if (threadIdx.x == 0) {
+        if (ro.norm) *ro.norm = tot;
+        if (ro.pmarked) *ro.pmarked = ptot;
+      }
+    }
+    return;  // two_reg is the same in every thread
+  }
   T *a = reinterpret_cast<T *>(smem);
   T *b = a + na;
   int32_t *srp = reinterpret_cast<int32_t *>(b + na);
@@ -224,66 +271,6 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
   for (int i = threadIdx.x + blockDim.x; i <= n; i += blockDim.x) srp[i] = g.rp[i];
   for (int i = threadIdx.x + blockDim.x; i < n_words; i += blockDim.x) smark[i] = g.markbits[i];
   __syncthreads();
-  // Every vertex of degree 2 and at most 64 of them (cycles, unions of
-  // cycles): lane v of the first wavefront keeps vertex v's two amplitudes
-  // (arcs 2v, 2v + 1) in registers and takes the shifted ones from the lane
-  // that owns the reverse arc, so a step needs no LDS array and no barrier.
-  // Arithmetic and rounding are those of the loops below.
-  int two_reg = n > 0 && n <= 64 && na == 2 * n && !g.sqrtp ? 1 : 0;  // the same in every thread
-  if (two_reg)
-    two_reg = __syncthreads_and(static_cast<int>(threadIdx.x) >= n ||
-                                srp[threadIdx.x + 1] - srp[threadIdx.x] == 2);
-  // A cycle in direction order (arc 2v = v -> v+1, arc 2v + 1 = v -> v-1)
-  // moves slot 1 of lane v+1 and slot 0 of lane v-1 into lane v: one-lane
-  // shifts instead of general permutes.
-  int ring = 0;
-  if (two_reg) {
-    const int v = static_cast<int>(threadIdx.x);
-    ring = __syncthreads_and(v >= n || (srev[2 * v] == 2 * ((v + 1) % n) + 1 &&
-                                        srev[2 * v + 1] == 2 * ((v + n - 1) % n)));
-  }
-  if (two_reg) {
-    if (threadIdx.x < 64) {
-      const int v = static_cast<int>(threadIdx.x) < n ? static_cast<int>(threadIdx.x) : 0;
-      T x0 = a[2 * v], x1 = a[2 * v + 1];
-      // new amplitude of arc 2v + k = coin output at arc rev[2v + k], held by
-      // lane rev >> 1 in its slot rev & 1
-      const int r0 = srev[2 * v], r1 = srev[2 * v + 1];
-      const bool mk = marked(smark, v);
-      const int rk = ring ? (n == 64 ? 2 : 1) : 0;
-      switch ((hadamard ? 6 : 0) + (g.n_marked > 0 ? 3 : 0) + rk) {
-        case 0: two_reg_steps<T, false, false, 0>(x0, x1, r0, r1, mk, n, steps); break;
-        case 1: two_reg_steps<T, false, false, 1>(x0, x1, r0, r1, mk, n, steps); break;
-        case 2: two_reg_steps<T, false, false, 2>(x0, x1, r0, r1, mk, n, steps); break;
-        case 3: two_reg_steps<T, false, true, 0>(x0, x1, r0, r1, mk, n, steps); break;
-        case 4: two_reg_steps<T, false, true, 1>(x0, x1, r0, r1, mk, n, steps); break;
-        case 5: two_reg_steps<T, false, true, 2>(x0, x1, r0, r1, mk, n, steps); break;
-        case 6: two_reg_steps<T, true, false, 0>(x0, x1, r0, r1, mk, n, steps); break;
-        case 7: two_reg_steps<T, true, false, 1>(x0, x1, r0, r1, mk, n, steps); break;
-        case 8: two_reg_steps<T, true, false, 2>(x0, x1, r0, r1, mk, n, steps); break;
-        case 9: two_reg_steps<T, true, true, 0>(x0, x1, r0, r1, mk, n, steps); break;
-        case 10: two_reg_steps<T, true, true, 1>(x0, x1, r0, r1, mk, n, steps); break;
-        default: two_reg_steps<T, true, true, 2>(x0, x1, r0, r1, mk, n, steps); break;
-      }
-      // store and read out from the registers: p_v, the norm and p_M are
-      // summed in the order of the LDS readout below, so the results match
-      // it bit for bit
-      const bool live = static_cast<int>(threadIdx.x) < n;
-      if (live) {
-        psi[2 * v] = x0;
-        psi[2 * v + 1] = x1;
-      }
-      const double pv = live ? (0.0 + abs2(cvt(x0))) + abs2(cvt(x1)) : 0.0;
-      if (ro.p && live) ro.p[v] = pv;
-      const double tot = wave_sum(0.0 + pv);
-      const double ptot = wave_sum(live && mk ? 0.0 + pv : 0.0);
-      if (threadIdx.x == 0) {
-        if (ro.norm) *ro.norm = tot;
-        if (ro.pmarked) *ro.pmarked = ptot;
-      }
-    }
-    return;  // every thread: two_reg is the same in all of them
-  }
   // One step per pass: each vertex's coin output goes straight to the
   // reverse arcs' slots of the other buffer (the flip-flop shift), so a step
   // is one LDS pass and one barrier.  When every vertex has a thread of its
@@ -300,8 +287,7 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
     for (int k = 0; k < kRegDeg; ++k) rrev[k] = k < rd ? srev[rlo + k] : 0;
   }
   own_ok = __syncthreads_and(own_ok && (threadIdx.x >= n || rd <= kRegDeg) && !g.sqrtp);
-  const int64_t lds_steps = two_reg ? 0 : steps;
-  for (int64_t s = 0; s < lds_steps && own_ok; ++s) {
+  for (int64_t s = 0; s < steps && own_ok; ++s) {
     if (threadIdx.x < n && rd > 0) {
       double2 x[kRegDeg];
 #pragma unroll
@@ -329,7 +315,7 @@ __device__ void coined_small_walk(const GraphView &g, T *psi, int hadamard, int6
     a = b;
     b = t;
   }
-  for (int64_t s = 0; s < lds_steps && !own_ok; ++s) {
+  for (int64_t s = 0; s < steps && !own_ok; ++s) {
     for (int v = threadIdx.x; v < n; v += blockDim.x) {
       const int lo = srp[v], hi = srp[v + 1], d = hi - lo;
       if (d == 0) continue;

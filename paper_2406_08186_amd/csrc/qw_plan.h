@@ -49,6 +49,7 @@ struct qw_plan {
   std::vector<qwk::StagTess> stag;
   size_t off_stag = 0, off_stagpart = 0;
   int32_t strip_rows = 0;   // grid CTQW blocked kernel: core rows per strip
+  int32_t two_reg = 0;      // one-workgroup coined walk in one wavefront's registers: 0 no, 1 permutes, 2 cycle shifts
   int32_t block_depth = 1;  // grid CTQW: Horner stages per launch (temporal blocking)
 };
 
