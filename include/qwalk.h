@@ -120,7 +120,9 @@ extern "C" {
 #define QW_STRUCT_CYCLE 1
 #define QW_STRUCT_TORUS 2
 #define QW_STRUCT_HYPERCUBE 3
-#define QW_STRUCT_SMALL 4 /* whole walk resident in one workgroup's LDS */
+#define QW_STRUCT_SMALL 4 /* whole walk in one launch on one workgroup: resident in its LDS, or, for a
+                             coined walk on at most 64 vertices all of degree 2, in one wavefront's
+                             registers */
 #define QW_STRUCT_ELL 5   /* CTQW on a regular graph: column-major neighbour table */
 #define QW_STRUCT_DENSE 6 /* CTQW with a dense H on MFMA (QW_LAYOUT_DENSE)        */
 #define QW_STRUCT_STAG_LATTICE 7 /* staggered walk on an even periodic l1 x l2
