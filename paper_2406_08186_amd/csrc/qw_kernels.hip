@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_finish(const double *partials, int coun
   }
 }
 
-// ---- coined: whole walk in one workgroup's LDS -------------------------------
+// ---- coined: whole walk in one workgroup (its LDS, or one wavefront's registers)
 // Steps of a graph whose vertices all have degree 2, at most 64 of them, held
 // in the first wavefront's registers: lane v has the amplitudes x0, x1 of arcs
 // 2v, 2v + 1, whose reverse arcs are r0, r1; mk marks vertex v.  HAD picks the
