@@ -512,6 +512,7 @@ def run_serve(args):
             j.arrival = float(a)
         done, el, cycles = served(jobs)
         st = latency_stats(done)
+        print(f"[serve] load {frac}: served {len(done)} jobs in {el:.1f} s", file=sys.stderr, flush=True)
         jobs = fresh()
         for j, a in zip(jobs, arrivals):
             j.arrival = float(a)
