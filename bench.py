@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--serve-batch-arcs", type=float, default=2 ** 21,
                     help="cap on the arcs in the batch lane (0: none)")
     ap.add_argument("--serve-solo-slots", type=int, default=3, help="solo lanes running at once")
+    ap.add_argument("--serve-no-idle-solo", action="store_true",
+                    help="serve: never route a mid-size job to an idle solo lane while the batch is empty")
     ap.add_argument("--serve-solo-units", type=int, default=16384,
                     help="jobs needing at least this many launches (steps x K) run in a solo lane (0: none)")
     ap.add_argument("--workers", type=int, default=16)
@@ -471,7 +473,7 @@ def run_serve(args):
     def served(jobs):
         srv = WalkServer(capacity=64, chunk=64, dtype="c64", workers=args.workers,
                          solo_arcs=int(args.serve_solo_arcs), solo_slots=args.serve_solo_slots,
-                         solo_units=args.serve_solo_units or None,
+                         solo_units=args.serve_solo_units or None, idle_solo=not args.serve_no_idle_solo,
                          batch_arcs=int(args.serve_batch_arcs) if args.serve_batch_arcs > 0 else None)
         t1 = time.perf_counter()
         done = serve_stream(srv, jobs, time_limit=900)
@@ -535,7 +537,7 @@ def run_serve(args):
                    "arcs_range": [1e3, args.serve_max_arcs], "steps_range": [100, args.serve_max_steps],
                    "slots": 64, "chunk": 64, "solo_lane_arcs": int(args.serve_solo_arcs),
                    "batch_arcs_cap": int(args.serve_batch_arcs), "solo_lanes": args.serve_solo_slots,
-                   "solo_lane_units": args.serve_solo_units,
+                   "solo_lane_units": args.serve_solo_units, "idle_solo": not args.serve_no_idle_solo,
                    "parallelism": "single-gpu"},
         "saturated_jobs_per_s": cap_jobs_s,
         "plain_saturated": plain_sat,

@@ -181,13 +181,17 @@ class WalkServer:
     `solo_slots` solo lanes for jobs of at least `solo_arcs` arcs or at least
     `solo_units` launches (steps, times the Taylor order for a CTQW).
     The batch admits jobs while their arcs total at most `batch_arcs`, which
-    bounds the time of one batch launch and so the latency of every job in it."""
+    bounds the time of one batch launch and so the latency of every job in it.
+    With `idle_solo`, a mid-size job whose plan is built while the batch holds
+    and awaits no job and a solo lane is free goes to that solo lane: at light
+    load it then runs alone on its fastest path instead of on the batch
+    kernel."""
 
     def __init__(self, capacity: int = 64, budget_bytes: int | None = None, chunk: int = 64,
                  dtype: str = "c64", max_tiles: int = 1 << 18, workers: int = 4, device=None,
                  keep_states: bool = False, solo_arcs: int = 1 << 19, solo_chunk: int = 64,
                  batch_arcs: int | None = 1 << 21, solo_slots: int = 3, small_group: int = 16,
-                 small_streams: int = 3, solo_units: int | None = 16384):
+                 small_streams: int = 3, solo_units: int | None = 16384, idle_solo: bool = True):
         import torch
 
         from .walk import Batch
@@ -200,6 +204,7 @@ class WalkServer:
         self.chunk = chunk
         self.solo_arcs = solo_arcs
         self.solo_units = solo_units
+        self.idle_solo = idle_solo
         self.solo_chunk = solo_chunk
         self.keep_states = keep_states
         self.s_batch = torch.cuda.Stream(self.device)
@@ -242,12 +247,21 @@ class WalkServer:
             units = job.steps * (int(plan.info.taylor_order) if job.kind == "ctqw" else 1)
             if solo or (self.solo_units is not None and units >= self.solo_units):
                 return plan, "solo"
+            if self.idle_solo and self._batch_idle():
+                return plan, "solo"
             plan.close()
             layout = "structured" if job.kind == "coined" else "csr"
             return Plan(job.graph, job.kind, dtype=self.dtype, layout=layout, device=self.device,
                         upload=False, **job.params), "batch"
 
         self.building.append((job, self.pool.submit(build)))
+
+    def _batch_idle(self) -> bool:
+        """No job in or waiting for the batch, and a solo lane free (read from
+        a plan-building thread: the sizes are a routing hint only, and either
+        lane runs any job)."""
+        a = self.adm
+        return not a.running and not a.queue and len(a.solo) + len(a.solo_queue) < len(self.solo_lanes)
 
     def cancel(self, job: Job) -> None:
         if not self.adm.cancel(job) and job.status == "running":

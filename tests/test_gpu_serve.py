@@ -12,17 +12,20 @@ from paper_2406_08186_amd.serve import WalkServer, make_job, serve_stream
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("solo_arcs,solo_units", [(1 << 40, None), (20000, None), (1 << 40, 400)])
-def test_served_results_equal_alone(solo_arcs, solo_units):
+@pytest.mark.parametrize("solo_arcs,solo_units,idle_solo", [(1 << 40, None, False), (20000, None, False),
+                                                            (1 << 40, 400, False), (1 << 40, None, True)])
+def test_served_results_equal_alone(solo_arcs, solo_units, idle_solo):
     from paper_2406_08186_amd.walk import Batch, Plan
     rng = np.random.default_rng(11)
     jobs = [make_job(i, rng, arc_range=(1e3, 6e4), steps_range=(20, 120)) for i in range(14)]
     for i, j in enumerate(jobs):
         j.arrival = 0.002 * i
-    print(f"[case] serve {len(jobs)} jobs, solo lane from {solo_arcs} arcs or {solo_units} launches", flush=True)
+    print(f"[case] serve {len(jobs)} jobs, solo lane from {solo_arcs} arcs or {solo_units} launches, "
+          f"idle solo {idle_solo}", flush=True)
     budget = 64 * 2**20
     srv = WalkServer(capacity=6, budget_bytes=budget, chunk=16, dtype="c64", max_tiles=1 << 14,
-                     keep_states=True, solo_arcs=solo_arcs, solo_chunk=16, solo_units=solo_units)
+                     keep_states=True, solo_arcs=solo_arcs, solo_chunk=16, solo_units=solo_units,
+                     idle_solo=idle_solo)
     peak = [0]
     orig_admit, orig_solo = srv.adm.admit, srv.adm.admit_solo
 
@@ -47,7 +50,9 @@ def test_served_results_equal_alone(solo_arcs, solo_units):
     assert len(done) == len(jobs) and all(j.status == "done" for j in done)
     assert peak[0] <= budget
     lanes = {j.lane for j in done}
-    if solo_units is not None:
+    if idle_solo:
+        assert "small" in lanes and lanes <= {"small", "batch", "solo"}
+    elif solo_units is not None:
         assert "solo" in lanes and "small" in lanes
         for j in done:
             if j.lane == "batch":
