@@ -383,9 +383,9 @@ def run_batch(args):
     gpu_ms = ev0.elapsed_time(ev1)
     arc_steps = sum(g.n_arcs * sc[2] for g, sc in zip(graphs, sched))
     arc_spmv = sum(g.n_arcs * sc[2] * sc[0] for g, sc in zip(graphs, sched))
-    # algorithmic bytes: per row-stage 4 (row_ptr) + 4d (col) + 8d? no: gathers ideally cached,
-    # so 4 + 4d + 3*8 (y gather once, psi, y')
-    alg_bytes = sum(g.n * (4 + 4 * sp["d"] + 24) * sc[2] * sc[0] for g, sp, sc in zip(graphs, specs, sched))
+    # algorithmic bytes per row-stage on the ELL layout (no row pointers): 4d of
+    # neighbour indices + 3 x 8 (the gathered vector once with ideal reuse, psi, y')
+    alg_bytes = sum(g.n * (4 * sp["d"] + 24) * sc[2] * sc[0] for g, sp, sc in zip(graphs, specs, sched))
     pm_final, pm_peak = [], []
     for i in range(len(plans)):
         _, norm, pm = batch.readout(i)
