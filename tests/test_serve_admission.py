@@ -100,3 +100,35 @@ def test_batch_arc_cap_and_solo_lane():
     assert b.admit_solo() is s[0] and b.admit_solo() is s[1] and b.admit_solo() is None
     b.release(s[0])
     assert b.admit_solo() is s[2] and b.used == 60
+
+
+def test_idle_solo_routing_predicate():
+    """A mid-size job goes to a solo lane only while the batch holds and awaits
+    no job and a solo lane is free (the predicate the plan-building threads read)."""
+    from types import SimpleNamespace
+
+    from paper_2406_08186_amd.serve import WalkServer
+    a = AdmissionController(capacity=4, budget_bytes=1000, solo_slots=2)
+    srv = SimpleNamespace(adm=a, solo_lanes=[None, None])
+    idle = lambda: WalkServer._batch_idle(srv)  # noqa: E731
+    assert idle()
+    batch_job = _job(1, 10)
+    a.offer(batch_job)                       # waiting for the batch
+    assert not idle()
+    a.admit()                                # now running in the batch
+    assert not idle()
+    a.release(batch_job)
+    assert idle()
+    solos = []
+    for i in range(2):
+        j = _job(10 + i, 10)
+        j.lane = "solo"
+        a.offer(j)
+        solos.append(j)
+    assert not idle()                        # both solo lanes spoken for (two jobs queued)
+    a.admit_solo()
+    assert not idle()                        # one running, one queued
+    a.release(solos[0])
+    assert idle()                            # one queued, one lane free
+    a.admit_solo()
+    assert idle()                            # one running, one lane free
