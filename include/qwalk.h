@@ -297,8 +297,9 @@ int qw_probabilities(const qw_plan *plan, const void *d_psi, double *d_p, double
 /* Advance `count` independent walks by steps[i] steps each (Sec. 3.1 for
  * CTQW, Sec. 3.2 for coined walks, QW_STAGGERED above for staggered walks)
  * in a single launch, one workgroup per
- * walk: each walk runs whole in its workgroup's LDS, with the arithmetic and
- * order of qw_evolve on the same plan, so results are bitwise those of
+ * walk: each walk runs whole in its workgroup (in LDS, or in one wavefront's
+ * registers where QW_STRUCT_SMALL says so), with the arithmetic and order of
+ * qw_evolve on the same plan, so results are bitwise those of
  * qw_evolve(plans[i], d_psi[i], ..., steps[i]).  Every plan must be uploaded,
  * share one dtype and have taken the one-workgroup path (info.structure ==
  * QW_STRUCT_SMALL, which QW_LAYOUT_AUTO picks for graphs whose vectors fit in
