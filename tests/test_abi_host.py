@@ -379,3 +379,16 @@ def test_staggered_validation_and_path():
     ok_amp = I.Tessellation(ct[0].poly_ptr, ct[0].poly_vert, np.tile([0.6, 0.8], 4))
     p, _ = _stag(cyc, [ok_amp, ct[1]])
     L.qw_plan_destroy(p)
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}), ([], {"WORLD_SIZE": "2"})])
+def test_bench_refuses_more_than_one_gpu(argv, env):
+    """bench.py measures one GPU: asked for more it exits with status 2 and a
+    message, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *argv], cwd=root,
+                       env={**os.environ, **env}, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
