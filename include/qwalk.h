@@ -244,7 +244,9 @@ typedef struct qw_plan_info {
                               when temporal blocking applies), else 1         */
 } qw_plan_info;
 
-/* Validate the graph and the walk, precompute the host-side tables (reverse
+/* The walk constructors of the paper's user interface: ContinuousTime(graph,
+ * gamma, time, marked) (Sec. 3.1) and Coined(graph, shift, coin) (Sec. 3.2).
+ * Validate the graph and the walk, precompute the host-side tables (reverse
  * arcs, degree tiles, structure recognition, Taylor order), and return a new
  * plan in *out.  Host only: touches no device.  Errors: QW_EINVAL (null
  * pointers, bad enums, gamma/dt not positive, marked vertex out of range or
@@ -260,7 +262,9 @@ int qw_plan_destroy(qw_plan *plan);
 /* Sizes and choices of a plan. */
 int qw_plan_get_info(const qw_plan *plan, qw_plan_info *info);
 
-/* Copy the plan's device tables into the caller's device buffer d_graph
+/* The explicit host-to-device move of the paper's library layer (Sec. 4.4:
+ * data is moved to the device by an explicit call and stays in the caller's
+ * ownership).  Copy the plan's device tables into the caller's device buffer d_graph
  * (at least info.graph_bytes bytes, 256-byte aligned) on `stream`, and bind
  * the plan to that buffer: later calls read it, so it must stay allocated
  * and unmodified while the plan is used.  A plan is bound to one buffer at a
@@ -269,7 +273,9 @@ int qw_plan_get_info(const qw_plan *plan, qw_plan_info *info);
  * QW_EDEVICE. */
 int qw_plan_upload(qw_plan *plan, void *d_graph, size_t graph_bytes, void *stream);
 
-/* Advance the state by `steps` steps in place: psi <- U^steps psi (coined,
+/* The time evolution of simulate() (Sec. 3.1: U(t) = exp(-iHt) applied to
+ * the state; Sec. 3.2: U = S C applied step after step).
+ * Advance the state by `steps` steps in place: psi <- U^steps psi (coined,
  * staggered) or psi <- T_K(-iH dt)^steps psi (CTQW).  d_psi: device state of
  * info.state_len complex elements in the boundary layout (coined: CSR arc
  * order; CTQW and staggered: vertex order), read and written.  d_work: device workspace of
@@ -366,8 +372,20 @@ int qw_batch_clear_slot(qw_batch *batch, int32_t slot);
  * max_tiles. */
 int qw_batch_commit(qw_batch *batch, void *stream);
 /* Enqueue `launches` batched launches on `stream` (graph replays plus single
- * launches).  Slots whose walks finished are skipped by the kernel. */
+ * launches, as qw_batch_launch_plan states).  Slots whose walks finished are
+ * skipped by the kernel. */
 int qw_batch_run(qw_batch *batch, int64_t launches, void *stream);
+/* Replay mode.  use_graph != 0 (the default): qw_batch_run replays a captured
+ * hipGraph of 16 launches and launches the remainder one by one.  use_graph
+ * == 0: every launch is a direct kernel launch on the stream (same kernels,
+ * same arithmetic and results; meant for profilers and counter collection,
+ * which cannot attribute graph-replayed dispatches reliably).  Host only. */
+int qw_batch_set_replay(qw_batch *batch, int32_t use_graph);
+/* How qw_batch_run(launches) issues its work in the current mode: number of
+ * graph replays (16 launches each) and of direct launches per batched unit.
+ * Host only; NULL outputs are skipped. */
+int qw_batch_launch_plan(const qw_batch *batch, int64_t launches, int64_t *graph_replays,
+                         int64_t *direct_launches);
 /* Launches still needed by a slot (host mirror; 0 for an empty or finished
  * slot), and launches enqueued since bind. */
 int qw_batch_remaining(const qw_batch *batch, int32_t slot, int64_t *remaining);

@@ -34,7 +34,7 @@ EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upl
            "qw_batch_create", "qw_batch_destroy", "qw_batch_device_bytes", "qw_batch_bind",
            "qw_batch_set_slot", "qw_batch_clear_slot", "qw_batch_commit", "qw_batch_run",
            "qw_batch_remaining", "qw_batch_launches", "qw_batch_readout", "qw_batch_set_schedule",
-           "qw_batch_autotune"]
+           "qw_batch_autotune", "qw_batch_set_replay", "qw_batch_launch_plan"]
 
 
 class QwCsr(C.Structure):
@@ -112,6 +112,8 @@ def lib():
         L.qw_batch_readout.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
         L.qw_batch_set_schedule.argtypes = [vp, C.c_int32, C.c_int32]
         L.qw_batch_autotune.argtypes = [vp, C.c_int32, vp, i32p, i32p, dp]
+        L.qw_batch_set_replay.argtypes = [vp, C.c_int32]
+        L.qw_batch_launch_plan.argtypes = [vp, C.c_int64, i64p, i64p]
         L.qw_last_error.restype = C.c_char_p
         L.qw_version.restype = C.c_char_p
         for name in EXPORTS:
@@ -253,6 +255,16 @@ def qw_batch_readout(batch, slot: int, d_p, d_norm, d_pmarked, stream: int) -> N
 
 def qw_batch_set_schedule(batch, rows_per_tile: int, xcd_aware: int) -> None:
     check(lib().qw_batch_set_schedule(batch, rows_per_tile, xcd_aware), "qw_batch_set_schedule")
+
+
+def qw_batch_set_replay(batch, use_graph: int) -> None:
+    check(lib().qw_batch_set_replay(batch, use_graph), "qw_batch_set_replay")
+
+
+def qw_batch_launch_plan(batch, launches: int) -> tuple[int, int]:
+    g, d = C.c_int64(), C.c_int64()
+    check(lib().qw_batch_launch_plan(batch, launches, C.byref(g), C.byref(d)), "qw_batch_launch_plan")
+    return g.value, d.value
 
 
 def qw_batch_autotune(batch, reps: int, stream: int):

@@ -50,6 +50,7 @@ struct qw_batch {
   int32_t capacity = 0, max_tiles = 0, dtype = QW_C64;
   int32_t rows_per_tile = 1024;
   bool xcd_aware = true;
+  bool use_graph = true;  // qw_batch_run replays captured launches (else launches each directly)
   int grid = 8;
   // host staging
   std::vector<WalkSlot> slots;
@@ -435,8 +436,9 @@ int qw_batch_run(qw_batch *b, int64_t launches, void *stream) {
   if (st != QW_OK) return st;
   if (launches < 0) return set_error(QW_EINVAL, "negative launch count");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int64_t left = launches;
-  if (left >= kGraphChunk) {
+  int64_t replays = 0, direct = 0;
+  qw_batch_launch_plan(b, launches, &replays, &direct);
+  if (replays > 0) {
     if (!b->exec) {
       hipGraph_t g = nullptr;
       QW_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed), "batch graph capture begin");
@@ -452,13 +454,25 @@ int qw_batch_run(qw_batch *b, int64_t launches, void *stream) {
         return dev_fail(ie, "batch graph instantiate");
       }
     }
-    while (left >= kGraphChunk) {
-      QW_TRY(hipGraphLaunch(b->exec, s), "batch graph launch");
-      left -= kGraphChunk;
-    }
+    for (int64_t i = 0; i < replays; ++i) QW_TRY(hipGraphLaunch(b->exec, s), "batch graph launch");
   }
-  for (; left > 0; --left) QW_TRY(launch_one(b, s), "batched stage kernel");
+  for (int64_t i = 0; i < direct; ++i) QW_TRY(launch_one(b, s), "batched stage kernel");
   b->L_host += static_cast<uint64_t>(launches);
+  return clear_error();
+}
+
+int qw_batch_set_replay(qw_batch *b, int32_t use_graph) {
+  if (!b) return set_error(QW_EINVAL, "null batch");
+  b->use_graph = use_graph != 0;
+  return clear_error();
+}
+
+int qw_batch_launch_plan(const qw_batch *b, int64_t launches, int64_t *graph_replays, int64_t *direct_launches) {
+  if (!b) return set_error(QW_EINVAL, "null batch");
+  if (launches < 0) return set_error(QW_EINVAL, "negative launch count");
+  const int64_t replays = b->use_graph ? launches / kGraphChunk : 0;
+  if (graph_replays) *graph_replays = replays;
+  if (direct_launches) *direct_launches = launches - replays * kGraphChunk;
   return clear_error();
 }
 

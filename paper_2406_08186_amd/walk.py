@@ -259,6 +259,10 @@ class Batch:
     def run(self, launches: int, stream=None) -> None:
         L.qw_batch_run(self._b, int(launches), _stream_ptr(stream, self.device))
 
+    def set_replay(self, use_graph: bool) -> None:
+        """Graph replay (default) or direct launches for qw_batch_run (same kernels and results)."""
+        L.qw_batch_set_replay(self._b, int(bool(use_graph)))
+
     def remaining(self, slot: int) -> int:
         return L.qw_batch_remaining(self._b, slot)
 

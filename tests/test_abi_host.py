@@ -210,6 +210,26 @@ def test_batch_host_side():
     assert lib.qw_batch_destroy(None) == L.QW_OK
 
 
+def test_batch_direct_launch_mode_issues_no_graph_replay():
+    """With replay off, qw_batch_run issues every launch directly (what
+    counter collection needs); with it on (the default), whole groups of 16
+    launches go out as graph replays and the rest directly."""
+    lib = L.lib()
+    b = L.qw_batch_create(4, 100, L.QW_C64)
+    assert L.qw_batch_launch_plan(b, 0) == (0, 0)
+    assert L.qw_batch_launch_plan(b, 15) == (0, 15)
+    assert L.qw_batch_launch_plan(b, 16) == (1, 0)
+    assert L.qw_batch_launch_plan(b, 1003) == (62, 11)
+    L.qw_batch_set_replay(b, 0)
+    for n in (0, 1, 16, 1003, 25046):
+        assert L.qw_batch_launch_plan(b, n) == (0, n)
+    L.qw_batch_set_replay(b, 1)
+    assert L.qw_batch_launch_plan(b, 32) == (2, 0)
+    assert lib.qw_batch_launch_plan(b, -1, None, None) == L.QW_EINVAL
+    assert lib.qw_batch_set_replay(None, 0) == L.QW_EINVAL
+    L.qw_batch_destroy(b)
+
+
 def test_dense_layout_plans():
     g = I.complete(50)
     p = _create(g, kind=1, dtype=1, layout=L.QW_LAYOUT_DENSE, gamma=0.02, dt=0.3, taylor_order=10,

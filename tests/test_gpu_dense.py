@@ -96,3 +96,36 @@ def test_dense_complete_graph_search(dtype, tol):
     torch.cuda.synchronize()
     assert abs(float(pm) - 2.0) < 2 * tol  # both columns reach p_w = 1
     assert abs(cf.complete_search_prob(n, t) - 1.0) < 1e-15
+
+
+WIDE = {
+    # n = 301: two k splits of 160 (the split-k partial products and their reduction)
+    "er301": (I.erdos_renyi(301, 0.3, seed=3), [0, 300]),
+    # n = 2100: eight k splits of 288, so the FP32 products fold into FP64 inside a split
+    "er2100": (I.erdos_renyi(2100, 0.02, seed=21), [5, 2099]),
+}
+
+
+@pytest.mark.parametrize("name", list(WIDE))
+@pytest.mark.parametrize("columns", [12, 16, 20, 32, 100, 128])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_dense_wide_tiles(name, columns, dtype):
+    """Every accumulator width of the matrix-core stage: 9-16 columns (two
+    16-wide real tiles), 17-32 (four), 65-128 (sixteen), full and ragged,
+    each walk against the oracle run on its own initial state (the dense
+    product that the paper times, Sec. 4.6.1, inside the Taylor step of
+    Sec. 3.1)."""
+    g, marked = WIDE[name]
+    dmax = int(np.diff(g.row_ptr).max())
+    gamma = 1.0 / dmax
+    steps, K, dt = 4, 12, 0.3
+    states, got, p, norm, pm = _dense_run(g, columns, dtype, gamma, dt, K, steps, marked, seed=50)
+    for b in range(columns):
+        ref = oracle.ctqw_evolve(g.row_ptr, g.col, states[:, b], steps, gamma=gamma, dt=dt, K=K, marked=marked)
+        if dtype == "c128":
+            assert np.abs(got[:, b] - ref).max() < 1e-12, b
+            assert np.abs(p[:, b] - np.abs(ref) ** 2).max() < 1e-12, b
+        else:
+            assert np.linalg.norm(got[:, b] - ref) < 1e-5, b
+    assert abs(norm - columns) < (1e-10 if dtype == "c128" else 1e-4)
+    assert abs(pm - p[marked, :].sum()) < 1e-11

@@ -258,6 +258,42 @@ def test_ctqw_torus_blocked(l1, l2, K, dtype, depth):
     assert abs(float(pm) - (np.abs(ref[marked]) ** 2).sum()) < (1e-12 if dtype == "c128" else 1e-6)
 
 
+@pytest.mark.parametrize("l1,l2,K,dtype,depth", [
+    (64, 64, 20, "c128", 5), (50, 130, 15, "c128", 5), (64, 96, 12, "c128", 4),
+    (64, 64, 20, "c64", 5), (96, 64, 15, "c64", 5), (64, 128, 12, "c64", 4),
+])
+def test_ctqw_torus_blocked_every_stage(l1, l2, K, dtype, depth):
+    """The blocked grid sweep at rho = dt ||H||_inf = 5 (gamma 1 with marks,
+    dt 1; the spectral radius of H is about 4): the Taylor terms of the
+    Sec. 3.1 propagator up to k = 20 are then all far above the tolerance
+    (4^20/20! = 4.5e-7), so a wrong coefficient, buffer or skipped stage in
+    any launch of a time step, including the first ones (k = K..K-2S+1),
+    moves the result out of it.  The order K-1 propagator is shown to
+    differ from order K by more than the tolerance."""
+    from paper_2406_08186_amd.walk import Plan
+    g = I.torus(l1, l2)
+    marked = sorted({0, 8 * l2 + 53, g.n // 2 + 7, g.n - 1})
+    gamma, dt, steps = 1.0, 1.0, 3
+    psi0 = I.random_state(g.n, seed=l1 * l2 + K)
+    pl = Plan(g, "ctqw", dtype=dtype, gamma=gamma, dt=dt, taylor_order=K, marked=marked, layout="structured")
+    assert pl.structure == "torus" and pl.info.block_depth == depth
+    assert abs(pl.info.h_norm_bound * dt - 5.0) < 1e-12
+    ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps, gamma=gamma, dt=dt, K=K, marked=marked)
+    ref_short = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps, gamma=gamma, dt=dt, K=K - 1, marked=marked)
+    psi = pl.state(psi0)
+    p, norm, pm = pl.evolve(psi, steps, readout=True)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy().astype(np.complex128)
+    if dtype == "c128":
+        assert np.abs(ref - ref_short).max() > 1e3 * C128_TOL
+        assert np.abs(got - ref).max() < C128_TOL
+        assert abs(float(pm) - (np.abs(ref[marked]) ** 2).sum()) < 1e-12
+    else:
+        assert np.linalg.norm(got - ref) < 1e-5
+        if K < 20:
+            assert np.linalg.norm(ref - ref_short) > 10 * 1e-5
+
+
 def test_zero_steps_is_readout_only():
     g = GRAPHS["rr"]
     psi0 = I.random_state(g.n_arcs, seed=3)

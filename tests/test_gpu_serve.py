@@ -1,11 +1,15 @@
 """GPU test of the serving loop: each job's result is the same alone and
 served (bitwise: batch-lane jobs against a one-slot batch, small- and
 solo-lane jobs against one uninterrupted evolve of the same plan; to rounding
-against the plain CSR path), jobs arriving while others run overlap with
-them, and the device budget is respected."""
+against the plain CSR path), each served result matches the FP64 oracle run
+on the job's own walk (coined steps of Sec. 3.2, Taylor steps of Sec. 3.1;
+complex64 L2 within 1e-5), jobs arriving while others run overlap with them,
+and the device budget is respected."""
 import numpy as np
 import pytest
 import torch
+
+import oracle
 
 from paper_2406_08186_amd.serve import WalkServer, make_job, serve_stream
 
@@ -87,3 +91,17 @@ def test_served_results_equal_alone(solo_arcs, solo_units, idle_solo):
         torch.cuda.synchronize()
         assert np.abs(plain.cpu().numpy() - j.result["psi"]).max() < 1e-5
         assert abs(j.result["norm"] - 1.0) < 1e-5
+        g = j.graph
+        if j.kind == "coined":
+            want = oracle.coined_evolve(g.row_ptr, g.col, j.psi0, j.steps, marked=j.params["marked"])
+            p_want = oracle.coined_prob(g.row_ptr, g.col, want)
+        else:
+            K = int(ref.info.taylor_order)  # the order the truncation rule chose for this job
+            assert K >= 2
+            want = oracle.ctqw_evolve(g.row_ptr, g.col, j.psi0, j.steps, gamma=j.params["gamma"],
+                                      dt=j.params["dt"], K=K, marked=j.params["marked"])
+            p_want = np.abs(want) ** 2
+        served = j.result["psi"].astype(np.complex128)
+        assert np.linalg.norm(served - want) < 1e-5, f"job {j.job_id} ({j.lane}) vs the oracle"
+        assert abs(j.result["p_marked"] - p_want[j.params["marked"]].sum()) < 1e-6
+        assert abs(j.result["norm"] - p_want.sum()) < 1e-6
