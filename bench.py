@@ -1,15 +1,22 @@
 """Benchmark of the quantum-walk step engine on one MI355X.
 
-Workload: continuous-time walk on the periodic 1024 x 1024 grid (N = 2^20
-vertices, 4 * 2^20 arcs), H = -gamma A with gamma = 0.25, Taylor order 20,
-dt = 0.1, started on the single vertex (512, 512).  One bench step is one
-pass of the hot path: 1000 time steps (20 Horner stages each) plus the FP64
-probability readout, on a state already resident in HBM.  The complex64 path
-(FP64 reductions) is the reported value; the complex128 path is timed beside
-it, and both are checked against the closed form (product of cycle Bessel
-sums) at the end.
+Default workload: a batch of 4096 continuous-time quantum-walk searches on
+seeded random d-regular graphs (N log-uniform in [1e3, 2e5], d uniform in
+3..8, gamma = 1/d, one uniformly drawn marked vertex, uniform start, total
+time 2 sqrt(N); time step and Taylor order from the truncation rule at
+rho <= 1 and tolerance 1e-8), all advanced together in complex64 by the
+batched kernel with an FP64 p_marked history per step.  One bench step is a
+fixed chunk of batch launches (--launches-per-step); each launch advances
+every active walk by one Horner stage.  After the timed chunks every walk's
+state holds its last completed time step; a seeded sample of walks is then
+checked against the FP64 oracle (final-state L2 and norm drift), the same
+walks are run alone on the single-walk path in complex64 (must equal the
+batch bitwise) and complex128 (must match the oracle to 1e-12), and a
+second sample is timed one walk at a time in both precisions (the plain
+form the batch is compared with).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py --workload grid      # 1024^2 grid CTQW, complex64 and complex128
 
 Prints one JSON line.
 """
@@ -32,12 +39,10 @@ DT = 0.1
 K_ORDER = 20
 STEPS_PER_PASS = 1000
 METRIC = "arc-steps/s (c64 batched vs c128 plain, L2 err<=1e-4); p50/p99 latency"
-# HBM bytes per launch of the grid kernel (1024 x 1024, c64, 10-row strips, two
-# wavefronts per SIMD, averaged over the four launches of a time step) measured
-# with rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a 256 MiB copy (x2.00 /
-# x1.00); profiles/ctqw_torus1024_sweep.md.  Valid only for the kernel version
-# and strip geometry named here; None for any other.
-MEASURED_TRAFFIC = {"k_ctqw_torus_sweep<float2,5>": ((4571.5 + 3 * 8972.9) / 4 * 2 + 8193.3) * 1024}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
+# 256 MiB copy (x2.00 / x1.00).  Each entry holds only for the kernel version
+# and launch configuration named in its key and source; any other reports None.
+MEASURED_TRAFFIC = {}
 
 
 def parse():
@@ -54,15 +59,33 @@ def parse():
     ap.add_argument("--dtypes", default="c64,c128")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
-    ap.add_argument("--workload", default="grid",
+    ap.add_argument("--workload", default="batch",
                     choices=["grid", "batch", "serve", "dense", "hypercube", "cycle", "snapshots", "staggered",
-                             "lattice", "sparse"],
-                    help="grid: the 1024^2 CTQW (default); batch: many CTQW searches on random "
-                         "regular graphs in one batch; serve: the Poisson job stream")
+                             "lattice", "sparse", "streamed"],
+                    help="batch: 4096 CTQW searches on random regular graphs in one batch (default); "
+                         "grid: the 1024^2 CTQW; serve: the Poisson job stream")
     ap.add_argument("--batch-walks", type=int, default=4096)
     ap.add_argument("--batch-seed", type=int, default=1)
-    ap.add_argument("--plain-sample", type=int, default=32,
-                    help="walks of the batch also run one at a time on the single-walk path")
+    ap.add_argument("--launches-per-step", type=int, default=256,
+                    help="batch: launches (one Horner stage of every active walk each) per bench step")
+    ap.add_argument("--graph-cache", default="",
+                    help="batch: directory to read the drawn graphs from, or to write them to")
+    ap.add_argument("--direct-launch", action="store_true",
+                    help="batch: launch each stage directly instead of replaying captured hipGraphs")
+    ap.add_argument("--stage-kernel", default="auto", choices=["auto", "lds", "gather"],
+                    help="batch: kernel for the walks' Horner stages (auto: the autotuner's choice)")
+    ap.add_argument("--oracle-walks", type=int, default=16, help="batch: walks checked against the oracle")
+    ap.add_argument("--oracle-budget", type=float, default=2.5e10,
+                    help="batch: bound on the oracle sample's work (time steps x K x arcs)")
+    ap.add_argument("--plain-sample", type=int, default=16,
+                    help="walks of the batch also run one at a time on the single-walk path (timed)")
+    ap.add_argument("--stream-n", type=int, default=2**21, help="streamed workload: vertices")
+    ap.add_argument("--stream-degree", type=int, default=32, help="streamed workload: mean degree")
+    ap.add_argument("--stream-steps", type=int, default=3, help="streamed workload: timed time steps")
+    ap.add_argument("--stream-budget-mib", type=int, default=64,
+                    help="streamed workload: device MiB for the streamed graph beyond state and workspace")
+    ap.add_argument("--gen-only", action="store_true",
+                    help="batch: only draw the graphs into --graph-cache (no GPU) and exit")
     ap.add_argument("--serve-jobs", type=int, default=120)
     ap.add_argument("--serve-rates", default="0.5,0.9",
                     help="arrival rates as fractions of the measured saturated capacity")
@@ -171,6 +194,9 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
+    if args.gen_only:
+        batch_walks(args)
+        return
     if args.workload == "batch":
         run_batch(args)
         return
@@ -198,6 +224,19 @@ def main():
     if args.workload == "sparse":
         run_sparse(args)
         return
+    if args.workload == "grid":
+        run_grid(args)
+        return
+    if args.workload == "streamed":
+        run_streamed(args)
+        return
+    raise SystemExit(f"unknown workload {args.workload}")
+
+
+def run_grid(args):
+    """The 1024 x 1024 grid CTQW (gamma 0.25, K 20, dt 0.1, from vertex (512, 512)):
+    passes of 1000 time steps plus the FP64 readout, complex64 and complex128,
+    both checked against the closed form (product of cycle Bessel sums)."""
     spp = args.steps_per_pass
     dtypes = args.dtypes.split(",")
     import numpy as np
@@ -223,10 +262,16 @@ def main():
         # algorithmic bytes of one row-stage of the matrix-free grid stencil: read y,
         # read psi, write y' (3 S); one launch runs block_depth stages of every row
         depth = int(pl.info.block_depth)
-        bytes_per_launch = depth * 3 * es * g.n
+        # bytes a launch must move: read y_in and psi, write y_out (3 S per row);
+        # the first launch of a time step reads psi as y_in (2 S).  Averaged over
+        # the K / depth launches of a step.
+        lps = max(1, K_ORDER // depth)
+        bytes_per_launch = (3 * lps - 1) / lps * es * g.n
+        stage_model_bytes = depth * 3 * es * g.n
         res[dtype] = dict(plan=pl, wall=wall, per=per, norm=float(norm), state=state,
                           total_steps=total_steps, launch_ms=launch_ms,
-                          bytes_per_launch=bytes_per_launch, structure=pl.structure,
+                          bytes_per_launch=bytes_per_launch, stage_model_bytes=stage_model_bytes,
+                          structure=pl.structure,
                         depth=depth)
         del psi
     t_final = res[dtypes[0]]["total_steps"] * DT
@@ -249,10 +294,7 @@ def main():
     achieved = r64["bytes_per_launch"] / (r64["launch_ms"] * 1e-3) / 1e9
     kname = (f"k_ctqw_torus_sweep<float2,{r64['depth']}>" if r64["depth"] > 1
              else "k_ctqw_struct<float2,TORUS>")
-    # counters were taken on the 1024 x 1024 grid; per launch they scale with the rows
-    traffic = MEASURED_TRAFFIC.get(kname)
-    if traffic is not None:
-        traffic *= g.n / (L_SIDE * L_SIDE)
+    traffic = MEASURED_TRAFFIC.get(f"{kname} {side}x{side}")
     line = {
         "metric": METRIC,
         "value": rate(r64),
@@ -276,7 +318,8 @@ def main():
         "c128": {"value": rate(r128), "ms_per_step": r128["wall"] / args.steps * 1e3,
                  "p50_ms": pct(r128["per"], 50), "p99_ms": pct(r128["per"], 99),
                  "stage_launch_ms": r128["launch_ms"],
-                 "stage_gbs": r128["bytes_per_launch"] / (r128["launch_ms"] * 1e-3) / 1e9,
+                 "launch_gbs": r128["bytes_per_launch"] / (r128["launch_ms"] * 1e-3) / 1e9,
+                 "launch_frac": r128["bytes_per_launch"] / (r128["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "l2_vs_closed_form": l2_128},
         "speedup_c64_vs_c128": rate(r64) / rate(r128),
         "l2_c64_vs_closed_form": l2_64,
@@ -289,19 +332,18 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": r64["bytes_per_launch"],
                      "launch_ms": r64["launch_ms"],
-                     "dram_gbs": None if traffic is None else traffic / (r64["launch_ms"] * 1e-3) / 1e9,
-                     "dram_frac": None if traffic is None else traffic / (r64["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "note": ("achieved counts the per-stage model bytes (read y, read psi, write y per "
-                              "row and stage) of every stage the launch runs; with several stages per "
-                              "launch kept in registers the DRAM traffic is a fraction of that, so frac "
-                              "can pass 1; dram_gbs is the measured traffic over the launch time")},
+                     "stage_model_gbs": r64["stage_model_bytes"] / (r64["launch_ms"] * 1e-3) / 1e9,
+                     "note": ("achieved counts the bytes one launch must move (psi and y_in read, y_out "
+                              "written; psi doubles as y_in in the first launch of a step); "
+                              "stage_model_gbs counts 3 S per row for every stage the launch runs, "
+                              "which several stages per launch in registers avoid moving")},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, v0, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
-# ---------------------------------------------------------------- batch workload
+# ---------------------------------------------------------------- batch workload (default)
 
 def _gen_regular(spec):
     from paper_2406_08186_amd import inputs as I
@@ -309,56 +351,106 @@ def _gen_regular(spec):
     return g.row_ptr, g.col
 
 
-def run_batch(args):
-    """Many CTQW searches on random d-regular graphs advanced in one batch.
-
-    Walk i: N log-uniform in [1e3, 2e5], d uniform in 3..8, gamma = 1/d, one
-    uniformly drawn marked vertex, uniform start, total time 2 sqrt(N); step
-    count and Taylor order from the truncation rule (rho <= 1, tolerance 1e-8
-    over the whole walk); complex64 with FP64 readouts and a per-step
-    p_marked history.
-    """
+def batch_csrs(args, specs):
+    """CSR arrays of the batch's graphs: drawn from their seeds in worker
+    processes, or read back from --graph-cache when that directory holds this
+    batch (it is written there after drawing).  Returns (list of (row_ptr,
+    col), source)."""
     import multiprocessing as mp
-    from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
-
-    from paper_2406_08186_amd import inputs as I
-    specs = I.batch_regular_specs(args.batch_walks, seed=args.batch_seed)
-    t0 = time.perf_counter()
-    if args.workers <= 1:  # serial (e.g. under a profiler, which should not see forked workers)
+    key = {"walks": len(specs), "seed": args.batch_seed, "format": 1}
+    cache = args.graph_cache
+    if cache and os.path.exists(os.path.join(cache, "meta.json")):
+        with open(os.path.join(cache, "meta.json")) as f:
+            meta = json.load(f)
+        if meta.get("key") == key:
+            rp_all = np.load(os.path.join(cache, "row_ptr.npy"), mmap_mode="r")
+            col_all = np.load(os.path.join(cache, "col.npy"), mmap_mode="r")
+            ro, co = meta["rp_off"], meta["col_off"]
+            return [(np.asarray(rp_all[ro[i]:ro[i + 1]]), np.asarray(col_all[co[i]:co[i + 1]]))
+                    for i in range(len(specs))], "cache"
+    if args.workers <= 1:
         csrs = [_gen_regular(sp) for sp in specs]
     else:
         with mp.get_context("fork").Pool(min(args.workers, os.cpu_count() or 1)) as pool:
             csrs = pool.map(_gen_regular, specs, chunksize=4)
-    gen_s = time.perf_counter() - t0
-    print(f"[batch] generated {len(specs)} graphs in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    if cache:
+        os.makedirs(cache, exist_ok=True)
+        ro = np.cumsum([0] + [rp.size for rp, _ in csrs]).tolist()
+        co = np.cumsum([0] + [c.size for _, c in csrs]).tolist()
+        np.save(os.path.join(cache, "row_ptr.npy"), np.concatenate([rp.astype(np.int64) for rp, _ in csrs]))
+        np.save(os.path.join(cache, "col.npy"), np.concatenate([c.astype(np.int32) for _, c in csrs]))
+        with open(os.path.join(cache, "meta.json"), "w") as f:
+            json.dump({"key": key, "rp_off": ro, "col_off": co}, f)
+    return csrs, "generated"
 
-    import torch
 
+def batch_walks(args):
+    """Specs, graphs and (K, dt, steps) schedules of the batch."""
     from paper_2406_08186_amd import _lib as L
-    from paper_2406_08186_amd.walk import Batch, Plan
+    from paper_2406_08186_amd import inputs as I
+    specs = I.batch_regular_specs(args.batch_walks, seed=args.batch_seed)
+    t0 = time.perf_counter()
+    csrs, src = batch_csrs(args, specs)
+    gen_s = time.perf_counter() - t0
+    print(f"[batch] {len(specs)} graphs {src} in {gen_s:.1f} s", file=sys.stderr, flush=True)
     graphs = [I.Graph(n=sp["n"], row_ptr=rp, col=cl, name=f"rr{i}") for i, (sp, (rp, cl)) in
               enumerate(zip(specs, csrs))]
     sched = []
     for sp in specs:
-        hb = sp["gamma"] * sp["d"] + 1.0
-        K, dt, steps = L.qw_taylor_plan(hb, sp["t_final"], 1.0, 1e-8)
+        # ||H||_inf = gamma d + 1 (the marked vertex); rho <= 1, tolerance 1e-8 over the whole walk
+        K, dt, steps = L.qw_taylor_plan(sp["gamma"] * sp["d"] + 1.0, sp["t_final"], 1.0, 1e-8)
         sched.append((K, dt, steps))
+    return specs, graphs, sched, gen_s
 
-    def mk(i):
-        sp = specs[i]
-        K, dt, steps = sched[i]
-        return Plan(graphs[i], "ctqw", dtype="c64", layout="structured", gamma=sp["gamma"], dt=dt,
-                    taylor_order=K, marked=[sp["marked"]], upload=False)
+
+def _walk_plan(graph, spec, sched, dtype, upload=True):
+    from paper_2406_08186_amd.walk import Plan
+    K, dt, _ = sched
+    return Plan(graph, "ctqw", dtype=dtype, layout="structured", gamma=spec["gamma"], dt=dt,
+                taylor_order=K, marked=[spec["marked"]], upload=upload)
+
+
+def oracle_sample(args, graphs, sched, done_steps):
+    """Seeded sample of walks for the oracle check, bounded by an estimate of
+    the oracle's work (steps x K x arcs summed over the sample)."""
+    import numpy as np
+    rng = np.random.default_rng(args.batch_seed + 7)
+    budget = args.oracle_budget
+    out = []
+    for i in rng.permutation(len(graphs)).tolist():
+        cost = done_steps[i] * sched[i][0] * max(1, graphs[i].n_arcs)
+        if done_steps[i] > 0 and cost <= budget:
+            out.append(i)
+            budget -= cost
+        if len(out) >= args.oracle_walks:
+            break
+    return out
+
+
+def run_batch(args):
+    """The default bench line: the 4096-walk CTQW search batch (module docstring)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    specs, graphs, sched, gen_s = batch_walks(args)
+
+    import torch
+
+    import oracle
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Batch
 
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max(1, args.workers)) as ex:
-        plans = list(ex.map(mk, range(len(specs))))
+        plans = list(ex.map(lambda i: _walk_plan(graphs[i], specs[i], sched[i], "c64", upload=False),
+                            range(len(specs))))
     plan_s = time.perf_counter() - t0
     total_rows = sum(g.n for g in graphs)
-    # tiles at 256 rows each, plus the XCD padding (8 lists, each at most the mean plus the
-    # largest walk's tiles under longest-first placement)
+    # tiles at 256 rows or more, plus the XCD padding (8 lists, each at most the
+    # mean plus the largest walk's tiles under longest-first placement)
     max_tiles = total_rows // 256 + len(graphs) + 8 * (max(g.n for g in graphs) // 256 + 1) + 64
     batch = Batch(capacity=len(plans), max_tiles=max_tiles, dtype="c64")
     states, hists = [], []
@@ -369,68 +461,160 @@ def run_batch(args):
         batch.set_slot(i, pl, psi, sched[i][2], hist=hist)
         states.append(psi)
         hists.append(hist)
+    if args.stage_kernel != "auto":
+        batch.set_stage_kernel(args.stage_kernel)
     batch.commit()
-    rows, xcd, probe_ms = batch.autotune(reps=2)
+    if args.direct_launch:
+        batch.set_replay(False)
+    if args.stage_kernel == "auto":
+        rows, xcd, _ = batch.autotune(reps=2)
+    sched_now = batch.schedule()
+    rows, xcd, stage_kernel = sched_now["rows_per_tile"], sched_now["xcd_aware"], sched_now["stage_kernel"]
     torch.cuda.synchronize()
-    launches = max(batch.remaining(i) for i in range(len(plans)))
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    print(f"[batch] plans built in {plan_s:.1f} s; schedule {rows} rows/tile, xcd {bool(xcd)}",
+          file=sys.stderr, flush=True)
+
+    units = np.array([batch.remaining(i) for i in range(len(plans))], dtype=np.int64)
+    Ks = np.array([s[0] for s in sched], dtype=np.int64)
+    A = np.array([g.n_arcs for g in graphs], dtype=np.float64)
+    Nv = np.array([g.n for g in graphs], dtype=np.float64)
+    D = np.array([sp["d"] for sp in specs], dtype=np.float64)
+    CH = args.launches_per_step
+    total = int(units.max())
+    if (args.warmup + args.steps) * CH > total:
+        CH = max(1, total // (args.warmup + args.steps))
+        print(f"[batch] launches per step cut to {CH} to stay inside one pass", file=sys.stderr, flush=True)
+
+    def finished_between(la, lb):
+        return [i for i in range(len(plans)) if la < units[i] <= lb]
+
+    for _ in range(args.warmup):
+        la = batch.launches
+        batch.run(CH)
+        for i in finished_between(la, batch.launches):
+            batch.readout(i)
+    torch.cuda.synchronize()
+    La = batch.launches
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t0 = time.perf_counter()
-    ev0.record()
-    batch.run(launches)
-    ev1.record()
+    for k in range(args.steps):
+        la = batch.launches
+        ev[k][0].record()
+        batch.run(CH)
+        ev[k][1].record()
+        for i in finished_between(la, batch.launches):  # fused-path readout of walks that just ended
+            batch.readout(i)
+        ev[k][2].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    arc_steps = sum(g.n_arcs * sc[2] for g, sc in zip(graphs, sched))
-    arc_spmv = sum(g.n_arcs * sc[2] * sc[0] for g, sc in zip(graphs, sched))
-    # algorithmic bytes per row-stage on the ELL layout (no row pointers): 4d of
-    # neighbour indices + 3 x 8 (the gathered vector once with ideal reuse, psi, y')
-    alg_bytes = sum(g.n * (4 * sp["d"] + 24) * sc[2] * sc[0] for g, sp, sc in zip(graphs, specs, sched))
-    pm_final, pm_peak = [], []
-    for i in range(len(plans)):
-        _, norm, pm = batch.readout(i)
-        pm_final.append(float(pm))
-    for h in hists:
-        pm_peak.append(float(h.max()))
-    torch.cuda.synchronize()
-    drift = max(abs(float(batch.readout(i)[1]) - 1.0) for i in range(0, len(plans), max(1, len(plans) // 64)))
-    # plain form on a sample: one walk at a time on the single-walk path
-    stride = max(1, len(plans) // max(1, args.plain_sample))
-    sample = list(range(0, len(plans), stride))[:args.plain_sample]
-    plain_as, plain_t, maxdiff = 0, 0.0, 0.0
+    Lb = batch.launches
+    print(f"[batch] timed launches {La}..{Lb} in {wall:.2f} s", file=sys.stderr, flush=True)
+    run_ms = sum(e[0].elapsed_time(e[1]) for e in ev)
+    per = sorted(e[0].elapsed_time(e[2]) for e in ev)
+    stages = np.clip(Lb, 0, units) - np.clip(La, 0, units)
+    arc_steps = float((A * stages / Ks).sum())
+    alg_bytes = float((Nv * (4 * D + 24) * stages).sum())
+    active_start = int((units > La).sum())
+    active_end = int((units > Lb).sum())
+    launches = args.steps * CH
+    launch_ms = run_ms / launches
+
+    # ---- parity on a seeded sample: oracle (FP64), the walk alone in c64 and c128
+    done = np.minimum(Lb, units) // Ks
+    sample = oracle_sample(args, graphs, sched, done)
+    l2s, drifts, c128_err, c64_alone_diff, oracle_s, oracle_as = [], [], [], [], 0.0, 0.0
     for i in sample:
-        pl = Plan(graphs[i], "ctqw", dtype="c64", layout="structured", gamma=specs[i]["gamma"], dt=sched[i][1],
-                  taylor_order=sched[i][0], marked=[specs[i]["marked"]])
-        psi = pl.state(I.uniform(graphs[i].n))
-        torch.cuda.synchronize()
+        g, sp, (K, dt, _) = graphs[i], specs[i], sched[i]
+        c = int(done[i])
+        got = states[i].cpu().numpy().astype(np.complex128)
         t1 = time.perf_counter()
-        pl.evolve(psi, sched[i][2])
-        torch.cuda.synchronize()
-        plain_t += time.perf_counter() - t1
-        plain_as += graphs[i].n_arcs * sched[i][2]
-        maxdiff = max(maxdiff, float((psi - states[i]).abs().max()))
-        pl.close()
+        ref = oracle.ctqw_evolve(g.row_ptr, g.col, I.uniform(g.n), c, gamma=sp["gamma"], dt=dt, K=K,
+                                 marked=[sp["marked"]])
+        oracle_s += time.perf_counter() - t1
+        oracle_as += g.n_arcs * c
+        l2s.append(float(np.linalg.norm(got - ref)))
+        drifts.append(abs(float(np.sum(np.abs(got) ** 2)) - 1.0))
+        for dtype in ("c64", "c128"):
+            pl = _walk_plan(g, sp, sched[i], dtype)
+            x = pl.state(I.uniform(g.n))
+            pl.evolve(x, c)
+            if dtype == "c64":
+                c64_alone_diff.append(float((x - states[i]).abs().max()))
+            else:
+                c128_err.append(float(np.abs(x.cpu().numpy() - ref).max()))
+            del x
+            pl.close()
+
+    print(f"[batch] parity on {len(sample)} walks; oracle {oracle_s:.1f} s", file=sys.stderr, flush=True)
+
+    # ---- the plain form: one walk at a time on the single-walk path, whole walks
+    stride = max(1, len(plans) // max(1, args.plain_sample))
+    psample = list(range(0, len(plans), stride))[:args.plain_sample]
+    plain = {}
+    for dtype in ("c64", "c128"):
+        as_, secs = 0.0, 0.0
+        for i in psample:
+            pl = _walk_plan(graphs[i], specs[i], sched[i], dtype)
+            x = pl.state(I.uniform(graphs[i].n))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pl.evolve(x, sched[i][2])
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t1
+            as_ += graphs[i].n_arcs * sched[i][2]
+            del x
+            pl.close()
+        print(f"[batch] plain form {dtype}: {len(psample)} walks in {secs:.1f} s", file=sys.stderr, flush=True)
+        plain[dtype] = {"value": as_ / secs if secs > 0 else None, "unit": "arc-steps/s",
+                        "walks": len(psample), "seconds": secs}
+
+    value = arc_steps / wall
+    l2_max = max(l2s) if l2s else None
+    kname = "k_batch_ell_lds<float2,1024,4,16384>" if stage_kernel == "lds" else "k_batch_stage<float2>"
+    traffic_key = f"{kname} batch{len(plans)} seed{args.batch_seed} launches{La}-{Lb}"
+    traffic = MEASURED_TRAFFIC.get(traffic_key)
     line = {
-        "metric": METRIC, "value": arc_steps / wall, "unit": "arc-steps/s", "n_gpus": 1,
-        "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
-        "config": {"workload": f"batch_{len(plans)}_ctqw_search_random_regular", "walks": len(plans),
-                   "path": sorted({pl.structure for pl in plans}),
-                   "total_vertices": total_rows, "total_arcs": sum(g.n_arcs for g in graphs),
-                   "launches": launches, "rows_per_tile": rows, "xcd_aware": bool(xcd),
+        "metric": METRIC, "value": value, "unit": "arc-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"batch_{len(plans)}_ctqw_search_random_regular_c64",
+                   "walks": len(plans), "n_range": [1e3, 2e5], "degree_range": [3, 8],
+                   "total_vertices": total_rows, "total_arcs": int(A.sum()),
+                   "launches_per_step": CH, "launches_per_pass": total,
+                   "timed_launches": [La, Lb], "walks_active_at_start": active_start,
+                   "walks_active_at_end": active_end,
+                   "path": sorted({pl.structure for pl in plans}), "stage_kernel": stage_kernel,
+                   "rows_per_tile": rows,
+                   "xcd_aware": bool(xcd), "replay": "direct" if args.direct_launch else "hipgraph",
                    "graph_gen_s": gen_s, "plan_build_s": plan_s, "parallelism": "single-gpu"},
-        "arc_spmv_per_s": arc_spmv / wall,
-        "gpu_ms": gpu_ms,
-        "roofline": {"bound": "hbm", "kernel": "k_batch_stage<float2>", "achieved": alg_bytes / (gpu_ms * 1e-3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": alg_bytes / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_total": alg_bytes, "launches": launches},
-        "plain_one_walk_per_launch": {"value": plain_as / plain_t, "unit": "arc-steps/s",
-                                      "walks": len(sample), "max_abs_diff_vs_batch": maxdiff},
-        "speedup_vs_plain": (arc_steps / wall) / (plain_as / plain_t),
-        "p_marked_peak_mean": float(np.mean(pm_peak)), "p_marked_final_mean": float(np.mean(pm_final)),
-        "norm_drift_max_sampled": drift,
+        "arc_spmv_per_s": float((A * stages).sum()) / wall,
+        "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+        "parity": {"walks": len(sample), "steps_checked": [int(done[i]) for i in sample],
+                   "l2_vs_oracle_max": l2_max, "l2_gate": 1e-4,
+                   "l2_gate_pass": l2_max is not None and l2_max <= 1e-4,
+                   "norm_drift_max": max(drifts) if drifts else None,
+                   "c64_alone_vs_batch_max_abs_diff": max(c64_alone_diff) if c64_alone_diff else None,
+                   "c128_plain_vs_oracle_max_abs": max(c128_err) if c128_err else None,
+                   "c128_gate": 1e-12},
+        "c128_plain": plain["c128"], "c64_plain": plain["c64"],
+        "speedup_vs_c128_plain": value / plain["c128"]["value"] if plain["c128"]["value"] else None,
+        "speedup_vs_c64_plain": value / plain["c64"]["value"] if plain["c64"]["value"] else None,
+        "roofline": {"bound": "hbm", "kernel": kname,
+                     "achieved": alg_bytes / (run_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg_bytes / (run_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": alg_bytes / launches, "launch_ms": launch_ms,
+                     "note": "algorithmic bytes per row-stage on the ELL layout: 4d neighbour indices + "
+                             "8 (the gathered vector once) + 8 (psi) + 8 (y out); launch_ms from HIP events "
+                             "around the timed batch launches on their stream"},
     }
+    if not args.no_cpu_baseline and sample:
+        line["cpu_baseline"] = {
+            "value": oracle_as / oracle_s, "unit": "arc-steps/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{len(sample)} walks of the batch (seeded choice), each from the uniform state for the "
+                      f"time steps it completed in the GPU run ({sum(int(done[i]) for i in sample)} steps, "
+                      f"{oracle_as:.3g} arc-steps): FP64 power-form Taylor, the same K and dt",
+            "seconds": oracle_s}
     print(json.dumps(line), flush=True)
 
 
@@ -912,6 +1096,98 @@ def run_sparse(args):
             pl.close()
         out[name] = res
     print(json.dumps({"workload": "ctqw_search_sparse_random_2^20", "steps": steps, **out}), flush=True)
+
+
+# ---------------------------------------------------------------- out-of-core (streamed) CTQW
+
+def run_streamed(args):
+    """Out-of-core CTQW: a CTQW search on G(N, d/(N-1)) whose neighbour table
+    (4 bytes per arc) stays in pinned host memory and streams through a ring of
+    device slots at every Horner stage, under a device budget of the state and
+    workspace plus --stream-budget-mib.  Timed beside the same walk in core
+    (stage kernels only) and a plain copy of the table from pinned memory in the
+    same tiles (copies only): the overlap is the share of the in-core stage
+    time that the streamed run hides behind its copies."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2406_08186_amd import _lib as L
+    from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd.walk import Plan
+
+    n, dbar, steps = args.stream_n, args.stream_degree, args.stream_steps
+    t0 = time.perf_counter()
+    g = I.erdos_renyi(n, dbar / (n - 1), seed=11)
+    print(f"[streamed] graph n={g.n} arcs={g.n_arcs} in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    gamma = 1.0 / dbar
+    dmax = int(np.diff(g.row_ptr).max())
+    dt = 1.0 / (gamma * dmax + 1.0)
+    K = L.qw_taylor_order(1.0, steps, 1e-8)
+    params = dict(gamma=gamma, dt=dt, taylor_order=K, marked=[0])
+    psi0 = I.uniform(g.n)
+    res = {}
+
+    def timed(pl, psi):
+        pl.evolve(psi, 1)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        pl.evolve(psi, steps)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    core = Plan(g, "ctqw", dtype="c64", layout="csr", **params)
+    x = core.state(psi0)
+    ms_core = timed(core, x)
+    core.evolve(x, 0)
+    ref_gpu = x.cpu().numpy()
+    walk = core.info.state_bytes + core.info.work_bytes
+    core.close()
+    del core
+    budget = walk + args.stream_budget_mib * 2**20
+    pl = Plan(g, "ctqw", dtype="c64", layout="csr", upload=False, **params)
+    sizes = pl.upload_streamed(budget)
+    y = pl.state(psi0)
+    ms_stream = timed(pl, y)
+    diff = float(np.abs(y.cpu().numpy() - ref_gpu).max())
+    # copies only: the same bytes in the same tile sizes from pinned memory to a device ring
+    tile_bytes = 4 * g.n_arcs // max(1, sizes["tiles"])
+    ring = torch.empty(3 * max(tile_bytes, 256), dtype=torch.uint8, device="cuda")
+    host = pl.h_graph
+    cs = torch.cuda.Stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(cs):
+        a.record()
+        for _ in range(steps * K):
+            for t in range(sizes["tiles"]):
+                lo = t * tile_bytes
+                hi = min(4 * g.n_arcs, lo + tile_bytes)
+                ring[(t % 3) * tile_bytes:(t % 3) * tile_bytes + (hi - lo)].copy_(host[lo:hi], non_blocking=True)
+        b.record()
+    torch.cuda.synchronize()
+    ms_copy = a.elapsed_time(b)
+    # parity: the streamed state against the oracle (c64 L2)
+    t1 = time.perf_counter()
+    ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps + 1, **{k: v for k, v in params.items()
+                                                                     if k != "taylor_order"}, K=K)
+    l2 = float(np.linalg.norm(y.cpu().numpy().astype(np.complex128) - ref))
+    stages = steps * K
+    line = {"workload": f"ctqw_search_er_{g.n}_d{dbar}_out_of_core", "dtype": "c64", "n": g.n, "arcs": g.n_arcs,
+            "K": K, "steps": steps, "device_budget_bytes": budget, "table_bytes_in_host_memory": 4 * g.n_arcs,
+            "device_graph_bytes": sizes["device_bytes"], "tiles_per_stage": sizes["tiles"],
+            "stage_ms_streamed": ms_stream / stages, "stage_ms_in_core": ms_core / stages,
+            "stage_ms_copies_only": ms_copy / stages,
+            "h2d_gbs_streamed": 4 * g.n_arcs * stages / (ms_stream * 1e-3) / 1e9,
+            "h2d_gbs_copies_only": 4 * g.n_arcs * stages / (ms_copy * 1e-3) / 1e9,
+            "overlap_of_compute": max(0.0, min(1.0, (ms_copy + ms_core - ms_stream) / ms_core)),
+            "arc_steps_per_s_streamed": g.n_arcs * steps / (ms_stream * 1e-3),
+            "arc_steps_per_s_in_core": g.n_arcs * steps / (ms_core * 1e-3),
+            "max_abs_diff_vs_in_core": diff, "l2_vs_oracle": l2, "oracle_s": time.perf_counter() - t1}
+    pl.close()
+    print(json.dumps(line), flush=True)
 
 
 # ---------------------------------------------------------------- 64-cycle latency

@@ -288,6 +288,36 @@ int qw_plan_upload(qw_plan *plan, void *d_graph, size_t graph_bytes, void *strea
 int qw_evolve(const qw_plan *plan, void *d_psi, void *d_work, size_t work_bytes, int64_t steps,
               double *d_p, double *d_norm, double *d_pmarked, void *stream);
 
+/* ---- Out-of-core evolution (Sec. 5: tiling operators larger than device memory)
+ * The paper names, as future work, splitting matrices that exceed device
+ * memory into tiles.  A CTQW plan on the CSR path (QW_LAYOUT_CSR) can keep its
+ * largest table, the neighbour indices (4 bytes per arc), in caller-pinned
+ * host memory: every Horner stage streams them in row tiles through a ring of
+ * three device slots, the copies (on a stream the plan owns) overlapping the
+ * stage kernels of earlier tiles.  The device holds the state, the workspace,
+ * the row pointers, the marked set and the ring.
+ *
+ * qw_plan_stream_sizes: for a device budget (bytes the walk may use on the
+ * device in total: state + info.work_bytes + the streamed graph buffer),
+ * the pinned host bytes (*host_bytes, the neighbour table), the device graph
+ * buffer (*device_bytes, <= budget - state - workspace) and the number of row
+ * tiles streamed per stage.  Host only.  Errors: QW_EUNSUPPORTED (not a CTQW
+ * plan on the CSR path), QW_ENOMEM (the budget does not hold state,
+ * workspace, resident tables and a slot of the largest row), QW_EINVAL.
+ * NULL outputs are skipped. */
+int qw_plan_stream_sizes(const qw_plan *plan, size_t device_budget, size_t *host_bytes, size_t *device_bytes,
+                         int64_t *n_tiles);
+/* Bind the plan for out-of-core evolution with the same budget: copies the
+ * neighbour table into h_pinned (host memory from hipHostMalloc / torch
+ * pin_memory, >= *host_bytes, caller-owned, kept unmodified while bound) and
+ * the resident tables into d_buf (device, >= *device_bytes, 256-byte
+ * aligned) on `stream`; creates the plan's copy stream and ring events.  Ends
+ * any previous binding; qw_plan_upload ends this one.  qw_evolve and
+ * qw_probabilities then work as usual (qw_evolve enqueues the tile copies and
+ * kernels; host calls, no host sync); the plan cannot join a batch. */
+int qw_plan_upload_streamed(qw_plan *plan, size_t device_budget, void *h_pinned, size_t host_bytes, void *d_buf,
+                            size_t device_bytes, void *stream);
+
 /* FP64 readout of a state (Sec. 3.1, Sec. 3.2): d_p[v] = probability of
  * vertex v (coined: summed over arcs with tail v; CTQW and
  * staggered: |psi_v|^2; dense
@@ -398,12 +428,28 @@ int qw_batch_readout(qw_batch *batch, int32_t slot, double *d_p, double *d_norm,
                      void *stream);
 /* Schedule knobs: CTQW rows per tile (64..2^20) and XCD-aware placement. */
 int qw_batch_set_schedule(qw_batch *batch, int32_t rows_per_tile, int32_t xcd_aware);
-/* Autotuner: time each candidate schedule (rows per tile in {256..4096}, XCD
- * placement on/off) with `reps` probe launches in which every active walk
- * computes its first unit without advancing (states unchanged), keep the
- * fastest, and cache it in-process by (dtype, log2 total rows, mean degree).
- * Synchronises `stream`.  QW_ESTATE unless every active walk is at its first
- * unit.  Outputs may be NULL; *ms_per_launch is -1 on a cache hit. */
+/* Kernel for the Horner stages of CTQW walks on regular graphs of degree <= 8
+ * (plans on the ELL path; the series of Sec. 3.1's evolution operator).
+ * QW_BATCH_LDS (the default): tiles of 4096 rows, one workgroup each, that
+ * pass over the walk's input vector in LDS-staged blocks, so the neighbour
+ * gathers read LDS instead of L2.  QW_BATCH_GATHER: the gather kernel that
+ * runs every other walk (rows_per_tile rows per tile, gathers through L2).
+ * Both add a row's neighbours in increasing index order in FP64, so results
+ * are bitwise equal.  Takes effect at the next commit.  Host only; QW_EINVAL
+ * for another value. */
+#define QW_BATCH_GATHER 0
+#define QW_BATCH_LDS 1
+int qw_batch_set_stage_kernel(qw_batch *batch, int32_t kernel);
+/* The current schedule (rows per tile, XCD placement, stage kernel); NULL
+ * outputs are skipped.  Host only. */
+int qw_batch_get_schedule(const qw_batch *batch, int32_t *rows_per_tile, int32_t *xcd_aware, int32_t *kernel);
+/* Autotuner: time each candidate schedule (stage kernel, rows per tile in
+ * {256..4096}, XCD placement on/off) with `reps` probe launches in which
+ * every active walk computes its first unit without advancing (states
+ * unchanged), keep the fastest, and cache it in-process by (dtype, log2 total
+ * rows, mean degree).  Synchronises `stream`.  QW_ESTATE unless every active
+ * walk is at its first unit.  Outputs may be NULL; *ms_per_launch is -1 on a
+ * cache hit. */
 int qw_batch_autotune(qw_batch *batch, int32_t reps, void *stream, int32_t *rows_per_tile,
                       int32_t *xcd_aware, double *ms_per_launch);
 

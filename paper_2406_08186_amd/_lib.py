@@ -23,6 +23,7 @@ QW_REFLECTION, QW_HAMILTONIAN = 0, 1
 QW_GROVER, QW_HADAMARD, QW_FOURIER, QW_MATRIX, QW_SZEGEDY = 0, 1, 2, 3, 4
 QW_FLIPFLOP, QW_PERSISTENT = 0, 1
 QW_C64, QW_C128 = 0, 1
+QW_BATCH_GATHER, QW_BATCH_LDS = 0, 1
 QW_LAYOUT_AUTO, QW_LAYOUT_CSR, QW_LAYOUT_STRUCTURED, QW_LAYOUT_DENSE = 0, 1, 2, 3
 STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small", 5: "ell", 6: "dense",
               7: "stag_lattice"}
@@ -34,7 +35,8 @@ EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upl
            "qw_batch_create", "qw_batch_destroy", "qw_batch_device_bytes", "qw_batch_bind",
            "qw_batch_set_slot", "qw_batch_clear_slot", "qw_batch_commit", "qw_batch_run",
            "qw_batch_remaining", "qw_batch_launches", "qw_batch_readout", "qw_batch_set_schedule",
-           "qw_batch_autotune", "qw_batch_set_replay", "qw_batch_launch_plan"]
+           "qw_batch_autotune", "qw_batch_set_replay", "qw_batch_launch_plan", "qw_batch_set_stage_kernel",
+           "qw_batch_get_schedule", "qw_plan_stream_sizes", "qw_plan_upload_streamed"]
 
 
 class QwCsr(C.Structure):
@@ -114,6 +116,10 @@ def lib():
         L.qw_batch_autotune.argtypes = [vp, C.c_int32, vp, i32p, i32p, dp]
         L.qw_batch_set_replay.argtypes = [vp, C.c_int32]
         L.qw_batch_launch_plan.argtypes = [vp, C.c_int64, i64p, i64p]
+        L.qw_batch_set_stage_kernel.argtypes = [vp, C.c_int32]
+        L.qw_plan_stream_sizes.argtypes = [vp, C.c_size_t, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), i64p]
+        L.qw_plan_upload_streamed.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, vp]
+        L.qw_batch_get_schedule.argtypes = [vp, i32p, i32p, i32p]
         L.qw_last_error.restype = C.c_char_p
         L.qw_version.restype = C.c_char_p
         for name in EXPORTS:
@@ -265,6 +271,29 @@ def qw_batch_launch_plan(batch, launches: int) -> tuple[int, int]:
     g, d = C.c_int64(), C.c_int64()
     check(lib().qw_batch_launch_plan(batch, launches, C.byref(g), C.byref(d)), "qw_batch_launch_plan")
     return g.value, d.value
+
+
+def qw_plan_stream_sizes(plan, device_budget: int) -> tuple[int, int, int]:
+    h, d, t = C.c_size_t(), C.c_size_t(), C.c_int64()
+    check(lib().qw_plan_stream_sizes(plan, device_budget, C.byref(h), C.byref(d), C.byref(t)),
+          "qw_plan_stream_sizes")
+    return h.value, d.value, t.value
+
+
+def qw_plan_upload_streamed(plan, device_budget: int, h_pinned: int, host_bytes: int, d_buf: int,
+                            device_bytes: int, stream: int) -> None:
+    check(lib().qw_plan_upload_streamed(plan, device_budget, h_pinned, host_bytes, d_buf, device_bytes, stream),
+          "qw_plan_upload_streamed")
+
+
+def qw_batch_set_stage_kernel(batch, kernel: int) -> None:
+    check(lib().qw_batch_set_stage_kernel(batch, kernel), "qw_batch_set_stage_kernel")
+
+
+def qw_batch_get_schedule(batch) -> tuple[int, int, int]:
+    r, x, k = C.c_int32(), C.c_int32(), C.c_int32()
+    check(lib().qw_batch_get_schedule(batch, C.byref(r), C.byref(x), C.byref(k)), "qw_batch_get_schedule")
+    return r.value, x.value, k.value
 
 
 def qw_batch_autotune(batch, reps: int, stream: int):

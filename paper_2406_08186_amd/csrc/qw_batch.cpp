@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kCoefStride = 128;  // doubles per slot: alpha[64], beta[64]
 constexpr int kMaxGrid = 2048;    // 8 workgroups per CU at 256 CUs
+constexpr int kLdsMaxGrid = 256;  // the LDS-staged kernel: one workgroup per CU (128 KiB of LDS each)
 constexpr int kGraphChunk = 16;   // launches per captured graph
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -41,8 +42,11 @@ struct ScheduleKey {
     return std::tie(dtype, rows_bucket, deg_bucket) < std::tie(o.dtype, o.rows_bucket, o.deg_bucket);
   }
 };
+struct Schedule {
+  int rows, xcd, kernel;
+};
 std::mutex g_tune_mu;
-std::map<ScheduleKey, std::pair<int, int>> g_tune_cache;
+std::map<ScheduleKey, Schedule> g_tune_cache;
 
 }  // namespace
 
@@ -50,21 +54,26 @@ struct qw_batch {
   int32_t capacity = 0, max_tiles = 0, dtype = QW_C64;
   int32_t rows_per_tile = 1024;
   bool xcd_aware = true;
+  int32_t stage_kernel = QW_BATCH_LDS;  // kernel for CTQW walks on the ELL layout of degree <= 8
   bool use_graph = true;  // qw_batch_run replays captured launches (else launches each directly)
-  int grid = 8;
+  int grid = 8;      // workgroups of the gather kernel
+  int grid_lds = 8;  // workgroups of the LDS-staged kernel
   // host staging
   std::vector<WalkSlot> slots;
   std::vector<const qw_plan *> plans;
   std::vector<int64_t> steps;
   std::vector<double> coefs;
-  std::vector<TileEntry> table;
-  int32_t n_tiles = 0;
+  std::vector<TileEntry> table;   // tiles of the gather and structured kernels
+  std::vector<TileEntry> ltable;  // tiles of the LDS-staged kernel
+  int32_t n_tiles = 0, n_ltiles = 0;
   uint64_t L_host = 0;
   std::vector<char> needs_perm_in;  // structured coined slots staged since the last commit
-  bool has_struct = false;          // any structured coined slot in the table (two kernels per unit)
+  bool has_struct = false;          // any structured coined slot in the table (k_batch_struct runs)
+  bool has_lds = false;             // any LDS-staged tile (k_batch_ell_lds runs, last in the unit)
+  bool run_gather = true;           // k_batch_stage runs (it has tiles, or it advances the counter)
   // device binding
   unsigned char *d_buf = nullptr;
-  size_t off_ctl = 0, off_slots = 0, off_coefs = 0, off_tiles = 0, off_ntiles = 0, bytes = 0;
+  size_t off_ctl = 0, off_slots = 0, off_coefs = 0, off_tiles = 0, off_ltiles = 0, off_ntiles = 0, bytes = 0;
   // pinned staging for table uploads, and the event that guards its reuse
   unsigned char *h_stage = nullptr;
   size_t stage_bytes = 0;
@@ -78,6 +87,8 @@ struct qw_batch {
   WalkSlot *dslots() const { return reinterpret_cast<WalkSlot *>(d_buf + off_slots); }
   double *dcoefs() const { return reinterpret_cast<double *>(d_buf + off_coefs); }
   TileEntry *dtiles() const { return reinterpret_cast<TileEntry *>(d_buf + off_tiles); }
+  TileEntry *dltiles() const { return reinterpret_cast<TileEntry *>(d_buf + off_ltiles); }
+  // tile counts: [0] the gather table, [1] the LDS-staged table
   int32_t *dntiles() const { return reinterpret_cast<int32_t *>(d_buf + off_ntiles); }
 };
 
@@ -104,7 +115,8 @@ void layout(qw_batch *b) {
   b->off_slots = sec(sizeof(WalkSlot) * b->capacity);
   b->off_coefs = sec(sizeof(double) * kCoefStride * b->capacity);
   b->off_tiles = sec(sizeof(TileEntry) * b->max_tiles);
-  b->off_ntiles = sec(sizeof(int32_t));
+  b->off_ltiles = sec(sizeof(TileEntry) * b->max_tiles);
+  b->off_ntiles = sec(2 * sizeof(int32_t));
   b->bytes = off;
 }
 
@@ -129,49 +141,22 @@ int wait_stage(qw_batch *b) {
   return QW_OK;
 }
 
-// Rebuild the tile table from the active slots.
-int build_table(qw_batch *b) {
-  struct Item {
-    int32_t slot;
-    int64_t load;
-    std::vector<TileEntry> tiles;
-  };
-  std::vector<Item> items;
-  for (int s = 0; s < b->capacity; ++s) {
-    const WalkSlot &w = b->slots[s];
-    if (w.kind < 0) continue;
-    Item it;
-    it.slot = s;
-    const qw_plan *p = b->plans[s];
-    if (w.kind == QW_CTQW) {
-      const int R = b->rows_per_tile;
-      for (int64_t r = 0; r < p->n; r += R)
-        it.tiles.push_back({s, static_cast<int32_t>(r), static_cast<int32_t>(std::min<int64_t>(p->n, r + R)), 0});
-      it.load = p->n_arcs + 3 * p->n;
-    } else if (w.structure != kGeneral) {
-      const int R = b->rows_per_tile;
-      for (int64_t v = 0; v < p->n; v += R)
-        it.tiles.push_back({s, static_cast<int32_t>(v), static_cast<int32_t>(std::min<int64_t>(p->n, v + R)), 0});
-      it.load = 2 * p->n_arcs;
-    } else {
-      const std::vector<int32_t> t = plan_tiles(p);
-      for (int32_t i = 0; i + 1 < static_cast<int32_t>(t.size()); ++i) it.tiles.push_back({s, t[i], t[i + 1], 0});
-      it.load = 2 * p->n_arcs;
-    }
-    items.push_back(std::move(it));
-  }
-  bool has_struct = false;
-  for (int s = 0; s < b->capacity; ++s)
-    has_struct |= b->slots[s].kind == QW_COINED && b->slots[s].structure != kGeneral;
-  if (has_struct != b->has_struct) {
-    b->has_struct = has_struct;
-    if (b->exec) {
-      (void)hipGraphExecDestroy(b->exec);  // the launch unit changed: re-captured at the next run
-      b->exec = nullptr;
-    }
-  }
+// True when a slot's CTQW walk runs on the LDS-staged kernel.
+bool lds_slot(const qw_batch *b, const WalkSlot &w) {
+  return b->stage_kernel == QW_BATCH_LDS && w.kind == QW_CTQW && w.ell_d >= 1 && w.ell_d <= 8;
+}
+
+// Lay out walks' tiles by XCD: longest walks first, each onto the XCD with
+// the least load so far; entry 8 i + x is the i-th tile of XCD x's list, so a
+// kernel whose grid is a multiple of 8 runs all of a walk's tiles on one XCD.
+struct Item {
+  int32_t slot;
+  int64_t load;
+  std::vector<TileEntry> tiles;
+};
+std::vector<TileEntry> lay_out(std::vector<Item> &items, bool xcd_aware) {
   std::vector<TileEntry> table;
-  if (b->xcd_aware) {
+  if (xcd_aware) {
     std::sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.load > y.load; });
     std::vector<std::vector<TileEntry>> lists(8);
     int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -188,19 +173,71 @@ int build_table(qw_batch *b) {
   } else {
     for (const Item &it : items) table.insert(table.end(), it.tiles.begin(), it.tiles.end());
   }
-  if (static_cast<int64_t>(table.size()) > b->max_tiles)
-    return set_error(QW_ENOMEM, "batch needs %zu tiles, capacity is %d", table.size(), b->max_tiles);
-  b->table = std::move(table);
-  b->n_tiles = static_cast<int32_t>(b->table.size());
-  // grid: a multiple of 8 (keeps the XCD placement), no larger than the work
-  const int grid = std::max(8, std::min(kMaxGrid, (b->n_tiles + 7) / 8 * 8));
-  if (grid != b->grid) {
-    b->grid = grid;
+  return table;
+}
+
+// Rebuild the tile tables from the active slots.
+int build_table(qw_batch *b) {
+  std::vector<Item> items, litems;
+  for (int s = 0; s < b->capacity; ++s) {
+    const WalkSlot &w = b->slots[s];
+    if (w.kind < 0) continue;
+    Item it;
+    it.slot = s;
+    const qw_plan *p = b->plans[s];
+    if (w.kind == QW_CTQW) {
+      const bool lds = lds_slot(b, w);
+      const int R = lds ? kLdsTileRows : b->rows_per_tile;
+      for (int64_t r = 0; r < p->n; r += R)
+        it.tiles.push_back({s, static_cast<int32_t>(r), static_cast<int32_t>(std::min<int64_t>(p->n, r + R)), 0});
+      it.load = p->n_arcs + 3 * p->n;
+      if (lds) {
+        litems.push_back(std::move(it));
+        continue;
+      }
+    } else if (w.structure != kGeneral) {
+      const int R = b->rows_per_tile;
+      for (int64_t v = 0; v < p->n; v += R)
+        it.tiles.push_back({s, static_cast<int32_t>(v), static_cast<int32_t>(std::min<int64_t>(p->n, v + R)), 0});
+      it.load = 2 * p->n_arcs;
+    } else {
+      const std::vector<int32_t> t = plan_tiles(p);
+      for (int32_t i = 0; i + 1 < static_cast<int32_t>(t.size()); ++i) it.tiles.push_back({s, t[i], t[i + 1], 0});
+      it.load = 2 * p->n_arcs;
+    }
+    items.push_back(std::move(it));
+  }
+  bool has_struct = false;
+  for (int s = 0; s < b->capacity; ++s)
+    has_struct |= b->slots[s].kind == QW_COINED && b->slots[s].structure != kGeneral;
+  std::vector<TileEntry> table = lay_out(items, b->xcd_aware);
+  std::vector<TileEntry> ltable = lay_out(litems, b->xcd_aware);
+  if (static_cast<int64_t>(table.size()) > b->max_tiles || static_cast<int64_t>(ltable.size()) > b->max_tiles)
+    return set_error(QW_ENOMEM, "batch needs %zu + %zu tiles, capacity is %d per table", table.size(),
+                     ltable.size(), b->max_tiles);
+  const bool has_lds = !ltable.empty();
+  // k_batch_stage runs when it has tiles, and also when nothing else would
+  // advance the launch counter
+  const bool run_gather = !table.empty() || !has_lds;
+  // grids: multiples of 8 (keeps the XCD placement), no larger than the work
+  const int grid = std::max(8, std::min(kMaxGrid, (static_cast<int>(table.size()) + 7) / 8 * 8));
+  const int grid_lds = std::max(8, std::min(kLdsMaxGrid, (static_cast<int>(ltable.size()) + 7) / 8 * 8));
+  if (has_struct != b->has_struct || has_lds != b->has_lds || run_gather != b->run_gather || grid != b->grid ||
+      grid_lds != b->grid_lds) {
     if (b->exec) {
-      (void)hipGraphExecDestroy(b->exec);  // re-captured with the new grid at the next run
+      (void)hipGraphExecDestroy(b->exec);  // the launch unit changed: re-captured at the next run
       b->exec = nullptr;
     }
   }
+  b->has_struct = has_struct;
+  b->has_lds = has_lds;
+  b->run_gather = run_gather;
+  b->grid = grid;
+  b->grid_lds = grid_lds;
+  b->table = std::move(table);
+  b->ltable = std::move(ltable);
+  b->n_tiles = static_cast<int32_t>(b->table.size());
+  b->n_ltiles = static_cast<int32_t>(b->ltable.size());
   return QW_OK;
 }
 
@@ -210,15 +247,20 @@ int upload_tables(qw_batch *b, hipStream_t s) {
   const size_t sl = sizeof(WalkSlot) * b->capacity;
   const size_t co = sizeof(double) * kCoefStride * b->capacity;
   const size_t ti = sizeof(TileEntry) * b->table.size();
+  const size_t lt = sizeof(TileEntry) * b->ltable.size();
   unsigned char *h = b->h_stage;
+  const size_t o_cnt = sl + co, o_ti = o_cnt + 256, o_lt = align256(o_ti + ti);
   std::memcpy(h, b->slots.data(), sl);
   std::memcpy(h + sl, b->coefs.data(), co);
-  std::memcpy(h + sl + co, &b->n_tiles, sizeof(int32_t));
-  if (ti) std::memcpy(h + sl + co + 256, b->table.data(), ti);
+  const int32_t counts[2] = {b->n_tiles, b->n_ltiles};
+  std::memcpy(h + o_cnt, counts, sizeof counts);
+  if (ti) std::memcpy(h + o_ti, b->table.data(), ti);
+  if (lt) std::memcpy(h + o_lt, b->ltable.data(), lt);
   QW_TRY(hipMemcpyAsync(b->dslots(), h, sl, hipMemcpyHostToDevice, s), "batch slot upload");
   QW_TRY(hipMemcpyAsync(b->dcoefs(), h + sl, co, hipMemcpyHostToDevice, s), "batch coefficient upload");
-  QW_TRY(hipMemcpyAsync(b->dntiles(), h + sl + co, sizeof(int32_t), hipMemcpyHostToDevice, s), "batch count upload");
-  if (ti) QW_TRY(hipMemcpyAsync(b->dtiles(), h + sl + co + 256, ti, hipMemcpyHostToDevice, s), "batch tile upload");
+  QW_TRY(hipMemcpyAsync(b->dntiles(), h + o_cnt, sizeof counts, hipMemcpyHostToDevice, s), "batch count upload");
+  if (ti) QW_TRY(hipMemcpyAsync(b->dtiles(), h + o_ti, ti, hipMemcpyHostToDevice, s), "batch tile upload");
+  if (lt) QW_TRY(hipMemcpyAsync(b->dltiles(), h + o_lt, lt, hipMemcpyHostToDevice, s), "batch tile upload");
   QW_TRY(hipEventRecord(b->staged, s), "batch staging event");
   b->staged_pending = true;
   return QW_OK;
@@ -236,13 +278,22 @@ int set_probe(qw_batch *b, unsigned int on, hipStream_t s) {
   return QW_OK;
 }
 
+// One batched unit: the structured coined tiles, then the gather kernel's
+// tiles, then the LDS-staged tiles; the last kernel of the unit advances the
+// launch counter.
 hipError_t launch_one(qw_batch *b, hipStream_t s) {
+  const bool c128 = b->dtype == QW_C128;
   if (b->has_struct) {
-    const hipError_t e =
-        batch_struct(b->dtype == QW_C128, b->ctl(), b->dslots(), b->dtiles(), b->dntiles(), b->grid, s);
+    const hipError_t e = batch_struct(c128, b->ctl(), b->dslots(), b->dtiles(), b->dntiles(), b->grid, s);
     if (e != hipSuccess) return e;
   }
-  return batch_stage(b->dtype == QW_C128, b->ctl(), b->dslots(), b->dtiles(), b->dntiles(), b->grid, s);
+  if (b->run_gather) {
+    const hipError_t e =
+        batch_stage(c128, b->ctl(), b->dslots(), b->dtiles(), b->dntiles(), b->grid, b->has_lds ? 0 : 1, s);
+    if (e != hipSuccess) return e;
+  }
+  if (b->has_lds) return batch_ell_lds(c128, b->ctl(), b->dslots(), b->dltiles(), b->dntiles() + 1, b->grid_lds, 1, s);
+  return hipSuccess;
 }
 
 int check_batch(const qw_batch *b) {
@@ -305,7 +356,7 @@ int qw_batch_bind(qw_batch *b, void *d_buf, size_t bytes, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!b->h_stage) {
     b->stage_bytes = sizeof(WalkSlot) * b->capacity + sizeof(double) * kCoefStride * b->capacity + 256 +
-                     sizeof(TileEntry) * b->max_tiles + 256;
+                     2 * (sizeof(TileEntry) * b->max_tiles + 256) + 256;
     QW_TRY(hipHostMalloc(reinterpret_cast<void **>(&b->h_stage), b->stage_bytes, hipHostMallocDefault),
            "pinned staging allocation");
     QW_TRY(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming), "batch event");
@@ -329,7 +380,8 @@ int qw_batch_bind(qw_batch *b, void *d_buf, size_t bytes, void *stream) {
     b->plans[i] = nullptr;
   }
   b->table.clear();
-  b->n_tiles = 0;
+  b->ltable.clear();
+  b->n_tiles = b->n_ltiles = 0;
   st = upload_tables(b, s);
   return st == QW_OK ? clear_error() : st;
 }
@@ -341,6 +393,7 @@ int qw_batch_set_slot(qw_batch *b, int32_t slot, const qw_plan *p, void *d_psi, 
   if (slot < 0 || slot >= b->capacity) return set_error(QW_EINVAL, "slot %d out of range", slot);
   if (!p || !d_psi || !d_work) return set_error(QW_EINVAL, "null plan, state or workspace");
   if (!p->d_graph) return set_error(QW_ESTATE, "plan not uploaded");
+  if (p->streamed) return set_error(QW_EUNSUPPORTED, "plans bound for out-of-core evolution cannot join a batch");
   if (p->dtype != b->dtype) return set_error(QW_EINVAL, "plan dtype differs from the batch's");
   if (p->kind == QW_STAGGERED) return set_error(QW_EUNSUPPORTED, "staggered walks cannot join a batch");
   const bool coined_struct = p->kind == QW_COINED &&
@@ -526,36 +579,60 @@ int qw_batch_set_schedule(qw_batch *b, int32_t rows_per_tile, int32_t xcd_aware)
   return clear_error();
 }
 
+int qw_batch_set_stage_kernel(qw_batch *b, int32_t kernel) {
+  if (!b) return set_error(QW_EINVAL, "null batch");
+  if (kernel != QW_BATCH_GATHER && kernel != QW_BATCH_LDS) return set_error(QW_EINVAL, "bad stage kernel %d", kernel);
+  b->stage_kernel = kernel;
+  return clear_error();
+}
+
+int qw_batch_get_schedule(const qw_batch *b, int32_t *rows_per_tile, int32_t *xcd_aware, int32_t *kernel) {
+  if (!b) return set_error(QW_EINVAL, "null batch");
+  if (rows_per_tile) *rows_per_tile = b->rows_per_tile;
+  if (xcd_aware) *xcd_aware = b->xcd_aware;
+  if (kernel) *kernel = b->stage_kernel;
+  return clear_error();
+}
+
 int qw_batch_autotune(qw_batch *b, int32_t reps, void *stream, int32_t *rows_per_tile, int32_t *xcd_aware,
                       double *ms_per_launch) {
   int st = check_batch(b);
   if (st != QW_OK) return st;
   if (reps < 1) return set_error(QW_EINVAL, "reps must be >= 1");
   int64_t rows = 0, arcs = 0, walks = 0;
+  bool any_ell8 = false, any_other = false;
   for (int s = 0; s < b->capacity; ++s) {
-    if (b->slots[s].kind < 0) continue;
-    if (b->L_host != static_cast<uint64_t>(b->slots[s].L0))
+    const WalkSlot &w = b->slots[s];
+    if (w.kind < 0) continue;
+    if (b->L_host != static_cast<uint64_t>(w.L0))
       return set_error(QW_ESTATE, "autotune needs every active walk at its first unit (slot %d has started)", s);
     rows += b->plans[s]->n;
     arcs += b->plans[s]->n_arcs;
     ++walks;
+    const bool ell8 = w.kind == QW_CTQW && w.ell_d >= 1 && w.ell_d <= 8;
+    any_ell8 |= ell8;
+    any_other |= !ell8;
   }
   if (walks == 0) return set_error(QW_ESTATE, "no active walks to tune on");
   const ScheduleKey key{b->dtype, static_cast<int64_t>(std::log2(static_cast<double>(rows))),
                         static_cast<int64_t>(std::lround(2.0 * arcs / rows))};
   hipStream_t s = static_cast<hipStream_t>(stream);
+  auto finish = [&](double ms) {
+    if (rows_per_tile) *rows_per_tile = b->rows_per_tile;
+    if (xcd_aware) *xcd_aware = b->xcd_aware;
+    if (ms_per_launch) *ms_per_launch = ms;
+    int r = build_table(b);
+    if (r == QW_OK) r = upload_tables(b, s);
+    return r == QW_OK ? clear_error() : r;
+  };
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      b->rows_per_tile = it->second.first;
-      b->xcd_aware = it->second.second != 0;
-      if (rows_per_tile) *rows_per_tile = b->rows_per_tile;
-      if (xcd_aware) *xcd_aware = b->xcd_aware;
-      if (ms_per_launch) *ms_per_launch = -1.0;
-      st = build_table(b);
-      if (st == QW_OK) st = upload_tables(b, s);
-      return st == QW_OK ? clear_error() : st;
+      b->rows_per_tile = it->second.rows;
+      b->xcd_aware = it->second.xcd != 0;
+      b->stage_kernel = it->second.kernel;
+      return finish(-1.0);
     }
   }
   hipEvent_t e0, e1;
@@ -563,35 +640,41 @@ int qw_batch_autotune(qw_batch *b, int32_t reps, void *stream, int32_t *rows_per
   QW_TRY(hipEventCreate(&e1), "event");
   st = set_probe(b, 1u, s);
   double best = 1e300;
-  int best_r = b->rows_per_tile, best_x = b->xcd_aware;
+  Schedule bestc{b->rows_per_tile, b->xcd_aware, b->stage_kernel};
   const int cand_r[] = {256, 512, 1024, 2048, 4096};
-  for (int xi = 1; xi >= 0 && st == QW_OK; --xi) {
-    for (int r : cand_r) {
-      b->rows_per_tile = r;
-      b->xcd_aware = xi != 0;
-      st = build_table(b);
-      if (st == QW_ENOMEM) {  // this schedule's tile table does not fit max_tiles: skip it
-        st = QW_OK;
-        continue;
-      }
-      if (st == QW_OK) st = upload_tables(b, s);
-      if (st != QW_OK) break;
-      hipError_t e = launch_one(b, s);
-      if (e == hipSuccess) e = hipEventRecord(e0, s);
-      for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_one(b, s);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        st = dev_fail(e, "autotune probe");
-        break;
-      }
-      const double per = ms / reps;
-      if (per < best) {
-        best = per;
-        best_r = r;
-        best_x = xi;
+  const int cand_k[] = {QW_BATCH_LDS, QW_BATCH_GATHER};
+  for (int kern : cand_k) {
+    if (kern == QW_BATCH_LDS && !any_ell8) continue;  // the same schedules as the gather kernel
+    for (int xi = 1; xi >= 0 && st == QW_OK; --xi) {
+      for (int r : cand_r) {
+        // with every walk on the LDS-staged kernel, rows per tile change nothing
+        if (kern == QW_BATCH_LDS && !any_other && r != cand_r[0]) continue;
+        b->rows_per_tile = r;
+        b->xcd_aware = xi != 0;
+        b->stage_kernel = kern;
+        st = build_table(b);
+        if (st == QW_ENOMEM) {  // this schedule's tile table does not fit max_tiles: skip it
+          st = QW_OK;
+          continue;
+        }
+        if (st == QW_OK) st = upload_tables(b, s);
+        if (st != QW_OK) break;
+        hipError_t e = launch_one(b, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_one(b, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          st = dev_fail(e, "autotune probe");
+          break;
+        }
+        const double per = ms / reps;
+        if (per < best) {
+          best = per;
+          bestc = {r, xi, kern};
+        }
       }
     }
   }
@@ -601,19 +684,14 @@ int qw_batch_autotune(qw_batch *b, int32_t reps, void *stream, int32_t *rows_per
   if (st != QW_OK) return st;
   if (st2 != QW_OK) return st2;
   if (best > 1e299) return set_error(QW_ENOMEM, "no candidate schedule fits max_tiles");
-  b->rows_per_tile = best_r;
-  b->xcd_aware = best_x != 0;
-  st = build_table(b);
-  if (st == QW_OK) st = upload_tables(b, s);
-  if (st != QW_OK) return st;
+  b->rows_per_tile = bestc.rows;
+  b->xcd_aware = bestc.xcd != 0;
+  b->stage_kernel = bestc.kernel;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {best_r, best_x};
+    g_tune_cache[key] = bestc;
   }
-  if (rows_per_tile) *rows_per_tile = best_r;
-  if (xcd_aware) *xcd_aware = best_x;
-  if (ms_per_launch) *ms_per_launch = best;
-  return clear_error();
+  return finish(best);
 }
 
 }  // extern "C"

@@ -667,11 +667,18 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   for (int64_t v = 0; v <= n; ++v) rp32[v] = static_cast<int32_t>(rp[v]);
   put(p->image, p->off_rp, rp32.data(), rp32.size());
   if (p->has_col && structure == kEll) {
-    // column-major: entry (j, v) = j-th neighbour of v in row order
+    // column-major: entry (j, v) = j-th smallest neighbour of v.  Sorted rows
+    // let the LDS-staged batch kernel, which visits the vector in blocks of
+    // increasing index, add a row's neighbours in the same order as the
+    // gather kernels.
     std::vector<int32_t> colT(static_cast<size_t>(na));
     const int64_t d = p->dims[0];
-    for (int64_t v = 0; v < n; ++v)
-      for (int64_t j = 0; j < d; ++j) colT[static_cast<size_t>(j) * n + v] = col[rp[v] + j];
+    std::vector<int32_t> row(static_cast<size_t>(d));
+    for (int64_t v = 0; v < n; ++v) {
+      std::copy(col + rp[v], col + rp[v] + d, row.begin());
+      std::sort(row.begin(), row.end());
+      for (int64_t j = 0; j < d; ++j) colT[static_cast<size_t>(j) * n + v] = row[j];
+    }
     put(p->image, p->off_col, colT.data(), colT.size());
   } else if (p->has_col) {
     put(p->image, p->off_col, col, static_cast<size_t>(na));
@@ -1001,6 +1008,7 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
     return fail(QW_ENOMEM, "graph buffer of %zu bytes, plan needs %zu", graph_bytes, need);
   if (reinterpret_cast<uintptr_t>(d_graph) % 256 != 0) return fail(QW_EINVAL, "graph buffer not 256-byte aligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  release_streamed(p);  // a plain upload ends an out-of-core binding
   QW_TRY(hipMemcpyAsync(d_graph, p->image.data(), p->image.size(), hipMemcpyHostToDevice, s), "graph upload");
   auto *base = static_cast<unsigned char *>(d_graph);
   p->d_graph = base;
@@ -1051,8 +1059,12 @@ int qw_evolve(const qw_plan *p, void *d_psi, void *d_work, size_t work_bytes, in
   if (!d_work) return fail(QW_EINVAL, "null workspace");
   if (work_bytes < p->work_bytes) return fail(QW_ENOMEM, "workspace of %zu bytes, plan needs %zu", work_bytes, p->work_bytes);
   auto *work = static_cast<unsigned char *>(d_work);
-  const Readout ro = make_readout(p, work, d_p, d_norm, d_pmarked);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->streamed) {
+    st = evolve_streamed(p, d_psi, work, steps, d_p, d_norm, d_pmarked, s);
+    return st == QW_OK ? ok() : st;
+  }
+  const Readout ro = make_readout(p, work, d_p, d_norm, d_pmarked);
   st = p->kind == QW_COINED     ? evolve_coined(p, d_psi, work, steps, ro, s)
        : p->kind == QW_STAGGERED ? evolve_staggered(p, d_psi, work, steps, ro, s)
                                  : evolve_ctqw(p, d_psi, work, steps, ro, s);

@@ -13,6 +13,9 @@ namespace qwk {
 // one workgroup's LDS tile are processed together.
 constexpr int kTileArcs = 2048;
 constexpr int kTileThreads = 256;
+constexpr int kLdsTileThreads = 1024;          // workgroup of the LDS-staged batch stage
+constexpr int kLdsTileRows = 4096;             // rows per tile of that kernel (4 per thread)
+constexpr int kLdsBlockBytes = 128 * 1024;     // LDS block of the input vector it stages
 constexpr int kTileMaxVerts = 1024;
 // Threads per workgroup of the elementwise/stencil kernels.
 constexpr int kBlock = 256;
@@ -259,8 +262,21 @@ struct TileEntry {
   int32_t pad;
 };
 
+// The gather-path stage of a batched launch (CSR and ELL CTQW tiles, general
+// coined tiles); the last workgroup advances the launch counter when
+// `advance` is nonzero.
 hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
-                       const int32_t *n_tiles, int grid, hipStream_t s);
+                       const int32_t *n_tiles, int grid, int advance, hipStream_t s);
+// Out-of-core CTQW stage on rows [r0, r1) whose neighbour indices (CSR arcs
+// [arc0, ...)) sit in a device slot: slot[a - arc0] = col[a].
+hipError_t ctqw_slot_stage(bool c128, const GraphView &g, const int32_t *slot, int64_t arc0, int r0, int r1,
+                           const void *y, const void *psi, void *out, double alpha, double beta, hipStream_t s);
+// The LDS-staged stage of the batch's CTQW walks on the ELL layout (degree
+// <= 8): tiles of kLdsTileRows rows, one workgroup of kLdsTileThreads each, the
+// input vector staged in blocks of kLdsBlockBytes.  The last workgroup
+// advances the launch counter when `advance` is nonzero.
+hipError_t batch_ell_lds(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
+                         const int32_t *n_tiles, int grid, int advance, hipStream_t s);
 // The structured coined tiles of a batched launch (run before batch_stage in
 // each launch unit; reads the launch counter, does not advance it).
 hipError_t batch_struct(bool c128, const BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,

@@ -724,6 +724,24 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_csr(GraphView g, const T *__res
   }
 }
 
+// Out-of-core stage: rows [r0, r1) of a CSR graph whose neighbour indices were
+// copied into a device slot (slot[a - arc0] = col[a]); one thread per row,
+// neighbours summed in arc order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ctqw_csr_slot(const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ slot, int64_t arc0,
+                                                          int r0, int r1, const uint32_t *markbits,
+                                                          const T *__restrict__ y, const T *psi, T *out,
+                                                          double alpha, double beta) {
+  const int r = r0 + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (r >= r1) return;
+  const int lo = static_cast<int>(rp[r] - arc0), hi = static_cast<int>(rp[r + 1] - arc0);
+  const double2 sum = gather_sum(y, slot, lo, hi);
+  const bool mk = marked(markbits, r);
+  const double2 yv = mk ? ld(y, r) : make_double2(0.0, 0.0);
+  st(out, r, horner_out(ld(psi, r), sum, yv, mk, alpha, beta));
+}
+
 // Regular graphs: ELL stage, one thread per row, column-major neighbour table.
 template <typename T, bool PROB>
 __global__ __launch_bounds__(kBlock) void k_ctqw_ell(GraphView g, const T *__restrict__ y, const T *psi,
@@ -1563,7 +1581,7 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_struct(const BatchCtl *c
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, const WalkSlot *slots,
                                                               const TileEntry *tiles,
-                                                              const int32_t *n_tiles) {
+                                                              const int32_t *n_tiles, int advance) {
   __shared__ T s[kTileArcs];
   const int64_t L = static_cast<int64_t>(ctl->L);
   const bool probe = ctl->probe != 0;
@@ -1584,13 +1602,115 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
     }
     __syncthreads();
   }
-  if (probe) return;
+  if (probe || !advance) return;
   // Launch ticket: the last workgroup to finish advances L.  Only atomicity
   // is needed -- every workgroup read L before taking its ticket, and the next
   // launch reads it after the kernel boundary -- so no fence is issued (an
   // agent-scope fence would write back the L2 once per workgroup).
   __syncthreads();
   if (threadIdx.x == 0) {
+    const unsigned int prev = atomicAdd(&ctl->done, 1u);
+    if (prev == gridDim.x - 1) {
+      atomicExch(&ctl->done, 0u);
+      atomicAdd(&ctl->L, 1ull);
+    }
+  }
+}
+
+// LDS-staged Horner stage for the batch's CTQW walks on regular graphs of
+// degree <= 8 (ELL layout).  A workgroup owns NT * RPL consecutive rows of one
+// walk (a tile) and makes one pass over the walk's input vector y in blocks of
+// BLK entries held in LDS, so every neighbour value is read from LDS in the
+// block that holds it and the random gathers never reach L2; the blocks are
+// coalesced loads, and the vector (at most a few MB) stays in the XCD's L2
+// while the walk's tiles read it.  Rows keep their neighbour indices in
+// registers.  The plan stores each row's neighbours in increasing order, so
+// adding, block after block, the neighbours each block holds adds them in row
+// order: the sums are bitwise those of the gather kernels.  The next block is
+// prefetched into registers while the current one is summed.  Tiles are taken
+// grid-stride (the host lays out the table by XCD); the last workgroup of the
+// launch advances the launch counter when `advance` is set.
+template <typename T, int NT, int RPL, int BLK>
+__global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkSlot *slots,
+                                                      const TileEntry *tiles, const int32_t *n_tiles,
+                                                      int advance) {
+  static_assert(BLK % NT == 0, "a block is staged as whole rounds of the workgroup");
+  constexpr int PF = BLK / NT;
+  __shared__ T xs[BLK];
+  const int64_t L = static_cast<int64_t>(ctl->L);
+  const bool probe = ctl->probe != 0;
+  const int nt = *n_tiles;
+  const int tid = threadIdx.x;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const TileEntry te = tiles[t];
+    if (te.slot < 0) continue;
+    const WalkSlot &w = slots[te.slot];
+    if (w.kind != 1 || w.ell_d <= 0 || w.ell_d > 8) continue;
+    const int64_t u = probe ? 0 : L - w.L0;
+    if (u < 0 || u >= w.units) continue;
+    const int K = w.K;
+    const int64_t step = u / K;
+    const int k = K - static_cast<int>(u % K);
+    const T *psi = static_cast<const T *>(w.psi);
+    const T *yin = (k == K) ? psi : static_cast<const T *>(((K - k - 1) & 1) ? w.w1 : w.w0);
+    T *yout = (k == 1) ? static_cast<T *>(w.psi) : static_cast<T *>(((K - k) & 1) ? w.w1 : w.w0);
+    const double alpha = w.alpha[k - 1], beta = w.beta[k - 1];
+    const int n = w.n, d = w.ell_d;
+    // neighbour indices of this lane's rows; 0x7fffffff (never inside a block) pads
+    // missing neighbours and rows past the tile
+    int c[RPL][8];
+    double2 acc[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int r = te.begin + tid + i * NT;
+      const bool ok = r < te.end;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) c[i][j] = (ok && j < d) ? w.col[static_cast<int64_t>(j) * n + r] : 0x7fffffff;
+      acc[i] = make_double2(0.0, 0.0);
+    }
+    T pf[PF];
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int idx = tid + e * NT;
+      pf[e] = idx < n ? yin[idx] : T{};
+    }
+    for (int base = 0; base < n; base += BLK) {
+      __syncthreads();  // the previous block (or tile) is no longer read
+#pragma unroll
+      for (int e = 0; e < PF; ++e) xs[tid + e * NT] = pf[e];
+      __syncthreads();
+      const int nxt = base + BLK;
+      if (nxt < n) {
+#pragma unroll
+        for (int e = 0; e < PF; ++e) {
+          const int idx = nxt + tid + e * NT;
+          pf[e] = idx < n ? yin[idx] : T{};
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RPL; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const unsigned off = static_cast<unsigned>(c[i][j] - base);
+          if (off < static_cast<unsigned>(BLK)) acc[i] = add(acc[i], cvt(xs[off]));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int r = te.begin + tid + i * NT;
+      if (r < te.end) {
+        const bool mk = marked(w.markbits, r);
+        const double2 yv = mk ? ld(yin, r) : make_double2(0.0, 0.0);
+        const T o = pack<T>(horner_out(ld(psi, r), acc[i], yv, mk, alpha, beta));
+        yout[r] = o;
+        if (k == 1 && mk && w.hist) atomicAdd(&w.hist[step], abs2(cvt(o)));
+      }
+    }
+  }
+  if (probe || !advance) return;
+  // launch ticket, as in k_batch_stage
+  __syncthreads();
+  if (tid == 0) {
     const unsigned int prev = atomicAdd(&ctl->done, 1u);
     if (prev == gridDim.x - 1) {
       atomicExch(&ctl->done, 0u);
@@ -2241,12 +2361,42 @@ hipError_t vertex_prob(bool c128, const GraphView &g, const void *psi, const Rea
 }
 
 hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
-                       const int32_t *n_tiles, int grid, hipStream_t s) {
+                       const int32_t *n_tiles, int grid, int advance, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (c128)
-    hipLaunchKernelGGL(k_batch_stage<double2>, dim3(grid), dim3(kTileThreads), 0, s, ctl, slots, tiles, n_tiles);
+    hipLaunchKernelGGL(k_batch_stage<double2>, dim3(grid), dim3(kTileThreads), 0, s, ctl, slots, tiles, n_tiles,
+                       advance);
   else
-    hipLaunchKernelGGL(k_batch_stage<float2>, dim3(grid), dim3(kTileThreads), 0, s, ctl, slots, tiles, n_tiles);
+    hipLaunchKernelGGL(k_batch_stage<float2>, dim3(grid), dim3(kTileThreads), 0, s, ctl, slots, tiles, n_tiles,
+                       advance);
+  return hipGetLastError();
+}
+
+hipError_t ctqw_slot_stage(bool c128, const GraphView &g, const int32_t *slot, int64_t arc0, int r0, int r1,
+                           const void *y, const void *psi, void *out, double alpha, double beta, hipStream_t s) {
+  if (r1 <= r0) return hipSuccess;
+  const dim3 grid(blocks_for(r1 - r0, kBlock));
+  if (c128)
+    hipLaunchKernelGGL(k_ctqw_csr_slot<double2>, grid, dim3(kBlock), 0, s, g.rp, slot, arc0, r0, r1, g.markbits,
+                       static_cast<const double2 *>(y), static_cast<const double2 *>(psi),
+                       static_cast<double2 *>(out), alpha, beta);
+  else
+    hipLaunchKernelGGL(k_ctqw_csr_slot<float2>, grid, dim3(kBlock), 0, s, g.rp, slot, arc0, r0, r1, g.markbits,
+                       static_cast<const float2 *>(y), static_cast<const float2 *>(psi),
+                       static_cast<float2 *>(out), alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t batch_ell_lds(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
+                         const int32_t *n_tiles, int grid, int advance, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  constexpr int NT = kLdsTileThreads, RPL = kLdsTileRows / kLdsTileThreads;
+  if (c128)
+    hipLaunchKernelGGL((k_batch_ell_lds<double2, NT, RPL, kLdsBlockBytes / 16>), dim3(grid), dim3(NT), 0, s, ctl,
+                       slots, tiles, n_tiles, advance);
+  else
+    hipLaunchKernelGGL((k_batch_ell_lds<float2, NT, RPL, kLdsBlockBytes / 8>), dim3(grid), dim3(NT), 0, s, ctl,
+                       slots, tiles, n_tiles, advance);
   return hipGetLastError();
 }
 

@@ -51,6 +51,22 @@ struct qw_plan {
   int32_t strip_rows = 0;   // grid CTQW blocked kernel: core rows per strip
   int32_t two_reg = 0;      // one-workgroup coined walk in one wavefront's registers: 0 no, 1 permutes, 2 cycle shifts
   int32_t block_depth = 1;  // grid CTQW: Horner stages per launch (temporal blocking)
+  // out-of-core binding (qw_plan_upload_streamed): the CSR neighbour table stays
+  // in caller-pinned host memory and is streamed, tile by tile, through a ring
+  // of device slots on the plan's copy stream while the stage kernels run
+  bool streamed = false;
+  const int32_t *h_col = nullptr;   // pinned host copy of col (CSR order)
+  std::vector<int32_t> st_row;      // tile t holds rows [st_row[t], st_row[t+1])
+  std::vector<int64_t> st_arc;      // and arcs [st_arc[t], st_arc[t+1])
+  int32_t st_slots = 0;             // device slots in the ring
+  int64_t st_slot_arcs = 0;         // neighbour indices per slot
+  int32_t *d_ring = nullptr;
+  hipStream_t st_copy = nullptr;
+  std::vector<hipEvent_t> st_free, st_copied;  // per slot: its kernel finished / its copy landed
+  qw_plan() = default;
+  qw_plan(const qw_plan &) = delete;
+  qw_plan &operator=(const qw_plan &) = delete;
+  ~qw_plan();
 };
 
 namespace qwk {
@@ -62,4 +78,9 @@ int plan_readout(const qw_plan *p, const void *psi, unsigned char *work, double 
 // Structured coined plans: slot-major `internal` -> boundary-order psi, with the readout fused.
 int plan_struct_out(const qw_plan *p, const void *internal, void *psi, unsigned char *work, double *d_p,
                     double *d_norm, double *d_pmarked, hipStream_t s);
+// Out-of-core CTQW evolution of a plan bound by qw_plan_upload_streamed (qw_stream.cpp).
+int evolve_streamed(const qw_plan *p, void *psi, unsigned char *work, int64_t steps, double *d_p, double *d_norm,
+                    double *d_pmarked, hipStream_t s);
+// Release the out-of-core binding's copy stream and events.
+void release_streamed(qw_plan *p);
 }  // namespace qwk

@@ -131,6 +131,20 @@ class Plan:
         L.qw_plan_upload(self._plan, self.d_graph.data_ptr(), self.d_graph.numel(),
                          _stream_ptr(stream, self.device))
 
+    def upload_streamed(self, device_budget: int, stream=None) -> dict:
+        """Out-of-core binding (CTQW on the CSR layout): the neighbour table goes to a
+        pinned host buffer and is streamed through a device ring at every Horner
+        stage; the walk uses at most `device_budget` bytes of device memory."""
+        host_bytes, dev_bytes, tiles = L.qw_plan_stream_sizes(self._plan, int(device_budget))
+        self.h_graph = torch.empty(max(host_bytes, 256), dtype=torch.uint8, pin_memory=True)
+        self.d_graph = torch.empty(max(dev_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(max(self.info.work_bytes, 256), dtype=torch.uint8, device=self.device)
+        self._p = torch.empty(max(self.p_len, 1), dtype=torch.float64, device=self.device)
+        self._scal = torch.zeros(2, dtype=torch.float64, device=self.device)
+        L.qw_plan_upload_streamed(self._plan, int(device_budget), self.h_graph.data_ptr(), self.h_graph.numel(),
+                                  self.d_graph.data_ptr(), self.d_graph.numel(), _stream_ptr(stream, self.device))
+        return {"host_bytes": host_bytes, "device_bytes": dev_bytes, "tiles": tiles}
+
     def release_device(self) -> None:
         """Drop the device buffers (the plan must not be used on the device afterwards)."""
         self.d_graph = self.work = self._p = self._scal = None
@@ -288,6 +302,15 @@ class Batch:
 
     def set_schedule(self, rows_per_tile: int, xcd_aware: bool = True) -> None:
         L.qw_batch_set_schedule(self._b, rows_per_tile, int(xcd_aware))
+
+    def set_stage_kernel(self, kernel: str) -> None:
+        """"lds" (default) or "gather" for CTQW walks on regular graphs of degree <= 8
+        (takes effect at the next commit)."""
+        L.qw_batch_set_stage_kernel(self._b, {"gather": L.QW_BATCH_GATHER, "lds": L.QW_BATCH_LDS}[kernel])
+
+    def schedule(self) -> dict:
+        r, x, k = L.qw_batch_get_schedule(self._b)
+        return {"rows_per_tile": r, "xcd_aware": bool(x), "stage_kernel": "lds" if k == L.QW_BATCH_LDS else "gather"}
 
     def autotune(self, reps: int = 3, stream=None):
         return L.qw_batch_autotune(self._b, reps, _stream_ptr(stream, self.device))

@@ -412,3 +412,33 @@ def test_bench_refuses_more_than_one_gpu(argv, env):
                        env={**os.environ, **env}, capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_out_of_core_schedule_host_side():
+    """qw_plan_stream_sizes (host only): the neighbour table goes to pinned host memory,
+    tiles shrink with the budget, and plans outside the CSR CTQW path or budgets below
+    the state, workspace and a slot of the largest row are refused."""
+    g = I.erdos_renyi(3000, 8 / 2999, seed=4)
+    pl = _create(g, kind=L.QW_CTQW, dtype=L.QW_C64, layout=L.QW_LAYOUT_CSR, gamma=0.125, dt=0.5,
+                 taylor_order=12)
+    info = L.qw_plan_get_info(pl)
+    walk = info.state_bytes + info.work_bytes
+    prev = None
+    for extra in (1 << 30, 256 * 1024, 64 * 1024, 24 * 1024):
+        host, dev, tiles = L.qw_plan_stream_sizes(pl, walk + extra)
+        assert host == 4 * g.n_arcs
+        assert dev <= extra
+        assert tiles >= 1
+        if prev is not None:
+            assert tiles >= prev
+        prev = tiles
+    assert L.qw_plan_stream_sizes(pl, walk + (1 << 30))[2] == 1
+    assert _code(lambda: L.qw_plan_stream_sizes(pl, walk)) == L.QW_ENOMEM
+    L.qw_plan_destroy(pl)
+    ell = _create(I.random_regular(500, 4, seed=1), kind=L.QW_CTQW, dtype=L.QW_C64,
+                  layout=L.QW_LAYOUT_STRUCTURED, gamma=0.25, dt=0.5, taylor_order=8)
+    assert _code(lambda: L.qw_plan_stream_sizes(ell, 1 << 30)) == L.QW_EUNSUPPORTED
+    L.qw_plan_destroy(ell)
+    coined = _create(I.erdos_renyi(300, 0.05, seed=2), kind=L.QW_COINED, dtype=L.QW_C64, layout=L.QW_LAYOUT_CSR)
+    assert _code(lambda: L.qw_plan_stream_sizes(coined, 1 << 30)) == L.QW_EUNSUPPORTED
+    L.qw_plan_destroy(coined)

@@ -247,3 +247,112 @@ def test_batch_structured_coined(dtype):
             assert np.abs(mixed[i][1].cpu().numpy() - pref).max() < 1e-12, i
         else:
             assert np.linalg.norm(got - ref) < 1e-5, i
+
+
+def _relabelled(n, edges, seed, name):
+    """A graph with its vertices relabelled by a seeded permutation (no structure to recognise)."""
+    perm = np.random.default_rng(seed).permutation(n)
+    e = perm[np.asarray(edges, dtype=np.int64)]
+    return I.from_edges(n, np.sort(e, axis=1), name=name)
+
+
+def _lds_walks():
+    """CTQW walks on regular graphs of degree 1..8 (the LDS-staged kernel), sized around its
+    tile (4096 rows) and block (16384 complex64 / 8192 complex128 entries) edges, marks on
+    those edges."""
+    m = 6000
+    matching = _relabelled(m, [(2 * i, 2 * i + 1) for i in range(m // 2)], 21, "matching")
+    ring = _relabelled(9001, [(i, (i + 1) % 9001) for i in range(9001)], 22, "ring")
+    return [
+        (matching, dict(gamma=1.0, dt=0.4, taylor_order=10, marked=[4095]), 5),
+        (ring, dict(gamma=0.5, dt=0.3, taylor_order=12, marked=[8191]), 7),
+        (I.random_regular(4096, 3, seed=31), dict(gamma=1 / 3, dt=0.5, taylor_order=14, marked=[4095]), 6),
+        (I.random_regular(4097 + 1, 5, seed=32), dict(gamma=0.2, dt=0.5, taylor_order=14, marked=[4096]), 5),
+        (I.random_regular(16384, 4, seed=33), dict(gamma=0.25, dt=0.4, taylor_order=13, marked=[16383]), 4),
+        (I.random_regular(16386, 6, seed=34), dict(gamma=1 / 6, dt=0.5, taylor_order=12, marked=[16384]), 4),
+        (I.random_regular(40001 + 1, 7, seed=35), dict(gamma=1 / 7, dt=0.5, taylor_order=14, marked=[32768]), 3),
+        (I.random_regular(1000, 8, seed=36), dict(gamma=0.125, dt=0.5, taylor_order=2, marked=[999]), 9),
+        (I.random_regular(200000, 8, seed=37), dict(gamma=0.125, dt=0.5, taylor_order=12, marked=[123456]), 2),
+    ]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_lds_kernel(dtype):
+    """The LDS-staged kernel on ragged tiles and blocks: bitwise equal to the gather kernel, to the
+    walk alone in the batch, and to the single-walk path; equal to the FP64 oracle."""
+    walks = _lds_walks()
+    entries = []
+    for i, (g, params, steps) in enumerate(walks):
+        pl = _plan(g, "ctqw", dict(params, layout="structured"), dtype)
+        assert pl.structure == "ell", (i, pl.structure)
+        entries.append((pl, _psi0(pl, 400 + i), steps))
+    print(f"[case] batch lds kernel {dtype} walks={len(walks)}", flush=True)
+    from paper_2406_08186_amd.walk import Batch
+
+    def run(kernel, ents):
+        b = Batch(capacity=len(ents), max_tiles=4096, dtype=dtype)
+        b.set_stage_kernel(kernel)
+        states = []
+        for slot, (pl, psi0, steps) in enumerate(ents):
+            psi = pl.state(psi0)
+            b.set_slot(slot, pl, psi, steps)
+            states.append(psi)
+        b.commit()
+        assert b.schedule()["stage_kernel"] == kernel
+        b.run_to_completion()
+        outs = []
+        for slot in range(len(ents)):
+            p, norm, pm = b.readout(slot)
+            outs.append((states[slot].clone(), p.clone(), float(norm), float(pm)))
+        torch.cuda.synchronize()
+        b.close()
+        return outs
+
+    lds = run("lds", entries)
+    gat = run("gather", entries)
+    for i, (pl, psi0, steps) in enumerate(entries):
+        assert torch.equal(lds[i][0], gat[i][0]), f"walk {i}: LDS-staged and gather kernels differ"
+        assert torch.equal(lds[i][1], gat[i][1]), i
+        alone = run("lds", [entries[i]])[0]
+        assert torch.equal(alone[0], lds[i][0]), f"walk {i} differs alone vs in the mix"
+        plain = pl.state(psi0)
+        pl.evolve(plain, steps)
+        torch.cuda.synchronize()
+        assert torch.equal(plain, lds[i][0]), f"walk {i}: single-walk path differs"
+        g, params, _ = walks[i]
+        ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps, gamma=params["gamma"], dt=params["dt"],
+                                 K=params["taylor_order"], marked=params["marked"])
+        got = lds[i][0].cpu().numpy().astype(np.complex128)
+        if dtype == "c128":
+            assert np.abs(got - ref).max() < 1e-12, i
+            assert np.abs(lds[i][1].cpu().numpy() - oracle.vertex_prob(ref)).max() < 1e-12, i
+        else:
+            assert np.linalg.norm(got - ref) < 1e-5, i
+        assert abs(lds[i][2] - float(np.sum(np.abs(got) ** 2))) < 1e-6
+
+
+def test_batch_lds_history_and_probe():
+    """p_marked history from the LDS-staged kernel equals the oracle's, and the autotuner's
+    probe launches leave states and the launch counter untouched."""
+    from paper_2406_08186_amd.walk import Batch
+    g = I.random_regular(20000, 6, seed=41)
+    params = dict(gamma=1 / 6, dt=0.5, taylor_order=14, marked=[19999])
+    steps = 12
+    pl = _plan(g, "ctqw", dict(params, layout="structured"), "c128")
+    b = Batch(capacity=2, max_tiles=1024, dtype="c128")
+    psi = pl.state(I.uniform(g.n))
+    hist = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    b.set_slot(0, pl, psi, steps, hist=hist)
+    b.commit()
+    b.autotune(reps=1)
+    assert b.launches == 0 and b.remaining(0) == steps * 14
+    torch.cuda.synchronize()
+    assert torch.equal(psi, pl.state(I.uniform(g.n)))
+    b.run_to_completion()
+    torch.cuda.synchronize()
+    x = I.uniform(g.n)
+    for s in range(steps):
+        x = oracle.ctqw_evolve(g.row_ptr, g.col, x, 1, K=14, gamma=params["gamma"], dt=params["dt"],
+                               marked=params["marked"])
+        assert abs(hist[s].item() - abs(x[19999]) ** 2) < 1e-12, s
+    b.close()

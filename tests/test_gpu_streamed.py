@@ -1,0 +1,118 @@
+"""GPU tests of out-of-core evolution (qw_plan_upload_streamed): the CSR
+neighbour table in pinned host memory, streamed through a device ring at
+every Horner stage under a forced small device budget.  Results equal the
+FP64 oracle (c128 within 1e-12, c64 L2 within 1e-5) and are bitwise the same
+for every tile count."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2406_08186_amd import _lib as L
+from paper_2406_08186_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    yield
+    torch.cuda.synchronize()
+
+
+def _graphs():
+    return [
+        (I.erdos_renyi(3000, 8 / 2999, seed=4), dict(gamma=0.125, dt=0.5, taylor_order=12, marked=[17]), 6),
+        (I.random_mixed(700, seed=3), dict(gamma=0.2, dt=0.3, taylor_order=10, marked=[0, 5]), 9),
+        (I.random_regular(20000, 5, seed=6), dict(gamma=0.2, dt=0.5, taylor_order=14, marked=[19999]), 3),
+    ]
+
+
+def _plan(g, params, dtype):
+    from paper_2406_08186_amd.walk import Plan
+    return Plan(g, "ctqw", dtype=dtype, layout="csr", upload=False, **params)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_streamed_matches_oracle_for_every_budget(dtype):
+    for gi, (g, params, steps) in enumerate(_graphs()):
+        psi0 = I.random_state(g.n, 60 + gi)
+        ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps, gamma=params["gamma"], dt=params["dt"],
+                                 K=params["taylor_order"], marked=params["marked"])
+        pref = oracle.vertex_prob(ref)
+        first = None
+        for extra in (1 << 30, 8 * g.n + 64 * 1024, 8 * g.n + 16 * 1024):
+            pl = _plan(g, params, dtype)
+            walk = pl.info.state_bytes + pl.info.work_bytes
+            sizes = pl.upload_streamed(walk + extra)
+            assert sizes["host_bytes"] == 4 * g.n_arcs
+            print(f"[case] streamed {dtype} graph {gi} n={g.n} tiles={sizes['tiles']}", flush=True)
+            psi = pl.state(psi0)
+            p, norm, pm = pl.evolve(psi, steps, readout=True)
+            torch.cuda.synchronize()
+            got = psi.cpu().numpy().astype(np.complex128)
+            if dtype == "c128":
+                assert np.abs(got - ref).max() < 1e-12, (gi, extra)
+                assert np.abs(p.cpu().numpy() - pref).max() < 1e-12
+                assert abs(float(pm) - pref[params["marked"]].sum()) < 1e-12
+            else:
+                assert np.linalg.norm(got - ref) < 1e-5, (gi, extra)
+            assert abs(float(norm) - float(np.sum(np.abs(got) ** 2))) < 1e-9
+            if first is None:
+                first = (sizes["tiles"], psi.clone())
+            else:
+                assert torch.equal(psi, first[1]), f"graph {gi}: {sizes['tiles']} tiles vs {first[0]}"
+            pl.close()
+        assert first[0] == 1
+
+
+def test_streamed_small_ring_many_tiles_and_rebinding():
+    """A budget whose slots hold little more than the largest row (hundreds of tiles per
+    stage), K = 1 and zero steps, then a plain upload of the same plan: same results."""
+    g = I.erdos_renyi(5000, 12 / 4999, seed=8)
+    params = dict(gamma=1 / 12, dt=0.25, taylor_order=16, marked=[4999])
+    psi0 = I.random_state(g.n, 9)
+    pl = _plan(g, params, "c128")
+    walk = pl.info.state_bytes + pl.info.work_bytes
+    resident = 4 * (g.n + 1) + 4 * ((g.n + 31) // 32) + 3 * 256 + 256
+    sizes = pl.upload_streamed(walk + resident + 3 * 4 * 256)
+    print(f"[case] streamed ring tiles={sizes['tiles']}", flush=True)
+    assert sizes["tiles"] > 100
+    psi = pl.state(psi0)
+    pl.evolve(psi, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(psi, pl.state(psi0))
+    pl.evolve(psi, 4)
+    ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 4, gamma=params["gamma"], dt=params["dt"], K=16,
+                             marked=params["marked"])
+    torch.cuda.synchronize()
+    assert np.abs(psi.cpu().numpy() - ref).max() < 1e-12
+    pl.upload()  # plain binding of the same plan
+    x = pl.state(psi0)
+    pl.evolve(x, 4)
+    torch.cuda.synchronize()
+    assert np.abs(x.cpu().numpy() - ref).max() < 1e-12
+    pl.close()
+    k1 = _plan(g, dict(params, taylor_order=1), "c128")
+    k1.upload_streamed(walk + (1 << 20))
+    y = k1.state(psi0)
+    k1.evolve(y, 3)
+    ref1 = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 3, gamma=params["gamma"], dt=params["dt"], K=1,
+                              marked=params["marked"])
+    torch.cuda.synchronize()
+    assert np.abs(y.cpu().numpy() - ref1).max() < 1e-12
+    k1.close()
+
+
+def test_streamed_plan_cannot_join_a_batch():
+    from paper_2406_08186_amd.walk import Batch
+    g = I.erdos_renyi(400, 0.02, seed=1)
+    pl = _plan(g, dict(gamma=0.2, dt=0.3, taylor_order=8, marked=[1]), "c64")
+    pl.upload_streamed(pl.info.state_bytes + pl.info.work_bytes + (1 << 20))
+    b = Batch(capacity=2, max_tiles=64, dtype="c64")
+    with pytest.raises(L.QwError) as e:
+        b.set_slot(0, pl, pl.state(I.uniform(g.n)), 3)
+    assert e.value.code == L.QW_EUNSUPPORTED
+    b.close()
+    pl.close()
