@@ -457,11 +457,15 @@ def serve_sequential(jobs: list[Job], dtype: str = "c64", device=None, time_limi
 
 
 def latency_stats(jobs: list[Job]) -> dict:
+    """p50 / p99 / mean / max latency of the finished jobs, with the sample count:
+    p99 is interpolated between order statistics, so with n samples it rests on
+    the ceil(n / 100) slowest jobs (`p99_tail_jobs`)."""
     lat = np.array([j.latency for j in jobs if j.status == "done"])
     if lat.size == 0:
-        return {"p50_s": None, "p99_s": None, "mean_s": None}
+        return {"p50_s": None, "p99_s": None, "mean_s": None, "max_s": None, "samples": 0, "p99_tail_jobs": 0}
     return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean())}
+            "mean_s": float(lat.mean()), "max_s": float(lat.max()), "samples": int(lat.size),
+            "p99_tail_jobs": int(-(-lat.size // 100))}
 
 
 # ---- the mixed job stream ------------------------------------------------------

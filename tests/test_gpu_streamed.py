@@ -24,7 +24,8 @@ def _gpu():
 def _graphs():
     return [
         (I.erdos_renyi(3000, 8 / 2999, seed=4), dict(gamma=0.125, dt=0.5, taylor_order=12, marked=[17]), 6),
-        (I.random_mixed(700, seed=3), dict(gamma=0.2, dt=0.3, taylor_order=10, marked=[0, 5]), 9),
+        # a hub of degree 696: gamma and dt keep rho = dt ||H||_inf below 1
+        (I.random_mixed(700, seed=3), dict(gamma=0.002, dt=0.4, taylor_order=10, marked=[0, 5]), 9),
         (I.random_regular(20000, 5, seed=6), dict(gamma=0.2, dt=0.5, taylor_order=14, marked=[19999]), 3),
     ]
 
