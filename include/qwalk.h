@@ -318,6 +318,25 @@ int qw_plan_stream_sizes(const qw_plan *plan, size_t device_budget, size_t *host
 int qw_plan_upload_streamed(qw_plan *plan, size_t device_budget, void *h_pinned, size_t host_bytes, void *d_buf,
                             size_t device_bytes, void *stream);
 
+/* ---- Allocation-free evolution
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): qw_evolve
+ * with its workspace taken from a device array the library holds, of
+ * QW_STATIC_SCRATCH_BYTES bytes on each GPU it runs on (held from the
+ * library's load until the process ends).  Same arguments and results as
+ * qw_evolve(plan, d_psi, <that array>, QW_STATIC_SCRATCH_BYTES, steps, d_p,
+ * d_norm, d_pmarked, stream); the caller still owns the state and the
+ * readout outputs.  The array is looked up on the stream's device at the
+ * first call there.  The call allocates no device memory (no hipMalloc or
+ * hipFree, no allocating library routine).  Every call on one GPU shares that GPU's array,
+ * which keeps the last call's contents (nothing in it needs to start at
+ * zero): calls that overlap on one GPU (two streams, two threads) race and
+ * must be serialised by the caller.  Errors: as qw_evolve, and QW_ENOMEM when
+ * the plan's info.work_bytes exceeds QW_STATIC_SCRATCH_BYTES. */
+#define QW_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int qw_evolve_static(const qw_plan *plan, void *d_psi, int64_t steps, double *d_p, double *d_norm,
+                     double *d_pmarked, void *stream);
+
 /* FP64 readout of a state (Sec. 3.1, Sec. 3.2): d_p[v] = probability of
  * vertex v (coined: summed over arcs with tail v; CTQW and
  * staggered: |psi_v|^2; dense

@@ -36,7 +36,7 @@ EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upl
            "qw_batch_set_slot", "qw_batch_clear_slot", "qw_batch_commit", "qw_batch_run",
            "qw_batch_remaining", "qw_batch_launches", "qw_batch_readout", "qw_batch_set_schedule",
            "qw_batch_autotune", "qw_batch_set_replay", "qw_batch_launch_plan", "qw_batch_set_stage_kernel",
-           "qw_batch_get_schedule", "qw_plan_stream_sizes", "qw_plan_upload_streamed"]
+           "qw_batch_get_schedule", "qw_plan_stream_sizes", "qw_plan_upload_streamed", "qw_evolve_static"]
 
 
 class QwCsr(C.Structure):
@@ -117,6 +117,7 @@ def lib():
         L.qw_batch_set_replay.argtypes = [vp, C.c_int32]
         L.qw_batch_launch_plan.argtypes = [vp, C.c_int64, i64p, i64p]
         L.qw_batch_set_stage_kernel.argtypes = [vp, C.c_int32]
+        L.qw_evolve_static.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp]
         L.qw_plan_stream_sizes.argtypes = [vp, C.c_size_t, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), i64p]
         L.qw_plan_upload_streamed.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, vp]
         L.qw_batch_get_schedule.argtypes = [vp, i32p, i32p, i32p]
@@ -271,6 +272,13 @@ def qw_batch_launch_plan(batch, launches: int) -> tuple[int, int]:
     g, d = C.c_int64(), C.c_int64()
     check(lib().qw_batch_launch_plan(batch, launches, C.byref(g), C.byref(d)), "qw_batch_launch_plan")
     return g.value, d.value
+
+
+QW_STATIC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def qw_evolve_static(plan, d_psi: int, steps: int, d_p, d_norm, d_pmarked, stream: int) -> None:
+    check(lib().qw_evolve_static(plan, d_psi, steps, d_p, d_norm, d_pmarked, stream), "qw_evolve_static")
 
 
 def qw_plan_stream_sizes(plan, device_budget: int) -> tuple[int, int, int]:

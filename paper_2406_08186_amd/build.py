@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqwalk.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["qw_host.cpp", "qw_batch.cpp", "qw_stream.cpp", "qw_kernels.hip"]
+SOURCES = ["qw_host.cpp", "qw_batch.cpp", "qw_stream.cpp", "qw_kernels.hip", "qw_static.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
