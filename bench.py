@@ -449,9 +449,9 @@ def run_batch(args):
                             range(len(specs))))
     plan_s = time.perf_counter() - t0
     total_rows = sum(g.n for g in graphs)
-    # tiles at 256 rows or more, plus the XCD padding (8 lists, each at most the
-    # mean plus the largest walk's tiles under longest-first placement)
-    max_tiles = total_rows // 256 + len(graphs) + 8 * (max(g.n for g in graphs) // 256 + 1) + 64
+    # tiles at 256 rows or more, plus the XCD padding (8 lists, each about the mean plus the
+    # largest walk's tiles under longest-first placement by load), with a tenth to spare
+    max_tiles = int(1.1 * (total_rows // 256 + len(graphs) + 8 * (max(g.n for g in graphs) // 256 + 1) + 64))
     batch = Batch(capacity=len(plans), max_tiles=max_tiles, dtype="c64")
     states, hists = [], []
     for i, pl in enumerate(plans):
@@ -1128,12 +1128,16 @@ def run_streamed(args):
     psi0 = I.uniform(g.n)
     res = {}
 
+    host_ms = {}
+
     def timed(pl, psi):
         pl.evolve(psi, 1)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
+        t1 = time.perf_counter()
         pl.evolve(psi, steps)
+        host_ms[id(pl)] = (time.perf_counter() - t1) * 1e3  # enqueue time on the host
         b.record()
         torch.cuda.synchronize()
         return a.elapsed_time(b)
@@ -1180,6 +1184,7 @@ def run_streamed(args):
             "device_graph_bytes": sizes["device_bytes"], "tiles_per_stage": sizes["tiles"],
             "stage_ms_streamed": ms_stream / stages, "stage_ms_in_core": ms_core / stages,
             "stage_ms_copies_only": ms_copy / stages,
+            "stage_ms_host_enqueue_streamed": host_ms[id(pl)] / stages,
             "h2d_gbs_streamed": 4 * g.n_arcs * stages / (ms_stream * 1e-3) / 1e9,
             "h2d_gbs_copies_only": 4 * g.n_arcs * stages / (ms_copy * 1e-3) / 1e9,
             "overlap_of_compute": max(0.0, min(1.0, (ms_copy + ms_core - ms_stream) / ms_core)),

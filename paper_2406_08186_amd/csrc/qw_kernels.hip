@@ -55,6 +55,35 @@ __device__ __forceinline__ bool marked(const uint32_t *bits, int v) {
   return (bits[v >> 5] >> (v & 31)) & 1u;
 }
 
+// Global-address-space views of pointers that kernels read from tables in
+// memory (the batch's slot table).  The compiler cannot tell where such a
+// pointer points and would address through flat instructions, which count
+// against the LDS wait counter too; through these views it emits global
+// loads and stores.
+#define QW_GLOBAL __attribute__((address_space(1)))
+template <typename T> using gptr = const QW_GLOBAL T *;
+template <typename T> using gmut = QW_GLOBAL T *;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(const T *p) { return (gptr<T>)p; }
+template <typename T> __device__ __forceinline__ gmut<T> as_global_mut(T *p) { return (gmut<T>)p; }
+// Complex elements through such views are moved as the compiler's own
+// two-element vectors (one 8- or 16-byte access each).
+typedef float qw_f2v __attribute__((ext_vector_type(2)));
+typedef double qw_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gld(gptr<float2> p, int64_t i) {
+  const qw_f2v v = reinterpret_cast<const QW_GLOBAL qw_f2v *>(p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 gld(gptr<double2> p, int64_t i) {
+  const qw_d2v v = reinterpret_cast<const QW_GLOBAL qw_d2v *>(p)[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(gmut<float2> p, int64_t i, float2 v) {
+  reinterpret_cast<QW_GLOBAL qw_f2v *>(p)[i] = qw_f2v{v.x, v.y};
+}
+__device__ __forceinline__ void gst(gmut<double2> p, int64_t i, double2 v) {
+  reinterpret_cast<QW_GLOBAL qw_d2v *>(p)[i] = qw_d2v{v.x, v.y};
+}
+
 // The value x holds in lane `src` of the wavefront (a cross-lane permute).
 __device__ __forceinline__ float2 lane_pull(float2 x, int src) {
   return make_float2(__shfl(x.x, src, 64), __shfl(x.y, src, 64));
@@ -1432,8 +1461,14 @@ __device__ void batch_ctqw_tile(const WalkSlot &w, const TileEntry &te, int64_t 
   if (w.ell_d > 0 && w.ell_d <= 8) {
     // regular graph: two rows per lane, every index load and then every gather
     // of both rows issued before the first add (row r1 clamped to a valid row
-    // when it is past the tile; its result is then discarded)
+    // when it is past the tile; its result is then discarded).  Memory is
+    // reached through global views of the slot's pointers (global, not flat,
+    // instructions).
     const int d = w.ell_d, n = w.n;
+    const gptr<int32_t> col = as_global(w.col);
+    const gptr<uint32_t> bits = as_global(w.markbits);
+    const gptr<T> gpsi = as_global(psi), gyin = as_global(yin);
+    const gmut<T> gyout = as_global_mut(yout);
     for (int r0 = te.begin + threadIdx.x; r0 < te.end; r0 += 2 * blockDim.x) {
       const int r1raw = r0 + blockDim.x;
       const bool h1 = r1raw < te.end;
@@ -1442,17 +1477,18 @@ __device__ void batch_ctqw_tile(const WalkSlot &w, const TileEntry &te, int64_t 
 #pragma unroll
       for (int j = 0; j < 8; ++j)
         if (j < d) {
-          c0[j] = w.col[static_cast<int64_t>(j) * n + r0];
-          c1[j] = w.col[static_cast<int64_t>(j) * n + r1];
+          c0[j] = col[static_cast<int64_t>(j) * n + r0];
+          c1[j] = col[static_cast<int64_t>(j) * n + r1];
         }
-      const double2 p0 = ld(psi, r0), p1 = ld(psi, r1);
-      const bool m0 = marked(w.markbits, r0), m1 = marked(w.markbits, r1);
+      const T p0 = gld(gpsi, r0), p1 = gld(gpsi, r1);
+      const T s0v = gld(gyin, r0), s1v = gld(gyin, r1);
+      const uint32_t mw0 = bits[r0 >> 5], mw1 = bits[r1 >> 5];
       T x0[8], x1[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j)
         if (j < d) {
-          x0[j] = yin[c0[j]];
-          x1[j] = yin[c1[j]];
+          x0[j] = gld(gyin, c0[j]);
+          x1[j] = gld(gyin, c1[j]);
         }
       double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
 #pragma unroll
@@ -1461,12 +1497,13 @@ __device__ void batch_ctqw_tile(const WalkSlot &w, const TileEntry &te, int64_t 
           s0 = add(s0, cvt(x0[j]));
           s1 = add(s1, cvt(x1[j]));
         }
-      const double2 yv0 = m0 ? ld(yin, r0) : make_double2(0.0, 0.0);
-      const double2 yv1 = m1 ? ld(yin, r1) : make_double2(0.0, 0.0);
-      const T o0 = pack<T>(horner_out(p0, s0, yv0, m0, alpha, beta));
-      const T o1 = pack<T>(horner_out(p1, s1, yv1, m1, alpha, beta));
-      yout[r0] = o0;
-      if (h1) yout[r1] = o1;
+      const bool m0 = (mw0 >> (r0 & 31)) & 1u, m1 = (mw1 >> (r1 & 31)) & 1u;
+      const double2 yv0 = m0 ? cvt(s0v) : make_double2(0.0, 0.0);
+      const double2 yv1 = m1 ? cvt(s1v) : make_double2(0.0, 0.0);
+      const T o0 = pack<T>(horner_out(cvt(p0), s0, yv0, m0, alpha, beta));
+      const T o1 = pack<T>(horner_out(cvt(p1), s1, yv1, m1, alpha, beta));
+      gst(gyout, r0, o0);
+      if (h1) gst(gyout, r1, o1);
       if (k == 1 && w.hist) {
         if (m0) atomicAdd(&w.hist[step], abs2(cvt(o0)));
         if (h1 && m1) atomicAdd(&w.hist[step], abs2(cvt(o1)));
@@ -1627,9 +1664,13 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
 // registers.  The plan stores each row's neighbours in increasing order, so
 // adding, block after block, the neighbours each block holds adds them in row
 // order: the sums are bitwise those of the gather kernels.  The next block is
-// prefetched into registers while the current one is summed.  Tiles are taken
-// grid-stride (the host lays out the table by XCD); the last workgroup of the
-// launch advances the launch counter when `advance` is set.
+// prefetched into registers while the current one is summed.
+// Memory is reached through global-address-space views of the slot table's
+// pointers, and every load is unconditional (indices clamped into range,
+// unused values dropped by a select), so a wave issues all of a phase's loads
+// before it waits, and waits on LDS reads never wait for memory loads.
+// Tiles are taken grid-stride (the host lays out the table by XCD); the last
+// workgroup of the launch advances the launch counter when `advance` is set.
 template <typename T, int NT, int RPL, int BLK>
 __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkSlot *slots,
                                                       const TileEntry *tiles, const int32_t *n_tiles,
@@ -1651,28 +1692,39 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
     const int K = w.K;
     const int64_t step = u / K;
     const int k = K - static_cast<int>(u % K);
-    const T *psi = static_cast<const T *>(w.psi);
-    const T *yin = (k == K) ? psi : static_cast<const T *>(((K - k - 1) & 1) ? w.w1 : w.w0);
-    T *yout = (k == 1) ? static_cast<T *>(w.psi) : static_cast<T *>(((K - k) & 1) ? w.w1 : w.w0);
-    const double alpha = w.alpha[k - 1], beta = w.beta[k - 1];
+    const gptr<T> psi = as_global(static_cast<const T *>(w.psi));
+    const gptr<T> yin = (k == K) ? psi : as_global(static_cast<const T *>(((K - k - 1) & 1) ? w.w1 : w.w0));
+    const gmut<T> yout = as_global_mut(static_cast<T *>((k == 1) ? w.psi : (((K - k) & 1) ? w.w1 : w.w0)));
+    const gptr<int32_t> col = as_global(w.col);
+    const gptr<uint32_t> bits = as_global(w.markbits);
+    const double alpha = as_global(w.alpha)[k - 1], beta = as_global(w.beta)[k - 1];
     const int n = w.n, d = w.ell_d;
     // neighbour indices of this lane's rows; 0x7fffffff (never inside a block) pads
-    // missing neighbours and rows past the tile
+    // missing neighbours and rows past the tile (their loads read a valid entry).
+    // All loads of a phase are issued before its first use (scheduling barrier).
     int c[RPL][8];
     double2 acc[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       const int r = te.begin + tid + i * NT;
-      const bool ok = r < te.end;
+      const int rc = r < te.end ? r : te.end - 1;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) c[i][j] = (ok && j < d) ? w.col[static_cast<int64_t>(j) * n + r] : 0x7fffffff;
+      for (int j = 0; j < 8; ++j) c[i][j] = col[static_cast<int64_t>(j < d ? j : d - 1) * n + rc];
       acc[i] = make_double2(0.0, 0.0);
     }
+    // entries past n are staged as copies of entry n-1 and never read
     T pf[PF];
 #pragma unroll
     for (int e = 0; e < PF; ++e) {
       const int idx = tid + e * NT;
-      pf[e] = idx < n ? yin[idx] : T{};
+      pf[e] = gld(yin, idx < n ? idx : n - 1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const bool ok = te.begin + tid + i * NT < te.end;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) c[i][j] = (ok && j < d) ? c[i][j] : 0x7fffffff;
     }
     for (int base = 0; base < n; base += BLK) {
       __syncthreads();  // the previous block (or tile) is no longer read
@@ -1684,7 +1736,7 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
 #pragma unroll
         for (int e = 0; e < PF; ++e) {
           const int idx = nxt + tid + e * NT;
-          pf[e] = idx < n ? yin[idx] : T{};
+          pf[e] = gld(yin, idx < n ? idx : n - 1);
         }
       }
 #pragma unroll
@@ -1695,14 +1747,26 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
           if (off < static_cast<unsigned>(BLK)) acc[i] = add(acc[i], cvt(xs[off]));
         }
     }
+    T pv[RPL], yv[RPL];
+    uint32_t mw[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       const int r = te.begin + tid + i * NT;
+      const int rc = r < te.end ? r : te.end - 1;
+      pv[i] = gld(psi, rc);
+      yv[i] = gld(yin, rc);
+      mw[i] = bits[rc >> 5];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int r = te.begin + tid + i * NT;
+      const int rc = r < te.end ? r : te.end - 1;
+      const bool mk = (mw[i] >> (rc & 31)) & 1u;
+      const double2 y_self = mk ? cvt(yv[i]) : make_double2(0.0, 0.0);
+      const T o = pack<T>(horner_out(cvt(pv[i]), acc[i], y_self, mk, alpha, beta));
       if (r < te.end) {
-        const bool mk = marked(w.markbits, r);
-        const double2 yv = mk ? ld(yin, r) : make_double2(0.0, 0.0);
-        const T o = pack<T>(horner_out(ld(psi, r), acc[i], yv, mk, alpha, beta));
-        yout[r] = o;
+        gst(yout, r, o);
         if (k == 1 && mk && w.hist) atomicAdd(&w.hist[step], abs2(cvt(o)));
       }
     }
