@@ -42,7 +42,11 @@ METRIC = "arc-steps/s (c64 batched vs c128 plain, L2 err<=1e-4); p50/p99 latency
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a
 # 256 MiB copy (x2.00 / x1.00).  Each entry holds only for the kernel version
 # and launch configuration named in its key and source; any other reports None.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # profiles/batch4096_ctqw_search_lds.md: mean over the 5120 timed launches of the
+    # default command, FETCH_SIZE 2,896,834.5 KiB x 2.00 + WRITE_SIZE 1,164,456.9 KiB x 1.00
+    "k_batch_ell_lds<float2,1024,4,16384> batch4096 seed1 launches1280-6400": (2896834.5 * 2 + 1164456.9) * 1024,
+}
 
 
 def parse():
@@ -84,6 +88,7 @@ def parse():
     ap.add_argument("--stream-steps", type=int, default=3, help="streamed workload: timed time steps")
     ap.add_argument("--stream-budget-mib", type=int, default=64,
                     help="streamed workload: device MiB for the streamed graph beyond state and workspace")
+    ap.add_argument("--progress", action="store_true", help="batch: a stderr line per timed step as it is enqueued")
     ap.add_argument("--gen-only", action="store_true",
                     help="batch: only draw the graphs into --graph-cache (no GPU) and exit")
     ap.add_argument("--serve-jobs", type=int, default=120)
@@ -488,11 +493,12 @@ def run_batch(args):
     def finished_between(la, lb):
         return [i for i in range(len(plans)) if la < units[i] <= lb]
 
-    for _ in range(args.warmup):
+    for w in range(args.warmup):
         la = batch.launches
         batch.run(CH)
         for i in finished_between(la, batch.launches):
             batch.readout(i)
+        print(f"[batch] warm-up step {w + 1}/{args.warmup} enqueued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     La = batch.launches
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
@@ -505,6 +511,8 @@ def run_batch(args):
         for i in finished_between(la, batch.launches):  # fused-path readout of walks that just ended
             batch.readout(i)
         ev[k][2].record()
+        if args.progress:
+            print(f"[batch] step {k + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     Lb = batch.launches

@@ -143,7 +143,10 @@ int wait_stage(qw_batch *b) {
 
 // True when a slot's CTQW walk runs on the LDS-staged kernel.
 bool lds_slot(const qw_batch *b, const WalkSlot &w) {
-  return b->stage_kernel == QW_BATCH_LDS && w.kind == QW_CTQW && w.ell_d >= 1 && w.ell_d <= 8;
+  // the LDS-staged kernel addresses the vector by 32-bit byte offsets
+  const int64_t elem = b->dtype == QW_C128 ? 16 : 8;
+  return b->stage_kernel == QW_BATCH_LDS && w.kind == QW_CTQW && w.ell_d >= 1 && w.ell_d <= 8 &&
+         static_cast<int64_t>(w.n) * elem < (int64_t{1} << 31);
 }
 
 // Lay out walks' tiles by XCD: longest walks first, each onto the XCD with

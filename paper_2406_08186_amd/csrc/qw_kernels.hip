@@ -1664,7 +1664,10 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
 // registers.  The plan stores each row's neighbours in increasing order, so
 // adding, block after block, the neighbours each block holds adds them in row
 // order: the sums are bitwise those of the gather kernels.  The next block is
-// prefetched into registers while the current one is summed.
+// prefetched into registers while the current one is summed.  Every lane
+// visits all 8 neighbour slots of its rows in every block (branch-free; a
+// slot outside the block adds -0), so the sum loop costs 8 LDS reads per row
+// and block: the kernel pays for walks whose vector spans many blocks.
 // Memory is reached through global-address-space views of the slot table's
 // pointers, and every load is unconditional (indices clamped into range,
 // unused values dropped by a select), so a wave issues all of a phase's loads
@@ -1677,7 +1680,15 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
                                                       int advance) {
   static_assert(BLK % NT == 0, "a block is staged as whole rounds of the workgroup");
   constexpr int PF = BLK / NT;
-  __shared__ T xs[BLK];
+  constexpr unsigned kPadByte = static_cast<unsigned>(BLK) * static_cast<unsigned>(sizeof(T));
+  // xs[BLK] is a pad entry holding (-0, -0): a neighbour outside the current
+  // block reads it, and adding -0 leaves every value (either zero included)
+  // bit for bit unchanged, so the sum loop has no branch
+  __shared__ T xs[BLK + 1];
+  if (threadIdx.x == 0) {
+    xs[BLK].x = -0.0;
+    xs[BLK].y = -0.0;
+  }
   const int64_t L = static_cast<int64_t>(ctl->L);
   const bool probe = ctl->probe != 0;
   const int nt = *n_tiles;
@@ -1720,11 +1731,12 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
       pf[e] = gld(yin, idx < n ? idx : n - 1);
     }
     __builtin_amdgcn_sched_barrier(0);
+    // held as byte offsets into the vector (the host keeps n * sizeof(T) below 2^31)
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       const bool ok = te.begin + tid + i * NT < te.end;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) c[i][j] = (ok && j < d) ? c[i][j] : 0x7fffffff;
+      for (int j = 0; j < 8; ++j) c[i][j] = (ok && j < d) ? c[i][j] * static_cast<int>(sizeof(T)) : 0x7fffffff;
     }
     for (int base = 0; base < n; base += BLK) {
       __syncthreads();  // the previous block (or tile) is no longer read
@@ -1739,12 +1751,22 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
           pf[e] = gld(yin, idx < n ? idx : n - 1);
         }
       }
+      // four LDS reads in flight per group, then their adds in neighbour order;
+      // a byte offset outside the block (below it, it wraps) clamps to the pad
+      const unsigned base_b = static_cast<unsigned>(base) * static_cast<unsigned>(sizeof(T));
+      const char *xs_b = reinterpret_cast<const char *>(xs);
 #pragma unroll
       for (int i = 0; i < RPL; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const unsigned off = static_cast<unsigned>(c[i][j] - base);
-          if (off < static_cast<unsigned>(BLK)) acc[i] = add(acc[i], cvt(xs[off]));
+        for (int h = 0; h < 8; h += 4) {
+          T xv[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const unsigned off = min(static_cast<unsigned>(c[i][h + j]) - base_b, kPadByte);
+            xv[j] = *reinterpret_cast<const T *>(xs_b + off);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i] = add(acc[i], cvt(xv[j]));
         }
     }
     T pv[RPL], yv[RPL];
