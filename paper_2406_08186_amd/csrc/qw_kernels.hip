@@ -4,8 +4,10 @@
 // kernel loads T, does its arithmetic in FP64 registers and rounds once when
 // it stores, so a complex64 walk differs from the FP64 one only by one
 // rounding of each stored amplitude per kernel (no systematically biased
-// coefficient such as a rounded 2/d).  All reductions are FP64 with a fixed
-// order, so results are bitwise reproducible.
+// coefficient such as a rounded 2/d).  The one exception is the blocked grid
+// sweep, which computes complex64 in FP32 with every coefficient split into
+// two floats (still no rounded coefficient).  All reductions are FP64 with a
+// fixed order, so results are bitwise reproducible.
 //
 // Coined step (Hiperwalk Sec. 3.2): psi' = S C psi with the flip-flop shift
 // S|v,w> = |w,v> and, per vertex block, the Grover coin
@@ -837,6 +839,14 @@ struct Coefs {
   double alpha[64];
   double beta[64];
 };
+// The same coefficients for FP32 arithmetic, each split into a float head and
+// the float rounding of its remainder (alpha = hi + lo to about 2^-48
+// relative), so that no coefficient of the propagator carries an FP32 rounding
+// error from step to step: only the arithmetic rounds.
+struct CoefsF32 {
+  float ahi[64], alo[64];
+  float bhi[64], blo[64];
+};
 
 // ---- one-lane wavefront shifts ---------------------------------------------------------
 template <int CTRL>
@@ -871,18 +881,49 @@ __device__ __forceinline__ float2 lane_shift(float2 v) {
 // outermost lanes read zeros, so the valid columns shrink by one per stage and
 // the core 64 - 2S lanes are exact after S stages.  Stage s starts at t = 2s,
 // where its rows become exact, and the last stage stores each core row as soon
-// as it is computed.  Values stay FP64 across the stages of a launch and are
-// rounded to the storage type once, when stored; the neighbours are summed in
-// the one-stage kernel's order.  Strips at the grid's right and bottom edges are
-// clamped and overlap their neighbour; duplicate stores write equal values.
+// as it is computed.  The sweep computes in its storage type: complex128 in
+// FP64, complex64 in FP32 with split coefficients (CoefsF32), which halves the
+// lane shifts (one DPP move per float instead of two per double) and needs no
+// conversions; the neighbours are summed in the one-stage kernel's order.
+// Strips at the grid's right and bottom edges are clamped and overlap their
+// neighbour; duplicate stores write equal values.
 constexpr int kSweepRing = 6;  // rows per unrolled body; holds psi for S <= 5 stages
 
 __device__ __forceinline__ constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
+template <typename T> struct SweepCoefs;
+template <> struct SweepCoefs<double2> { using type = Coefs; };
+template <> struct SweepCoefs<float2> { using type = CoefsF32; };
+
+__device__ __forceinline__ float2 sweep_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 sweep_add(double2 a, double2 b) { return add(a, b); }
+__device__ __forceinline__ float2 sweep_zero(float2) { return make_float2(0.0f, 0.0f); }
+__device__ __forceinline__ double2 sweep_zero(double2) { return make_double2(0.0, 0.0); }
+
+// psi + i (alpha nsum + beta [marked] y) at stage k (index k - 1)
+__device__ __forceinline__ double2 sweep_out(double2 psi, double2 nsum, double2 yv, bool mk, const Coefs &c,
+                                             int ki) {
+  return horner_out(psi, nsum, yv, mk, c.alpha[ki], c.beta[ki]);
+}
+__device__ __forceinline__ float2 sweep_out(float2 psi, float2 nsum, float2 yv, bool mk, const CoefsF32 &c,
+                                            int ki) {
+  float re = __fmaf_rn(-c.ahi[ki], nsum.y, psi.x);
+  float im = __fmaf_rn(c.ahi[ki], nsum.x, psi.y);
+  re = __fmaf_rn(-c.alo[ki], nsum.y, re);
+  im = __fmaf_rn(c.alo[ki], nsum.x, im);
+  if (mk) {
+    re = __fmaf_rn(-c.bhi[ki], yv.y, re);
+    im = __fmaf_rn(c.bhi[ki], yv.x, im);
+    re = __fmaf_rn(-c.blo[ki], yv.y, re);
+    im = __fmaf_rn(c.blo[ki], yv.x, im);
+  }
+  return make_float2(re, im);
+}
+
 template <typename T, int S, bool YP, bool MARK>
 __device__ __forceinline__ void sweep_strip(const GraphView &g, const T *__restrict__ P, const T *__restrict__ Yin,
-                                            T *__restrict__ Out, int kfirst, const Coefs &c, int R, int rb,
-                                            int lane, int gcol, unsigned boff) {
+                                            T *__restrict__ Out, int kfirst, const typename SweepCoefs<T>::type &c,
+                                            int R, int rb, int lane, int gcol, unsigned boff) {
   constexpr int RING = kSweepRing, W = 64;
   static_assert(S >= 2 && S < RING, "psi ring holds rows t-S .. t");
   const int l1 = g.dims[0], l2 = g.dims[1];
@@ -911,15 +952,15 @@ __device__ __forceinline__ void sweep_strip(const GraphView &g, const T *__restr
       }
     }
   };
-  double2 yv[S][3];  // stage s-1 (s = 1 .. S) rows, slot = window row mod 3
-  double2 pr[RING];  // psi, slot = window row mod RING
+  T yv[S][3];        // stage s-1 (s = 1 .. S) rows, slot = window row mod 3
+  T pr[RING];        // psi, slot = window row mod RING
   uint32_t mr = 0;   // bit k: window row t - k is marked
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) yv[s][j] = make_double2(0.0, 0.0);
+    for (int j = 0; j < 3; ++j) yv[s][j] = sweep_zero(T{});
 #pragma unroll
-  for (int j = 0; j < RING; ++j) pr[j] = make_double2(0.0, 0.0);
+  for (int j = 0; j < RING; ++j) pr[j] = sweep_zero(T{});
 
   // one body: window rows t0 .. t0 + RING - 1.  FULL: every row exists and
   // every stage is past its warm-up, so the body has no branches.
@@ -941,27 +982,26 @@ __device__ __forceinline__ void sweep_strip(const GraphView &g, const T *__restr
     for (int i = 0; i < RING; ++i) {
       const int t = t0 + i;  // t0 is a multiple of RING, so every ring slot below is static
       if (!FULL && t >= n_in) break;
-      yv[0][i % 3] = cvt(cy[i]);
-      pr[i] = cvt(cp[i]);
+      yv[0][i % 3] = cy[i];
+      pr[i] = cp[i];
       if (MARK) mr = (mr << 1) | ((cmw[i] >> cms[i]) & 1u);
 #pragma unroll
       for (int st = 1; st <= S; ++st) {
         if (!FULL && t < 2 * st) break;  // window rows above stage st's exact region
-        const double2 up = yv[st - 1][pmod(i - st - 1, 3)];
-        const double2 self = yv[st - 1][pmod(i - st, 3)];
-        const double2 dn = yv[st - 1][pmod(i - st + 1, 3)];
-        const double2 left = lane_shift<kFromLower>(self), right = lane_shift<kFromUpper>(self);
+        const T up = yv[st - 1][pmod(i - st - 1, 3)];
+        const T self = yv[st - 1][pmod(i - st, 3)];
+        const T dn = yv[st - 1][pmod(i - st + 1, 3)];
+        const T left = lane_shift<kFromLower>(self), right = lane_shift<kFromUpper>(self);
         // the one-stage kernel's order: right, left, below, above
-        double2 sum = add(right, left);
-        sum = add(sum, dn);
-        sum = add(sum, up);
+        T sum = sweep_add(right, left);
+        sum = sweep_add(sum, dn);
+        sum = sweep_add(sum, up);
         const bool m = MARK && ((mr >> st) & 1u);
-        const double2 val = horner_out(pr[pmod(i - st, RING)], sum, self, m, c.alpha[kfirst - st],
-                                       c.beta[kfirst - st]);
+        const T val = sweep_out(pr[pmod(i - st, RING)], sum, self, m, c, kfirst - st);
         if (st < S) {
           yv[st][pmod(i - st, 3)] = val;
         } else if (lane >= S && lane < W - S) {
-          *reinterpret_cast<T *>(reinterpret_cast<char *>(Out + row_off(t - S)) + boff) = pack<T>(val);
+          *reinterpret_cast<T *>(reinterpret_cast<char *>(Out + row_off(t - S)) + boff) = val;
         }
       }
     }
@@ -976,7 +1016,8 @@ __device__ __forceinline__ void sweep_strip(const GraphView &g, const T *__restr
 template <typename T, int S, bool YP>
 __global__ __launch_bounds__(64 * kStripWaves) void k_ctqw_torus_sweep(GraphView g, const T *__restrict__ P,
                                                                        const T *__restrict__ Yin,
-                                                                       T *__restrict__ Out, int kfirst, Coefs c) {
+                                                                       T *__restrict__ Out, int kfirst,
+                                                                       typename SweepCoefs<T>::type c) {
   constexpr int CORE = 64 - 2 * S;
   const int l1 = g.dims[0], l2 = g.dims[1], R = g.strip_rows;
   const int tiles_c = (l2 + CORE - 1) / CORE, tiles_r = (l1 + R - 1) / R;
@@ -1710,8 +1751,8 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
     const gptr<uint32_t> bits = as_global(w.markbits);
     const double alpha = as_global(w.alpha)[k - 1], beta = as_global(w.beta)[k - 1];
     const int n = w.n, d = w.ell_d;
-    // neighbour indices of this lane's rows; 0x7fffffff (never inside a block) pads
-    // missing neighbours and rows past the tile (their loads read a valid entry).
+    // neighbour indices of this lane's rows; missing neighbours and rows past the
+    // tile (their loads read a valid entry) become the pad offset below.
     // All loads of a phase are issued before its first use (scheduling barrier).
     int c[RPL][8];
     double2 acc[RPL];
@@ -1731,12 +1772,14 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
       pf[e] = gld(yin, idx < n ? idx : n - 1);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // held as byte offsets into the vector (the host keeps n * sizeof(T) below 2^31)
+    // held as byte offsets into the vector (the host keeps n * sizeof(T) below 2^31);
+    // a pad is 0xffffffff, whose offset from any block start (below 2^31) is at
+    // least 2^31 and so always clamps to the pad entry
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       const bool ok = te.begin + tid + i * NT < te.end;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) c[i][j] = (ok && j < d) ? c[i][j] * static_cast<int>(sizeof(T)) : 0x7fffffff;
+      for (int j = 0; j < 8; ++j) c[i][j] = (ok && j < d) ? c[i][j] * static_cast<int>(sizeof(T)) : -1;
     }
     for (int base = 0; base < n; base += BLK) {
       __syncthreads();  // the previous block (or tile) is no longer read
@@ -2551,8 +2594,8 @@ int torus_block_depth(bool c128, const GraphView &g, int K) {
 }
 
 template <typename T, int S>
-hipError_t launch_sweep(const GraphView &g, const void *P, const void *Yin, void *Out, int kfirst, const Coefs &c,
-                        hipStream_t s) {
+hipError_t launch_sweep(const GraphView &g, const void *P, const void *Yin, void *Out, int kfirst,
+                        const typename SweepCoefs<T>::type &c, hipStream_t s) {
   const StripGrid sg = torus_strips(sizeof(T) == 16, g.dims[0], g.dims[1], S);
   if (sg.count() == 0 || sg.rows != g.strip_rows || !g.tmark) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>((sg.count() + kStripWaves - 1) / kStripWaves)), block(64 * kStripWaves);
@@ -2566,12 +2609,12 @@ hipError_t launch_sweep(const GraphView &g, const void *P, const void *Yin, void
 
 hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *P, const void *Yin, void *Out,
                               int kfirst, const double *alpha, const double *beta, hipStream_t s) {
-  Coefs c;
-  for (int k = 0; k < 64; ++k) {
-    c.alpha[k] = alpha[k];
-    c.beta[k] = beta[k];
-  }
   if (c128) {
+    Coefs c;
+    for (int k = 0; k < 64; ++k) {
+      c.alpha[k] = alpha[k];
+      c.beta[k] = beta[k];
+    }
     switch (S) {
       case 5: return launch_sweep<double2, 5>(g, P, Yin, Out, kfirst, c, s);
       case 4: return launch_sweep<double2, 4>(g, P, Yin, Out, kfirst, c, s);
@@ -2579,6 +2622,13 @@ hipError_t torus_block_stages(bool c128, const GraphView &g, int S, const void *
       case 2: return launch_sweep<double2, 2>(g, P, Yin, Out, kfirst, c, s);
       default: return hipErrorInvalidValue;
     }
+  }
+  CoefsF32 c;
+  for (int k = 0; k < 64; ++k) {
+    c.ahi[k] = static_cast<float>(alpha[k]);
+    c.alo[k] = static_cast<float>(alpha[k] - static_cast<double>(c.ahi[k]));
+    c.bhi[k] = static_cast<float>(beta[k]);
+    c.blo[k] = static_cast<float>(beta[k] - static_cast<double>(c.bhi[k]));
   }
   switch (S) {
     case 5: return launch_sweep<float2, 5>(g, P, Yin, Out, kfirst, c, s);
