@@ -294,8 +294,11 @@ int qw_evolve(const qw_plan *plan, void *d_psi, void *d_work, size_t work_bytes,
  * largest table, the neighbour indices (4 bytes per arc), in caller-pinned
  * host memory: every Horner stage streams them in row tiles through a ring of
  * three device slots, the copies (on a stream the plan owns) overlapping the
- * stage kernels of earlier tiles.  The device holds the state, the workspace,
- * the row pointers, the marked set and the ring.
+ * stage kernels of earlier tiles.  Stages visit the tiles in alternating
+ * order and skip the copy of a tile the ring still holds, so a stage streams
+ * the table minus the ring (nothing after the first stage of a call when the
+ * ring holds every tile).  The device holds the state, the workspace, the row
+ * pointers, the marked set and the ring.
  *
  * qw_plan_stream_sizes: for a device budget (bytes the walk may use on the
  * device in total: state + info.work_bytes + the streamed graph buffer),

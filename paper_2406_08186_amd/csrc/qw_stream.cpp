@@ -11,7 +11,13 @@
 // finished, and the stage kernel for that tile runs on the caller's stream
 // once its copy has landed, so copies of later tiles overlap the kernels of
 // earlier ones.  The stages of a step, and the steps, stay in order on the
-// caller's stream.
+// caller's stream.  The table does not change between stages, so the ring is
+// also a cache: stages visit the tiles in alternating order (forward, then
+// backward), each stage starts with the tiles the previous one ended with,
+// and a tile already in a slot is not copied again (slots are reused least
+// recently used first).  A stage then streams its table minus what the ring
+// holds; a ring that holds every tile streams nothing after the first stage.
+// The order of the tiles within a stage does not change any row's arithmetic.
 
 #include <algorithm>
 #include <cstring>
@@ -115,26 +121,44 @@ int evolve_streamed(const qw_plan *p, void *psi, unsigned char *work, int64_t st
     void *w0 = work, *w1 = work + p->off_w1;
     const int64_t tiles = static_cast<int64_t>(p->st_row.size()) - 1;
     const size_t stride = align256(sizeof(int32_t) * static_cast<size_t>(p->st_slot_arcs));
-    // every slot starts free once the caller's earlier work on `s` is done
+    // every slot starts free (and empty) once the caller's earlier work on `s` is done
     for (int i = 0; i < p->st_slots; ++i) QW_TRY(hipEventRecord(p->st_free[i], s), "ring event");
-    int64_t q = 0;
+    std::vector<int64_t> held(p->st_slots, -1), used(p->st_slots, -1);  // tile in each slot, its last use
+    int64_t q = 0, stage = 0;
     for (int64_t i = 0; i < steps; ++i) {
       const void *yin = psi;
-      for (int k = K; k >= 1; --k) {
+      for (int k = K; k >= 1; --k, ++stage) {
         void *yout = (k == 1) ? (K == 1 ? w0 : psi) : (((K - k) & 1) ? w1 : w0);
         const double alpha = p->gamma * p->dt / k, beta = p->dt / k;
-        for (int64_t t = 0; t < tiles; ++t, ++q) {
-          const int slot = static_cast<int>(q % p->st_slots);
-          int32_t *dst = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(p->d_ring) + slot * stride);
-          const int64_t a0 = p->st_arc[t], na = p->st_arc[t + 1] - a0;
-          QW_TRY(hipStreamWaitEvent(p->st_copy, p->st_free[slot], 0), "ring wait");
-          if (na > 0)
-            QW_TRY(hipMemcpyAsync(dst, p->h_col + a0, sizeof(int32_t) * static_cast<size_t>(na),
-                                  hipMemcpyHostToDevice, p->st_copy),
-                   "neighbour tile copy");
-          QW_TRY(hipEventRecord(p->st_copied[slot], p->st_copy), "ring event");
-          QW_TRY(hipStreamWaitEvent(s, p->st_copied[slot], 0), "ring wait");
-          QW_TRY(ctqw_slot_stage(c128, g, dst, a0, p->st_row[t], p->st_row[t + 1], yin, psi, yout, alpha, beta, s),
+        for (int64_t j = 0; j < tiles; ++j, ++q) {
+          const int64_t t = (stage & 1) ? tiles - 1 - j : j;
+          int slot = -1;
+          for (int x = 0; x < p->st_slots; ++x)
+            if (held[x] == t) slot = x;
+          int32_t *dst;
+          if (slot >= 0) {
+            // in the ring since an earlier stage: the kernels on `s` that read it
+            // already waited for its copy, and no copy can refill the slot before
+            // this kernel's free event
+            dst = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(p->d_ring) + slot * stride);
+          } else {
+            slot = 0;
+            for (int x = 1; x < p->st_slots; ++x)
+              if (used[x] < used[slot]) slot = x;
+            dst = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(p->d_ring) + slot * stride);
+            const int64_t a0 = p->st_arc[t], na = p->st_arc[t + 1] - a0;
+            QW_TRY(hipStreamWaitEvent(p->st_copy, p->st_free[slot], 0), "ring wait");
+            if (na > 0)
+              QW_TRY(hipMemcpyAsync(dst, p->h_col + a0, sizeof(int32_t) * static_cast<size_t>(na),
+                                    hipMemcpyHostToDevice, p->st_copy),
+                     "neighbour tile copy");
+            QW_TRY(hipEventRecord(p->st_copied[slot], p->st_copy), "ring event");
+            QW_TRY(hipStreamWaitEvent(s, p->st_copied[slot], 0), "ring wait");
+            held[slot] = t;
+          }
+          used[slot] = q;
+          QW_TRY(ctqw_slot_stage(c128, g, dst, p->st_arc[t], p->st_row[t], p->st_row[t + 1], yin, psi, yout, alpha,
+                                 beta, s),
                  "out-of-core CTQW stage kernel");
           QW_TRY(hipEventRecord(p->st_free[slot], s), "ring event");
         }

@@ -117,3 +117,38 @@ def test_streamed_plan_cannot_join_a_batch():
     assert e.value.code == L.QW_EUNSUPPORTED
     b.close()
     pl.close()
+
+
+@pytest.mark.parametrize("K", [7, 8, 1])
+def test_streamed_ring_reuse_across_stages_and_calls(K):
+    """Rings that hold every tile (2-3 tiles: nothing is copied after the first stage
+    of a call) or part of them (5-13 tiles, alternating tile order), odd and even K
+    (the tile order alternates per stage, so across steps too) and K = 1, evolved in
+    two calls: bitwise equal to the in-core plan and to the oracle."""
+    g = I.erdos_renyi(3000, 10 / 2999, seed=12)
+    params = dict(gamma=0.1, dt=0.3, taylor_order=K, marked=[5, 2999])
+    psi0 = I.random_state(g.n, 13)
+    ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 5, gamma=params["gamma"], dt=params["dt"], K=K,
+                             marked=params["marked"])
+    core = _plan(g, params, "c128")
+    core.upload()
+    x = core.state(psi0)
+    core.evolve(x, 5)
+    torch.cuda.synchronize()
+    assert np.abs(x.cpu().numpy() - ref).max() < 1e-12
+    seen = set()
+    for div in (0.6, 0.95, 1.9, 3.5, 8.5):
+        pl = _plan(g, params, "c128")
+        walk = pl.info.state_bytes + pl.info.work_bytes
+        slot = int(4 * g.n_arcs / div / 3)
+        sizes = pl.upload_streamed(walk + 8 * g.n + 4096 + 3 * slot)
+        seen.add(sizes["tiles"])
+        print(f"[case] streamed ring reuse K={K} tiles={sizes['tiles']}", flush=True)
+        psi = pl.state(psi0)
+        pl.evolve(psi, 3)
+        pl.evolve(psi, 2)
+        torch.cuda.synchronize()
+        assert torch.equal(psi, x), f"{sizes['tiles']} tiles"
+        pl.close()
+    assert min(seen) <= 3 and max(seen) >= 6, seen
+    core.close()
