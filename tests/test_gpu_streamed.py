@@ -124,16 +124,16 @@ def test_streamed_ring_reuse_across_stages_and_calls(K):
     """Rings that hold every tile (2-3 tiles: nothing is copied after the first stage
     of a call) or part of them (5-13 tiles, alternating tile order), odd and even K
     (the tile order alternates per stage, so across steps too) and K = 1, evolved in
-    two calls: bitwise equal to the in-core plan and to the oracle."""
+    two calls: bitwise equal to one call on a one-tile ring, and to the oracle."""
     g = I.erdos_renyi(3000, 10 / 2999, seed=12)
     params = dict(gamma=0.1, dt=0.3, taylor_order=K, marked=[5, 2999])
     psi0 = I.random_state(g.n, 13)
     ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 5, gamma=params["gamma"], dt=params["dt"], K=K,
                              marked=params["marked"])
-    core = _plan(g, params, "c128")
-    core.upload()
-    x = core.state(psi0)
-    core.evolve(x, 5)
+    one = _plan(g, params, "c128")
+    assert one.upload_streamed(one.info.state_bytes + one.info.work_bytes + (1 << 30))["tiles"] == 1
+    x = one.state(psi0)
+    one.evolve(x, 5)
     torch.cuda.synchronize()
     assert np.abs(x.cpu().numpy() - ref).max() < 1e-12
     seen = set()
@@ -151,4 +151,4 @@ def test_streamed_ring_reuse_across_stages_and_calls(K):
         assert torch.equal(psi, x), f"{sizes['tiles']} tiles"
         pl.close()
     assert min(seen) <= 3 and max(seen) >= 6, seen
-    core.close()
+    one.close()
