@@ -1111,12 +1111,13 @@ def run_sparse(args):
 
 def run_streamed(args):
     """Out-of-core CTQW: a CTQW search on G(N, d/(N-1)) whose neighbour table
-    (4 bytes per arc) stays in pinned host memory and streams through a ring of
-    device slots at every Horner stage, under a device budget of the state and
-    workspace plus --stream-budget-mib.  Timed beside the same walk in core
-    (stage kernels only) and a plain copy of the table from pinned memory in the
-    same tiles (copies only): the overlap is the share of the in-core stage
-    time that the streamed run hides behind its copies."""
+    (4 bytes per arc) stays in pinned host memory, under a device budget of the
+    state and workspace plus --stream-budget-mib, in both modes: direct (the
+    device keeps what fits of the table, the stage kernel reads the rest from
+    host memory itself) and ring (the table streams through a ring of device
+    slots at every Horner stage, the copies overlapping the stage kernels).
+    Timed beside the same walk in core (stage kernels only) and the ring's
+    copies alone (same tiles, same count)."""
     import numpy as np
     import torch
 
@@ -1135,8 +1136,7 @@ def run_streamed(args):
     K = L.qw_taylor_order(1.0, steps, 1e-8)
     params = dict(gamma=gamma, dt=dt, taylor_order=K, marked=[0])
     psi0 = I.uniform(g.n)
-    res = {}
-
+    stages = steps * K
     host_ms = {}
 
     def timed(pl, psi):
@@ -1160,22 +1160,30 @@ def run_streamed(args):
     core.close()
     del core
     budget = walk + args.stream_budget_mib * 2**20
-    pl = Plan(g, "ctqw", dtype="c64", layout="csr", upload=False, **params)
-    sizes = pl.upload_streamed(budget)
-    y = pl.state(psi0)
-    ms_stream = timed(pl, y)
-    diff = float(np.abs(y.cpu().numpy() - ref_gpu).max())
-    # copies only: the tiles the streamed call copies, in the same sizes, from pinned
-    # memory to a device ring.  The call copies every tile at its first stage; each
-    # later stage starts with the tiles the ring still holds (alternating tile order)
-    # and copies the others.
-    tiles = sizes["tiles"]
+    modes = {}
+    states = {}
+    for mode in ("direct", "ring"):
+        pl = Plan(g, "ctqw", dtype="c64", layout="csr", upload=False, **params)
+        sizes = pl.upload_streamed(budget, mode=mode)
+        y = pl.state(psi0)
+        ms = timed(pl, y)
+        states[mode] = y
+        modes[mode] = {"sizes": sizes, "ms": ms, "host_ms": host_ms[id(pl)],
+                       "diff_vs_in_core": float(np.abs(y.cpu().numpy() - ref_gpu).max()), "plan": pl}
+    # direct: every stage reads the table's host part across the link
+    d = modes["direct"]
+    host_part = 4 * (g.n_arcs - d["sizes"]["device_arcs"])
+    # ring: the tiles the streamed call copies, in the same sizes, from pinned memory to
+    # a device ring.  The call copies every tile at its first stage; each later stage
+    # starts with the tiles the ring still holds (alternating tile order) and copies the
+    # others.
+    r = modes["ring"]
+    tiles = r["sizes"]["tiles"]
     hits = min(3, tiles)
-    stages = steps * K
     copies = tiles + (stages - 1) * (tiles - hits)
     tile_bytes = 4 * g.n_arcs // max(1, tiles)
     ring = torch.empty(3 * max(tile_bytes, 256), dtype=torch.uint8, device="cuda")
-    host = pl.h_graph
+    host = r["plan"].h_graph
     cs = torch.cuda.Stream()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -1189,28 +1197,38 @@ def run_streamed(args):
         b.record()
     torch.cuda.synchronize()
     ms_copy = a.elapsed_time(b)
-    # parity: the streamed state against the oracle (c64 L2)
+    # parity: both streamed states against the oracle (c64 L2), and against each other
     t1 = time.perf_counter()
     ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, steps + 1, **{k: v for k, v in params.items()
                                                                      if k != "taylor_order"}, K=K)
-    l2 = float(np.linalg.norm(y.cpu().numpy().astype(np.complex128) - ref))
+    l2 = {m: float(np.linalg.norm(states[m].cpu().numpy().astype(np.complex128) - ref)) for m in states}
     copied = copies * tile_bytes  # tiles of about the average size
     line = {"workload": f"ctqw_search_er_{g.n}_d{dbar}_out_of_core", "dtype": "c64", "n": g.n, "arcs": g.n_arcs,
             "K": K, "steps": steps, "device_budget_bytes": budget, "table_bytes_in_host_memory": 4 * g.n_arcs,
-            "device_graph_bytes": sizes["device_bytes"], "tiles_per_stage": sizes["tiles"],
-            "stage_ms_streamed": ms_stream / stages, "stage_ms_in_core": ms_core / stages,
-            "stage_ms_copies_only": ms_copy / stages,
-            "stage_ms_host_enqueue_streamed": host_ms[id(pl)] / stages,
-            "tile_copies_per_call": copies, "tiles_held_by_the_ring": hits,
-            "h2d_bytes_per_stage_approx": copied / stages,
-            "table_gbs_streamed": 4 * g.n_arcs * stages / (ms_stream * 1e-3) / 1e9,
-            "h2d_gbs_streamed": copied / (ms_stream * 1e-3) / 1e9,
-            "h2d_gbs_copies_only": copied / (ms_copy * 1e-3) / 1e9,
-            "overlap_of_compute": max(0.0, min(1.0, (ms_copy + ms_core - ms_stream) / ms_core)),
-            "arc_steps_per_s_streamed": g.n_arcs * steps / (ms_stream * 1e-3),
+            "stage_ms_in_core": ms_core / stages,
+            "direct": {"device_graph_bytes": d["sizes"]["device_bytes"],
+                       "device_arcs": d["sizes"]["device_arcs"], "workgroup_tiles": d["sizes"]["tiles"],
+                       "host_bytes_read_per_stage": host_part,
+                       "stage_ms": d["ms"] / stages, "stage_ms_host_enqueue": d["host_ms"] / stages,
+                       "host_read_gbs": host_part * stages / (d["ms"] * 1e-3) / 1e9,
+                       "table_gbs": 4 * g.n_arcs * stages / (d["ms"] * 1e-3) / 1e9,
+                       "arc_steps_per_s": g.n_arcs * steps / (d["ms"] * 1e-3),
+                       "max_abs_diff_vs_in_core": d["diff_vs_in_core"], "l2_vs_oracle": l2["direct"]},
+            "ring": {"device_graph_bytes": r["sizes"]["device_bytes"], "tiles_per_stage": tiles,
+                     "stage_ms": r["ms"] / stages, "stage_ms_copies_only": ms_copy / stages,
+                     "stage_ms_host_enqueue": r["host_ms"] / stages,
+                     "tile_copies_per_call": copies, "tiles_held_by_the_ring": hits,
+                     "h2d_bytes_per_stage_approx": copied / stages,
+                     "table_gbs": 4 * g.n_arcs * stages / (r["ms"] * 1e-3) / 1e9,
+                     "h2d_gbs": copied / (r["ms"] * 1e-3) / 1e9,
+                     "h2d_gbs_copies_only": copied / (ms_copy * 1e-3) / 1e9,
+                     "arc_steps_per_s": g.n_arcs * steps / (r["ms"] * 1e-3),
+                     "max_abs_diff_vs_in_core": r["diff_vs_in_core"], "l2_vs_oracle": l2["ring"]},
+            "direct_equals_ring_bitwise": bool(torch.equal(states["direct"], states["ring"])),
             "arc_steps_per_s_in_core": g.n_arcs * steps / (ms_core * 1e-3),
-            "max_abs_diff_vs_in_core": diff, "l2_vs_oracle": l2, "oracle_s": time.perf_counter() - t1}
-    pl.close()
+            "oracle_s": time.perf_counter() - t1}
+    for m in modes.values():
+        m["plan"].close()
     print(json.dumps(line), flush=True)
 
 

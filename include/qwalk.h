@@ -292,34 +292,53 @@ int qw_evolve(const qw_plan *plan, void *d_psi, void *d_work, size_t work_bytes,
  * The paper names, as future work, splitting matrices that exceed device
  * memory into tiles.  A CTQW plan on the CSR path (QW_LAYOUT_CSR) can keep its
  * largest table, the neighbour indices (4 bytes per arc), in caller-pinned
- * host memory: every Horner stage streams them in row tiles through a ring of
- * three device slots, the copies (on a stream the plan owns) overlapping the
- * stage kernels of earlier tiles.  Stages visit the tiles in alternating
- * order and skip the copy of a tile the ring still holds, so a stage streams
- * the table minus the ring (nothing after the first stage of a call when the
- * ring holds every tile).  The device holds the state, the workspace, the row
- * pointers, the marked set and the ring.
+ * host memory; the device holds the state, the workspace, the row pointers,
+ * the marked set and what the mode below keeps there.  Two modes:
  *
- * qw_plan_stream_sizes: for a device budget (bytes the walk may use on the
- * device in total: state + info.work_bytes + the streamed graph buffer),
- * the pinned host bytes (*host_bytes, the neighbour table), the device graph
- * buffer (*device_bytes, <= budget - state - workspace) and the number of row
- * tiles streamed per stage.  Host only.  Errors: QW_EUNSUPPORTED (not a CTQW
- * plan on the CSR path), QW_ENOMEM (the budget does not hold state,
- * workspace, resident tables and a slot of the largest row), QW_EINVAL.
+ * QW_STREAM_DIRECT (the default): the device keeps the indices of as many
+ * arcs as the budget allows (a prefix of the CSR table) and the stage kernel
+ * reads the others from the pinned buffer itself, across the host link, in
+ * workgroup tiles staged through LDS: one launch per Horner stage, no copies
+ * and no events.  The pinned buffer must be device-mapped (hipHostMalloc,
+ * torch pin_memory); others are refused with QW_EINVAL.
+ *
+ * QW_STREAM_RING: every Horner stage streams the indices in row tiles
+ * through a ring of three device slots, the copies (on a stream the plan
+ * owns) overlapping the stage kernels of earlier tiles.  Stages visit the
+ * tiles in alternating order and skip the copy of a tile the ring still
+ * holds, so a stage streams the table minus the ring (nothing after the
+ * first stage of a call when the ring holds every tile).
+ *
+ * Both modes sum every row's neighbours in arc order, so they give the same
+ * bits as each other at every budget. */
+#define QW_STREAM_DIRECT 0
+#define QW_STREAM_RING 1
+/* qw_plan_stream_sizes: for a device budget (bytes the walk may use on the
+ * device in total: state + info.work_bytes + the streamed graph buffer) and a
+ * mode, the pinned host bytes (*host_bytes: the neighbour table, padded to a
+ * multiple of 16 bytes), the device graph buffer (*device_bytes,
+ * <= budget - state - workspace), the number of row tiles a stage runs
+ * (*n_tiles: ring tiles, or direct mode's workgroup tiles) and the arcs whose
+ * indices stay on the device (*device_arcs; 0 in ring mode).  Host only.
+ * Errors: QW_EUNSUPPORTED (not a CTQW plan on the CSR path), QW_ENOMEM (the
+ * budget does not hold state, workspace and resident tables, and in ring
+ * mode a slot of the largest row), QW_EINVAL (null plan, unknown mode).
  * NULL outputs are skipped. */
-int qw_plan_stream_sizes(const qw_plan *plan, size_t device_budget, size_t *host_bytes, size_t *device_bytes,
-                         int64_t *n_tiles);
-/* Bind the plan for out-of-core evolution with the same budget: copies the
- * neighbour table into h_pinned (host memory from hipHostMalloc / torch
- * pin_memory, >= *host_bytes, caller-owned, kept unmodified while bound) and
- * the resident tables into d_buf (device, >= *device_bytes, 256-byte
- * aligned) on `stream`; creates the plan's copy stream and ring events.  Ends
- * any previous binding; qw_plan_upload ends this one.  qw_evolve and
- * qw_probabilities then work as usual (qw_evolve enqueues the tile copies and
- * kernels; host calls, no host sync); the plan cannot join a batch. */
-int qw_plan_upload_streamed(qw_plan *plan, size_t device_budget, void *h_pinned, size_t host_bytes, void *d_buf,
-                            size_t device_bytes, void *stream);
+int qw_plan_stream_sizes(const qw_plan *plan, size_t device_budget, int mode, size_t *host_bytes,
+                         size_t *device_bytes, int64_t *n_tiles, int64_t *device_arcs);
+/* Bind the plan for out-of-core evolution with the same budget and mode:
+ * copies the neighbour table into h_pinned (pinned host memory, 16-byte
+ * aligned, >= *host_bytes, caller-owned, kept unmodified while bound) and the
+ * resident tables into d_buf (device, >= *device_bytes, 256-byte aligned) on
+ * `stream`; ring mode also creates the plan's copy stream and ring events.
+ * Ends any previous binding; qw_plan_upload ends this one.  qw_evolve and
+ * qw_probabilities then work as usual (qw_evolve enqueues the stage kernels,
+ * and in ring mode the tile copies; host calls, no host sync); the plan
+ * cannot join a batch.  Errors: as qw_plan_stream_sizes, QW_ENOMEM (buffers
+ * below the sizes), QW_EINVAL (misaligned buffers, or in direct mode a host
+ * buffer the device cannot read), QW_EDEVICE. */
+int qw_plan_upload_streamed(qw_plan *plan, size_t device_budget, int mode, void *h_pinned, size_t host_bytes,
+                            void *d_buf, size_t device_bytes, void *stream);
 
 /* ---- Allocation-free evolution
  * For callers that cannot allocate device memory (code under HIP graph

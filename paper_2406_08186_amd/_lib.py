@@ -24,6 +24,7 @@ QW_GROVER, QW_HADAMARD, QW_FOURIER, QW_MATRIX, QW_SZEGEDY = 0, 1, 2, 3, 4
 QW_FLIPFLOP, QW_PERSISTENT = 0, 1
 QW_C64, QW_C128 = 0, 1
 QW_BATCH_GATHER, QW_BATCH_LDS = 0, 1
+QW_STREAM_DIRECT, QW_STREAM_RING = 0, 1
 QW_LAYOUT_AUTO, QW_LAYOUT_CSR, QW_LAYOUT_STRUCTURED, QW_LAYOUT_DENSE = 0, 1, 2, 3
 STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small", 5: "ell", 6: "dense",
               7: "stag_lattice"}
@@ -118,8 +119,9 @@ def lib():
         L.qw_batch_launch_plan.argtypes = [vp, C.c_int64, i64p, i64p]
         L.qw_batch_set_stage_kernel.argtypes = [vp, C.c_int32]
         L.qw_evolve_static.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp]
-        L.qw_plan_stream_sizes.argtypes = [vp, C.c_size_t, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), i64p]
-        L.qw_plan_upload_streamed.argtypes = [vp, C.c_size_t, vp, C.c_size_t, vp, C.c_size_t, vp]
+        L.qw_plan_stream_sizes.argtypes = [vp, C.c_size_t, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                           i64p, i64p]
+        L.qw_plan_upload_streamed.argtypes = [vp, C.c_size_t, C.c_int, vp, C.c_size_t, vp, C.c_size_t, vp]
         L.qw_batch_get_schedule.argtypes = [vp, i32p, i32p, i32p]
         L.qw_last_error.restype = C.c_char_p
         L.qw_version.restype = C.c_char_p
@@ -281,16 +283,17 @@ def qw_evolve_static(plan, d_psi: int, steps: int, d_p, d_norm, d_pmarked, strea
     check(lib().qw_evolve_static(plan, d_psi, steps, d_p, d_norm, d_pmarked, stream), "qw_evolve_static")
 
 
-def qw_plan_stream_sizes(plan, device_budget: int) -> tuple[int, int, int]:
-    h, d, t = C.c_size_t(), C.c_size_t(), C.c_int64()
-    check(lib().qw_plan_stream_sizes(plan, device_budget, C.byref(h), C.byref(d), C.byref(t)),
+def qw_plan_stream_sizes(plan, device_budget: int, mode: int = 0) -> tuple[int, int, int, int]:
+    h, d, t, a = C.c_size_t(), C.c_size_t(), C.c_int64(), C.c_int64()
+    check(lib().qw_plan_stream_sizes(plan, device_budget, mode, C.byref(h), C.byref(d), C.byref(t), C.byref(a)),
           "qw_plan_stream_sizes")
-    return h.value, d.value, t.value
+    return h.value, d.value, t.value, a.value
 
 
-def qw_plan_upload_streamed(plan, device_budget: int, h_pinned: int, host_bytes: int, d_buf: int,
+def qw_plan_upload_streamed(plan, device_budget: int, mode: int, h_pinned: int, host_bytes: int, d_buf: int,
                             device_bytes: int, stream: int) -> None:
-    check(lib().qw_plan_upload_streamed(plan, device_budget, h_pinned, host_bytes, d_buf, device_bytes, stream),
+    check(lib().qw_plan_upload_streamed(plan, device_budget, mode, h_pinned, host_bytes, d_buf, device_bytes,
+                                        stream),
           "qw_plan_upload_streamed")
 
 

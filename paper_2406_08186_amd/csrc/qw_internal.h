@@ -16,6 +16,8 @@ constexpr int kTileThreads = 256;
 constexpr int kLdsTileThreads = 1024;          // workgroup of the LDS-staged batch stage
 constexpr int kLdsTileRows = 4096;             // rows per tile of that kernel (4 per thread)
 constexpr int kLdsBlockBytes = 128 * 1024;     // LDS block of the input vector it stages
+constexpr int kDirRows = 256;   // rows per workgroup tile of the direct out-of-core stage (one per thread)
+constexpr int kDirArcs = 8192;  // neighbour indices such a tile stages in LDS (32 KiB)
 constexpr int kTileMaxVerts = 1024;
 // Threads per workgroup of the elementwise/stencil kernels.
 constexpr int kBlock = 256;
@@ -271,6 +273,14 @@ hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const Ti
 // [arc0, ...)) sit in a device slot: slot[a - arc0] = col[a].
 hipError_t ctqw_slot_stage(bool c128, const GraphView &g, const int32_t *slot, int64_t arc0, int r0, int r1,
                            const void *y, const void *psi, void *out, double alpha, double beta, hipStream_t s);
+// Direct out-of-core CTQW stage: workgroup tile w holds rows [wg_row[w],
+// wg_row[w+1]) (at most kDirRows rows and kDirArcs arcs, or one longer row);
+// neighbour indices of arcs below `split` (a multiple of 4) come from the
+// device prefix dcol, the others straight from pinned host memory hcol (both
+// 16-byte aligned, hcol padded to a multiple of 4 entries).
+hipError_t ctqw_direct_stage(bool c128, const GraphView &g, const int32_t *wg_row, int64_t n_wg, const int32_t *dcol,
+                             const int32_t *hcol, int64_t split, const void *y, const void *psi, void *out,
+                             double alpha, double beta, hipStream_t s);
 // The LDS-staged stage of the batch's CTQW walks on the ELL layout (degree
 // <= 8): tiles of kLdsTileRows rows, one workgroup of kLdsTileThreads each, the
 // input vector staged in blocks of kLdsBlockBytes.  The last workgroup

@@ -773,6 +773,72 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_csr_slot(const int32_t *__restr
   st(out, r, horner_out(ld(psi, r), sum, yv, mk, alpha, beta));
 }
 
+// Direct out-of-core stage.  The neighbour indices of most arcs sit in pinned
+// host memory and are read across the host link by the kernel itself: a
+// workgroup stages its tile's indices into LDS with 16-byte loads (a
+// contiguous run of arcs, so every load instruction of a wavefront reads 1 KiB
+// of consecutive host memory), then each thread sums its row from LDS in arc
+// order, as the other CSR stages do.  A row with more arcs than the LDS holds
+// is its own tile, staged chunk by chunk and summed by one thread.
+__device__ __forceinline__ void dir_stage(int32_t *cs, const int32_t *dcol, const int32_t *hcol, int64_t split,
+                                          int64_t a0, int64_t a1) {
+  // cs[a - (a0 & ~3)] = col[a] for a in [a0 & ~3, (a1 + 3) & ~3): whole 16-byte groups,
+  // each from one side of `split`
+  const int64_t q0 = a0 >> 2, q1 = (a1 + 3) >> 2;
+  const int4 *d4 = reinterpret_cast<const int4 *>(dcol);
+  const int4 *h4 = reinterpret_cast<const int4 *>(hcol);
+  int4 *c4 = reinterpret_cast<int4 *>(cs);
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) c4[q - q0] = (q << 2) < split ? d4[q] : h4[q];
+}
+
+template <typename T>
+__device__ __forceinline__ double2 gather_fold(double2 s, const T *__restrict__ y, const int32_t *col, int lo,
+                                               int hi) {
+  for (int a = lo; a < hi; ++a) s = add(s, cvt(y[col[a]]));
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDirRows) void k_ctqw_csr_direct(const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ wg_row,
+                                                            const int32_t *dcol, const int32_t *hcol,
+                                                            int64_t split, const uint32_t *markbits,
+                                                            const T *__restrict__ y, const T *psi, T *out,
+                                                            double alpha, double beta) {
+  __shared__ __align__(16) int32_t cs[kDirArcs + 8];
+  const int rb = wg_row[blockIdx.x], re = wg_row[blockIdx.x + 1];
+  const int64_t ab = rp[rb], ae = rp[re];
+  if (ae - ab <= kDirArcs) {
+    dir_stage(cs, dcol, hcol, split, ab, ae);
+    __syncthreads();
+    const int r = rb + static_cast<int>(threadIdx.x);
+    if (r >= re) return;
+    const int base = static_cast<int>(ab & 3) - static_cast<int>(ab);  // cs index of arc a: a + base
+    const double2 sum = gather_sum(y, static_cast<const int32_t *>(cs), rp[r] + base, rp[r + 1] + base);
+    const bool mk = marked(markbits, r);
+    const double2 yv = mk ? ld(y, r) : make_double2(0.0, 0.0);
+    st(out, r, horner_out(ld(psi, r), sum, yv, mk, alpha, beta));
+    return;
+  }
+  // one row (re = rb + 1) longer than a tile: its arcs in chunks of kDirArcs, folded in order
+  double2 sum = make_double2(0.0, 0.0);
+  for (int64_t c0 = ab; c0 < ae; c0 += kDirArcs) {
+    const int64_t c1 = c0 + kDirArcs < ae ? c0 + kDirArcs : ae;
+    __syncthreads();  // the previous chunk is no longer read
+    dir_stage(cs, dcol, hcol, split, c0, c1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int lo = static_cast<int>(c0 & 3);
+      sum = gather_fold(sum, y, static_cast<const int32_t *>(cs), lo, lo + static_cast<int>(c1 - c0));
+    }
+  }
+  if (threadIdx.x == 0) {
+    const bool mk = marked(markbits, rb);
+    const double2 yv = mk ? ld(y, rb) : make_double2(0.0, 0.0);
+    st(out, rb, horner_out(ld(psi, rb), sum, yv, mk, alpha, beta));
+  }
+}
+
 // Regular graphs: ELL stage, one thread per row, column-major neighbour table.
 template <typename T, bool PROB>
 __global__ __launch_bounds__(kBlock) void k_ctqw_ell(GraphView g, const T *__restrict__ y, const T *psi,
@@ -2512,6 +2578,22 @@ hipError_t ctqw_slot_stage(bool c128, const GraphView &g, const int32_t *slot, i
   else
     hipLaunchKernelGGL(k_ctqw_csr_slot<float2>, grid, dim3(kBlock), 0, s, g.rp, slot, arc0, r0, r1, g.markbits,
                        static_cast<const float2 *>(y), static_cast<const float2 *>(psi),
+                       static_cast<float2 *>(out), alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t ctqw_direct_stage(bool c128, const GraphView &g, const int32_t *wg_row, int64_t n_wg, const int32_t *dcol,
+                             const int32_t *hcol, int64_t split, const void *y, const void *psi, void *out,
+                             double alpha, double beta, hipStream_t s) {
+  if (n_wg <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(n_wg));
+  if (c128)
+    hipLaunchKernelGGL(k_ctqw_csr_direct<double2>, grid, dim3(kDirRows), 0, s, g.rp, wg_row, dcol, hcol, split,
+                       g.markbits, static_cast<const double2 *>(y), static_cast<const double2 *>(psi),
+                       static_cast<double2 *>(out), alpha, beta);
+  else
+    hipLaunchKernelGGL(k_ctqw_csr_direct<float2>, grid, dim3(kDirRows), 0, s, g.rp, wg_row, dcol, hcol, split,
+                       g.markbits, static_cast<const float2 *>(y), static_cast<const float2 *>(psi),
                        static_cast<float2 *>(out), alpha, beta);
   return hipGetLastError();
 }

@@ -52,10 +52,18 @@ struct qw_plan {
   int32_t two_reg = 0;      // one-workgroup coined walk in one wavefront's registers: 0 no, 1 permutes, 2 cycle shifts
   int32_t block_depth = 1;  // grid CTQW: Horner stages per launch (temporal blocking)
   // out-of-core binding (qw_plan_upload_streamed): the CSR neighbour table stays
-  // in caller-pinned host memory and is streamed, tile by tile, through a ring
-  // of device slots on the plan's copy stream while the stage kernels run
+  // in caller-pinned host memory.  Ring mode streams it, tile by tile, through
+  // a ring of device slots on the plan's copy stream while the stage kernels
+  // run; direct mode keeps a prefix of it on the device and the stage kernel
+  // reads the rest from host memory itself.
   bool streamed = false;
+  int32_t st_mode = 0;              // QW_STREAM_DIRECT or QW_STREAM_RING
   const int32_t *h_col = nullptr;   // pinned host copy of col (CSR order)
+  const int32_t *h_col_dev = nullptr;  // the same memory as the device addresses it
+  int32_t *d_wg_row = nullptr;      // direct: workgroup tiles' first rows (n_wg + 1)
+  int64_t st_n_wg = 0;
+  int32_t *d_prefix = nullptr;      // direct: col[0, st_split) on the device
+  int64_t st_split = 0;
   std::vector<int32_t> st_row;      // tile t holds rows [st_row[t], st_row[t+1])
   std::vector<int64_t> st_arc;      // and arcs [st_arc[t], st_arc[t+1])
   int32_t st_slots = 0;             // device slots in the ring

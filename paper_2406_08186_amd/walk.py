@@ -131,19 +131,23 @@ class Plan:
         L.qw_plan_upload(self._plan, self.d_graph.data_ptr(), self.d_graph.numel(),
                          _stream_ptr(stream, self.device))
 
-    def upload_streamed(self, device_budget: int, stream=None) -> dict:
+    def upload_streamed(self, device_budget: int, mode: str = "direct", stream=None) -> dict:
         """Out-of-core binding (CTQW on the CSR layout): the neighbour table goes to a
-        pinned host buffer and is streamed through a device ring at every Horner
-        stage; the walk uses at most `device_budget` bytes of device memory."""
-        host_bytes, dev_bytes, tiles = L.qw_plan_stream_sizes(self._plan, int(device_budget))
+        pinned host buffer; the walk uses at most `device_budget` bytes of device
+        memory.  mode "direct": the device keeps what fits of the table and the
+        stage kernel reads the rest from host memory; "ring": the table streams
+        through a ring of device slots at every Horner stage."""
+        m = {"direct": L.QW_STREAM_DIRECT, "ring": L.QW_STREAM_RING}[mode]
+        host_bytes, dev_bytes, tiles, dev_arcs = L.qw_plan_stream_sizes(self._plan, int(device_budget), m)
         self.h_graph = torch.empty(max(host_bytes, 256), dtype=torch.uint8, pin_memory=True)
         self.d_graph = torch.empty(max(dev_bytes, 256), dtype=torch.uint8, device=self.device)
         self.work = torch.empty(max(self.info.work_bytes, 256), dtype=torch.uint8, device=self.device)
         self._p = torch.empty(max(self.p_len, 1), dtype=torch.float64, device=self.device)
         self._scal = torch.zeros(2, dtype=torch.float64, device=self.device)
-        L.qw_plan_upload_streamed(self._plan, int(device_budget), self.h_graph.data_ptr(), self.h_graph.numel(),
+        L.qw_plan_upload_streamed(self._plan, int(device_budget), m, self.h_graph.data_ptr(), self.h_graph.numel(),
                                   self.d_graph.data_ptr(), self.d_graph.numel(), _stream_ptr(stream, self.device))
-        return {"host_bytes": host_bytes, "device_bytes": dev_bytes, "tiles": tiles}
+        return {"host_bytes": host_bytes, "device_bytes": dev_bytes, "tiles": tiles, "device_arcs": dev_arcs,
+                "mode": mode}
 
     def release_device(self) -> None:
         """Drop the device buffers (the plan must not be used on the device afterwards)."""

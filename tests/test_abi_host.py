@@ -415,9 +415,12 @@ def test_bench_refuses_more_than_one_gpu(argv, env):
 
 
 def test_out_of_core_schedule_host_side():
-    """qw_plan_stream_sizes (host only): the neighbour table goes to pinned host memory,
-    tiles shrink with the budget, and plans outside the CSR CTQW path or budgets below
-    the state, workspace and a slot of the largest row are refused."""
+    """qw_plan_stream_sizes (host only): the neighbour table goes to pinned host memory.
+    Ring mode: tiles shrink with the budget.  Direct mode: the device prefix grows
+    with the budget up to the whole table (a multiple of 4 arcs), the workgroup tiles
+    do not depend on it.  Plans outside the CSR CTQW path, unknown modes and budgets
+    below the state, workspace and resident tables (ring: and a slot of the largest
+    row) are refused."""
     g = I.erdos_renyi(3000, 8 / 2999, seed=4)
     pl = _create(g, kind=L.QW_CTQW, dtype=L.QW_C64, layout=L.QW_LAYOUT_CSR, gamma=0.125, dt=0.5,
                  taylor_order=12)
@@ -425,19 +428,40 @@ def test_out_of_core_schedule_host_side():
     walk = info.state_bytes + info.work_bytes
     prev = None
     for extra in (1 << 30, 256 * 1024, 64 * 1024, 24 * 1024):
-        host, dev, tiles = L.qw_plan_stream_sizes(pl, walk + extra)
-        assert host == 4 * g.n_arcs
+        host, dev, tiles, dev_arcs = L.qw_plan_stream_sizes(pl, walk + extra, L.QW_STREAM_RING)
+        assert host == 4 * g.n_arcs and dev_arcs == 0
         assert dev <= extra
         assert tiles >= 1
         if prev is not None:
             assert tiles >= prev
         prev = tiles
-    assert L.qw_plan_stream_sizes(pl, walk + (1 << 30))[2] == 1
-    assert _code(lambda: L.qw_plan_stream_sizes(pl, walk)) == L.QW_ENOMEM
+    assert L.qw_plan_stream_sizes(pl, walk + (1 << 30), L.QW_STREAM_RING)[2] == 1
+    assert _code(lambda: L.qw_plan_stream_sizes(pl, walk, L.QW_STREAM_RING)) == L.QW_ENOMEM
+    padded = (g.n_arcs + 3) // 4 * 4
+    deg = np.diff(g.row_ptr)
+    prev, wg = None, None
+    for extra in (1 << 30, 4 * g.n_arcs, 64 * 1024, 40 * 1024, 25 * 1024):
+        host, dev, tiles, dev_arcs = L.qw_plan_stream_sizes(pl, walk + extra, L.QW_STREAM_DIRECT)
+        assert host == 4 * padded
+        assert dev <= extra
+        assert dev_arcs % 4 == 0 or dev_arcs == g.n_arcs
+        assert 0 <= dev_arcs <= g.n_arcs
+        if prev is not None:
+            assert dev_arcs <= prev
+        prev = dev_arcs
+        # workgroup tiles: at most 256 rows and 8192 arcs each (rows here are short)
+        assert tiles >= max(g.n // 256, g.n_arcs // 8192) and tiles <= g.n
+        wg = tiles if wg is None else wg
+        assert tiles == wg
+    assert L.qw_plan_stream_sizes(pl, walk + (1 << 30), L.QW_STREAM_DIRECT)[3] == g.n_arcs
+    assert deg.max() < 8192
+    assert _code(lambda: L.qw_plan_stream_sizes(pl, walk, L.QW_STREAM_DIRECT)) == L.QW_ENOMEM
+    assert _code(lambda: L.qw_plan_stream_sizes(pl, 1 << 30, 2)) == L.QW_EINVAL
     L.qw_plan_destroy(pl)
     ell = _create(I.random_regular(500, 4, seed=1), kind=L.QW_CTQW, dtype=L.QW_C64,
                   layout=L.QW_LAYOUT_STRUCTURED, gamma=0.25, dt=0.5, taylor_order=8)
-    assert _code(lambda: L.qw_plan_stream_sizes(ell, 1 << 30)) == L.QW_EUNSUPPORTED
+    for mode in (L.QW_STREAM_DIRECT, L.QW_STREAM_RING):
+        assert _code(lambda: L.qw_plan_stream_sizes(ell, 1 << 30, mode)) == L.QW_EUNSUPPORTED
     L.qw_plan_destroy(ell)
     coined = _create(I.erdos_renyi(300, 0.05, seed=2), kind=L.QW_COINED, dtype=L.QW_C64, layout=L.QW_LAYOUT_CSR)
     assert _code(lambda: L.qw_plan_stream_sizes(coined, 1 << 30)) == L.QW_EUNSUPPORTED

@@ -1,8 +1,9 @@
 """GPU tests of out-of-core evolution (qw_plan_upload_streamed): the CSR
-neighbour table in pinned host memory, streamed through a device ring at
-every Horner stage under a forced small device budget.  Results equal the
-FP64 oracle (c128 within 1e-12, c64 L2 within 1e-5) and are bitwise the same
-for every tile count."""
+neighbour table in pinned host memory, either read by the stage kernel itself
+with a device-resident prefix (direct mode) or streamed through a device ring
+at every Horner stage (ring mode), under forced small device budgets.
+Results equal the FP64 oracle (c128 within 1e-12, c64 L2 within 1e-5) and
+are bitwise the same for every budget and both modes."""
 import numpy as np
 import pytest
 import torch
@@ -43,12 +44,18 @@ def test_streamed_matches_oracle_for_every_budget(dtype):
                                  K=params["taylor_order"], marked=params["marked"])
         pref = oracle.vertex_prob(ref)
         first = None
-        for extra in (1 << 30, 8 * g.n + 64 * 1024, 8 * g.n + 16 * 1024):
+        cases = [("ring", e) for e in (1 << 30, 8 * g.n + 64 * 1024, 8 * g.n + 16 * 1024)]
+        cases += [("direct", e) for e in (1 << 30, 8 * g.n + 4 * g.n_arcs // 3, 8 * g.n + 16 * 1024, 0)]
+        for mode, extra in cases:
             pl = _plan(g, params, dtype)
             walk = pl.info.state_bytes + pl.info.work_bytes
-            sizes = pl.upload_streamed(walk + extra)
-            assert sizes["host_bytes"] == 4 * g.n_arcs
-            print(f"[case] streamed {dtype} graph {gi} n={g.n} tiles={sizes['tiles']}", flush=True)
+            if extra == 0:  # about the smallest direct budget: a prefix of at most 128 arcs on the device
+                extra = L.qw_plan_stream_sizes(pl._plan, 1 << 40, L.QW_STREAM_DIRECT)[1] - 16 * ((g.n_arcs + 3) // 4)
+                extra = (extra + 255) // 256 * 256 + 256
+            sizes = pl.upload_streamed(walk + extra, mode=mode)
+            assert sizes["host_bytes"] == (4 * g.n_arcs if mode == "ring" else 16 * ((g.n_arcs + 3) // 4))
+            print(f"[case] streamed {mode} {dtype} graph {gi} n={g.n} tiles={sizes['tiles']} "
+                  f"device_arcs={sizes['device_arcs']}", flush=True)
             psi = pl.state(psi0)
             p, norm, pm = pl.evolve(psi, steps, readout=True)
             torch.cuda.synchronize()
@@ -62,10 +69,10 @@ def test_streamed_matches_oracle_for_every_budget(dtype):
             assert abs(float(norm) - float(np.sum(np.abs(got) ** 2))) < 1e-9
             if first is None:
                 first = (sizes["tiles"], psi.clone())
+                assert first[0] == 1
             else:
-                assert torch.equal(psi, first[1]), f"graph {gi}: {sizes['tiles']} tiles vs {first[0]}"
+                assert torch.equal(psi, first[1]), f"graph {gi}: {mode} {sizes['tiles']} tiles"
             pl.close()
-        assert first[0] == 1
 
 
 def test_streamed_small_ring_many_tiles_and_rebinding():
@@ -77,7 +84,7 @@ def test_streamed_small_ring_many_tiles_and_rebinding():
     pl = _plan(g, params, "c128")
     walk = pl.info.state_bytes + pl.info.work_bytes
     resident = 4 * (g.n + 1) + 4 * ((g.n + 31) // 32) + 3 * 256 + 256
-    sizes = pl.upload_streamed(walk + resident + 3 * 4 * 256)
+    sizes = pl.upload_streamed(walk + resident + 3 * 4 * 256, mode="ring")
     print(f"[case] streamed ring tiles={sizes['tiles']}", flush=True)
     assert sizes["tiles"] > 100
     psi = pl.state(psi0)
@@ -96,7 +103,7 @@ def test_streamed_small_ring_many_tiles_and_rebinding():
     assert np.abs(x.cpu().numpy() - ref).max() < 1e-12
     pl.close()
     k1 = _plan(g, dict(params, taylor_order=1), "c128")
-    k1.upload_streamed(walk + (1 << 20))
+    k1.upload_streamed(walk + (1 << 20), mode="ring")
     y = k1.state(psi0)
     k1.evolve(y, 3)
     ref1 = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 3, gamma=params["gamma"], dt=params["dt"], K=1,
@@ -131,7 +138,7 @@ def test_streamed_ring_reuse_across_stages_and_calls(K):
     ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 5, gamma=params["gamma"], dt=params["dt"], K=K,
                              marked=params["marked"])
     one = _plan(g, params, "c128")
-    assert one.upload_streamed(one.info.state_bytes + one.info.work_bytes + (1 << 30))["tiles"] == 1
+    assert one.upload_streamed(one.info.state_bytes + one.info.work_bytes + (1 << 30), mode="ring")["tiles"] == 1
     x = one.state(psi0)
     one.evolve(x, 5)
     torch.cuda.synchronize()
@@ -141,7 +148,7 @@ def test_streamed_ring_reuse_across_stages_and_calls(K):
         pl = _plan(g, params, "c128")
         walk = pl.info.state_bytes + pl.info.work_bytes
         slot = int(4 * g.n_arcs / div / 3)
-        sizes = pl.upload_streamed(walk + 8 * g.n + 4096 + 3 * slot)
+        sizes = pl.upload_streamed(walk + 8 * g.n + 4096 + 3 * slot, mode="ring")
         seen.add(sizes["tiles"])
         print(f"[case] streamed ring reuse K={K} tiles={sizes['tiles']}", flush=True)
         psi = pl.state(psi0)
@@ -152,3 +159,75 @@ def test_streamed_ring_reuse_across_stages_and_calls(K):
         pl.close()
     assert min(seen) <= 3 and max(seen) >= 6, seen
     one.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_direct_mode_long_rows_and_small_many_calls(dtype):
+    """Direct mode on a graph with rows longer than a workgroup tile's LDS (a hub of
+    degree 12000 and one of 8193: chunked staging, one thread's ordered fold) beside
+    short rows whose arc runs start inside 16-byte groups, with the device prefix
+    ending inside either hub's row; several calls and zero steps; ring mode: the same
+    bits; K = 1 direct and rebound in core against the oracle."""
+    n = 21000
+    edges = [(0, v) for v in range(1, 12001)] + [(1, v) for v in range(12001, 12001 + 8193)]
+    edges += [(v, v + 1) for v in range(2, n - 1)]
+    g = I.from_edges(n, edges, name="two_hubs")
+    assert int(np.diff(g.row_ptr).max()) > 8192
+    params = dict(gamma=4e-5, dt=0.5, taylor_order=9, marked=[0, 7, n - 1])
+    psi0 = I.random_state(g.n, 71)
+    ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 4, gamma=params["gamma"], dt=params["dt"], K=9,
+                             marked=params["marked"])
+    out = None
+    for mode, extra_arcs in (("direct", 0), ("direct", 5001), ("direct", 12003), ("direct", 1 << 28),
+                             ("ring", 1 << 28)):
+        pl = _plan(g, params, dtype)
+        walk = pl.info.state_bytes + pl.info.work_bytes
+        fixed = L.qw_plan_stream_sizes(pl._plan, 1 << 40, L.QW_STREAM_DIRECT)[1] - 16 * ((g.n_arcs + 3) // 4)
+        budget = walk + (fixed + 255) // 256 * 256 + 256 + 4 * extra_arcs
+        sizes = pl.upload_streamed(budget, mode=mode)
+        print(f"[case] direct long rows {dtype} {mode} device_arcs={sizes['device_arcs']}", flush=True)
+        if mode == "direct" and extra_arcs < 1 << 20:
+            assert sizes["device_arcs"] < g.n_arcs
+        psi = pl.state(psi0)
+        pl.evolve(psi, 0)
+        pl.evolve(psi, 3)
+        pl.evolve(psi, 1)
+        torch.cuda.synchronize()
+        if out is None:
+            out = psi.clone()
+            got = psi.cpu().numpy().astype(np.complex128)
+            if dtype == "c128":
+                assert np.abs(got - ref).max() < 1e-12
+            else:
+                assert np.linalg.norm(got - ref) < 1e-5
+        else:
+            assert torch.equal(psi, out), (mode, extra_arcs)
+        pl.close()
+    k1 = _plan(g, dict(params, taylor_order=1), dtype)
+    k1.upload_streamed(k1.info.state_bytes + k1.info.work_bytes + (1 << 22))
+    y = k1.state(psi0)
+    k1.evolve(y, 2)
+    r1 = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 2, gamma=params["gamma"], dt=params["dt"], K=1,
+                            marked=params["marked"])
+    torch.cuda.synchronize()
+    assert np.linalg.norm(y.cpu().numpy().astype(np.complex128) - r1) < (1e-12 if dtype == "c128" else 1e-5)
+    k1.upload()
+    z = k1.state(psi0)
+    k1.evolve(z, 2)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(z.cpu().numpy().astype(np.complex128) - r1) < (1e-12 if dtype == "c128" else 1e-5)
+    k1.close()
+
+
+def test_direct_mode_refuses_pageable_host_memory():
+    g = I.erdos_renyi(500, 0.02, seed=3)
+    pl = _plan(g, dict(gamma=0.2, dt=0.3, taylor_order=8, marked=[1]), "c64")
+    budget = pl.info.state_bytes + pl.info.work_bytes + (1 << 20)
+    host, dev, _, _ = L.qw_plan_stream_sizes(pl._plan, budget, L.QW_STREAM_DIRECT)
+    pageable = torch.empty(host, dtype=torch.uint8)  # not pinned
+    d = torch.empty(max(dev, 256), dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.QwError) as e:
+        L.qw_plan_upload_streamed(pl._plan, budget, L.QW_STREAM_DIRECT, pageable.data_ptr(), host, d.data_ptr(),
+                                  d.numel(), 0)
+    assert e.value.code == L.QW_EINVAL
+    pl.close()
