@@ -418,10 +418,13 @@ class WalkServer:
         self.batch.close()
 
 
-def serve_stream(server: WalkServer, jobs: list[Job], time_limit: float = 600.0) -> list[Job]:
-    """Release jobs at their arrival times (seconds after start) and serve until all finish."""
+def serve_stream(server: WalkServer, jobs: list[Job], time_limit: float = 600.0, progress=None,
+                 progress_every: int = 200) -> list[Job]:
+    """Release jobs at their arrival times (seconds after start) and serve until all finish.
+    `progress(done, seconds)` is called each time another `progress_every` jobs have finished."""
     pending = deque(sorted(jobs, key=lambda j: j.arrival))
     server.t0 = time.perf_counter()
+    reported = 0
     while pending or server.busy():
         t = server.now()
         if t > time_limit:
@@ -430,11 +433,16 @@ def serve_stream(server: WalkServer, jobs: list[Job], time_limit: float = 600.0)
             server.submit(pending.popleft())
         if server.cycle() == 0:
             time.sleep(0.0002)
+        if progress is not None and len(server.done) // progress_every > reported:
+            reported = len(server.done) // progress_every
+            progress(len(server.done), server.now())
     return server.done
 
 
-def serve_sequential(jobs: list[Job], dtype: str = "c64", device=None, time_limit: float = 600.0):
-    """The plain form: one job at a time, in arrival order, each on its fastest single-walk path."""
+def serve_sequential(jobs: list[Job], dtype: str = "c64", device=None, time_limit: float = 600.0, progress=None,
+                     progress_every: int = 200):
+    """The plain form: one job at a time, in arrival order, each on its fastest single-walk path.
+    `progress(done, seconds)` is called after every `progress_every` finished jobs."""
     import torch
 
     from .walk import Plan
@@ -453,6 +461,9 @@ def serve_sequential(jobs: list[Job], dtype: str = "c64", device=None, time_limi
         plan.close()
         if job.finished_at > time_limit:
             raise TimeoutError("sequential stream exceeded its time limit")
+        done = sum(1 for j in jobs if j.status == "done")
+        if progress is not None and done % progress_every == 0:
+            progress(done, job.finished_at)
     return jobs
 
 
