@@ -231,3 +231,21 @@ def test_direct_mode_refuses_pageable_host_memory():
                                   d.numel(), 0)
     assert e.value.code == L.QW_EINVAL
     pl.close()
+
+
+@pytest.mark.parametrize("mode", ["direct", "ring"])
+def test_streamed_edgeless_graph(mode):
+    """No arcs at all (nothing to stage or copy): only the marked vertices' term acts."""
+    g = I.Graph(n=300, row_ptr=np.zeros(301, np.int64), col=np.zeros(0, np.int32), name="edgeless")
+    params = dict(gamma=0.3, dt=0.4, taylor_order=6, marked=[0, 299])
+    psi0 = I.random_state(g.n, 5)
+    pl = _plan(g, params, "c128")
+    sizes = pl.upload_streamed(pl.info.state_bytes + pl.info.work_bytes + (1 << 20), mode=mode)
+    assert sizes["device_arcs"] == 0
+    psi = pl.state(psi0)
+    pl.evolve(psi, 3)
+    ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 3, gamma=params["gamma"], dt=params["dt"], K=6,
+                             marked=params["marked"])
+    torch.cuda.synchronize()
+    assert np.abs(psi.cpu().numpy() - ref).max() < 1e-12
+    pl.close()
