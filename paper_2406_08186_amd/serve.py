@@ -50,7 +50,7 @@ class Job:
     steps: int
     arrival: float = 0.0          # seconds after the server's start
     # filled in by the server
-    lane: str = "batch"           # "small", "batch" or "solo"
+    lane: str = "batch"           # "small", "batch" or "solo"; "plain" in the one-at-a-time form
     footprint: int = 0
     slot: int = -1
     admitted_at: float = math.nan
@@ -457,6 +457,7 @@ def serve_sequential(jobs: list[Job], dtype: str = "c64", device=None, time_limi
         torch.cuda.synchronize(dev)
         job.result = {"norm": float(norm), "p_marked": float(pm)}
         job.status = "done"
+        job.lane = "plain"
         job.finished_at = time.perf_counter() - t0
         plan.close()
         if job.finished_at > time_limit:
