@@ -16,6 +16,10 @@ constexpr int kTileThreads = 256;
 constexpr int kLdsTileThreads = 1024;          // workgroup of the LDS-staged batch stage
 constexpr int kLdsTileRows = 4096;             // rows per tile of that kernel (4 per thread)
 constexpr int kLdsBlockBytes = 128 * 1024;     // LDS block of the input vector it stages
+#ifndef QW_ELL_SLICE_BYTES
+#define QW_ELL_SLICE_BYTES (2 << 20)
+#endif
+constexpr int64_t kEllSliceBytes = QW_ELL_SLICE_BYTES;  // single-walk ELL stage: gathered slice of the vector
 constexpr int kDirRows = 256;   // rows per workgroup tile of the direct out-of-core stage (one per thread)
 constexpr int kDirArcs = 8192;  // neighbour indices such a tile stages in LDS (32 KiB)
 constexpr int kTileMaxVerts = 1024;

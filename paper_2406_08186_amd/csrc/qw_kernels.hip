@@ -865,6 +865,73 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_ell(GraphView g, const T *__res
   }
 }
 
+// Regular graphs whose vector exceeds an XCD's L2 share: the same ELL stage,
+// column-sliced.  A thread takes RPT rows of a row group and loads their
+// neighbour indices once; then, for each slice of kEllSliceBytes of the input
+// vector in turn, it gathers only the neighbours inside that slice.  The grid
+// is what the GPU holds at once (groups taken grid-stride), so its
+// workgroups walk the slices together and an XCD's L2 holds the slice being
+// gathered instead of a random part of the whole vector.  Rows are sorted by
+// neighbour, so adding slice after slice adds each row's neighbours in row
+// order: the result is bitwise that of k_ctqw_ell.
+template <typename T, int RPT>
+__global__ __launch_bounds__(kBlock) void k_ctqw_ell_sliced(GraphView g, const T *__restrict__ y, const T *psi,
+                                                            T *out, double alpha, double beta, int slice) {
+  const int n = g.n, d = g.ell_d;
+  const int n_groups = (n + kBlock * RPT - 1) / (kBlock * RPT);
+  for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    const int r0 = grp * (kBlock * RPT) + static_cast<int>(threadIdx.x);
+    int c[RPT][8];  // neighbour indices; -1 (never inside a slice as unsigned) pads
+    double2 acc[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = r0 + i * kBlock;
+      const int rc = r < n ? r : n - 1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) c[i][j] = g.col[static_cast<int64_t>(j < d ? j : d - 1) * n + rc];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) c[i][j] = (r < n && j < d) ? c[i][j] : -1;
+      acc[i] = make_double2(0.0, 0.0);
+    }
+    for (int s0 = 0; s0 < n; s0 += slice) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        T x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (static_cast<unsigned>(c[i][j] - s0) < static_cast<unsigned>(slice)) x[j] = y[c[i][j]];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (static_cast<unsigned>(c[i][j] - s0) < static_cast<unsigned>(slice)) acc[i] = add(acc[i], cvt(x[j]));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = r0 + i * kBlock;
+      if (r >= n) continue;
+      const bool mk = marked(g.markbits, r);
+      const double2 yv = mk ? ld(y, r) : make_double2(0.0, 0.0);
+      st(out, r, horner_out(ld(psi, r), acc[i], yv, mk, alpha, beta));
+    }
+  }
+}
+
+// workgroups of `kernel` (kBlock threads) the current device holds at once
+template <typename K> int resident_groups(K kernel) {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+  if (cached[dev] > 0) return cached[dev];
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu <= 0 ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+    (void)hipGetLastError();
+    return 1024;
+  }
+  cached[dev] = per_cu * cus;
+  return cached[dev];
+}
+
 // Structured stencils (no index arrays): neighbours computed from v.
 template <typename T, int KIND, bool PROB>
 __global__ __launch_bounds__(kBlock) void k_ctqw_struct(GraphView g, const T *__restrict__ y,
@@ -2317,8 +2384,16 @@ hipError_t launch_ctqw_stage(const GraphView &g, const T *y, const T *psi, T *ou
                            out, c.alpha, c.beta, p, partials);
         break;
       case kEll:
-        hipLaunchKernelGGL((k_ctqw_ell<T, PROB>), grid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta, p,
-                           partials);
+        if (!PROB && g.ell_d <= 8 && static_cast<int64_t>(g.n) * static_cast<int64_t>(sizeof(T)) > kEllSliceBytes) {
+          constexpr int RPT = 2;
+          const int groups = static_cast<int>(blocks_for(g.n, kBlock * RPT));
+          const dim3 sgrid(std::min(groups, resident_groups(k_ctqw_ell_sliced<T, RPT>)));
+          hipLaunchKernelGGL((k_ctqw_ell_sliced<T, RPT>), sgrid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta,
+                             static_cast<int>(kEllSliceBytes / static_cast<int64_t>(sizeof(T))));
+        } else {
+          hipLaunchKernelGGL((k_ctqw_ell<T, PROB>), grid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta, p,
+                             partials);
+        }
         break;
       default: return hipErrorInvalidValue;
     }
