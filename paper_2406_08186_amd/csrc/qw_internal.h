@@ -16,10 +16,11 @@ constexpr int kTileThreads = 256;
 constexpr int kLdsTileThreads = 1024;          // workgroup of the LDS-staged batch stage
 constexpr int kLdsTileRows = 4096;             // rows per tile of that kernel (4 per thread)
 constexpr int kLdsBlockBytes = 128 * 1024;     // LDS block of the input vector it stages
-#ifndef QW_ELL_SLICE_BYTES
-#define QW_ELL_SLICE_BYTES (2 << 20)
-#endif
-constexpr int64_t kEllSliceBytes = QW_ELL_SLICE_BYTES;  // single-walk ELL stage: gathered slice of the vector
+// single-walk ELL stage: vectors above kEllSliceFrom bytes are gathered in
+// slices of kEllSliceEntries entries (measured best on 2^20 vertices for both
+// types, against 64Ki and 256Ki: 1 MiB complex64, 2 MiB complex128)
+constexpr int64_t kEllSliceFrom = int64_t{2} << 20;
+constexpr int kEllSliceEntries = 131072;
 constexpr int kDirRows = 256;   // rows per workgroup tile of the direct out-of-core stage (one per thread)
 constexpr int kDirArcs = 8192;  // neighbour indices such a tile stages in LDS (32 KiB)
 constexpr int kTileMaxVerts = 1024;
@@ -107,6 +108,7 @@ struct GraphView {
   int32_t n_marked = 0;
   int32_t n_tiles = 0;
   int32_t group = 1;           // CTQW CSR: lanes per row
+  int32_t sorted_rows = 0;     // CTQW CSR: every row's neighbours in increasing order
   const int32_t *rp = nullptr;      // n+1
   const int32_t *col = nullptr;     // n_arcs (CTQW general/small: CSR order; ELL: col[j*n + v])
   int32_t ell_d = 0;                // ELL degree

@@ -867,8 +867,8 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_ell(GraphView g, const T *__res
 
 // Regular graphs whose vector exceeds an XCD's L2 share: the same ELL stage,
 // column-sliced.  A thread takes RPT rows of a row group and loads their
-// neighbour indices once; then, for each slice of kEllSliceBytes of the input
-// vector in turn, it gathers only the neighbours inside that slice.  The grid
+// neighbour indices once; then, for each slice of kEllSliceEntries entries of
+// the input vector in turn, it gathers only the neighbours inside that slice.  The grid
 // is what the GPU holds at once (groups taken grid-stride), so its
 // workgroups walk the slices together and an XCD's L2 holds the slice being
 // gathered instead of a random part of the whole vector.  Rows are sorted by
@@ -903,6 +903,63 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_ell_sliced(GraphView g, const T
 #pragma unroll
         for (int j = 0; j < 8; ++j)
           if (static_cast<unsigned>(c[i][j] - s0) < static_cast<unsigned>(slice)) acc[i] = add(acc[i], cvt(x[j]));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = r0 + i * kBlock;
+      if (r >= n) continue;
+      const bool mk = marked(g.markbits, r);
+      const double2 yv = mk ? ld(y, r) : make_double2(0.0, 0.0);
+      st(out, r, horner_out(ld(psi, r), acc[i], yv, mk, alpha, beta));
+    }
+  }
+}
+
+// The same slicing for irregular graphs on the CSR layout (rows sorted by
+// neighbour): a thread keeps a cursor into each of its RPT rows; in the pass
+// over a slice it takes, four at a time, the row's next neighbours while they
+// fall inside the slice (a prefix of what is left, the row being sorted).
+// Each row's neighbours are added in arc order, as in k_ctqw_csr with one
+// lane per row.
+template <typename T, int RPT>
+__global__ __launch_bounds__(kBlock) void k_ctqw_csr_sliced(GraphView g, const T *__restrict__ y, const T *psi,
+                                                            T *out, double alpha, double beta, int slice) {
+  const int n = g.n;
+  const int n_groups = (n + kBlock * RPT - 1) / (kBlock * RPT);
+  for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    const int r0 = grp * (kBlock * RPT) + static_cast<int>(threadIdx.x);
+    int a[RPT], hi[RPT];
+    double2 acc[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = r0 + i * kBlock;
+      a[i] = r < n ? g.rp[r] : 0;
+      hi[i] = r < n ? g.rp[r + 1] : 0;
+      acc[i] = make_double2(0.0, 0.0);
+    }
+    for (int s0 = 0; s0 < n; s0 += slice) {
+      const unsigned s1 = static_cast<unsigned>(s0) + static_cast<unsigned>(slice);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        for (;;) {
+          unsigned c[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) c[k] = a[i] + k < hi[i] ? static_cast<unsigned>(g.col[a[i] + k]) : 0xffffffffu;
+          T x[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (c[k] < s1) x[k] = y[c[k]];
+          int taken = 0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (c[k] < s1) {
+              acc[i] = add(acc[i], cvt(x[k]));
+              ++taken;
+            }
+          a[i] += taken;
+          if (taken < 4) break;
+        }
       }
     }
 #pragma unroll
@@ -2358,7 +2415,14 @@ void launch_csr_g(const GraphView &g, const T *y, const T *psi, T *out, StageCoe
 template <typename T, bool PROB>
 hipError_t launch_ctqw_stage(const GraphView &g, const T *y, const T *psi, T *out, StageCoef c, double *p,
                              double *partials, hipStream_t s) {
-  if (g.structure == kGeneral) {
+  if (g.structure == kGeneral &&
+      (!PROB && g.sorted_rows && static_cast<int64_t>(g.n) * static_cast<int64_t>(sizeof(T)) > kEllSliceFrom)) {
+    constexpr int RPT = 2;
+    const int groups = static_cast<int>(blocks_for(g.n, kBlock * RPT));
+    const dim3 sgrid(std::min(groups, resident_groups(k_ctqw_csr_sliced<T, RPT>)));
+    hipLaunchKernelGGL((k_ctqw_csr_sliced<T, RPT>), sgrid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta,
+                       kEllSliceEntries);
+  } else if (g.structure == kGeneral) {
     switch (g.group) {
       case 1: launch_csr_g<T, 1, PROB>(g, y, psi, out, c, p, partials, s); break;
       case 2: launch_csr_g<T, 2, PROB>(g, y, psi, out, c, p, partials, s); break;
@@ -2384,12 +2448,12 @@ hipError_t launch_ctqw_stage(const GraphView &g, const T *y, const T *psi, T *ou
                            out, c.alpha, c.beta, p, partials);
         break;
       case kEll:
-        if (!PROB && g.ell_d <= 8 && static_cast<int64_t>(g.n) * static_cast<int64_t>(sizeof(T)) > kEllSliceBytes) {
+        if (!PROB && g.ell_d <= 8 && static_cast<int64_t>(g.n) * static_cast<int64_t>(sizeof(T)) > kEllSliceFrom) {
           constexpr int RPT = 2;
           const int groups = static_cast<int>(blocks_for(g.n, kBlock * RPT));
           const dim3 sgrid(std::min(groups, resident_groups(k_ctqw_ell_sliced<T, RPT>)));
           hipLaunchKernelGGL((k_ctqw_ell_sliced<T, RPT>), sgrid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta,
-                             static_cast<int>(kEllSliceBytes / static_cast<int64_t>(sizeof(T))));
+                             kEllSliceEntries);
         } else {
           hipLaunchKernelGGL((k_ctqw_ell<T, PROB>), grid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta, p,
                              partials);
