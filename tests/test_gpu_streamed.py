@@ -279,7 +279,7 @@ def test_sliced_in_core_stages_match_streamed(dtype):
             assert np.linalg.norm(got - ref) < 1e-5
         if layout == "csr":
             st = _plan(g, params, dtype)
-            st.upload_streamed(st.info.state_bytes + st.info.work_bytes + (1 << 20))
+            st.upload_streamed(st.info.state_bytes + st.info.work_bytes + 8 * g.n + (1 << 22))
             y = st.state(psi0)
             st.evolve(y, 2)
             torch.cuda.synchronize()
