@@ -916,63 +916,6 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_ell_sliced(GraphView g, const T
   }
 }
 
-// The same slicing for irregular graphs on the CSR layout (rows sorted by
-// neighbour): a thread keeps a cursor into each of its RPT rows; in the pass
-// over a slice it takes, four at a time, the row's next neighbours while they
-// fall inside the slice (a prefix of what is left, the row being sorted).
-// Each row's neighbours are added in arc order, as in k_ctqw_csr with one
-// lane per row.
-template <typename T, int RPT>
-__global__ __launch_bounds__(kBlock) void k_ctqw_csr_sliced(GraphView g, const T *__restrict__ y, const T *psi,
-                                                            T *out, double alpha, double beta, int slice) {
-  const int n = g.n;
-  const int n_groups = (n + kBlock * RPT - 1) / (kBlock * RPT);
-  for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
-    const int r0 = grp * (kBlock * RPT) + static_cast<int>(threadIdx.x);
-    int a[RPT], hi[RPT];
-    double2 acc[RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = r0 + i * kBlock;
-      a[i] = r < n ? g.rp[r] : 0;
-      hi[i] = r < n ? g.rp[r + 1] : 0;
-      acc[i] = make_double2(0.0, 0.0);
-    }
-    for (int s0 = 0; s0 < n; s0 += slice) {
-      const unsigned s1 = static_cast<unsigned>(s0) + static_cast<unsigned>(slice);
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        for (;;) {
-          unsigned c[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) c[k] = a[i] + k < hi[i] ? static_cast<unsigned>(g.col[a[i] + k]) : 0xffffffffu;
-          T x[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (c[k] < s1) x[k] = y[c[k]];
-          int taken = 0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (c[k] < s1) {
-              acc[i] = add(acc[i], cvt(x[k]));
-              ++taken;
-            }
-          a[i] += taken;
-          if (taken < 4) break;
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = r0 + i * kBlock;
-      if (r >= n) continue;
-      const bool mk = marked(g.markbits, r);
-      const double2 yv = mk ? ld(y, r) : make_double2(0.0, 0.0);
-      st(out, r, horner_out(ld(psi, r), acc[i], yv, mk, alpha, beta));
-    }
-  }
-}
-
 // workgroups of `kernel` (kBlock threads) the current device holds at once
 template <typename K> int resident_groups(K kernel) {
   static int cached[64] = {0};
@@ -2415,14 +2358,7 @@ void launch_csr_g(const GraphView &g, const T *y, const T *psi, T *out, StageCoe
 template <typename T, bool PROB>
 hipError_t launch_ctqw_stage(const GraphView &g, const T *y, const T *psi, T *out, StageCoef c, double *p,
                              double *partials, hipStream_t s) {
-  if (g.structure == kGeneral &&
-      (!PROB && g.sorted_rows && static_cast<int64_t>(g.n) * static_cast<int64_t>(sizeof(T)) > kEllSliceFrom)) {
-    constexpr int RPT = 2;
-    const int groups = static_cast<int>(blocks_for(g.n, kBlock * RPT));
-    const dim3 sgrid(std::min(groups, resident_groups(k_ctqw_csr_sliced<T, RPT>)));
-    hipLaunchKernelGGL((k_ctqw_csr_sliced<T, RPT>), sgrid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta,
-                       kEllSliceEntries);
-  } else if (g.structure == kGeneral) {
+  if (g.structure == kGeneral) {
     switch (g.group) {
       case 1: launch_csr_g<T, 1, PROB>(g, y, psi, out, c, p, partials, s); break;
       case 2: launch_csr_g<T, 2, PROB>(g, y, psi, out, c, p, partials, s); break;

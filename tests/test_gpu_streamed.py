@@ -252,11 +252,10 @@ def test_streamed_edgeless_graph(mode):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_sliced_in_core_stages_match_streamed(dtype):
-    """Vectors above 2 MiB take the column-sliced stage in core (ELL for a regular
-    graph, CSR for an irregular one with sorted rows).  Both add every row's neighbours
-    in arc order, as the out-of-core stages do: the in-core CSR walk equals the
-    direct-mode walk bitwise, and both walks equal the oracle."""
+def test_sliced_in_core_stage_and_streamed(dtype):
+    """A regular graph whose vector exceeds 2 MiB takes the column-sliced ELL stage in
+    core; an irregular one the CSR stages in core and out of core (direct mode): every
+    walk equals the oracle."""
     from paper_2406_08186_amd.walk import Plan
     n = 300000
     cases = [(I.erdos_renyi(n, 7 / (n - 1), seed=17), "csr"), (I.random_regular(n, 5, seed=18), "structured")]
@@ -266,23 +265,27 @@ def test_sliced_in_core_stages_match_streamed(dtype):
         psi0 = I.random_state(g.n, 90 + gi)
         ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 2, gamma=params["gamma"], dt=params["dt"], K=10,
                                  marked=params["marked"])
+
+        def check(x):
+            got = x.cpu().numpy().astype(np.complex128)
+            if dtype == "c128":
+                assert np.abs(got - ref).max() < 1e-12
+            else:
+                assert np.linalg.norm(got - ref) < 1e-5
+
         core = Plan(g, "ctqw", dtype=dtype, layout=layout, **params)
         assert core.structure == ("general" if layout == "csr" else "ell"), core.structure
         x = core.state(psi0)
         core.evolve(x, 2)
         torch.cuda.synchronize()
-        got = x.cpu().numpy().astype(np.complex128)
         print(f"[case] sliced in core {dtype} {core.structure}", flush=True)
-        if dtype == "c128":
-            assert np.abs(got - ref).max() < 1e-12
-        else:
-            assert np.linalg.norm(got - ref) < 1e-5
+        check(x)
         if layout == "csr":
             st = _plan(g, params, dtype)
             st.upload_streamed(st.info.state_bytes + st.info.work_bytes + 8 * g.n + (1 << 22))
             y = st.state(psi0)
             st.evolve(y, 2)
             torch.cuda.synchronize()
-            assert torch.equal(x, y)
+            check(y)
             st.close()
         core.close()
