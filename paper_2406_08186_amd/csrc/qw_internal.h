@@ -18,8 +18,13 @@ constexpr int kLdsTileRows = 4096;             // rows per tile of that kernel (
 constexpr int kLdsBlockBytes = 128 * 1024;     // LDS block of the input vector it stages
 // single-walk ELL stage: vectors above kEllSliceFrom bytes are gathered in
 // slices of kEllSliceEntries entries (measured best on 2^20 vertices for both
-// types, against 64Ki and 256Ki: 1 MiB complex64, 2 MiB complex128)
-constexpr int64_t kEllSliceFrom = int64_t{2} << 20;
+// types, against 64Ki and 256Ki: 1 MiB complex64, 2 MiB complex128).  The
+// slicing pays from about 8 MiB on (random 6-regular graphs: 9.6 MiB and up
+// faster, 4.8 MiB complex64 even, 7.2 MiB complex128 and below slower).
+#ifndef QW_ELL_SLICE_FROM
+#define QW_ELL_SLICE_FROM (int64_t{15} << 19)
+#endif
+constexpr int64_t kEllSliceFrom = QW_ELL_SLICE_FROM;
 constexpr int kEllSliceEntries = 131072;
 constexpr int kDirRows = 256;   // rows per workgroup tile of the direct out-of-core stage (one per thread)
 constexpr int kDirArcs = 8192;  // neighbour indices such a tile stages in LDS (32 KiB)

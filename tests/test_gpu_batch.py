@@ -259,7 +259,8 @@ def _relabelled(n, edges, seed, name):
 def _lds_walks():
     """CTQW walks on regular graphs of degree 1..8 (the LDS-staged kernel), sized around its
     tile (4096 rows) and block (16384 complex64 / 8192 complex128 entries) edges, marks on
-    those edges; the largest also exceed the single-walk path's 2 MiB column slice."""
+    those edges; the largest also exceeds the size from which the single-walk path gathers
+    in column slices (7.5 MiB)."""
     m = 6000
     matching = _relabelled(m, [(2 * i, 2 * i + 1) for i in range(m // 2)], 21, "matching")
     ring = _relabelled(9001, [(i, (i + 1) % 9001) for i in range(9001)], 22, "ring")
@@ -273,8 +274,8 @@ def _lds_walks():
         (I.random_regular(40001 + 1, 7, seed=35), dict(gamma=1 / 7, dt=0.5, taylor_order=14, marked=[32768]), 3),
         (I.random_regular(1000, 8, seed=36), dict(gamma=0.125, dt=0.5, taylor_order=2, marked=[999]), 9),
         (I.random_regular(200000, 8, seed=37), dict(gamma=0.125, dt=0.5, taylor_order=12, marked=[123456]), 2),
-        # vectors above 2 MiB: the single-walk path takes the column-sliced ELL stage
-        (I.random_regular(300000, 6, seed=38), dict(gamma=1 / 6, dt=0.5, taylor_order=11, marked=[299999]), 2),
+        # vectors above 7.5 MiB: the single-walk path takes the column-sliced ELL stage
+        (I.random_regular(1000000, 6, seed=38), dict(gamma=1 / 6, dt=0.5, taylor_order=11, marked=[999999]), 2),
     ]
 
 

@@ -253,13 +253,13 @@ def test_streamed_edgeless_graph(mode):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_sliced_in_core_stage_and_streamed(dtype):
-    """A regular graph whose vector exceeds 2 MiB takes the column-sliced ELL stage in
+    """A regular graph whose vector exceeds 7.5 MiB takes the column-sliced ELL stage in
     core; an irregular one the CSR stages in core and out of core (direct mode): every
     walk equals the oracle."""
     from paper_2406_08186_amd.walk import Plan
-    n = 300000
-    cases = [(I.erdos_renyi(n, 7 / (n - 1), seed=17), "csr"), (I.random_regular(n, 5, seed=18), "structured")]
+    cases = [(I.erdos_renyi(300000, 7 / 299999, seed=17), "csr"), (I.random_regular(1000000, 5, seed=18), "structured")]
     for gi, (g, layout) in enumerate(cases):
+        n = g.n
         dmax = int(np.diff(g.row_ptr).max())
         params = dict(gamma=0.15, dt=1.0 / (0.15 * dmax + 1.0), taylor_order=10, marked=[3, n - 2])
         psi0 = I.random_state(g.n, 90 + gi)
