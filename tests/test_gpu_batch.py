@@ -293,7 +293,7 @@ def test_batch_lds_kernel(dtype):
     from paper_2406_08186_amd.walk import Batch
 
     def run(kernel, ents):
-        b = Batch(capacity=len(ents), max_tiles=4096, dtype=dtype)
+        b = Batch(capacity=len(ents), max_tiles=16384, dtype=dtype)
         b.set_stage_kernel(kernel)
         states = []
         for slot, (pl, psi0, steps) in enumerate(ents):
