@@ -592,13 +592,30 @@ __global__ __launch_bounds__(kBlock) void k_copy(const T *__restrict__ in, T *__
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prob_csr(GraphView g, const T *__restrict__ psi, double *p,
                                                      double *partials) {
+  // The workgroup's vertices own one contiguous run of arcs: it is staged
+  // through LDS in chunks with coalesced loads, and each thread adds its
+  // vertex's |psi_a|^2 from there in arc order (a vertex block of d arcs read
+  // by one thread straight from memory would touch d cache lines per step of
+  // the wavefront).
+  constexpr int kChunk = 2048;
+  __shared__ T cs[kChunk];
   __shared__ double red[16];
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = g.n;
+  const int v0 = blockIdx.x * blockDim.x;
+  const int v = v0 + threadIdx.x;
+  const int v1 = v0 + static_cast<int>(blockDim.x) < n ? v0 + static_cast<int>(blockDim.x) : n;
+  const int ab = g.rp[v0], ae = g.rp[v1];
+  const int lo = v < n ? g.rp[v] : 0, hi = v < n ? g.rp[v + 1] : 0;
   double pv = 0.0;
-  if (v < g.n) {
-    for (int i = g.rp[v]; i < g.rp[v + 1]; ++i) pv += abs2(ld(psi, i));
-    p[v] = pv;
+  for (int c0 = ab; c0 < ae; c0 += kChunk) {
+    const int c1 = c0 + kChunk < ae ? c0 + kChunk : ae;
+    __syncthreads();  // the previous chunk is no longer read
+    for (int i = threadIdx.x; i < c1 - c0; i += blockDim.x) cs[i] = psi[c0 + i];
+    __syncthreads();
+    const int a0 = lo > c0 ? lo : c0, a1 = hi < c1 ? hi : c1;
+    for (int a = a0; a < a1; ++a) pv += abs2(cvt(cs[a - c0]));
   }
+  if (v < n) p[v] = pv;
   double tot = block_sum(pv, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
