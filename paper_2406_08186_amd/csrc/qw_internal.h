@@ -26,6 +26,10 @@ constexpr int kLdsBlockBytes = 128 * 1024;     // LDS block of the input vector 
 #endif
 constexpr int64_t kEllSliceFrom = QW_ELL_SLICE_FROM;
 constexpr int kEllSliceEntries = 131072;
+#ifndef QW_ELL_SLICE_ROWS
+#define QW_ELL_SLICE_ROWS 2
+#endif
+constexpr int kEllSliceRows = QW_ELL_SLICE_ROWS;  // rows per thread of the sliced stage
 constexpr int kDirRows = 256;   // rows per workgroup tile of the direct out-of-core stage (one per thread)
 constexpr int kDirArcs = 8192;  // neighbour indices such a tile stages in LDS (32 KiB)
 constexpr int kTileMaxVerts = 1024;

@@ -2402,7 +2402,7 @@ hipError_t launch_ctqw_stage(const GraphView &g, const T *y, const T *psi, T *ou
         break;
       case kEll:
         if (!PROB && g.ell_d <= 8 && static_cast<int64_t>(g.n) * static_cast<int64_t>(sizeof(T)) > kEllSliceFrom) {
-          constexpr int RPT = 2;
+          constexpr int RPT = kEllSliceRows;
           const int groups = static_cast<int>(blocks_for(g.n, kBlock * RPT));
           const dim3 sgrid(std::min(groups, resident_groups(k_ctqw_ell_sliced<T, RPT>)));
           hipLaunchKernelGGL((k_ctqw_ell_sliced<T, RPT>), sgrid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta,
