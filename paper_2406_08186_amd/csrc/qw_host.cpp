@@ -576,6 +576,13 @@ int build_plan(const qw_csr *g, const qw_walk_desc *w, qw_plan *p) {
   if (ctqw && structure == kGeneral) {
     const double avg = n > 0 ? static_cast<double>(na) / n : 0.0;
     p->group = avg <= 6 ? 1 : avg <= 12 ? 2 : avg <= 24 ? 4 : avg <= 48 ? 8 : avg <= 96 ? 16 : avg <= 192 ? 32 : 64;
+    p->sorted_rows = 1;
+    for (int64_t v = 0; v < n && p->sorted_rows; ++v)
+      for (int64_t a = rp[v] + 1; a < rp[v + 1]; ++a)
+        if (col[a] <= col[a - 1]) {
+          p->sorted_rows = 0;
+          break;
+        }
   }
 
   // grid CTQW: stages per launch and, per strip of the blocked kernel, whether
@@ -1022,6 +1029,7 @@ int qw_plan_upload(qw_plan *p, void *d_graph, size_t graph_bytes, void *stream) 
   g.n_marked = p->n_marked;
   g.n_tiles = p->n_tiles;
   g.group = p->group;
+  g.sorted_rows = p->sorted_rows;
   g.rp = reinterpret_cast<const int32_t *>(base + p->off_rp);
   if (p->has_col) g.col = reinterpret_cast<const int32_t *>(base + p->off_col);
   if (p->structure == kEll) g.ell_d = p->dims[0];

@@ -117,6 +117,7 @@ struct GraphView {
   int32_t n_marked = 0;
   int32_t n_tiles = 0;
   int32_t group = 1;           // CTQW CSR: lanes per row
+  int32_t sorted_rows = 0;     // CTQW CSR: every row's neighbours in increasing order
   const int32_t *rp = nullptr;      // n+1
   const int32_t *col = nullptr;     // n_arcs (CTQW general/small: CSR order; ELL: col[j*n + v])
   int32_t ell_d = 0;                // ELL degree

@@ -933,6 +933,60 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_ell_sliced(GraphView g, const T
   }
 }
 
+// The same slicing on the CSR layout (rows sorted by neighbour), G lanes per
+// row as in k_ctqw_csr<G>: lane l of a row takes its arcs lo + l + G m, the
+// first eight of them held in registers, the rest (rows longer than 8 G) read
+// from memory behind a cursor.  In each slice's pass a lane adds its arcs that
+// fall inside the slice in increasing m, so each lane's sum, and the butterfly
+// across the row's lanes, are those of k_ctqw_csr<G>: the same bits.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_ctqw_csr_sliced(GraphView g, const T *__restrict__ y, const T *psi,
+                                                            T *out, double alpha, double beta, int slice) {
+  constexpr int RPW = kBlock / G;  // rows per workgroup
+  const int n = g.n;
+  const int n_groups = (n + RPW - 1) / RPW;
+  const int lane = static_cast<int>(threadIdx.x) % G;
+  for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    const int row = grp * RPW + static_cast<int>(threadIdx.x) / G;
+    const int lo = row < n ? g.rp[row] : 0, hi = row < n ? g.rp[row + 1] : 0;
+    unsigned c[8];  // 0xffffffff (never inside a slice) pads
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int a = lo + lane + G * m;
+      c[m] = a < hi ? static_cast<unsigned>(g.col[a]) : 0xffffffffu;
+    }
+    int cur = lo + lane + 8 * G;  // next arc of this lane beyond the registers
+    double2 acc = make_double2(0.0, 0.0);
+    for (int s0 = 0; s0 < n; s0 += slice) {
+      const unsigned b0 = static_cast<unsigned>(s0), b1 = b0 + static_cast<unsigned>(slice);
+      T x[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        if (c[m] - b0 < b1 - b0) x[m] = y[c[m]];
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        if (c[m] - b0 < b1 - b0) acc = add(acc, cvt(x[m]));
+      while (cur < hi) {  // rows longer than 8 G: the lane's later arcs, in order
+        const unsigned cc = static_cast<unsigned>(g.col[cur]);
+        if (cc >= b1) break;
+        acc = add(acc, cvt(y[cc]));
+        cur += G;
+      }
+    }
+    double sx = acc.x, sy = acc.y;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+      sx += __shfl_xor(sx, off, 64);
+      sy += __shfl_xor(sy, off, 64);
+    }
+    if (row < n && lane == 0) {
+      const bool mk = marked(g.markbits, row);
+      const double2 yv = mk ? ld(y, row) : make_double2(0.0, 0.0);
+      st(out, row, horner_out(ld(psi, row), make_double2(sx, sy), yv, mk, alpha, beta));
+    }
+  }
+}
+
 // workgroups of `kernel` (kBlock threads) the current device holds at once
 template <typename K> int resident_groups(K kernel) {
   static int cached[64] = {0};
@@ -2367,6 +2421,15 @@ hipError_t launch_coined_struct(const GraphView &g, const void *in, void *out, i
 template <typename T, int G, bool PROB>
 void launch_csr_g(const GraphView &g, const T *y, const T *psi, T *out, StageCoef c, double *p,
                   double *partials, hipStream_t s) {
+  if (!PROB && g.sorted_rows && G <= 16 &&
+      static_cast<int64_t>(g.n) * static_cast<int64_t>(sizeof(T)) > kEllSliceFrom) {
+    constexpr int GS = G <= 16 ? G : 16;
+    const int groups = static_cast<int>(blocks_for(g.n, kBlock / GS));
+    const dim3 sgrid(std::min(groups, resident_groups(k_ctqw_csr_sliced<T, GS>)));
+    hipLaunchKernelGGL((k_ctqw_csr_sliced<T, GS>), sgrid, dim3(kBlock), 0, s, g, y, psi, out, c.alpha, c.beta,
+                       kEllSliceEntries);
+    return;
+  }
   const int64_t threads = static_cast<int64_t>(g.n) * G;
   hipLaunchKernelGGL((k_ctqw_csr<T, G, PROB>), dim3(blocks_for(threads, kBlock)), dim3(kBlock), 0, s, g, y,
                      psi, out, c.alpha, c.beta, p, partials);

@@ -25,6 +25,7 @@ struct qw_plan {
   int32_t n_marked = 0;
   int32_t n_tiles = 0;
   int32_t group = 1;
+  int32_t sorted_rows = 0;  // CTQW CSR: every row's neighbours in increasing order
   // dense layout: walks per state, leading dimension and padded rows of H,
   // and where H sits in the device graph buffer (after the uploaded image)
   int32_t columns = 1;

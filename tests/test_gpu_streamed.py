@@ -289,3 +289,41 @@ def test_sliced_in_core_stage_and_streamed(dtype):
             check(y)
             st.close()
         core.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sliced_csr_stage(dtype):
+    """Irregular graphs whose vector exceeds 7.5 MiB take the column-sliced CSR stage
+    (one lane per row for mean degree <= 6, two up to 12; rows longer than eight arcs
+    per lane continue from memory).  One lane per row adds each row in arc order, as
+    the direct out-of-core stage does: bitwise equal; both lane counts equal the
+    oracle."""
+    from paper_2406_08186_amd.walk import Plan
+    n = 1050000
+    for gi, dbar in enumerate((5.0, 9.0)):
+        g = I.erdos_renyi(n, dbar / (n - 1), seed=30 + gi)
+        dmax = int(np.diff(g.row_ptr).max())
+        assert dmax > 8 * (1 if dbar < 6 else 2)  # some rows take the cursor path
+        params = dict(gamma=1.0 / dbar, dt=1.0 / (dmax / dbar + 1.0), taylor_order=9, marked=[11, n - 5])
+        psi0 = I.random_state(g.n, 70 + gi)
+        ref = oracle.ctqw_evolve(g.row_ptr, g.col, psi0, 2, gamma=params["gamma"], dt=params["dt"], K=9,
+                                 marked=params["marked"])
+        core = Plan(g, "ctqw", dtype=dtype, layout="csr", **params)
+        x = core.state(psi0)
+        core.evolve(x, 2)
+        torch.cuda.synchronize()
+        print(f"[case] sliced csr {dtype} mean degree {dbar}", flush=True)
+        got = x.cpu().numpy().astype(np.complex128)
+        if dtype == "c128":
+            assert np.abs(got - ref).max() < 1e-12
+        else:
+            assert np.linalg.norm(got - ref) < 1e-5
+        if dbar < 6:
+            st = _plan(g, params, dtype)
+            st.upload_streamed(st.info.state_bytes + st.info.work_bytes + 8 * g.n + (1 << 24))
+            y = st.state(psi0)
+            st.evolve(y, 2)
+            torch.cuda.synchronize()
+            assert torch.equal(x, y)
+            st.close()
+        core.close()
