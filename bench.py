@@ -47,6 +47,9 @@ MEASURED_TRAFFIC = {
     # default command, FETCH_SIZE 2,897,211.7 KiB x 2.00 + WRITE_SIZE 1,164,456.9 KiB x 1.00
     # (the kernel with 0xffffffff neighbour pads)
     "k_batch_ell_lds<float2,1024,4,16384> batch4096 seed1 launches1280-6400": (2897211.7 * 2 + 1164456.9) * 1024,
+    # profiles/ctqw_torus1024_sweep.md: the FP32 complex64 sweep, averaged over the four
+    # launches of a step, FETCH_SIZE (4543.1 + 3 x 8942.0) / 4 KiB x 2.00 + WRITE_SIZE 8193.3 KiB
+    "k_ctqw_torus_sweep<float2,5> 1024x1024": ((4543.1 + 3 * 8942.0) / 4 * 2 + 8193.3) * 1024,
 }
 
 
