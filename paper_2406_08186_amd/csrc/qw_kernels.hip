@@ -882,15 +882,16 @@ __global__ __launch_bounds__(kBlock) void k_ctqw_ell(GraphView g, const T *__res
   }
 }
 
-// Regular graphs whose vector exceeds an XCD's L2 share: the same ELL stage,
-// column-sliced.  A thread takes RPT rows of a row group and loads their
-// neighbour indices once; then, for each slice of kEllSliceEntries entries of
-// the input vector in turn, it gathers only the neighbours inside that slice.  The grid
-// is what the GPU holds at once (groups taken grid-stride), so its
-// workgroups walk the slices together and an XCD's L2 holds the slice being
-// gathered instead of a random part of the whole vector.  Rows are sorted by
-// neighbour, so adding slice after slice adds each row's neighbours in row
-// order: the result is bitwise that of k_ctqw_ell.
+// Regular graphs whose vector is several times an XCD's L2 (above
+// kEllSliceFrom bytes): the same ELL stage, column-sliced.  A thread takes RPT
+// rows of a row group and loads their neighbour indices once; then, for each
+// slice of kEllSliceEntries entries of the input vector in turn, it gathers
+// only the neighbours inside that slice.  The grid is what the GPU holds at
+// once (groups taken grid-stride), so its workgroups walk the slices together
+// and an XCD's L2 holds the slice being gathered instead of a random part of
+// the whole vector.  Rows are sorted by neighbour, so adding slice after slice
+// adds each row's neighbours in row order: the result is bitwise that of
+// k_ctqw_ell.
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_ctqw_ell_sliced(GraphView g, const T *__restrict__ y, const T *psi,
                                                             T *out, double alpha, double beta, int slice) {
