@@ -853,13 +853,15 @@ def run_hypercube(args):
 def run_snapshots(args):
     """The 1024 x 1024 grid CTQW pass (1000 steps, complex64) with a snapshot
     every --snap-every steps brought to host memory: compute alone, the naive
-    form (evolve, then a synchronous copy per snapshot), and the streamed form
-    (device ring + pinned host buffers, copies on a second stream), for states
-    and for FP64 distributions."""
+    form (evolve, then a synchronous copy per snapshot), the streamed form
+    (qw_copy_to_host: a copy kernel on the walk's stream writes each snapshot
+    into its pinned host buffer), for states and for FP64 distributions, and
+    the copy-engine form (device ring, copies on a second stream) beside it."""
     import numpy as np
     import torch
 
     from paper_2406_08186_amd import inputs as I
+    from paper_2406_08186_amd import _lib as L
     from paper_2406_08186_amd.walk import Plan, stream_snapshots
     g = I.torus(L_SIDE, L_SIDE)
     v0 = (L_SIDE // 2) * L_SIDE + L_SIDE // 2
@@ -892,19 +894,31 @@ def run_snapshots(args):
     timed(compute)                                  # warm-up
     t_comp, _, ref = timed(compute)
     t_naive, out_n, _ = timed(naive)
+    t_ce, out_ce, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "state", host=pinned_s, via="copy_engine"))
+    out_ce = [x.copy() for x in out_ce]             # the buffers are reused below
+    t_ce_prob, _, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "probability", host=pinned_p,
+                                                         via="copy_engine"))
     t_state, out_s, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "state", host=pinned_s))
     t_prob, out_p, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "probability", host=pinned_p))
     same = all(np.array_equal(a, b) for a, b in zip(out_n, out_s))
+    same_ce = all(np.array_equal(a, b) for a, b in zip(out_ce, out_s))
     final_ok = np.array_equal(out_s[-1], ref.cpu().numpy())
-    # the copy engine's rate alone: the same device-to-pinned copies, nothing
+    # each transfer's rate alone: the same device-to-pinned copies, nothing
     # else running (this overwrites the pinned buffers, so it comes last)
     src = pl.state(psi0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for h in pinned_s:
-        h.copy_(src, non_blocking=True)
-    torch.cuda.synchronize()
-    t_d2h = time.perf_counter() - t0
+    cs = int(torch.cuda.current_stream().cuda_stream)
+    rates = {}
+    for via in ("copy_engine", "link"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for h in pinned_s:
+            if via == "link":
+                L.qw_copy_to_host(h.data_ptr(), src.data_ptr(), g.n * 8, cs)
+            else:
+                h.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        rates[via] = time.perf_counter() - t0
+    t_d2h, t_link = rates["copy_engine"], rates["link"]
     mb_state = len(snaps) * g.n * 8 / 1e6
     mb_prob = len(snaps) * g.n * 8 / 1e6
     print(json.dumps({
@@ -915,8 +929,11 @@ def run_snapshots(args):
         "streamed_overhead_vs_compute": t_state / t_comp - 1.0,
         "naive_overhead_vs_compute": t_naive / t_comp - 1.0,
         "states_MB": mb_state, "probabilities_MB": mb_prob,
-        "streamed_states_GBps": mb_state / 1e3 / t_state, "d2h_alone_GBps": mb_state / 1e3 / t_d2h,
-        "streamed_equals_naive": same, "final_equals_unsnapshotted": final_ok,
+        "streamed_states_GBps": mb_state / 1e3 / t_state, "link_copy_alone_GBps": mb_state / 1e3 / t_link,
+        "copy_engine_states_ms": t_ce * 1e3, "copy_engine_probabilities_ms": t_ce_prob * 1e3,
+        "copy_engine_alone_GBps": mb_state / 1e3 / t_d2h,
+        "streamed_equals_naive": same, "copy_engine_equals_streamed": same_ce,
+        "final_equals_unsnapshotted": final_ok,
         "arc_steps_per_s_streamed": g.n_arcs * STEPS_PER_PASS / t_state}), flush=True)
 
 

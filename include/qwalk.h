@@ -370,6 +370,21 @@ int qw_evolve_static(const qw_plan *plan, void *d_psi, int64_t steps, double *d_
 int qw_probabilities(const qw_plan *plan, const void *d_psi, double *d_p, double *d_norm,
                      double *d_pmarked, void *d_work, size_t work_bytes, void *stream);
 
+/* Snapshot transfer for simulate(range=...) (Sec. 3.1, Sec. 3.2: the state,
+ * or its probabilities, at every step of a range, handed back to the caller
+ * in host memory).  Copy `bytes` bytes from device memory d_src to h_dst,
+ * pinned host memory the device can write (hipHostMalloc, or a framework's
+ * pinned allocation built on it), by a kernel on `stream` whose stores cross
+ * the host link directly; no copy engine takes part, so the copy is ordered
+ * with the stream's kernels like any other launch and does not compete with
+ * them for a second queue.  Both pointers 16-byte aligned; d_src lies in one
+ * device allocation of at least `bytes` bytes from d_src on; h_dst holds at
+ * least `bytes` bytes.  The caller owns both buffers; h_dst may be read once
+ * the stream has passed the call.  bytes == 0 is a no-op.  Errors:
+ * QW_EINVAL (null or misaligned buffer, source not device memory or shorter
+ * than `bytes`, destination not pinned), QW_EDEVICE. */
+int qw_copy_to_host(void *h_dst, const void *d_src, size_t bytes, void *stream);
+
 /* ---- many small walks in one launch ------------------------------------- */
 /* Advance `count` independent walks by steps[i] steps each (Sec. 3.1 for
  * CTQW, Sec. 3.2 for coined walks, QW_STAGGERED above for staggered walks)

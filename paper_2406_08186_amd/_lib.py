@@ -30,7 +30,7 @@ STRUCTURES = {0: "general", 1: "cycle", 2: "torus", 3: "hypercube", 4: "small", 
               7: "stag_lattice"}
 
 EXPORTS = ["qw_plan_create", "qw_plan_destroy", "qw_plan_get_info", "qw_plan_upload", "qw_evolve",
-           "qw_probabilities", "qw_small_many_desc_bytes", "qw_small_many",
+           "qw_probabilities", "qw_copy_to_host", "qw_small_many_desc_bytes", "qw_small_many",
            "qw_taylor_order", "qw_taylor_plan", "qw_taylor_tail_bound",
            "qw_last_error", "qw_version",
            "qw_batch_create", "qw_batch_destroy", "qw_batch_device_bytes", "qw_batch_bind",
@@ -91,6 +91,7 @@ def lib():
         L.qw_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
         L.qw_evolve.argtypes = [vp, vp, vp, C.c_size_t, C.c_int64, vp, vp, vp, vp]
         L.qw_probabilities.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.qw_copy_to_host.argtypes = [vp, vp, C.c_size_t, vp]
         L.qw_small_many_desc_bytes.argtypes = [C.c_int32]
         L.qw_small_many_desc_bytes.restype = C.c_size_t
         L.qw_small_many.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32, vp,
@@ -169,6 +170,10 @@ def qw_probabilities(plan, d_psi: int, d_p, d_norm, d_pmarked, d_work: int, work
                      stream: int) -> None:
     check(lib().qw_probabilities(plan, d_psi, d_p, d_norm, d_pmarked, d_work, work_bytes, stream),
           "qw_probabilities")
+
+
+def qw_copy_to_host(h_dst: int, d_src: int, nbytes: int, stream: int) -> None:
+    check(lib().qw_copy_to_host(h_dst, d_src, nbytes, stream), "qw_copy_to_host")
 
 
 def qw_small_many_desc_bytes(count: int) -> int:

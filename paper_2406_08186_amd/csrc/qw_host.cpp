@@ -1092,6 +1092,34 @@ int qw_probabilities(const qw_plan *p, const void *d_psi, double *d_p, double *d
   return st == QW_OK ? ok() : st;
 }
 
+int qw_copy_to_host(void *h_dst, const void *d_src, size_t bytes, void *stream) {
+  if (bytes == 0) return ok();
+  if (!h_dst || !d_src) return fail(QW_EINVAL, "null buffer");
+  if ((reinterpret_cast<uintptr_t>(h_dst) | reinterpret_cast<uintptr_t>(d_src)) & 15)
+    return fail(QW_EINVAL, "buffers must be 16-byte aligned");
+  hipPointerAttribute_t attr{};
+  if (hipPointerGetAttributes(&attr, d_src) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(QW_EINVAL, "source is not device memory");
+  }
+  void *base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(reinterpret_cast<hipDeviceptr_t *>(&base), &size, const_cast<void *>(d_src)) !=
+          hipSuccess ||
+      static_cast<const char *>(d_src) + bytes > static_cast<const char *>(base) + size) {
+    (void)hipGetLastError();
+    return fail(QW_EINVAL, "source allocation holds fewer than %zu bytes", bytes);
+  }
+  void *dp = nullptr;
+  if (hipHostGetDevicePointer(&dp, h_dst, 0) != hipSuccess || !dp || (reinterpret_cast<uintptr_t>(dp) & 15)) {
+    (void)hipGetLastError();
+    return fail(QW_EINVAL, "destination is not pinned host memory the device can write (hipHostMalloc)");
+  }
+  const hipError_t e = copy_link(dp, d_src, bytes, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(QW_EDEVICE, "copy launch: %s", hipGetErrorString(e));
+  return ok();
+}
+
 size_t qw_small_many_desc_bytes(int32_t count) {
   return count > 0 ? sizeof(SmallWalk) * static_cast<size_t>(count) : 0;
 }

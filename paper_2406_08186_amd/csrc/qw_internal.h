@@ -32,6 +32,7 @@ constexpr int kEllSliceEntries = 131072;
 constexpr int kEllSliceRows = QW_ELL_SLICE_ROWS;  // rows per thread of the sliced stage
 constexpr int kDirRows = 256;   // rows per workgroup tile of the direct out-of-core stage (one per thread)
 constexpr int kDirArcs = 8192;  // neighbour indices such a tile stages in LDS (32 KiB)
+constexpr int kLinkCopyGroups = 16;  // workgroups of the device-to-pinned-host copy (enough for the link)
 constexpr int kTileMaxVerts = 1024;
 // Threads per workgroup of the elementwise/stencil kernels.
 constexpr int kBlock = 256;
@@ -288,6 +289,9 @@ hipError_t batch_stage(bool c128, BatchCtl *ctl, const WalkSlot *slots, const Ti
 // [arc0, ...)) sit in a device slot: slot[a - arc0] = col[a].
 hipError_t ctqw_slot_stage(bool c128, const GraphView &g, const int32_t *slot, int64_t arc0, int r0, int r1,
                            const void *y, const void *psi, void *out, double alpha, double beta, hipStream_t s);
+// Copy `bytes` bytes of device memory src to dst, the device view of pinned
+// host memory, by a kernel on stream s (both 16-byte aligned).
+hipError_t copy_link(void *dst, const void *src, size_t bytes, hipStream_t s);
 // Direct out-of-core CTQW stage: workgroup tile w holds rows [wg_row[w],
 // wg_row[w+1]) (at most kDirRows rows and kDirArcs arcs, or one longer row);
 // neighbour indices of arcs below `split` (a multiple of 4) come from the

@@ -28,6 +28,8 @@ namespace {
 
 constexpr double kInvSqrt2 = 0.70710678118654752440;
 
+typedef int i32x4 __attribute__((ext_vector_type(4)));  // 16-byte vector for the non-temporal builtin
+
 inline int blocks_for(int64_t n, int per) { return static_cast<int>((n + per - 1) / per); }
 
 // ---- storage <-> FP64 -------------------------------------------------------
@@ -2053,6 +2055,20 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
   }
 }
 
+// ---- snapshots: device memory straight into pinned host memory ------------------
+// A grid-stride copy whose stores cross the link as the kernel issues them
+// (no copy engine): 16-byte vector loads from device memory, non-temporal
+// 16-byte stores to the device view of a pinned host buffer, then the last
+// bytes % 16 bytes one by one.  Both pointers are 16-byte aligned.
+__global__ __launch_bounds__(256) void k_copy_link(const i32x4 *__restrict__ src, i32x4 *__restrict__ dst,
+                                                   int64_t n16, const unsigned char *__restrict__ src_tail,
+                                                   unsigned char *__restrict__ dst_tail, int tail) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t i = first; i < n16; i += stride) __builtin_nontemporal_store(src[i], &dst[i]);
+  if (first < tail) dst_tail[first] = src_tail[first];
+}
+
 // ---- dense H on the matrix cores -------------------------------------------------
 // H (n x n real, rows padded to kDenseRows, leading dimension ld) times the
 // real view of the state block Y (n x 2C: each complex column b is the real
@@ -2735,6 +2751,17 @@ hipError_t ctqw_slot_stage(bool c128, const GraphView &g, const int32_t *slot, i
     hipLaunchKernelGGL(k_ctqw_csr_slot<float2>, grid, dim3(kBlock), 0, s, g.rp, slot, arc0, r0, r1, g.markbits,
                        static_cast<const float2 *>(y), static_cast<const float2 *>(psi),
                        static_cast<float2 *>(out), alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t copy_link(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const int64_t n16 = static_cast<int64_t>(bytes / 16);
+  const int tail = static_cast<int>(bytes % 16);
+  const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kLinkCopyGroups, (n16 + 255) / 256)));
+  hipLaunchKernelGGL(k_copy_link, dim3(grid), dim3(256), 0, s, static_cast<const i32x4 *>(src),
+                     static_cast<i32x4 *>(dst), n16, static_cast<const unsigned char *>(src) + 16 * n16,
+                     static_cast<unsigned char *>(dst) + 16 * n16, tail);
   return hipGetLastError();
 }
 

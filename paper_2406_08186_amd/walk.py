@@ -329,31 +329,58 @@ def _steps_of(rng) -> list[int]:
 
 
 def stream_snapshots(plan: Plan, psi: torch.Tensor, steps: Sequence[int], kind: str = "state",
-                     ring: int = 3, host: Sequence[torch.Tensor] | None = None) -> list[np.ndarray]:
+                     ring: int = 3, host: Sequence[torch.Tensor] | None = None,
+                     via: str = "link") -> list[np.ndarray]:
     """Evolve psi in place through the step indices `steps` (increasing, from the
     state's current step 0) and return, for each, the state (kind "state") or
     its FP64 vertex probabilities (kind "probability") in host memory.
 
-    Each snapshot is produced on torch's current stream into one of `ring`
-    device slots (a copy of the state, or the qw_probabilities readout) and
-    copied to pinned host memory on a second stream while the walk moves on;
-    a slot is reused only after its copy has finished.  The snapshots equal
-    those of evolve calls stopped at each step (the same kernels run).  `host`
-    may supply the pinned destination tensors (one per step) for reuse."""
+    via "link" (the default): on torch's current stream, after the evolve that
+    reaches each step, qw_copy_to_host writes the state (or the
+    qw_probabilities readout) straight into the pinned host buffer with a
+    kernel, ordered with the walk like any other launch.  via "copy_engine":
+    each snapshot is copied into one of `ring` device slots and from there to
+    the host buffer by the copy engine on a second stream while the walk moves
+    on; a slot is reused only after its copy has finished.  Either way the
+    snapshots equal those of evolve calls stopped at each step (the same
+    kernels run).  `host` may supply the pinned, contiguous destination
+    tensors (one per step) for reuse."""
     if kind not in ("state", "probability"):
         raise ValueError("kind is 'state' or 'probability'")
+    if via not in ("link", "copy_engine"):
+        raise ValueError("via is 'link' or 'copy_engine'")
     steps = list(steps)
     if any(b <= a for a, b in zip(steps, steps[1:])) or (steps and steps[0] < 0):
         raise ValueError("steps must be increasing and non-negative")
     plan._check(psi)
     dev = plan.device
     cs = torch.cuda.current_stream(dev)
-    xs = torch.cuda.Stream(dev)
     shape, dt = (psi.shape, psi.dtype) if kind == "state" else ((plan.p_len,), torch.float64)
     if host is None:
         host = [torch.empty(shape, dtype=dt, pin_memory=True) for _ in steps]
-    elif len(host) != len(steps) or any(h.shape != shape or h.dtype != dt or not h.is_pinned() for h in host):
-        raise ValueError("host buffers must be pinned, one per step, of the snapshot's shape and dtype")
+    elif len(host) != len(steps) or any(h.shape != shape or h.dtype != dt or not h.is_pinned()
+                                        or not h.is_contiguous() for h in host):
+        raise ValueError("host buffers must be pinned and contiguous, one per step, of the snapshot's "
+                         "shape and dtype")
+    if via == "link":
+        if kind == "probability":
+            pbuf = torch.empty(max(plan.p_len, 1), dtype=torch.float64, device=dev)
+            scal = torch.empty(2, dtype=torch.float64, device=dev)
+        at = 0
+        for j, k in enumerate(steps):
+            plan.evolve(psi, k - at, stream=cs)
+            at = k
+            if kind == "state":
+                src = psi
+            else:
+                L.qw_probabilities(plan._plan, psi.data_ptr(), pbuf.data_ptr(), scal.data_ptr(), None,
+                                   plan.work.data_ptr(), plan.work.numel(), int(cs.cuda_stream))
+                src = pbuf
+            L.qw_copy_to_host(host[j].data_ptr(), src.data_ptr(), host[j].numel() * host[j].element_size(),
+                              int(cs.cuda_stream))
+        cs.synchronize()
+        return [h.numpy() for h in host]
+    xs = torch.cuda.Stream(dev)
     if kind == "state":
         slots = [torch.empty_like(psi) for _ in range(ring)]
     else:
@@ -406,7 +433,8 @@ class _Walk:
     def simulate_host(self, range=1, state=None, kind: str = "state") -> list[np.ndarray]:
         """simulate() streamed to host memory: states (or, with kind
         "probability", FP64 distributions) at the step indices of range(...),
-        copied out on a second stream while the walk continues."""
+        written into pinned host memory by a copy kernel on the walk's stream
+        as each step is reached."""
         psi = self.plan.state(state)
         return stream_snapshots(self.plan, psi, _steps_of(range), kind)
 

@@ -1,5 +1,6 @@
-"""Streamed snapshots (states and FP64 distributions copied to pinned host
-memory on a second stream while the walk continues): each equals the state of
+"""Streamed snapshots (states and FP64 distributions written into pinned host
+memory by the link-copy kernel on the walk's stream, or copied by the copy
+engine on a second stream while the walk continues): each equals the state of
 an evolve stopped at that step, bitwise, and the oracle to the usual bar."""
 import numpy as np
 import pytest
@@ -44,3 +45,58 @@ def test_coined_snapshots_structured():
         assert np.array_equal(h, d.cpu().numpy())
     ref = oracle.coined_evolve(g.row_ptr, g.col, psi0, 6, marked=[0])
     assert np.abs(host[-1] - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("via", ["link", "copy_engine"])
+def test_snapshot_transfer_modes_agree(via):
+    from paper_2406_08186_amd.walk import Plan, stream_snapshots
+    g = I.random_regular(3000, 5, seed=4)
+    print(f"[case] snapshots {via} {g.name}", flush=True)
+    pl = Plan(g, "ctqw", dtype="c64", gamma=0.2, dt=0.3, taylor_order=10, marked=[7])
+    psi0 = I.random_state(g.n, seed=2)
+    steps = [1, 2, 5, 9, 10, 17]
+    s_host = stream_snapshots(pl, pl.state(psi0), steps, "state", via=via)
+    p_host = stream_snapshots(pl, pl.state(psi0), steps, "probability", via=via)
+    psi = pl.state(psi0)
+    at = 0
+    for k, hs, hp in zip(steps, s_host, p_host):
+        pl.evolve(psi, k - at)
+        at = k
+        assert np.array_equal(hs, psi.cpu().numpy()), k
+        assert np.array_equal(hp, pl.probabilities(psi)[0].cpu().numpy()), k
+
+
+@pytest.mark.parametrize("nbytes", [0, 8, 16, 24, 4096 + 15, (3 << 20) + 7])
+def test_copy_to_host_sizes(nbytes):
+    from paper_2406_08186_amd import _lib as L
+    print(f"[case] qw_copy_to_host {nbytes} bytes", flush=True)
+    gen = torch.Generator().manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes + 32,), dtype=torch.uint8, generator=gen).cuda()
+    dst = torch.full((nbytes + 32,), 0xA5, dtype=torch.uint8).pin_memory()
+    L.qw_copy_to_host(dst.data_ptr(), src.data_ptr(), nbytes, int(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.current_stream().synchronize()
+    got, want = dst.numpy(), src.cpu().numpy()
+    assert np.array_equal(got[:nbytes], want[:nbytes])
+    assert (got[nbytes:] == 0xA5).all()       # nothing past the range is written
+
+
+def test_copy_to_host_refusals():
+    from paper_2406_08186_amd import _lib as L
+    print("[case] qw_copy_to_host refusals", flush=True)
+    s = int(torch.cuda.current_stream().cuda_stream)
+    src = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    pinned = torch.zeros(1024, dtype=torch.uint8).pin_memory()
+    pageable = np.zeros(1024, dtype=np.uint8)
+    host_src = torch.zeros(1024, dtype=torch.uint8)
+    with pytest.raises(RuntimeError, match="pinned"):
+        L.qw_copy_to_host(pageable.ctypes.data, src.data_ptr(), 1024, s)
+    with pytest.raises(RuntimeError, match="aligned"):
+        L.qw_copy_to_host(pinned.data_ptr() + 8, src.data_ptr(), 512, s)
+    with pytest.raises(RuntimeError, match="aligned"):
+        L.qw_copy_to_host(pinned.data_ptr(), src.data_ptr() + 4, 512, s)
+    with pytest.raises(RuntimeError, match="device memory"):
+        L.qw_copy_to_host(pinned.data_ptr(), host_src.data_ptr(), 512, s)
+    with pytest.raises(RuntimeError, match="fewer than"):
+        L.qw_copy_to_host(pinned.data_ptr(), src.data_ptr(), 1 << 40, s)
+    with pytest.raises(RuntimeError, match="null"):
+        L.qw_copy_to_host(None, src.data_ptr(), 16, s)
