@@ -856,7 +856,8 @@ def run_snapshots(args):
     form (evolve, then a synchronous copy per snapshot), the streamed form
     (qw_copy_to_host: a copy kernel on the walk's stream writes each snapshot
     into its pinned host buffer), for states and for FP64 distributions, and
-    the copy-engine form (device ring, copies on a second stream) beside it."""
+    the runtime-copy form (device ring, hipMemcpyAsync on a second stream)
+    beside it."""
     import numpy as np
     import torch
 
@@ -894,10 +895,10 @@ def run_snapshots(args):
     timed(compute)                                  # warm-up
     t_comp, _, ref = timed(compute)
     t_naive, out_n, _ = timed(naive)
-    t_ce, out_ce, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "state", host=pinned_s, via="copy_engine"))
+    t_ce, out_ce, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "state", host=pinned_s, via="memcpy"))
     out_ce = [x.copy() for x in out_ce]             # the buffers are reused below
     t_ce_prob, _, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "probability", host=pinned_p,
-                                                         via="copy_engine"))
+                                                         via="memcpy"))
     t_state, out_s, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "state", host=pinned_s))
     t_prob, out_p, _ = timed(lambda psi: stream_snapshots(pl, psi, snaps, "probability", host=pinned_p))
     same = all(np.array_equal(a, b) for a, b in zip(out_n, out_s))
@@ -908,7 +909,7 @@ def run_snapshots(args):
     src = pl.state(psi0)
     cs = int(torch.cuda.current_stream().cuda_stream)
     rates = {}
-    for via in ("copy_engine", "link"):
+    for via in ("memcpy", "link"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for h in pinned_s:
@@ -918,7 +919,7 @@ def run_snapshots(args):
                 h.copy_(src, non_blocking=True)
         torch.cuda.synchronize()
         rates[via] = time.perf_counter() - t0
-    t_d2h, t_link = rates["copy_engine"], rates["link"]
+    t_d2h, t_link = rates["memcpy"], rates["link"]
     mb_state = len(snaps) * g.n * 8 / 1e6
     mb_prob = len(snaps) * g.n * 8 / 1e6
     print(json.dumps({
@@ -930,9 +931,9 @@ def run_snapshots(args):
         "naive_overhead_vs_compute": t_naive / t_comp - 1.0,
         "states_MB": mb_state, "probabilities_MB": mb_prob,
         "streamed_states_GBps": mb_state / 1e3 / t_state, "link_copy_alone_GBps": mb_state / 1e3 / t_link,
-        "copy_engine_states_ms": t_ce * 1e3, "copy_engine_probabilities_ms": t_ce_prob * 1e3,
-        "copy_engine_alone_GBps": mb_state / 1e3 / t_d2h,
-        "streamed_equals_naive": same, "copy_engine_equals_streamed": same_ce,
+        "memcpy_states_ms": t_ce * 1e3, "memcpy_probabilities_ms": t_ce_prob * 1e3,
+        "memcpy_alone_GBps": mb_state / 1e3 / t_d2h,
+        "streamed_equals_naive": same, "memcpy_equals_streamed": same_ce,
         "final_equals_unsnapshotted": final_ok,
         "arc_steps_per_s_streamed": g.n_arcs * STEPS_PER_PASS / t_state}), flush=True)
 

@@ -338,17 +338,17 @@ def stream_snapshots(plan: Plan, psi: torch.Tensor, steps: Sequence[int], kind: 
     via "link" (the default): on torch's current stream, after the evolve that
     reaches each step, qw_copy_to_host writes the state (or the
     qw_probabilities readout) straight into the pinned host buffer with a
-    kernel, ordered with the walk like any other launch.  via "copy_engine":
-    each snapshot is copied into one of `ring` device slots and from there to
-    the host buffer by the copy engine on a second stream while the walk moves
-    on; a slot is reused only after its copy has finished.  Either way the
+    kernel, ordered with the walk like any other launch.  via "memcpy": each
+    snapshot is copied into one of `ring` device slots and from there to the
+    host buffer by the runtime's asynchronous copy on a second stream while
+    the walk moves on; a slot is reused only after its copy has finished.  Either way the
     snapshots equal those of evolve calls stopped at each step (the same
     kernels run).  `host` may supply the pinned, contiguous destination
     tensors (one per step) for reuse."""
     if kind not in ("state", "probability"):
         raise ValueError("kind is 'state' or 'probability'")
-    if via not in ("link", "copy_engine"):
-        raise ValueError("via is 'link' or 'copy_engine'")
+    if via not in ("link", "memcpy"):
+        raise ValueError("via is 'link' or 'memcpy'")
     steps = list(steps)
     if any(b <= a for a, b in zip(steps, steps[1:])) or (steps and steps[0] < 0):
         raise ValueError("steps must be increasing and non-negative")

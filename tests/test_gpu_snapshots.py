@@ -1,6 +1,6 @@
 """Streamed snapshots (states and FP64 distributions written into pinned host
-memory by the link-copy kernel on the walk's stream, or copied by the copy
-engine on a second stream while the walk continues): each equals the state of
+memory by the link-copy kernel on the walk's stream, or copied by the
+runtime's asynchronous copy on a second stream while the walk continues): each equals the state of
 an evolve stopped at that step, bitwise, and the oracle to the usual bar."""
 import numpy as np
 import pytest
@@ -47,7 +47,7 @@ def test_coined_snapshots_structured():
     assert np.abs(host[-1] - ref).max() < 1e-12
 
 
-@pytest.mark.parametrize("via", ["link", "copy_engine"])
+@pytest.mark.parametrize("via", ["link", "memcpy"])
 def test_snapshot_transfer_modes_agree(via):
     from paper_2406_08186_amd.walk import Plan, stream_snapshots
     g = I.random_regular(3000, 5, seed=4)
