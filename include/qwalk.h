@@ -486,9 +486,11 @@ int qw_batch_readout(qw_batch *batch, int32_t slot, double *d_p, double *d_norm,
 int qw_batch_set_schedule(qw_batch *batch, int32_t rows_per_tile, int32_t xcd_aware);
 /* Kernel for the Horner stages of CTQW walks on regular graphs of degree <= 8
  * (plans on the ELL path; the series of Sec. 3.1's evolution operator).
- * QW_BATCH_LDS (the default): tiles of 4096 rows, one workgroup each, that
+ * QW_BATCH_LDS (the default): tiles of 6144 rows, one workgroup each, that
  * pass over the walk's input vector in LDS-staged blocks, so the neighbour
- * gathers read LDS instead of L2.  QW_BATCH_GATHER: the gather kernel that
+ * gathers read LDS instead of L2 (walks whose state and workspace are 16-byte
+ * aligned and whose state holds at least 16 bytes; others, like every other
+ * walk, take the gather kernel).  QW_BATCH_GATHER: the gather kernel that
  * runs every other walk (rows_per_tile rows per tile, gathers through L2).
  * Both add a row's neighbours in increasing index order in FP64, so results
  * are bitwise equal.  Takes effect at the next commit.  Host only; QW_EINVAL

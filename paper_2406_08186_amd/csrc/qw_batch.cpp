@@ -143,10 +143,14 @@ int wait_stage(qw_batch *b) {
 
 // True when a slot's CTQW walk runs on the LDS-staged kernel.
 bool lds_slot(const qw_batch *b, const WalkSlot &w) {
-  // the LDS-staged kernel addresses the vector by 32-bit byte offsets
+  // the LDS-staged kernel addresses the vector by 32-bit byte offsets and
+  // stages it with 16-byte loads (aligned buffers, at least 16 bytes of state)
   const int64_t elem = b->dtype == QW_C128 ? 16 : 8;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(w.psi) | reinterpret_cast<uintptr_t>(w.w0) |
+                         reinterpret_cast<uintptr_t>(w.w1)) & 15) == 0;
   return b->stage_kernel == QW_BATCH_LDS && w.kind == QW_CTQW && w.ell_d >= 1 && w.ell_d <= 8 &&
-         static_cast<int64_t>(w.n) * elem < (int64_t{1} << 31);
+         static_cast<int64_t>(w.n) * elem < (int64_t{1} << 31) && static_cast<int64_t>(w.n) * elem >= 16 &&
+         aligned;
 }
 
 // Lay out walks' tiles by XCD: longest walks first, each onto the XCD with

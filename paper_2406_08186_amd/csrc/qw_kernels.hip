@@ -1906,33 +1906,39 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
 // degree <= 8 (ELL layout).  A workgroup owns NT * RPL consecutive rows of one
 // walk (a tile) and makes one pass over the walk's input vector y in blocks of
 // BLK entries held in LDS, so every neighbour value is read from LDS in the
-// block that holds it and the random gathers never reach L2; the blocks are
-// coalesced loads, and the vector (at most a few MB) stays in the XCD's L2
-// while the walk's tiles read it.  Rows keep their neighbour indices in
-// registers.  The plan stores each row's neighbours in increasing order, so
-// adding, block after block, the neighbours each block holds adds them in row
-// order: the sums are bitwise those of the gather kernels.  The next block is
-// prefetched into registers while the current one is summed.  Every lane
-// visits all 8 neighbour slots of its rows in every block (branch-free; a
-// slot outside the block adds -0), so the sum loop costs 8 LDS reads per row
-// and block: the kernel pays for walks whose vector spans many blocks.
-// Memory is reached through global-address-space views of the slot table's
-// pointers, and every load is unconditional (indices clamped into range,
-// unused values dropped by a select), so a wave issues all of a phase's loads
-// before it waits, and waits on LDS reads never wait for memory loads.
-// Tiles are taken grid-stride (the host lays out the table by XCD); the last
-// workgroup of the launch advances the launch counter when `advance` is set.
+// block that holds it and the random gathers never reach L2; the vector (at
+// most a few MB) stays in the XCD's L2 while the walk's tiles read it.  Rows
+// keep their neighbour indices in registers.  The plan stores each row's
+// neighbours in increasing order, so adding, block after block, the
+// neighbours each block holds adds them in row order: the sums are bitwise
+// those of the gather kernels.  Blocks are staged by LDS-direct loads
+// (global_load_lds_dwordx4: each lane's 16 bytes land at the wave's LDS base
+// plus 16 * lane, 1 KiB per wave instruction), which need no registers and no
+// LDS write instructions; the registers that a prefetch would hold carry six
+// rows per thread instead of four, so a walk has a third fewer tiles to pass
+// over its vector.  Every lane visits all 8 neighbour slots of its rows in
+// every block (branch-free; a slot outside the block adds -0), so the sum loop
+// costs 8 LDS reads per row and block: the kernel pays for walks whose vector
+// spans many blocks.  Memory is reached through global-address-space views of
+// the slot table's pointers, and every load is unconditional (indices clamped
+// into range, unused values dropped by a select).  Tiles are taken
+// grid-stride (the host lays out the table by XCD); the last workgroup of the
+// launch advances the launch counter when `advance` is set.  The host sends
+// only walks with n >= 2 whose psi and work buffers are 16-byte aligned.
 template <typename T, int NT, int RPL, int BLK>
 __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkSlot *slots,
                                                       const TileEntry *tiles, const int32_t *n_tiles,
                                                       int advance) {
-  static_assert(BLK % NT == 0, "a block is staged as whole rounds of the workgroup");
-  constexpr int PF = BLK / NT;
+  constexpr int kWaves = NT / 64;
+  constexpr int EPL = 16 / static_cast<int>(sizeof(T));  // entries per lane of one direct load
+  constexpr int EPW = 64 * EPL;                           // entries per wave load (1 KiB)
+  static_assert(NT % 64 == 0 && BLK % (kWaves * EPW) == 0, "a block is whole rounds of wave loads");
+  constexpr int LPW = BLK / (kWaves * EPW);  // direct loads per wave and block
   constexpr unsigned kPadByte = static_cast<unsigned>(BLK) * static_cast<unsigned>(sizeof(T));
   // xs[BLK] is a pad entry holding (-0, -0): a neighbour outside the current
   // block reads it, and adding -0 leaves every value (either zero included)
   // bit for bit unchanged, so the sum loop has no branch
-  __shared__ T xs[BLK + 1];
+  __shared__ __attribute__((aligned(16))) T xs[BLK + 1];
   if (threadIdx.x == 0) {
     xs[BLK].x = -0.0;
     xs[BLK].y = -0.0;
@@ -1941,26 +1947,31 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
   const bool probe = ctl->probe != 0;
   const int nt = *n_tiles;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     const TileEntry te = tiles[t];
     if (te.slot < 0) continue;
     const WalkSlot &w = slots[te.slot];
-    if (w.kind != 1 || w.ell_d <= 0 || w.ell_d > 8) continue;
+    if (w.kind != 1 || w.ell_d <= 0 || w.ell_d > 8 || w.n < EPL) continue;
     const int64_t u = probe ? 0 : L - w.L0;
     if (u < 0 || u >= w.units) continue;
     const int K = w.K;
     const int64_t step = u / K;
     const int k = K - static_cast<int>(u % K);
+    const T *yin_p = (k == K) ? static_cast<const T *>(w.psi) : static_cast<const T *>(((K - k - 1) & 1) ? w.w1 : w.w0);
     const gptr<T> psi = as_global(static_cast<const T *>(w.psi));
-    const gptr<T> yin = (k == K) ? psi : as_global(static_cast<const T *>(((K - k - 1) & 1) ? w.w1 : w.w0));
+    const gptr<T> yin = as_global(yin_p);
     const gmut<T> yout = as_global_mut(static_cast<T *>((k == 1) ? w.psi : (((K - k) & 1) ? w.w1 : w.w0)));
     const gptr<int32_t> col = as_global(w.col);
     const gptr<uint32_t> bits = as_global(w.markbits);
     const double alpha = as_global(w.alpha)[k - 1], beta = as_global(w.beta)[k - 1];
     const int n = w.n, d = w.ell_d;
+    // the last whole group of EPL entries: a lane whose group runs past the
+    // vector loads it instead (those LDS entries are never read, but for n-1
+    // when n is odd in complex64, written in place below)
+    const int last_group = (n - EPL) / EPL * EPL;
     // neighbour indices of this lane's rows; missing neighbours and rows past the
     // tile (their loads read a valid entry) become the pad offset below.
-    // All loads of a phase are issued before its first use (scheduling barrier).
     int c[RPL][8];
     double2 acc[RPL];
 #pragma unroll
@@ -1971,14 +1982,6 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
       for (int j = 0; j < 8; ++j) c[i][j] = col[static_cast<int64_t>(j < d ? j : d - 1) * n + rc];
       acc[i] = make_double2(0.0, 0.0);
     }
-    // entries past n are staged as copies of entry n-1 and never read
-    T pf[PF];
-#pragma unroll
-    for (int e = 0; e < PF; ++e) {
-      const int idx = tid + e * NT;
-      pf[e] = gld(yin, idx < n ? idx : n - 1);
-    }
-    __builtin_amdgcn_sched_barrier(0);
     // held as byte offsets into the vector (the host keeps n * sizeof(T) below 2^31);
     // a pad is 0xffffffff, whose offset from any block start (below 2^31) is at
     // least 2^31 and so always clamps to the pad entry
@@ -1991,14 +1994,19 @@ __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkS
     for (int base = 0; base < n; base += BLK) {
       __syncthreads();  // the previous block (or tile) is no longer read
 #pragma unroll
-      for (int e = 0; e < PF; ++e) xs[tid + e * NT] = pf[e];
-      __syncthreads();
-      const int nxt = base + BLK;
-      if (nxt < n) {
-#pragma unroll
-        for (int e = 0; e < PF; ++e) {
-          const int idx = nxt + tid + e * NT;
-          pf[e] = gld(yin, idx < n ? idx : n - 1);
+      for (int e = 0; e < LPW; ++e) {
+        const int lbase = (e * kWaves + wave) * EPW;  // first entry of this wave load
+        const int idx = base + lbase + EPL * lane;
+        const int src = idx + EPL <= n ? idx : last_group;
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(yin_p + src),
+                                         (void __attribute__((address_space(3))) *)(xs + lbase), 16, 0, 0);
+      }
+      __syncthreads();  // the direct loads have landed (the barrier waits for them)
+      if constexpr (EPL == 2) {
+        // odd n: entry n-1 sits in a group that runs past the vector
+        if ((n & 1) && n - 1 >= base && n - 1 < base + BLK) {
+          if (tid == 0) xs[n - 1 - base] = gld(yin, n - 1);
+          __syncthreads();
         }
       }
       // four LDS reads in flight per group, then their adds in neighbour order;

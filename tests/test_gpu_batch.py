@@ -258,13 +258,24 @@ def _relabelled(n, edges, seed, name):
 
 def _lds_walks():
     """CTQW walks on regular graphs of degree 1..8 (the LDS-staged kernel), sized around its
-    tile (4096 rows) and block (16384 complex64 / 8192 complex128 entries) edges, marks on
-    those edges; the largest also exceeds the size from which the single-walk path gathers
-    in column slices (7.5 MiB)."""
+    tile (6144 rows) and block (16384 complex64 / 8192 complex128 entries) edges, marks on
+    those edges, odd and even n (complex64 stages pairs of entries with 16-byte loads, so an
+    odd n leaves a last entry alone; the tiniest walks have 4 and 7 vertices); the largest
+    also exceeds the size from which the single-walk path gathers in column slices
+    (7.5 MiB)."""
     m = 6000
     matching = _relabelled(m, [(2 * i, 2 * i + 1) for i in range(m // 2)], 21, "matching")
     ring = _relabelled(9001, [(i, (i + 1) % 9001) for i in range(9001)], 22, "ring")
+
+    def cyc(n, seed):
+        return _relabelled(n, [(i, (i + 1) % n) for i in range(n)], seed, f"ring{n}")
     return [
+        (_relabelled(4, [(0, 1), (2, 3)], 23, "edges2"), dict(gamma=1.0, dt=0.4, taylor_order=10, marked=[1]), 6),
+        (_relabelled(7, [(0, 1), (1, 2), (2, 0), (3, 4), (4, 5), (5, 6), (6, 3)], 24, "tri_sq"),
+         dict(gamma=0.5, dt=0.3, taylor_order=12, marked=[6]), 6),
+        (cyc(6145, 25), dict(gamma=0.5, dt=0.3, taylor_order=12, marked=[6144]), 5),
+        (cyc(16385, 26), dict(gamma=0.5, dt=0.3, taylor_order=12, marked=[16384]), 4),
+        (I.random_regular(12289, 4, seed=39), dict(gamma=0.25, dt=0.4, taylor_order=13, marked=[12288]), 4),
         (matching, dict(gamma=1.0, dt=0.4, taylor_order=10, marked=[4095]), 5),
         (ring, dict(gamma=0.5, dt=0.3, taylor_order=12, marked=[8191]), 7),
         (I.random_regular(4096, 3, seed=31), dict(gamma=1 / 3, dt=0.5, taylor_order=14, marked=[4095]), 6),
