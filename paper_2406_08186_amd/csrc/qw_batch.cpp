@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kCoefStride = 128;  // doubles per slot: alpha[64], beta[64]
 constexpr int kMaxGrid = 2048;    // 8 workgroups per CU at 256 CUs
-constexpr int kLdsMaxGrid = 256;  // the LDS-staged kernel: one workgroup per CU (128 KiB of LDS each)
+constexpr int kLdsMaxGrid = 256;  // the LDS-staged kernel: one workgroup per CU (144 KiB of LDS each)
 constexpr int kGraphChunk = 16;   // launches per captured graph
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }

@@ -15,7 +15,7 @@ constexpr int kTileArcs = 2048;
 constexpr int kTileThreads = 256;
 constexpr int kLdsTileThreads = 1024;          // workgroup of the LDS-staged batch stage
 constexpr int kLdsTileRows = 6144;             // rows per tile of that kernel (6 per thread)
-constexpr int kLdsBlockBytes = 128 * 1024;     // LDS block of the input vector it stages
+constexpr int kLdsBlockBytes = 144 * 1024;     // LDS block of the input vector it stages
 // single-walk ELL stage: vectors above kEllSliceFrom bytes are gathered in
 // slices of kEllSliceEntries entries (measured best on 2^20 vertices for both
 // types, against 64Ki and 256Ki: 1 MiB complex64, 2 MiB complex128).  The
