@@ -1924,7 +1924,8 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
 // into range, unused values dropped by a select).  Tiles are taken
 // grid-stride (the host lays out the table by XCD); the last workgroup of the
 // launch advances the launch counter when `advance` is set.  The host sends
-// only walks with n >= 2 whose psi and work buffers are 16-byte aligned.
+// only walks whose state holds at least 16 bytes and whose psi and work
+// buffers are 16-byte aligned.
 template <typename T, int NT, int RPL, int BLK>
 __global__ __launch_bounds__(NT) void k_batch_ell_lds(BatchCtl *ctl, const WalkSlot *slots,
                                                       const TileEntry *tiles, const int32_t *n_tiles,
