@@ -44,9 +44,9 @@ METRIC = "arc-steps/s (c64 batched vs c128 plain, L2 err<=1e-4); p50/p99 latency
 # and launch configuration named in its key and source; any other reports None.
 MEASURED_TRAFFIC = {
     # profiles/batch4096_ctqw_search_lds.md: mean over the 5120 timed launches of the
-    # default command, FETCH_SIZE 3,039,500.8 KiB x 2.00 + WRITE_SIZE 1,164,456.9 KiB x 1.00
-    # (blocks of 18432 entries staged by LDS-direct loads, six rows per thread)
-    "k_batch_ell_lds<float2,1024,6,18432> batch4096 seed1 launches1280-6400": (3039500.8 * 2 + 1164456.9) * 1024,
+    # default command, FETCH_SIZE 3,088,620.9 KiB x 2.00 + WRITE_SIZE 1,164,456.9 KiB x 1.00
+    # (768 threads x 9 rows, 19968-entry blocks staged by LDS-direct loads)
+    "k_batch_ell_lds<float2,768,9,19968> batch4096 seed1 launches1280-6400": (3088620.9 * 2 + 1164456.9) * 1024,
     # profiles/ctqw_torus1024_sweep.md: the FP32 complex64 sweep, averaged over the four
     # launches of a step, FETCH_SIZE (4543.1 + 3 x 8942.0) / 4 KiB x 2.00 + WRITE_SIZE 8193.3 KiB
     "k_ctqw_torus_sweep<float2,5> 1024x1024": ((4543.1 + 3 * 8942.0) / 4 * 2 + 8193.3) * 1024,
@@ -584,7 +584,7 @@ def run_batch(args):
 
     value = arc_steps / wall
     l2_max = max(l2s) if l2s else None
-    kname = "k_batch_ell_lds<float2,1024,6,18432>" if stage_kernel == "lds" else "k_batch_stage<float2>"
+    kname = "k_batch_ell_lds<float2,768,9,19968>" if stage_kernel == "lds" else "k_batch_stage<float2>"
     traffic_key = f"{kname} batch{len(plans)} seed{args.batch_seed} launches{La}-{Lb}"
     traffic = MEASURED_TRAFFIC.get(traffic_key)
     line = {

@@ -486,7 +486,8 @@ int qw_batch_readout(qw_batch *batch, int32_t slot, double *d_p, double *d_norm,
 int qw_batch_set_schedule(qw_batch *batch, int32_t rows_per_tile, int32_t xcd_aware);
 /* Kernel for the Horner stages of CTQW walks on regular graphs of degree <= 8
  * (plans on the ELL path; the series of Sec. 3.1's evolution operator).
- * QW_BATCH_LDS (the default): tiles of 6144 rows, one workgroup each, that
+ * QW_BATCH_LDS (the default): tiles of 6912 rows (complex64) or 6144
+ * (complex128), one workgroup each, that
  * pass over the walk's input vector in LDS-staged blocks, so the neighbour
  * gathers read LDS instead of L2 (walks whose state and workspace are 16-byte
  * aligned and whose state holds at least 16 bytes; others, like every other

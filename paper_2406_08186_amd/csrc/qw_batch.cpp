@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kCoefStride = 128;  // doubles per slot: alpha[64], beta[64]
 constexpr int kMaxGrid = 2048;    // 8 workgroups per CU at 256 CUs
-constexpr int kLdsMaxGrid = 256;  // the LDS-staged kernel: one workgroup per CU (144 KiB of LDS each)
+constexpr int kLdsMaxGrid = 256;  // the LDS-staged kernel: one workgroup per CU (144-156 KiB of LDS each)
 constexpr int kGraphChunk = 16;   // launches per captured graph
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -194,7 +194,7 @@ int build_table(qw_batch *b) {
     const qw_plan *p = b->plans[s];
     if (w.kind == QW_CTQW) {
       const bool lds = lds_slot(b, w);
-      const int R = lds ? kLdsTileRows : b->rows_per_tile;
+      const int R = lds ? (b->dtype == QW_C128 ? kLdsTileRows128 : kLdsTileRows64) : b->rows_per_tile;
       for (int64_t r = 0; r < p->n; r += R)
         it.tiles.push_back({s, static_cast<int32_t>(r), static_cast<int32_t>(std::min<int64_t>(p->n, r + R)), 0});
       it.load = p->n_arcs + 3 * p->n;

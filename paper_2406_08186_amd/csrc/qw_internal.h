@@ -13,9 +13,17 @@ namespace qwk {
 // one workgroup's LDS tile are processed together.
 constexpr int kTileArcs = 2048;
 constexpr int kTileThreads = 256;
-constexpr int kLdsTileThreads = 1024;          // workgroup of the LDS-staged batch stage
-constexpr int kLdsTileRows = 6144;             // rows per tile of that kernel (6 per thread)
-constexpr int kLdsBlockBytes = 144 * 1024;     // LDS block of the input vector it stages
+// The LDS-staged batch stage, per state type: workgroup size, rows per tile
+// (a whole number per thread) and the LDS block of the input vector it
+// stages (whole rounds of 1 KiB direct loads by every wavefront).  complex64:
+// 768 threads x 9 rows, 156 KiB blocks; complex128 (whose sum registers are
+// twice as wide): 1024 threads x 6 rows, 144 KiB blocks.
+constexpr int kLdsTileThreads64 = 768;
+constexpr int kLdsTileRows64 = 6912;
+constexpr int kLdsBlockBytes64 = 156 * 1024;
+constexpr int kLdsTileThreads128 = 1024;
+constexpr int kLdsTileRows128 = 6144;
+constexpr int kLdsBlockBytes128 = 144 * 1024;
 // single-walk ELL stage: vectors above kEllSliceFrom bytes are gathered in
 // slices of kEllSliceEntries entries (measured best on 2^20 vertices for both
 // types, against 64Ki and 256Ki: 1 MiB complex64, 2 MiB complex128).  The
@@ -301,8 +309,9 @@ hipError_t ctqw_direct_stage(bool c128, const GraphView &g, const int32_t *wg_ro
                              const int32_t *hcol, int64_t split, const void *y, const void *psi, void *out,
                              double alpha, double beta, hipStream_t s);
 // The LDS-staged stage of the batch's CTQW walks on the ELL layout (degree
-// <= 8): tiles of kLdsTileRows rows, one workgroup of kLdsTileThreads each, the
-// input vector staged in blocks of kLdsBlockBytes.  The last workgroup
+// <= 8): tiles of kLdsTileRows64/128 rows, one workgroup of
+// kLdsTileThreads64/128 each, the input vector staged in blocks of
+// kLdsBlockBytes64/128.  The last workgroup
 // advances the launch counter when `advance` is nonzero.
 hipError_t batch_ell_lds(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
                          const int32_t *n_tiles, int grid, int advance, hipStream_t s);

@@ -1914,9 +1914,10 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_stage(BatchCtl *ctl, con
 // those of the gather kernels.  Blocks are staged by LDS-direct loads
 // (global_load_lds_dwordx4: each lane's 16 bytes land at the wave's LDS base
 // plus 16 * lane, 1 KiB per wave instruction), which need no registers and no
-// LDS write instructions; the registers that a prefetch would hold carry six
-// rows per thread instead of four, so a walk has a third fewer tiles to pass
-// over its vector.  Every lane visits all 8 neighbour slots of its rows in
+// LDS write instructions; the registers that a prefetch would hold carry more
+// rows per thread (complex64: 9 of 768 threads; complex128: 6 of 1024; the
+// register-prefetching form fitted 4), so a walk has fewer tiles to pass over
+// its vector.  Every lane visits all 8 neighbour slots of its rows in
 // every block (branch-free; a slot outside the block adds -0), so the sum loop
 // costs 8 LDS reads per row and block: the kernel pays for walks whose vector
 // spans many blocks.  Memory is reached through global-address-space views of
@@ -2793,13 +2794,16 @@ hipError_t ctqw_direct_stage(bool c128, const GraphView &g, const int32_t *wg_ro
 hipError_t batch_ell_lds(bool c128, BatchCtl *ctl, const WalkSlot *slots, const TileEntry *tiles,
                          const int32_t *n_tiles, int grid, int advance, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  constexpr int NT = kLdsTileThreads, RPL = kLdsTileRows / kLdsTileThreads;
+  static_assert(kLdsTileRows64 % kLdsTileThreads64 == 0 && kLdsTileRows128 % kLdsTileThreads128 == 0,
+                "whole rows per thread");
   if (c128)
-    hipLaunchKernelGGL((k_batch_ell_lds<double2, NT, RPL, kLdsBlockBytes / 16>), dim3(grid), dim3(NT), 0, s, ctl,
-                       slots, tiles, n_tiles, advance);
+    hipLaunchKernelGGL((k_batch_ell_lds<double2, kLdsTileThreads128, kLdsTileRows128 / kLdsTileThreads128,
+                                        kLdsBlockBytes128 / 16>),
+                       dim3(grid), dim3(kLdsTileThreads128), 0, s, ctl, slots, tiles, n_tiles, advance);
   else
-    hipLaunchKernelGGL((k_batch_ell_lds<float2, NT, RPL, kLdsBlockBytes / 8>), dim3(grid), dim3(NT), 0, s, ctl,
-                       slots, tiles, n_tiles, advance);
+    hipLaunchKernelGGL((k_batch_ell_lds<float2, kLdsTileThreads64, kLdsTileRows64 / kLdsTileThreads64,
+                                        kLdsBlockBytes64 / 8>),
+                       dim3(grid), dim3(kLdsTileThreads64), 0, s, ctl, slots, tiles, n_tiles, advance);
   return hipGetLastError();
 }
 

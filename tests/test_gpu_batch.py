@@ -258,8 +258,8 @@ def _relabelled(n, edges, seed, name):
 
 def _lds_walks():
     """CTQW walks on regular graphs of degree 1..8 (the LDS-staged kernel), sized around its
-    tile (6144 rows) and block (18432 complex64 / 9216 complex128 entries) edges, marks on
-    those edges, odd and even n (complex64 stages pairs of entries with 16-byte loads, so an
+    tiles (6912 complex64 / 6144 complex128 rows) and blocks (19968 / 9216 entries, and
+    18432) edges, marks on those edges, odd and even n (complex64 stages pairs of entries with 16-byte loads, so an
     odd n leaves a last entry alone; the tiniest walks have 4 and 7 vertices); the largest
     also exceeds the size from which the single-walk path gathers in column slices
     (7.5 MiB)."""
@@ -277,6 +277,8 @@ def _lds_walks():
         (cyc(16385, 26), dict(gamma=0.5, dt=0.3, taylor_order=12, marked=[16384]), 4),
         (I.random_regular(12289, 4, seed=39), dict(gamma=0.25, dt=0.4, taylor_order=13, marked=[12288]), 4),
         (cyc(18433, 27), dict(gamma=0.5, dt=0.3, taylor_order=12, marked=[18432]), 4),
+        (cyc(19969, 28), dict(gamma=0.5, dt=0.3, taylor_order=12, marked=[19968]), 4),
+        (I.random_regular(6914, 3, seed=43), dict(gamma=1 / 3, dt=0.5, taylor_order=12, marked=[6912]), 4),
         (I.random_regular(9218, 3, seed=40), dict(gamma=1 / 3, dt=0.5, taylor_order=12, marked=[9216]), 4),
         (I.random_regular(36865, 4, seed=42), dict(gamma=0.25, dt=0.4, taylor_order=12, marked=[36864]), 3),
         (matching, dict(gamma=1.0, dt=0.4, taylor_order=10, marked=[4095]), 5),
